@@ -1,0 +1,61 @@
+"""Write the stored expected values used by the full-size GPU parity tests.
+
+Every number here is computed by the CPU oracle (oracle/) from the seeded
+inputs (cigen); nothing comes from the GPU library.  Run from the repository
+root:  python tests/golden/make_golden.py [workload ...]
+
+Per workload it stores the basis dimension, the nonzero counts (from the
+brute-force pattern, cross-checked against the class-pair count), and the
+lowest eigenvalues of H in float64 and of the float32-rounded H (both by
+ARPACK on the oracle's half-stored matrix, D <= 2e4 also by dense LAPACK).
+"""
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import cigen  # noqa: E402
+import oracle as O  # noqa: E402
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def make(name):
+    w = cigen.WORKLOADS[name]
+    t0 = time.time()
+    b = O.Basis(w.spec)
+    tables = cigen.make_tables(w.spec, w.seed)
+    inter = O.Interaction(b, tables)
+    rp, col, val = O.half_csr(b, inter)
+    full, half = O.nnz_class_count(w.spec)
+    assert half == int(rp[-1]), (half, int(rp[-1]))
+    k = max(w.nev, 10) + 3
+    ev64, _ = O.eigs_sparse(rp, col, val, k)
+    val32 = val.astype(np.float32).astype(np.float64)
+    ev32, _ = O.eigs_sparse(rp, col, val32, k)
+    out = dict(workload=name, spec=dict(n_species=w.spec.n_species, nmax=list(w.spec.nmax),
+                                        n_particles=list(w.spec.n_particles),
+                                        two_M=w.spec.two_M, cut=w.spec.cut),
+               seed=w.seed, D=b.D, nnz_half=half, nnz_full=full,
+               evals_f64=ev64[:k - 3].tolist(), evals_f32H=ev32[:k - 3].tolist(),
+               diag_first=val[rp[:-1][:8]].tolist(),
+               method="ARPACK eigsh(which='SA', tol=1e-13) on the oracle half CSR",
+               source="tests/golden/make_golden.py (oracle/ and cigen/ only)")
+    if b.D <= 20100:
+        H = O.full_from_half(rp, col, val, b.D).toarray()
+        out["evals_f64_lapack"] = O.eigs_dense(H, k - 3).tolist()
+    out["seconds"] = round(time.time() - t0, 1)
+    with open(os.path.join(HERE, name + ".json"), "w") as f:
+        json.dump(out, f, indent=1)
+    print(name, b.D, half, out["seconds"], "s", flush=True)
+
+
+if __name__ == "__main__":
+    names = sys.argv[1:] or list(cigen.WORKLOADS)
+    for n in names:
+        make(n)
