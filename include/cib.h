@@ -1,0 +1,269 @@
+/* cib.h -- configuration-interaction Hamiltonian engine for AMD MI355X (gfx950).
+ *
+ * C ABI of the data-parallel hot path of a configuration-interaction (CI)
+ * calculation as described in "Accelerating quantum many-body configuration
+ * interaction with directives" (Cook, Fasano, Maris, Yang, Oryspayev):
+ *
+ *   cib_build_basis  Slater-determinant bit-string basis (Sec. 2; Fig. 1 step 1)
+ *   cib_build_H      pair screen by popcount(xor) <= 4, fermionic phase and
+ *                    two-body matrix-element lookup, counts -> offsets -> fill
+ *                    of a half-stored symmetric CSR (Sec. 2.1-2.3; Fig. 1
+ *                    steps 2-14)
+ *   cib_apply_H      symmetric SpMM Y = H X (Sec. 2: sparse matrix-matrix
+ *                    products of the eigensolver; Fig. 2 'FMA' variant)
+ *   cib_lobpcg       lowest eigenpairs by block LOBPCG (Fig. 1 step 15)
+ *   cib_serve        continuous-batching loop over many eigensolve requests
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Status: every call returns CIB_OK (0) or a negative cib_status.  Out
+ *   parameters are written only on CIB_OK (cib_lobpcg also fills eigenvalues
+ *   and residuals on CIB_E_NOT_CONVERGED).  cib_last_error() returns a
+ *   message for the calling thread's most recent failure; the string stays
+ *   valid until the thread's next cib_* call.  No C++ exception crosses the
+ *   ABI.  Arguments are validated before any device work is launched.
+ * Ownership: handles (cib_ctx, cib_basis, cib_matrix, cib_interaction) are
+ *   owned by the library and released with the matching cib_*_free /
+ *   cib_destroy.  Host arrays passed in are owned by the caller and are
+ *   copied before the call returns.  Device pointers passed to cib_apply_H /
+ *   cib_lobpcg are owned by the caller and must stay valid until the context
+ *   stream has passed the call.
+ * Streams: a context issues all of its device work on one HIP stream (the
+ *   caller's, or one it creates).  Calls on one context are not thread-safe;
+ *   use one context per host thread.
+ * Integers: offsets and counts that can exceed 2^31 are int64 (row
+ *   pointers, nonzero counts, dimensions).
+ */
+#ifndef CIB_H
+#define CIB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t cib_status;
+#define CIB_OK 0
+#define CIB_E_INVALID (-1)       /* bad argument or spec                     */
+#define CIB_E_NOMEM (-2)         /* allocator returned NULL / over budget    */
+#define CIB_E_DEVICE (-3)        /* HIP runtime error                        */
+#define CIB_E_NOT_CONVERGED (-4) /* max_iter reached before the tolerance    */
+#define CIB_E_OVERFLOW (-5)      /* a count exceeds the index type           */
+#define CIB_E_EMPTY_BASIS (-6)   /* the spec admits no state (D = 0)         */
+#define CIB_E_BUSY (-7)          /* context already inside a call            */
+#define CIB_E_CANCELLED (-8)     /* deadline reached                         */
+
+typedef enum { CIB_F64 = 0, CIB_F32 = 1 } cib_dtype;
+
+typedef struct cib_ctx cib_ctx;
+typedef struct cib_basis cib_basis;
+typedef struct cib_interaction cib_interaction;
+typedef struct cib_matrix cib_matrix;
+
+/* Device-memory hooks.  alloc returns device memory of at least `bytes`
+ * (256-byte aligned) or NULL; free releases it.  NULL hooks: hipMalloc and
+ * hipFree behind a per-context cache of freed blocks. */
+typedef struct {
+  void *(*alloc)(size_t bytes, void *user);
+  void (*free)(void *ptr, void *user);
+  void *user;
+} cib_allocator;
+
+/* Create a context on HIP device `device`.  hip_stream: a hipStream_t to issue
+ * work on (NULL: the context creates its own default-priority stream). */
+cib_status cib_create(int device, const cib_allocator *alloc, void *hip_stream, cib_ctx **out);
+void cib_destroy(cib_ctx *ctx);
+const char *cib_last_error(void);
+/* Device bytes currently held by the context's allocations (live, not cached). */
+cib_status cib_ctx_bytes(const cib_ctx *ctx, int64_t *live_bytes, int64_t *peak_bytes);
+
+/* ---------------------------------------------------------------- basis --
+ * Sec. 2: many-body states are antisymmetrised products of single-particle
+ * states.  Single-particle orbitals of one species are harmonic-oscillator
+ * shells n = 0..nmax; shell n has levels 2j = 1..2n+1 (odd) and each level the
+ * projections 2m = -2j..2j step 2, in ascending (n, 2j, 2m) order (orbital
+ * index = position).  A state is an N_A-subset of species-A orbitals times an
+ * N_B-subset of species-B orbitals with sum(2m) = two_M and, if cut >= 0,
+ * sum over all particles of n <= Qmin(N_A) + Qmin(N_B) + cut (Qmin fills the
+ * shells from n = 0).  n_species = 1: species B is absent (nmax[1] and
+ * n_particles[1] are ignored).
+ *
+ * Bit string BIN(Phi) (Sec. 2.1): bit k of species s is orbital k of s.  Each
+ * species occupies ceil(n_orb/64) little-endian 64-bit words (at most 3:
+ * nmax <= 6).
+ *
+ * Canonical order of the basis: ascending (A bits as an unsigned integer,
+ * summed quanta Q_B of species B, B bits as an unsigned integer).  Within the
+ * states of one A configuration ("A-block", the grouping of Sec. 2 into
+ * many-body basis orbitals) the B configurations therefore form a prefix of
+ * one list per 2M_B ordered by (Q_B, B).
+ */
+typedef struct {
+  int32_t n_species;      /* 1 or 2                                        */
+  int32_t nmax[2];        /* highest shell per species, 0..6               */
+  int32_t n_particles[2]; /* particles per species, 1..n_orb               */
+  int32_t two_M;          /* twice the total projection                    */
+  int32_t cut;            /* summed-quanta truncation above minimum; <0: none */
+} cib_basis_spec;
+
+/* Enumerate the basis on the device.  *dim receives D.  Errors:
+ * CIB_E_INVALID (n_species not 1/2, nmax outside 0..6, N outside 1..n_orb,
+ * two_M parity differs from N_A + N_B), CIB_E_EMPTY_BASIS (D = 0),
+ * CIB_E_OVERFLOW (D >= 2^31). */
+cib_status cib_build_basis(cib_ctx *ctx, const cib_basis_spec *spec, cib_basis **out, int64_t *dim);
+/* D, words per species (species B: 0 when absent), orbitals per species, and
+ * the number of non-empty A-blocks. */
+cib_status cib_basis_info(const cib_basis *b, int64_t *dim, int32_t words[2], int32_t n_orb[2],
+                          int64_t *n_ablocks);
+/* Copy the basis to caller-owned host memory: D x (words[0] + words[1])
+ * uint64, state-major, species A words first.  Synchronises the ctx stream. */
+cib_status cib_basis_export(const cib_basis *b, uint64_t *host_words);
+void cib_basis_free(cib_basis *b);
+
+/* ----------------------------------------------------------- interaction --
+ * H = sum_s sum_a eps^s_a n_a
+ *   + sum_s sum_{a<b, c<d} V^s_{ab,cd} a+_a a+_b a_d a_c
+ *   + sum_{a,c in A; b,d in B} V^AB_{ab,cd} a+_a b+_b b_d a_c
+ * Table layout ("M-blocked"): pairs are grouped by 2M_pair = 2m_a + 2m_b in
+ * ascending order; inside a block pairs are lexicographic in (a, b).
+ * Same-species pairs have a < b; cross-species pairs are all (a in A, b in B).
+ * Each block is a full n_M x n_M row-major matrix, blocks concatenated; the
+ * value for creation pair p and annihilation pair q is block[p * n_M + q].
+ * The library reads only what the operator needs and does not require the
+ * blocks to be symmetric, but H is symmetric only if they are.
+ * Sign convention: a creation or annihilation operator acting on global mode
+ * k (species A orbital k, or species B orbital k + n_orb[0]) contributes
+ * (-1)^(occupied modes below k). */
+typedef struct {
+  const double *eps[2];    /* one-body energies, n_orb[s] each              */
+  const double *v_same[2]; /* same-species blocked tables                   */
+  const double *v_ab;      /* cross-species blocked table; NULL for 1 species */
+} cib_tables;
+
+/* Upload the tables for `basis`'s orbital sets (host arrays, copied). */
+cib_status cib_upload_interaction(cib_ctx *ctx, const cib_basis *basis, const cib_tables *t,
+                                  cib_interaction **out);
+void cib_interaction_free(cib_interaction *it);
+
+/* -------------------------------------------------------------- build H --
+ * H_ij = <Phi_i|H|Phi_j> stored as the upper triangle (j >= i, diagonal first)
+ * in CSR: int64 row_ptr[D+1], int32 col[nnz_half] ascending within a row,
+ * values float64 or float32 (float32 = round-to-nearest-even of the float64
+ * value).  The stored pattern is structural: every pair whose bit strings
+ * differ in at most four orbitals (Sec. 2.1), whether or not its value is
+ * zero.  Counting pass, counts -> offsets prefix sum, and a filling pass
+ * (Fig. 1 steps 6-14; Sec. 2.2-2.3) with a deterministic in-row order.
+ * One host synchronisation (the nonzero total sizes the allocation). */
+cib_status cib_build_H(cib_ctx *ctx, const cib_basis *basis, const cib_tables *t, cib_dtype dtype,
+                       cib_matrix **out, int64_t *nnz_half);
+/* Same, with tables already on the device. */
+cib_status cib_build_H_resident(cib_ctx *ctx, const cib_basis *basis, const cib_interaction *it,
+                                cib_dtype dtype, cib_matrix **out, int64_t *nnz_half);
+
+typedef struct {
+  /* device time of each stage of the last build, from HIP events, seconds */
+  double t_screen_s;  /* A-configuration tile screen + B-configuration adjacency */
+  double t_count_s;   /* per-row counting pass                           */
+  double t_scan_s;    /* counts -> offsets                               */
+  double t_fill_s;    /* per-row filling pass                            */
+  double t_total_s;   /* sum of the above                                */
+  int64_t n_tiles;    /* A-configuration pairs kept by the screen        */
+  int64_t n_adjacent; /* B-configuration pairs kept by the screen        */
+} cib_build_stats;
+
+cib_status cib_matrix_info(const cib_matrix *H, int64_t *dim, int64_t *nnz_half, cib_dtype *dtype);
+cib_status cib_matrix_stats(const cib_matrix *H, cib_build_stats *stats);
+/* Copy the CSR to caller-owned host arrays (any may be NULL to skip).
+ * val receives nnz_half elements of the matrix dtype.  Synchronises. */
+cib_status cib_matrix_export(const cib_matrix *H, int64_t *row_ptr, int32_t *col, void *val);
+/* Device pointers of the CSR arrays (owned by the matrix). */
+cib_status cib_matrix_device(const cib_matrix *H, const int64_t **row_ptr, const int32_t **col,
+                             const void **val);
+void cib_matrix_free(cib_matrix *H);
+
+/* -------------------------------------------------------------- apply H --
+ * Y = H X for nvec vectors (1..64).  X and Y are device arrays of the matrix
+ * dtype, D rows, row-major: element (i, v) at X[i * ldx + v], ldx >= nvec
+ * (same for Y).  Asynchronous on the context stream; Y is overwritten.  The
+ * transposed half of the matrix is applied with device atomics, so results
+ * may differ in the last bits between calls. */
+cib_status cib_apply_H(cib_ctx *ctx, const cib_matrix *H, const void *X, int64_t ldx, void *Y,
+                       int64_t ldy, int32_t nvec);
+
+/* --------------------------------------------------------------- LOBPCG --
+ * Lowest nev eigenpairs of H (Fig. 1 step 15) by block LOBPCG with block size
+ * `block` (nev <= block <= 16, 3*block <= D).  Search space [X, W, P]; all
+ * dense work (Gram matrices, Rayleigh-Ritz, residual norms) in float64 on the
+ * device; the SpMM runs in the matrix dtype.  Preconditioner: diagonal,
+ * W = R / (diag(H) - lambda) with |diag - lambda| clamped below at 1e-2.
+ * Converged when ||H x_k - lambda_k x_k|| <= tol * max(|lambda_k|, 1) for all
+ * k < nev (tol <= 0: 1e-9 for float64 H, 1e-6 for float32 H).
+ * X0: unit vectors at the `block` smallest diagonal entries (ties: lower
+ * index) plus 1e-3 * noise from a counter-based generator keyed by `seed`,
+ * unless x0 (device, D x block float64 row-major) is given. */
+typedef struct {
+  int32_t nev, block, max_iter;
+  double tol;
+  uint64_t seed;
+  const double *x0;
+} cib_lobpcg_opts;
+
+typedef struct {
+  int32_t iters, n_converged;
+  double resid[64];     /* relative residual per eigenpair                 */
+  double t_total_s;     /* wall time of the call                           */
+  double t_spmm_s;      /* device time in the SpMM (events)                */
+  int64_t n_spmm;       /* SpMM launches                                   */
+} cib_lobpcg_info;
+
+/* evals: host, nev float64.  evecs: device, D x nev float64 row-major with
+ * leading dimension ld_evecs (>= nev), or NULL. */
+cib_status cib_lobpcg(cib_ctx *ctx, const cib_matrix *H, const cib_lobpcg_opts *opts, double *evals,
+                      double *evecs, int64_t ld_evecs, cib_lobpcg_info *info);
+
+/* ---------------------------------------------------------------- serve --
+ * Continuous batching of eigensolve requests.  Requests arrive at arrival_s
+ * (relative to the call start; replayed in real time when opts->realtime,
+ * else all are available at once).  A request is admitted when a slot is free
+ * (max_active) and its device footprint fits the HBM budget; each step of the
+ * loop advances every active request by one stage (basis, H build, LOBPCG
+ * initialisation, one LOBPCG iteration) on a pool of streams so that the
+ * requests' work overlaps, reads all convergence flags back in one
+ * transfer, and retires finished requests, releasing their memory. */
+typedef struct {
+  uint64_t id;
+  double arrival_s;
+  cib_basis_spec basis;
+  const cib_tables *tables;  /* host, read during the call */
+  cib_dtype dtype;
+  cib_lobpcg_opts solve;     /* nev <= 16; x0 must be NULL */
+} cib_request;
+
+typedef struct {
+  uint64_t id;
+  cib_status status;         /* CIB_OK, CIB_E_NOT_CONVERGED, CIB_E_EMPTY_BASIS, ... */
+  int64_t dim, nnz_half;
+  int32_t iters;
+  double evals[16], resid[16];
+  double t_arrive, t_admit, t_done;  /* seconds since the call started */
+} cib_result;
+
+typedef struct {
+  size_t hbm_budget_bytes;   /* 0: 90% of free device memory at the call   */
+  int32_t max_active;        /* <= 0: 64                                    */
+  int32_t realtime;          /* honour arrival_s in wall-clock time         */
+  double deadline_s;         /* <= 0: none; later requests get CIB_E_CANCELLED */
+  int32_t n_streams;         /* <= 0: 8                                     */
+} cib_serve_opts;
+
+/* results: caller-owned array of n.  The return value reports only
+ * infrastructure failure; per-request outcome is in results[i].status. */
+cib_status cib_serve(cib_ctx *ctx, const cib_request *reqs, int32_t n, const cib_serve_opts *opts,
+                     cib_result *results);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CIB_H */

@@ -1,0 +1,318 @@
+// extern "C" entry points: argument checks, error translation, handle life.
+#include <chrono>
+#include <memory>
+
+#include "cib_internal.hpp"
+
+namespace cib {
+const char *last_error_cstr();
+cib_interaction *upload_interaction(cib_ctx *ctx, const cib_basis &b, const cib_tables &t);
+}  // namespace cib
+
+using namespace cib;
+
+namespace {
+
+template <typename F>
+cib_status guarded(F &&f) {
+  try {
+    f();
+    set_last_error("");
+    return CIB_OK;
+  } catch (const cib::Error &e) {
+    set_last_error(e.what());
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    set_last_error("host allocation failed");
+    return CIB_E_NOMEM;
+  } catch (const std::exception &e) {
+    set_last_error(e.what());
+    return CIB_E_DEVICE;
+  } catch (...) {
+    set_last_error("unknown error");
+    return CIB_E_DEVICE;
+  }
+}
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    CIB_HIP(hipGetDevice(&prev));
+    if (prev != dev) CIB_HIP(hipSetDevice(dev));
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (hipGetDevice(&cur) == hipSuccess && cur != prev && prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+struct BusyGuard {
+  cib_ctx *c;
+  explicit BusyGuard(cib_ctx *ctx) : c(ctx) {
+    CIB_REQUIRE(!c->busy, CIB_E_BUSY, "context is already inside a call");
+    c->busy = true;
+  }
+  ~BusyGuard() { c->busy = false; }
+};
+
+}  // namespace
+
+extern "C" {
+
+const char *cib_last_error(void) { return last_error_cstr(); }
+
+cib_status cib_create(int device, const cib_allocator *a, void *hip_stream, cib_ctx **out) {
+  return guarded([&] {
+    CIB_REQUIRE(out, CIB_E_INVALID, "out is NULL");
+    int n = 0;
+    CIB_HIP(hipGetDeviceCount(&n));
+    CIB_REQUIRE(device >= 0 && device < n, CIB_E_INVALID, "no such device");
+    if (a) CIB_REQUIRE(a->alloc && a->free, CIB_E_INVALID, "allocator needs alloc and free");
+    std::unique_ptr<cib_ctx> c(new cib_ctx);
+    c->device = device;
+    DeviceGuard g(device);
+    if (a) { c->user = *a; c->has_user = true; }
+    if (hip_stream) {
+      c->stream = static_cast<hipStream_t>(hip_stream);
+    } else {
+      CIB_HIP(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+      c->own_stream = true;
+    }
+    *out = c.release();
+  });
+}
+
+void cib_destroy(cib_ctx *ctx) {
+  if (!ctx) return;
+  try {
+    DeviceGuard g(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    ctx->release_cache();
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+  } catch (...) {
+  }
+  delete ctx;
+}
+
+cib_status cib_ctx_bytes(const cib_ctx *ctx, int64_t *live, int64_t *peak) {
+  return guarded([&] {
+    CIB_REQUIRE(ctx, CIB_E_INVALID, "ctx is NULL");
+    if (live) *live = ctx->live;
+    if (peak) *peak = ctx->peak;
+  });
+}
+
+// ------------------------------------------------------------------ basis
+cib_status cib_build_basis(cib_ctx *ctx, const cib_basis_spec *spec, cib_basis **out, int64_t *dim) {
+  return guarded([&] {
+    CIB_REQUIRE(ctx && spec && out, CIB_E_INVALID, "NULL argument");
+    BusyGuard busy(ctx);
+    DeviceGuard g(ctx->device);
+    std::unique_ptr<cib_basis> b(new cib_basis);
+    b->ctx = ctx;
+    make_plan(*spec, b->plan);
+    const Plan &p = b->plan;
+    CIB_REQUIRE(p.D > 0, CIB_E_EMPTY_BASIS, "the spec admits no state");
+    CIB_REQUIRE(p.D < (int64_t(1) << 31), CIB_E_OVERFLOW, "basis dimension exceeds 2^31-1");
+    hipStream_t s = ctx->stream;
+    const int W = p.W, nA = p.nA(), nB = p.nB();
+    std::vector<uint64_t> soa((size_t)W * nA);
+    for (int k = 0; k < nA; ++k)
+      for (int w = 0; w < W; ++w) soa[(size_t)w * nA + k] = p.A.bits[(size_t)k * kMaxWords + w];
+    b->a_bits.reset(ctx, soa.size());
+    b->a_bits.upload(soa.data(), soa.size(), s);
+    std::vector<uint64_t> sob((size_t)W * nB);
+    for (int k = 0; k < nB; ++k)
+      for (int w = 0; w < W; ++w) sob[(size_t)w * nB + k] = p.B.bits[(size_t)k * kMaxWords + w];
+    b->b_bits.reset(ctx, sob.size());
+    b->b_bits.upload(sob.data(), sob.size(), s);
+    auto up32 = [&](DBuf<int32_t> &d, const std::vector<int32_t> &h) {
+      d.reset(ctx, std::max<size_t>(h.size(), 1));
+      d.upload(h.data(), h.size(), s);
+    };
+    up32(b->a_m2, p.A.m2);
+    up32(b->a_q, p.A.q);
+    up32(b->a_len, p.a_len);
+    up32(b->a_seg, p.a_seg);
+    up32(b->b_m2, p.B.m2);
+    up32(b->b_q, p.B.q);
+    up32(b->b_seg, p.b_seg);
+    up32(b->bseg_start, p.bseg_start);
+    b->a_off.reset(ctx, p.a_off.size());
+    b->a_off.upload(p.a_off.data(), p.a_off.size(), s);
+    b->row_a.reset(ctx, p.D);
+    b->row_p.reset(ctx, p.D);
+    b->words.reset(ctx, (size_t)(p.WA + p.WB) * p.D);
+    launch_expand_basis(*b, s);
+    CIB_HIP(hipStreamSynchronize(s));  // host staging vectors go out of scope
+    if (dim) *dim = p.D;
+    *out = b.release();
+  });
+}
+
+cib_status cib_basis_info(const cib_basis *b, int64_t *dim, int32_t words[2], int32_t n_orb[2],
+                          int64_t *n_ablocks) {
+  return guarded([&] {
+    CIB_REQUIRE(b, CIB_E_INVALID, "basis is NULL");
+    if (dim) *dim = b->plan.D;
+    if (words) { words[0] = b->plan.WA; words[1] = b->plan.WB; }
+    if (n_orb) { n_orb[0] = b->plan.oA.n_orb; n_orb[1] = b->plan.ns == 2 ? b->plan.oB.n_orb : 0; }
+    if (n_ablocks) *n_ablocks = b->plan.nA();
+  });
+}
+
+cib_status cib_basis_export(const cib_basis *b, uint64_t *host_words) {
+  return guarded([&] {
+    CIB_REQUIRE(b && host_words, CIB_E_INVALID, "NULL argument");
+    DeviceGuard g(b->ctx->device);
+    const Plan &p = b->plan;
+    const int nw = p.WA + p.WB;
+    std::vector<uint64_t> soa((size_t)nw * p.D);
+    CIB_HIP(hipMemcpyAsync(soa.data(), b->words.p, soa.size() * sizeof(uint64_t),
+                           hipMemcpyDeviceToHost, b->ctx->stream));
+    CIB_HIP(hipStreamSynchronize(b->ctx->stream));
+    for (int64_t i = 0; i < p.D; ++i)
+      for (int w = 0; w < nw; ++w) host_words[i * nw + w] = soa[(size_t)w * p.D + i];
+  });
+}
+
+void cib_basis_free(cib_basis *b) {
+  if (!b) return;
+  try {
+    DeviceGuard g(b->ctx->device);
+    (void)hipStreamSynchronize(b->ctx->stream);
+  } catch (...) {
+  }
+  delete b;
+}
+
+// ------------------------------------------------------------ interaction
+cib_status cib_upload_interaction(cib_ctx *ctx, const cib_basis *b, const cib_tables *t,
+                                  cib_interaction **out) {
+  return guarded([&] {
+    CIB_REQUIRE(ctx && b && t && out, CIB_E_INVALID, "NULL argument");
+    BusyGuard busy(ctx);
+    DeviceGuard g(ctx->device);
+    *out = upload_interaction(ctx, *b, *t);
+  });
+}
+
+void cib_interaction_free(cib_interaction *it) {
+  if (!it) return;
+  try {
+    DeviceGuard g(it->ctx->device);
+    (void)hipStreamSynchronize(it->ctx->stream);
+  } catch (...) {
+  }
+  delete it;
+}
+
+// ---------------------------------------------------------------- build H
+cib_status cib_build_H_resident(cib_ctx *ctx, const cib_basis *b, const cib_interaction *it,
+                                cib_dtype dt, cib_matrix **out, int64_t *nnz) {
+  return guarded([&] {
+    CIB_REQUIRE(ctx && b && it && out, CIB_E_INVALID, "NULL argument");
+    CIB_REQUIRE(dt == CIB_F64 || dt == CIB_F32, CIB_E_INVALID, "dtype must be CIB_F64 or CIB_F32");
+    CIB_REQUIRE(it->nA == b->plan.oA.n_orb && it->nB == (b->plan.ns == 2 ? b->plan.oB.n_orb : 0),
+                CIB_E_INVALID, "interaction was uploaded for another orbital set");
+    BusyGuard busy(ctx);
+    DeviceGuard g(ctx->device);
+    std::unique_ptr<cib_matrix> H(new cib_matrix);
+    H->ctx = ctx;
+    build_matrix(ctx, *b, *it, dt, *H);
+    if (nnz) *nnz = H->nnz;
+    *out = H.release();
+  });
+}
+
+cib_status cib_build_H(cib_ctx *ctx, const cib_basis *b, const cib_tables *t, cib_dtype dt,
+                       cib_matrix **out, int64_t *nnz) {
+  cib_interaction *it = nullptr;
+  cib_status st = cib_upload_interaction(ctx, b, t, &it);
+  if (st != CIB_OK) return st;
+  st = cib_build_H_resident(ctx, b, it, dt, out, nnz);
+  std::string err = st == CIB_OK ? "" : cib_last_error();
+  cib_interaction_free(it);
+  if (st != CIB_OK) set_last_error(err);
+  return st;
+}
+
+cib_status cib_matrix_info(const cib_matrix *H, int64_t *dim, int64_t *nnz, cib_dtype *dt) {
+  return guarded([&] {
+    CIB_REQUIRE(H, CIB_E_INVALID, "matrix is NULL");
+    if (dim) *dim = H->D;
+    if (nnz) *nnz = H->nnz;
+    if (dt) *dt = H->dtype;
+  });
+}
+
+cib_status cib_matrix_stats(const cib_matrix *H, cib_build_stats *st) {
+  return guarded([&] {
+    CIB_REQUIRE(H && st, CIB_E_INVALID, "NULL argument");
+    *st = H->stats;
+  });
+}
+
+cib_status cib_matrix_export(const cib_matrix *H, int64_t *row_ptr, int32_t *col, void *val) {
+  return guarded([&] {
+    CIB_REQUIRE(H, CIB_E_INVALID, "matrix is NULL");
+    DeviceGuard g(H->ctx->device);
+    hipStream_t s = H->ctx->stream;
+    if (row_ptr)
+      CIB_HIP(hipMemcpyAsync(row_ptr, H->row_ptr.p, sizeof(int64_t) * (H->D + 1), hipMemcpyDeviceToHost, s));
+    if (col) CIB_HIP(hipMemcpyAsync(col, H->col.p, sizeof(int32_t) * H->nnz, hipMemcpyDeviceToHost, s));
+    if (val)
+      CIB_HIP(hipMemcpyAsync(val, H->val(), (H->dtype == CIB_F64 ? 8 : 4) * (size_t)H->nnz,
+                             hipMemcpyDeviceToHost, s));
+    CIB_HIP(hipStreamSynchronize(s));
+  });
+}
+
+cib_status cib_matrix_device(const cib_matrix *H, const int64_t **row_ptr, const int32_t **col,
+                             const void **val) {
+  return guarded([&] {
+    CIB_REQUIRE(H, CIB_E_INVALID, "matrix is NULL");
+    if (row_ptr) *row_ptr = H->row_ptr.p;
+    if (col) *col = H->col.p;
+    if (val) *val = H->val();
+  });
+}
+
+void cib_matrix_free(cib_matrix *H) {
+  if (!H) return;
+  try {
+    DeviceGuard g(H->ctx->device);
+    (void)hipStreamSynchronize(H->ctx->stream);
+  } catch (...) {
+  }
+  delete H;
+}
+
+// ---------------------------------------------------------------- apply H
+cib_status cib_apply_H(cib_ctx *ctx, const cib_matrix *H, const void *X, int64_t ldx, void *Y,
+                       int64_t ldy, int32_t nvec) {
+  return guarded([&] {
+    CIB_REQUIRE(ctx && H && X && Y, CIB_E_INVALID, "NULL argument");
+    CIB_REQUIRE(nvec >= 1 && nvec <= 64, CIB_E_INVALID, "nvec must be in 1..64");
+    CIB_REQUIRE(ldx >= nvec && ldy >= nvec, CIB_E_INVALID, "leading dimension smaller than nvec");
+    CIB_REQUIRE(H->ctx == ctx, CIB_E_INVALID, "matrix belongs to another context");
+    BusyGuard busy(ctx);
+    DeviceGuard g(ctx->device);
+    spmm_sym(*H, X, ldx, Y, ldy, nvec, ctx->stream);
+  });
+}
+
+}  // extern "C"
+
+// placeholders until the solver and the serving loop land
+extern "C" cib_status cib_lobpcg(cib_ctx *, const cib_matrix *, const cib_lobpcg_opts *, double *,
+                                 double *, int64_t, cib_lobpcg_info *) {
+  set_last_error("cib_lobpcg: not available in this build");
+  return CIB_E_INVALID;
+}
+extern "C" cib_status cib_serve(cib_ctx *, const cib_request *, int32_t, const cib_serve_opts *,
+                                cib_result *) {
+  set_last_error("cib_serve: not available in this build");
+  return CIB_E_INVALID;
+}

@@ -1,0 +1,677 @@
+// Hamiltonian construction on the device (Fig. 1 steps 1-14 of the paper).
+//
+// Two-level screen.  Every state is a pair (alpha, beta) of one species-A and
+// one species-B configuration, and popcount(BIN_i ^ BIN_j) is the sum of the
+// A and B popcounts, so the popcount(xor) <= 4 screen of Sec. 2.1 factorises:
+//   * tiles: A-configuration pairs (alpha, alpha') with popcount <= 4
+//     (kA = popcount/2 orbitals differ); the analogue of the tile screen over
+//     many-body basis orbitals of Fig. 1 steps 2-5;
+//   * adjacency: B-configuration pairs with popcount <= 4 in the same 2M_B
+//     list (used inside an A-block) and popcount <= 2 in any list (used by
+//     kA = 1 tiles); kA = 2 tiles pair each state with the same B position.
+// Per-pair phases and matrix elements that depend on one species only are
+// computed once per tile / adjacency entry; the per-row passes only combine
+// them.  Counting pass -> exclusive scan -> filling pass, one wave per row,
+// lanes over tiles, ballot/scan compaction: the columns of a row come out in
+// ascending order without atomics (Sec. 2.2-2.3).
+#include <algorithm>
+
+#include "cib_internal.hpp"
+#include "device_common.hpp"
+
+namespace cib {
+using namespace dev;
+
+// ------------------------------------------------------------ table access
+// V_{(a,b),(c,d)} for valid pairs of the blocked layout; 0 across 2M blocks.
+__device__ __forceinline__ double v_pair(const int32_t *pidx, int n2, const int64_t *vbase,
+                                         const int32_t *vn, const double *v, int a, int b, int c,
+                                         int d) {
+  const int pk = pidx[a * n2 + b], qk = pidx[c * n2 + d];
+  const int blk = pk >> 16;
+  if (blk != (qk >> 16)) return 0.0;
+  return v[vbase[blk] + (int64_t)(pk & 0xffff) * vn[blk] + (qk & 0xffff)];
+}
+
+// Antisymmetrised same-species element Vbar_{(a,x),(c,x)}: V stored for
+// ordered pairs, one sign flip per pair that has to be reordered.
+__device__ __forceinline__ double vbar_same(const int32_t *pidx, int n, const int64_t *vbase,
+                                            const int32_t *vn, const double *v, int a, int x,
+                                            int c) {
+  int s = 1, p0 = a, p1 = x, q0 = c, q1 = x;
+  if (a > x) { p0 = x; p1 = a; s = -s; }
+  if (c > x) { q0 = x; q1 = c; s = -s; }
+  return s * v_pair(pidx, n, vbase, vn, v, p0, p1, q0, q1);
+}
+
+__device__ __forceinline__ double vab(const DevInter &it, int a, int b, int c, int d) {
+  return v_pair(it.pidxAB, it.nB, it.vbaseAB, it.vnAB, it.vAB, a, b, c, d);
+}
+
+template <int W>
+__device__ __forceinline__ void load_bits(const uint64_t *soa, int64_t n, int64_t k, uint64_t *out) {
+#pragma unroll
+  for (int w = 0; w < W; ++w) out[w] = soa[(int64_t)w * n + k];
+}
+
+// ------------------------------------------------------------ basis expansion
+template <int W>
+__global__ __launch_bounds__(256) void k_expand_basis(int64_t D, int nA, int nB, int WA, int WB,
+                                                      const int64_t *__restrict__ a_off,
+                                                      const int32_t *__restrict__ a_seg,
+                                                      const int32_t *__restrict__ bseg_start,
+                                                      const uint64_t *__restrict__ a_bits,
+                                                      const uint64_t *__restrict__ b_bits,
+                                                      uint64_t *__restrict__ words,
+                                                      int32_t *__restrict__ row_a,
+                                                      int32_t *__restrict__ row_p) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= D) return;
+  int lo = 0, hi = nA;  // largest alpha with a_off[alpha] <= i
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (a_off[mid] <= i) lo = mid; else hi = mid;
+  }
+  const int p = (int)(i - a_off[lo]);
+  const int beta = bseg_start[a_seg[lo]] + p;
+  row_a[i] = lo;
+  row_p[i] = p;
+  for (int w = 0; w < WA; ++w) words[(int64_t)w * D + i] = a_bits[(int64_t)w * nA + lo];
+  for (int w = 0; w < WB; ++w) words[(int64_t)(WA + w) * D + i] = b_bits[(int64_t)w * nB + beta];
+}
+
+// ------------------------------------------------------------ configuration energies
+// E(config) = sum_a eps_a + sum_{a<b in config} V_{ab,ab} (diagonal of one species)
+template <int W>
+__global__ __launch_bounds__(256) void k_config_energy(int n, const uint64_t *__restrict__ bits,
+                                                       const double *__restrict__ eps,
+                                                       const int32_t *pidx, int norb,
+                                                       const int64_t *vbase, const int32_t *vn,
+                                                       const double *v, double *__restrict__ e) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  uint64_t s[W];
+  load_bits<W>(bits, n, k, s);
+  double acc = 0.0;
+  uint64_t t[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) t[w] = s[w];
+  for (int a = pop_lowest<W>(t); a >= 0; a = pop_lowest<W>(t)) {
+    acc += eps[a];
+    uint64_t u[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) u[w] = t[w];
+    for (int b = pop_lowest<W>(u); b >= 0; b = pop_lowest<W>(u))
+      acc += v_pair(pidx, norb, vbase, vn, v, a, b, a, b);
+  }
+  e[k] = acc;
+}
+
+__global__ void k_dab(DevInter it, double *dab) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= it.nA * it.nB) return;
+  const int x = k / it.nB, y = k % it.nB;
+  dab[k] = vab(it, x, y, x, y);
+}
+
+// ------------------------------------------------------------ tile screen
+// One wave per A configuration alpha; lanes over alpha' > alpha.  Kept: kA = 1,
+// or kA = 2 with equal 2M_A (a kA = 2 pair needs identical B configurations).
+struct TileArgs {
+  int nA;
+  const uint64_t *a_bits;
+  const int32_t *a_m2, *a_len, *a_seg;
+  const int64_t *a_off;
+  DevInter it;
+  int32_t *tcnt;          // count pass
+  const int64_t *t_ptr;   // fill pass
+  int64_t *t_off;
+  int32_t *t_len, *t_info;
+  double *t_val;
+};
+
+template <int W, bool FILL>
+__global__ __launch_bounds__(256) void k_tile_pass(TileArgs g) {
+  const int alpha = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6);
+  if (alpha >= g.nA) return;
+  const int lane = lane_id();
+  uint64_t ra[W];
+  load_bits<W>(g.a_bits, g.nA, alpha, ra);
+  const int m = g.a_m2[alpha];
+  int64_t out = FILL ? g.t_ptr[alpha] : 0;
+  int cnt = 0;
+  for (int j0 = alpha + 1; j0 < g.nA; j0 += kWave) {
+    const int j = j0 + lane;
+    bool ok = false;
+    uint64_t ca[W];
+    if (j < g.nA) {
+      load_bits<W>(g.a_bits, g.nA, j, ca);
+      const int d = popc_xor<W>(ra, ca);
+      ok = d <= 2 || (d == 4 && g.a_m2[j] == m);
+    }
+    const uint64_t msk = ballot(ok);
+    if (FILL && ok) {
+      const int64_t o = out + cnt + mask_rank(msk);
+      g.t_off[o] = g.a_off[j];
+      g.t_len[o] = g.a_len[j];
+      uint64_t part[W], hole[W], common[W];
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        part[w] = ra[w] & ~ca[w];
+        hole[w] = ca[w] & ~ra[w];
+        common[w] = ra[w] & ca[w];
+      }
+      const int p1 = pop_lowest<W>(part), h1 = pop_lowest<W>(hole);
+      const int p2 = pop_lowest<W>(part), h2 = pop_lowest<W>(hole);
+      int info;
+      double val;
+      if (p2 < 0) {  // kA = 1: p1 <- h1, spectators in common
+        const int s = sign_single<W>(ca, p1, h1);
+        double sum = 0.0;
+        for (int x = pop_lowest<W>(common); x >= 0; x = pop_lowest<W>(common))
+          sum += vbar_same(g.it.pidxA, g.it.nA, g.it.vbaseA, g.it.vnA, g.it.vA, p1, x, h1);
+        val = s * sum;
+        info = 1 | (p1 << 2) | (h1 << 10) | ((s < 0) << 18) | (g.a_seg[j] << 19);
+      } else {       // kA = 2
+        const int s = sign_double<W>(ca, p1, p2, h1, h2);
+        val = s * v_pair(g.it.pidxA, g.it.nA, g.it.vbaseA, g.it.vnA, g.it.vA, p1, p2, h1, h2);
+        info = 2;
+      }
+      g.t_info[o] = info;
+      g.t_val[o] = val;
+    }
+    cnt += __popcll(msk);
+  }
+  if (!FILL && lane == 0) g.tcnt[alpha] = cnt;
+}
+
+// ------------------------------------------------------------ B adjacency
+// One wave per B configuration beta.  Lsame(beta): beta' in beta's own 2M_B
+// list with popcount <= 4, ascending position; carries the B-only value part.
+// L1(beta): beta' in any list with popcount <= 2, grouped by list, ascending.
+struct AdjArgs {
+  int nB, nseg;
+  const uint64_t *b_bits;
+  const int32_t *b_seg, *bseg_start;
+  const double *eB;
+  DevInter it;
+  int32_t *ls_cnt, *l1_cnt;           // count pass
+  const int64_t *ls_ptr, *l1_seg;     // fill pass
+  int32_t *ls_self, *ls_pos, *ls_info, *l1_pos, *l1_info;
+  double *ls_val;
+};
+
+template <int W, bool FILL>
+__global__ __launch_bounds__(256) void k_adj_pass(AdjArgs g) {
+  const int beta = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6);
+  if (beta >= g.nB) return;
+  const int lane = lane_id();
+  uint64_t rb[W];
+  load_bits<W>(g.b_bits, g.nB, beta, rb);
+  const int gs = g.b_seg[beta];
+  for (int h = 0; h < g.nseg; ++h) {
+    const int lo = g.bseg_start[h], hi = g.bseg_start[h + 1];
+    int c_ls = 0, c_l1 = 0;
+    const int64_t ls0 = FILL && h == gs ? g.ls_ptr[beta] : 0;
+    const int64_t l10 = FILL ? g.l1_seg[(int64_t)beta * g.nseg + h] : 0;
+    for (int j0 = lo; j0 < hi; j0 += kWave) {
+      const int j = j0 + lane;
+      int d = 99;
+      uint64_t cb[W];
+      if (j < hi) {
+        load_bits<W>(g.b_bits, g.nB, j, cb);
+        d = popc_xor<W>(rb, cb);
+      }
+      const bool in_ls = h == gs && d <= 4;
+      const bool in_l1 = d <= 2;
+      const uint64_t m_ls = ballot(in_ls), m_l1 = ballot(in_l1);
+      if (FILL && (in_ls || in_l1)) {
+        uint64_t part[W], hole[W], common[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+          part[w] = rb[w] & ~cb[w];
+          hole[w] = cb[w] & ~rb[w];
+          common[w] = rb[w] & cb[w];
+        }
+        const int p1 = pop_lowest<W>(part), h1 = pop_lowest<W>(hole);
+        const int p2 = pop_lowest<W>(part), h2 = pop_lowest<W>(hole);
+        int info = 0, s = 1;
+        double val = 0.0;
+        if (d == 0) {
+          val = g.eB[beta];
+        } else if (d == 2) {
+          s = sign_single<W>(cb, p1, h1);
+          info = 1 | (p1 << 2) | (h1 << 10) | ((s < 0) << 18);
+          if (in_ls) {
+            double sum = 0.0;
+            for (int y = pop_lowest<W>(common); y >= 0; y = pop_lowest<W>(common))
+              sum += vbar_same(g.it.pidxB, g.it.nB, g.it.vbaseB, g.it.vnB, g.it.vB, p1, y, h1);
+            val = s * sum;
+          }
+        } else {
+          s = sign_double<W>(cb, p1, p2, h1, h2);
+          info = 2;
+          val = s * v_pair(g.it.pidxB, g.it.nB, g.it.vbaseB, g.it.vnB, g.it.vB, p1, p2, h1, h2);
+        }
+        if (in_ls) {
+          const int64_t o = ls0 + c_ls + mask_rank(m_ls);
+          g.ls_pos[o] = j - lo;
+          g.ls_info[o] = info;
+          g.ls_val[o] = val;
+          if (d == 0) g.ls_self[beta] = (int32_t)o;
+        }
+        if (in_l1) {
+          const int64_t o = l10 + c_l1 + mask_rank(m_l1);
+          g.l1_pos[o] = j - lo;
+          g.l1_info[o] = info;
+        }
+      }
+      c_ls += __popcll(m_ls);
+      c_l1 += __popcll(m_l1);
+    }
+    if (!FILL && lane == 0) {
+      g.l1_cnt[(int64_t)beta * g.nseg + h] = c_l1;
+      if (h == gs) g.ls_cnt[beta] = c_ls;
+    }
+  }
+}
+
+// ------------------------------------------------------------ row passes
+struct RowArgs {
+  int64_t D;
+  int nA, nB, nseg;
+  const int32_t *row_a, *row_p, *a_seg, *a_len, *bseg_start;
+  const int64_t *a_off;
+  const uint64_t *a_bits, *b_bits;
+  const double *eA;
+  const int64_t *t_ptr, *t_off;
+  const int32_t *t_len, *t_info;
+  const double *t_val;
+  const int64_t *ls_ptr, *l1_seg;
+  const int32_t *ls_self, *ls_pos, *ls_info, *l1_pos, *l1_info;
+  const double *ls_val;
+  DevInter it;
+  int32_t *rcnt;            // count pass
+  const int64_t *row_ptr;   // fill pass
+  int32_t *col;
+  void *val;
+};
+
+// One wave per row i = (alpha, p).  Entries in column order: first the
+// diagonal A-block (Lsame of beta from beta itself on, positions < len(alpha)),
+// then the tiles alpha' > alpha in ascending order.
+template <int W, bool FILL, typename T>
+__global__ __launch_bounds__(256) void k_row_pass(RowArgs g) {
+  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t i = blk * (blockDim.x / kWave) + (threadIdx.x >> 6);
+  if (i >= g.D) return;
+  const int lane = lane_id();
+  const int alpha = g.row_a[i], p = g.row_p[i];
+  const int beta = g.bseg_start[g.a_seg[alpha]] + p;
+  const int len_a = g.a_len[alpha];
+  const int64_t off_a = g.a_off[alpha];
+  T *val = static_cast<T *>(g.val);
+  uint64_t ab[W], bb[W];
+  if (FILL) {
+    load_bits<W>(g.a_bits, g.nA, alpha, ab);
+    load_bits<W>(g.b_bits, g.nB, beta, bb);
+  }
+  const int64_t out = FILL ? g.row_ptr[i] : 0;
+  int64_t cnt = 0;
+
+  // diagonal A-block: Lsame entries from beta itself, a prefix by position
+  {
+    const int64_t e0 = g.ls_self[beta], e1 = g.ls_ptr[beta + 1];
+    for (int64_t k0 = e0; k0 < e1; k0 += kWave) {
+      const int64_t k = k0 + lane;
+      const bool valid = k < e1;
+      const bool ok = valid && g.ls_pos[k] < len_a;
+      const uint64_t m = ballot(ok);
+      if (FILL && ok) {
+        const int info = g.ls_info[k];
+        double v = g.ls_val[k];
+        const int kb = info & 3;
+        if (kb == 0) {  // diagonal: E_A + E_B + sum_{x in alpha, y in beta} V^AB_{xy,xy}
+          v += g.eA[alpha];
+          if (g.it.nB > 0) {
+            uint64_t t[W];
+#pragma unroll
+            for (int w = 0; w < W; ++w) t[w] = ab[w];
+            for (int x = pop_lowest<W>(t); x >= 0; x = pop_lowest<W>(t)) {
+              uint64_t u[W];
+#pragma unroll
+              for (int w = 0; w < W; ++w) u[w] = bb[w];
+              for (int y = pop_lowest<W>(u); y >= 0; y = pop_lowest<W>(u))
+                v += g.it.dab[x * g.it.nB + y];
+            }
+          }
+        } else if (kb == 1) {  // B single: + s_B sum_{x in alpha} V^AB_{(x,b),(x,d)}
+          const int b = (info >> 2) & 0xff, d = (info >> 10) & 0xff;
+          const double s = (info >> 18) & 1 ? -1.0 : 1.0;
+          double sum = 0.0;
+          uint64_t t[W];
+#pragma unroll
+          for (int w = 0; w < W; ++w) t[w] = ab[w];
+          for (int x = pop_lowest<W>(t); x >= 0; x = pop_lowest<W>(t)) sum += vab(g.it, x, b, x, d);
+          v += s * sum;
+        }
+        const int64_t o = out + (k - e0);
+        g.col[o] = (int32_t)(off_a + g.ls_pos[k]);
+        val[o] = (T)v;
+      }
+      cnt += __popcll(m);
+      if (m != ballot(valid)) break;
+    }
+  }
+
+  // tiles alpha' > alpha
+  const int64_t t0 = g.t_ptr[alpha], t1 = g.t_ptr[alpha + 1];
+  const int64_t l1b = (int64_t)beta * g.nseg;
+  for (int64_t tb = t0; tb < t1; tb += kWave) {
+    const int64_t t = tb + lane;
+    int ne = 0, info = 0, len = 0;
+    int64_t l0 = 0;
+    if (t < t1) {
+      info = g.t_info[t];
+      len = g.t_len[t];
+      if ((info & 3) == 2) {
+        ne = p < len;
+      } else {
+        const int gt = (info >> 19) & 0x7f;
+        l0 = g.l1_seg[l1b + gt];
+        const int64_t le = g.l1_seg[l1b + gt + 1];
+        while (l0 + ne < le && g.l1_pos[l0 + ne] < len) ++ne;
+      }
+    }
+    const int incl = wave_incl_scan(ne);
+    const int total = __shfl(incl, kWave - 1, kWave);
+    if (FILL && ne) {
+      int64_t o = out + cnt + (incl - ne);
+      const int64_t coff = g.t_off[t];
+      const double tv = g.t_val[t];
+      if ((info & 3) == 2) {
+        g.col[o] = (int32_t)(coff + p);
+        val[o] = (T)tv;
+      } else {
+        const int a = (info >> 2) & 0xff, c = (info >> 10) & 0xff;
+        const double sa = (info >> 18) & 1 ? -1.0 : 1.0;
+        for (int q = 0; q < ne; ++q, ++o) {
+          const int li = g.l1_info[l0 + q];
+          double v;
+          if ((li & 3) == 0) {  // B unchanged: AA part + s_A sum_{y in beta} V^AB_{(a,y),(c,y)}
+            double sum = 0.0;
+            if (g.it.nB > 0) {
+              uint64_t u[W];
+#pragma unroll
+              for (int w = 0; w < W; ++w) u[w] = bb[w];
+              for (int y = pop_lowest<W>(u); y >= 0; y = pop_lowest<W>(u)) sum += vab(g.it, a, y, c, y);
+            }
+            v = tv + sa * sum;
+          } else {              // one A and one B orbital change
+            const int b = (li >> 2) & 0xff, d = (li >> 10) & 0xff;
+            const double sb = (li >> 18) & 1 ? -1.0 : 1.0;
+            v = sa * sb * vab(g.it, a, b, c, d);
+          }
+          g.col[o] = (int32_t)(coff + g.l1_pos[l0 + q]);
+          val[o] = (T)v;
+        }
+      }
+    }
+    cnt += total;
+  }
+  if (!FILL && lane == 0) g.rcnt[i] = (int32_t)cnt;
+}
+
+// ------------------------------------------------------------ exclusive scan
+constexpr int kScanThreads = 256, kScanItems = 16, kScanTile = kScanThreads * kScanItems;
+
+__device__ int64_t block_excl_scan(int64_t v, int64_t *lds, int64_t &total) {
+  const int lane = lane_id(), wv = threadIdx.x >> 6;
+  const int64_t incl = wave_incl_scan(v);
+  if (lane == kWave - 1) lds[wv] = incl;
+  __syncthreads();
+  int64_t wbase = 0;
+  total = 0;
+  for (int k = 0; k < kScanThreads / kWave; ++k) {
+    if (k < wv) wbase += lds[k];
+    total += lds[k];
+  }
+  __syncthreads();
+  return wbase + incl - v;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const int32_t *in, int64_t n,
+                                                              int64_t *bsum) {
+  __shared__ int64_t lds[kScanThreads / kWave];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  int64_t s = 0;
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t idx = base + (int64_t)k * kScanThreads + threadIdx.x;
+    if (idx < n) s += in[idx];
+  }
+  int64_t total;
+  block_excl_scan(s, lds, total);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_top(int64_t *bsum, int64_t nb) {
+  __shared__ int64_t lds[kScanThreads / kWave];
+  int64_t carry = 0;
+  for (int64_t c0 = 0; c0 < nb; c0 += kScanThreads) {
+    const int64_t idx = c0 + threadIdx.x;
+    const int64_t v = idx < nb ? bsum[idx] : 0;
+    int64_t total;
+    const int64_t ex = block_excl_scan(v, lds, total);
+    if (idx < nb) bsum[idx] = carry + ex;
+    carry += total;
+  }
+  if (threadIdx.x == 0) bsum[nb] = carry;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_down(const int32_t *in, int64_t n,
+                                                            const int64_t *boff, int64_t *out) {
+  __shared__ int64_t lds[kScanThreads / kWave];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  int32_t v[kScanItems];
+  int64_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    v[k] = base + k < n ? in[base + k] : 0;
+    s += v[k];
+  }
+  int64_t total;
+  int64_t run = boff[blockIdx.x] + block_excl_scan(s, lds, total);
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    if (base + k < n) out[base + k] = run;
+    run += v[k];
+  }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = boff[gridDim.x];
+}
+
+size_t scan_scratch(int64_t n) { return (size_t)((n + kScanTile - 1) / kScanTile + 2); }
+
+void launch_scan(const int32_t *in, int64_t n, int64_t *out, int64_t *scratch, hipStream_t s) {
+  const int64_t nb = std::max<int64_t>(1, (n + kScanTile - 1) / kScanTile);
+  hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, n, scratch);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, s, scratch, nb);
+  hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, n,
+                     (const int64_t *)scratch, out);
+  CIB_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------ launchers
+template <int W>
+static void expand_w(const cib_basis &b, hipStream_t s) {
+  const Plan &p = b.plan;
+  const unsigned nblk = (unsigned)((p.D + 255) / 256);
+  hipLaunchKernelGGL(k_expand_basis<W>, dim3(nblk), dim3(256), 0, s, p.D, p.nA(), p.nB(), p.WA,
+                     p.WB, b.a_off.p, b.a_seg.p, b.bseg_start.p, b.a_bits.p, b.b_bits.p,
+                     b.words.p, b.row_a.p, b.row_p.p);
+}
+
+void launch_expand_basis(const cib_basis &b, hipStream_t s) {
+  switch (b.plan.W) {
+    case 1: expand_w<1>(b, s); break;
+    case 2: expand_w<2>(b, s); break;
+    default: expand_w<3>(b, s); break;
+  }
+  CIB_HIP(hipGetLastError());
+}
+
+template <int W>
+static void energy_w(const cib_basis &b, const DevInter &it, double *eA, double *eB, hipStream_t s) {
+  const Plan &p = b.plan;
+  hipLaunchKernelGGL(k_config_energy<W>, dim3((p.nA() + 255) / 256), dim3(256), 0, s, p.nA(),
+                     b.a_bits.p, it.epsA, it.pidxA, it.nA, it.vbaseA, it.vnA, it.vA, eA);
+  if (it.nB > 0)
+    hipLaunchKernelGGL(k_config_energy<W>, dim3((p.nB() + 255) / 256), dim3(256), 0, s, p.nB(),
+                       b.b_bits.p, it.epsB, it.pidxB, it.nB, it.vbaseB, it.vnB, it.vB, eB);
+  else
+    CIB_HIP(hipMemsetAsync(eB, 0, sizeof(double) * p.nB(), s));
+}
+
+void launch_substate_energy(const cib_basis &b, const DevInter &it, double *eA, double *eB,
+                            hipStream_t s) {
+  switch (b.plan.W) {
+    case 1: energy_w<1>(b, it, eA, eB, s); break;
+    case 2: energy_w<2>(b, it, eA, eB, s); break;
+    default: energy_w<3>(b, it, eA, eB, s); break;
+  }
+  CIB_HIP(hipGetLastError());
+}
+
+void launch_dab(const DevInter &it, double *dab, hipStream_t s) {
+  const int n = it.nA * it.nB;
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_dab, dim3((n + 255) / 256), dim3(256), 0, s, it, dab);
+  CIB_HIP(hipGetLastError());
+}
+
+static int64_t read_i64(cib_ctx *ctx, const int64_t *dptr) {
+  int64_t *h = static_cast<int64_t *>(ctx->pinned_buf(sizeof(int64_t)));
+  CIB_HIP(hipMemcpyAsync(h, dptr, sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
+  CIB_HIP(hipStreamSynchronize(ctx->stream));
+  return *h;
+}
+
+struct Events {
+  hipEvent_t e[10];
+  Events() { for (auto &x : e) CIB_HIP(hipEventCreate(&x)); }
+  ~Events() { for (auto &x : e) (void)hipEventDestroy(x); }
+  double ms(int a, int b) {
+    float t = 0;
+    CIB_HIP(hipEventElapsedTime(&t, e[a], e[b]));
+    return t * 1e-3;
+  }
+};
+
+template <int W>
+static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr, cib_dtype dt,
+                    cib_matrix &H) {
+  const Plan &p = b.plan;
+  hipStream_t s = ctx->stream;
+  const DevInter it = itr.view();
+  const int nA = p.nA(), nB = p.nB(), nseg = p.nseg();
+  Events ev;
+
+  CIB_HIP(hipEventRecord(ev.e[0], s));
+  DBuf<double> eA(ctx, nA), eB(ctx, nB);
+  launch_substate_energy(b, it, eA.p, eB.p, s);
+
+  // ---- counting passes of the two screens
+  DBuf<int32_t> tcnt(ctx, nA), ls_cnt(ctx, nB), l1_cnt(ctx, (size_t)nB * nseg);
+  DBuf<int64_t> t_ptr(ctx, nA + 1), ls_ptr(ctx, nB + 1), l1_seg(ctx, (size_t)nB * nseg + 1);
+  const int64_t nscr = std::max(scan_scratch(p.D), scan_scratch((int64_t)nB * nseg));
+  DBuf<int64_t> scratch(ctx, nscr);
+  TileArgs ta{};
+  ta.nA = nA; ta.a_bits = b.a_bits.p; ta.a_m2 = b.a_m2.p; ta.a_len = b.a_len.p;
+  ta.a_seg = b.a_seg.p; ta.a_off = b.a_off.p; ta.it = it; ta.tcnt = tcnt.p;
+  const unsigned tblk = (unsigned)((nA + 3) / 4);
+  hipLaunchKernelGGL((k_tile_pass<W, false>), dim3(tblk), dim3(256), 0, s, ta);
+  AdjArgs aa{};
+  aa.nB = nB; aa.nseg = nseg; aa.b_bits = b.b_bits.p; aa.b_seg = b.b_seg.p;
+  aa.bseg_start = b.bseg_start.p; aa.eB = eB.p; aa.it = it; aa.ls_cnt = ls_cnt.p; aa.l1_cnt = l1_cnt.p;
+  const unsigned ablk = (unsigned)((nB + 3) / 4);
+  hipLaunchKernelGGL((k_adj_pass<W, false>), dim3(ablk), dim3(256), 0, s, aa);
+  CIB_HIP(hipGetLastError());
+  launch_scan(tcnt.p, nA, t_ptr.p, scratch.p, s);
+  launch_scan(ls_cnt.p, nB, ls_ptr.p, scratch.p, s);
+  launch_scan(l1_cnt.p, (int64_t)nB * nseg, l1_seg.p, scratch.p, s);
+  CIB_HIP(hipEventRecord(ev.e[1], s));
+  const int64_t n_tiles = read_i64(ctx, t_ptr.p + nA);
+  const int64_t n_ls = read_i64(ctx, ls_ptr.p + nB);
+  const int64_t n_l1 = read_i64(ctx, l1_seg.p + (int64_t)nB * nseg);
+
+  // ---- filling passes of the two screens
+  DBuf<int64_t> t_off(ctx, std::max<int64_t>(n_tiles, 1));
+  DBuf<int32_t> t_len(ctx, std::max<int64_t>(n_tiles, 1)), t_info(ctx, std::max<int64_t>(n_tiles, 1));
+  DBuf<double> t_val(ctx, std::max<int64_t>(n_tiles, 1));
+  DBuf<int32_t> ls_self(ctx, nB), ls_pos(ctx, n_ls), ls_info(ctx, n_ls), l1_pos(ctx, n_l1),
+      l1_info(ctx, n_l1);
+  DBuf<double> ls_val(ctx, n_ls);
+  CIB_HIP(hipEventRecord(ev.e[2], s));
+  ta.t_ptr = t_ptr.p; ta.t_off = t_off.p; ta.t_len = t_len.p; ta.t_info = t_info.p; ta.t_val = t_val.p;
+  hipLaunchKernelGGL((k_tile_pass<W, true>), dim3(tblk), dim3(256), 0, s, ta);
+  aa.ls_ptr = ls_ptr.p; aa.l1_seg = l1_seg.p; aa.ls_self = ls_self.p; aa.ls_pos = ls_pos.p;
+  aa.ls_info = ls_info.p; aa.l1_pos = l1_pos.p; aa.l1_info = l1_info.p; aa.ls_val = ls_val.p;
+  hipLaunchKernelGGL((k_adj_pass<W, true>), dim3(ablk), dim3(256), 0, s, aa);
+  CIB_HIP(hipGetLastError());
+  CIB_HIP(hipEventRecord(ev.e[3], s));
+
+  // ---- per-row counting pass, offsets, filling pass
+  RowArgs ra{};
+  ra.D = p.D; ra.nA = nA; ra.nB = nB; ra.nseg = nseg;
+  ra.row_a = b.row_a.p; ra.row_p = b.row_p.p; ra.a_seg = b.a_seg.p; ra.a_len = b.a_len.p;
+  ra.bseg_start = b.bseg_start.p; ra.a_off = b.a_off.p; ra.a_bits = b.a_bits.p; ra.b_bits = b.b_bits.p;
+  ra.eA = eA.p; ra.t_ptr = t_ptr.p; ra.t_off = t_off.p; ra.t_len = t_len.p; ra.t_info = t_info.p;
+  ra.t_val = t_val.p; ra.ls_ptr = ls_ptr.p; ra.l1_seg = l1_seg.p; ra.ls_self = ls_self.p;
+  ra.ls_pos = ls_pos.p; ra.ls_info = ls_info.p; ra.l1_pos = l1_pos.p; ra.l1_info = l1_info.p;
+  ra.ls_val = ls_val.p; ra.it = it;
+  DBuf<int32_t> rcnt(ctx, p.D);
+  ra.rcnt = rcnt.p;
+  const unsigned rblk = (unsigned)((p.D + 3) / 4);
+  hipLaunchKernelGGL((k_row_pass<W, false, double>), dim3(rblk), dim3(256), 0, s, ra);
+  CIB_HIP(hipGetLastError());
+  CIB_HIP(hipEventRecord(ev.e[4], s));
+  H.row_ptr.reset(ctx, p.D + 1);
+  launch_scan(rcnt.p, p.D, H.row_ptr.p, scratch.p, s);
+  CIB_HIP(hipEventRecord(ev.e[5], s));
+  const int64_t nnz = read_i64(ctx, H.row_ptr.p + p.D);
+  H.col.reset(ctx, std::max<int64_t>(nnz, 1));
+  if (dt == CIB_F64) H.val64.reset(ctx, std::max<int64_t>(nnz, 1));
+  else H.val32.reset(ctx, std::max<int64_t>(nnz, 1));
+  ra.row_ptr = H.row_ptr.p;
+  ra.col = H.col.p;
+  ra.val = dt == CIB_F64 ? (void *)H.val64.p : (void *)H.val32.p;
+  CIB_HIP(hipEventRecord(ev.e[6], s));
+  if (dt == CIB_F64)
+    hipLaunchKernelGGL((k_row_pass<W, true, double>), dim3(rblk), dim3(256), 0, s, ra);
+  else
+    hipLaunchKernelGGL((k_row_pass<W, true, float>), dim3(rblk), dim3(256), 0, s, ra);
+  CIB_HIP(hipGetLastError());
+  CIB_HIP(hipEventRecord(ev.e[7], s));
+  CIB_HIP(hipStreamSynchronize(s));
+
+  H.D = p.D;
+  H.nnz = nnz;
+  H.dtype = dt;
+  H.stats.t_screen_s = ev.ms(0, 1) + ev.ms(2, 3);
+  H.stats.t_count_s = ev.ms(3, 4);
+  H.stats.t_scan_s = ev.ms(4, 5);
+  H.stats.t_fill_s = ev.ms(6, 7);
+  H.stats.t_total_s = H.stats.t_screen_s + H.stats.t_count_s + H.stats.t_scan_s + H.stats.t_fill_s;
+  H.stats.n_tiles = n_tiles;
+  H.stats.n_adjacent = n_ls + n_l1;
+}
+
+void build_matrix(cib_ctx *ctx, const cib_basis &b, const cib_interaction &it, cib_dtype dt,
+                  cib_matrix &H) {
+  switch (b.plan.W) {
+    case 1: build_w<1>(ctx, b, it, dt, H); break;
+    case 2: build_w<2>(ctx, b, it, dt, H); break;
+    default: build_w<3>(ctx, b, it, dt, H); break;
+  }
+}
+
+}  // namespace cib

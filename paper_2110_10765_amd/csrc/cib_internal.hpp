@@ -1,0 +1,206 @@
+// Internal declarations of the cib library (host runtime + HIP kernels).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <stdexcept>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/cib.h"
+
+namespace cib {
+
+// ------------------------------------------------------------------ errors
+struct Error : std::runtime_error {
+  cib_status code;
+  Error(cib_status c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+void set_last_error(const std::string &msg);
+
+#define CIB_HIP(expr)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      throw ::cib::Error(CIB_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define CIB_REQUIRE(cond, code, msg)                                               \
+  do {                                                                             \
+    if (!(cond)) throw ::cib::Error((code), (msg));                                \
+  } while (0)
+
+constexpr int kMaxWords = 3;     // 64-bit words per species (nmax <= 6)
+constexpr int kMaxBlock = 16;    // LOBPCG block size limit
+constexpr int kMaxSeg = 127;     // 2M_B segments (7 bits in tile info)
+
+}  // namespace cib
+
+// ------------------------------------------------------------------ context
+struct cib_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  cib_allocator user{};
+  bool has_user = false;
+  std::mutex mu;
+  // cache of freed blocks (hipMalloc path): size -> pointers
+  std::unordered_multimap<size_t, void *> cache;
+  std::unordered_map<void *, size_t> sizes;
+  int64_t live = 0, peak = 0, cached = 0;
+  bool busy = false;
+  void *pinned = nullptr;  // small pinned host staging buffer
+  size_t pinned_bytes = 0;
+
+  void *alloc(size_t bytes);
+  void free(void *p);
+  void release_cache();
+  void *pinned_buf(size_t bytes);
+};
+
+namespace cib {
+
+// Typed device buffer owned through the context allocator.
+template <typename T>
+struct DBuf {
+  cib_ctx *ctx = nullptr;
+  T *p = nullptr;
+  size_t n = 0;
+  DBuf() = default;
+  DBuf(cib_ctx *c, size_t count) { reset(c, count); }
+  DBuf(const DBuf &) = delete;
+  DBuf &operator=(const DBuf &) = delete;
+  DBuf(DBuf &&o) noexcept : ctx(o.ctx), p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DBuf &operator=(DBuf &&o) noexcept {
+    if (this != &o) { release(); ctx = o.ctx; p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+    return *this;
+  }
+  ~DBuf() { release(); }
+  void reset(cib_ctx *c, size_t count) {
+    release();
+    ctx = c;
+    n = count;
+    p = count ? static_cast<T *>(c->alloc(count * sizeof(T))) : nullptr;
+  }
+  void release() {
+    if (p && ctx) ctx->free(p);
+    p = nullptr;
+    n = 0;
+  }
+  size_t bytes() const { return n * sizeof(T); }
+  void upload(const T *h, size_t count, hipStream_t s) {
+    if (count) CIB_HIP(hipMemcpyAsync(p, h, count * sizeof(T), hipMemcpyHostToDevice, s));
+  }
+};
+
+// ------------------------------------------------------------------ planner
+struct Orbs {
+  int nmax = -1, n_orb = 0, words = 0;
+  std::vector<int> n, twoj, twom;
+};
+Orbs make_orbs(int nmax);
+int q_min(int N, const Orbs &o);
+
+struct SubList {
+  std::vector<uint64_t> bits;  // size * kMaxWords, state-major, zero padded
+  std::vector<int32_t> m2, q;
+  size_t size() const { return m2.size(); }
+};
+
+struct Plan {
+  cib_basis_spec spec{};
+  int ns = 1;
+  Orbs oA, oB;
+  int W = 1;           // kernel word count: max over species
+  int WA = 1, WB = 0;  // real word counts
+  int qmax = -1;       // -1: no truncation
+  SubList A, B;        // A: non-empty blocks, ascending integer; B: (2M, Q, integer)
+  std::vector<int64_t> a_off;                     // nA + 1
+  std::vector<int32_t> a_len, a_seg;              // nA
+  std::vector<int32_t> b_seg;                     // nB: segment of each B configuration
+  std::vector<int32_t> bseg_start, bseg_m2;       // nseg + 1, nseg
+  int64_t D = 0;
+  int nA() const { return (int)A.size(); }
+  int nB() const { return (int)B.size(); }
+  int nseg() const { return (int)bseg_m2.size(); }
+};
+void validate_spec(const cib_basis_spec &s);
+void make_plan(const cib_basis_spec &s, Plan &p);
+
+// Per-interaction device tables.
+struct DevInter {
+  int nA = 0, nB = 0;
+  const double *epsA = nullptr, *epsB = nullptr;
+  const int32_t *pidxA = nullptr, *vnA = nullptr;
+  const int64_t *vbaseA = nullptr;
+  const double *vA = nullptr;
+  const int32_t *pidxB = nullptr, *vnB = nullptr;
+  const int64_t *vbaseB = nullptr;
+  const double *vB = nullptr;
+  const int32_t *pidxAB = nullptr, *vnAB = nullptr;
+  const int64_t *vbaseAB = nullptr;
+  const double *vAB = nullptr;
+  const double *dab = nullptr;  // nA * nB: V^AB_{(x,y),(x,y)}
+};
+
+}  // namespace cib
+
+struct cib_basis {
+  cib_ctx *ctx = nullptr;
+  cib::Plan plan;
+  // device copies
+  cib::DBuf<uint64_t> a_bits, b_bits;   // SoA: word w of configuration k at [w * n + k]
+  cib::DBuf<int32_t> a_m2, a_q, a_len, a_seg, b_m2, b_q, b_seg, bseg_start;
+  cib::DBuf<int64_t> a_off;
+  cib::DBuf<int32_t> row_a, row_p;      // per state: A-block and position in it
+  cib::DBuf<uint64_t> words;            // SoA: (WA + WB) words x D
+};
+
+struct cib_interaction {
+  cib_ctx *ctx = nullptr;
+  int nA = 0, nB = 0;
+  cib::DBuf<double> epsA, epsB, vA, vB, vAB, dab;
+  cib::DBuf<int32_t> pidxA, vnA, pidxB, vnB, pidxAB, vnAB;
+  cib::DBuf<int64_t> vbaseA, vbaseB, vbaseAB;
+  cib::DevInter view() const;
+};
+
+struct cib_matrix {
+  cib_ctx *ctx = nullptr;
+  int64_t D = 0, nnz = 0;
+  cib_dtype dtype = CIB_F64;
+  cib::DBuf<int64_t> row_ptr;
+  cib::DBuf<int32_t> col;
+  cib::DBuf<double> val64;
+  cib::DBuf<float> val32;
+  cib_build_stats stats{};
+  const void *val() const { return dtype == CIB_F64 ? (const void *)val64.p : (const void *)val32.p; }
+};
+
+namespace cib {
+
+// ------------------------------------------------------------------ kernels
+// (launchers defined in the .hip files; all asynchronous on `s`)
+void launch_expand_basis(const cib_basis &b, hipStream_t s);
+void launch_substate_energy(const cib_basis &b, const DevInter &it, double *eA, double *eB,
+                            hipStream_t s);
+void launch_dab(const DevInter &it, double *dab, hipStream_t s);
+
+// exclusive scan of n int32 counts into n+1 int64 offsets; scratch >= scan_scratch(n)
+size_t scan_scratch(int64_t n);
+void launch_scan(const int32_t *in, int64_t n, int64_t *out, int64_t *scratch, hipStream_t s);
+
+struct BuildWork;  // defined in build.hip
+void build_matrix(cib_ctx *ctx, const cib_basis &b, const cib_interaction &it, cib_dtype dt,
+                  cib_matrix &H);
+
+void spmm_sym(const cib_matrix &H, const void *X, int64_t ldx, void *Y, int64_t ldy, int nvec,
+              hipStream_t s);
+
+}  // namespace cib

@@ -1,0 +1,120 @@
+// Device helpers shared by the HIP kernels of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace cib {
+namespace dev {
+
+constexpr int kWave = 64;
+
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
+
+// Number of set lanes below the calling lane in a 64-bit ballot mask.
+__device__ __forceinline__ int mask_rank(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+// Inclusive and exclusive wave-wide prefix sums.
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T v) {
+  const int l = lane_id();
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    T o = __shfl_up(v, d, kWave);
+    if (l >= d) v += o;
+  }
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
+  return v;
+}
+
+// Map a linear block index so that each XCD (blocks are dispatched to the 8
+// XCDs round-robin) works on one contiguous range of logical blocks, which
+// keeps the data those blocks share inside one XCD's L2.
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
+  const int64_t q = nb >> 3, r = nb & 7;
+  const int64_t x = b & 7, k = b >> 3;
+  const int64_t start = x * q + (x < r ? x : r);
+  return start + k;
+}
+
+// ---- multiword bit strings (W little-endian 64-bit words) ----
+template <int W>
+__device__ __forceinline__ int popc_xor(const uint64_t *a, const uint64_t *b) {
+  int d = 0;
+#pragma unroll
+  for (int w = 0; w < W; ++w) d += __popcll(a[w] ^ b[w]);
+  return d;
+}
+
+// number of set bits of s strictly below bit k
+template <int W>
+__device__ __forceinline__ int count_below(const uint64_t *s, int k) {
+  int c = 0;
+  const int kw = k >> 6;
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    uint64_t m = w < kw ? ~0ull : (w == kw ? ((1ull << (k & 63)) - 1ull) : 0ull);
+    c += __popcll(s[w] & m);
+  }
+  return c;
+}
+
+// index of the lowest set bit of (a & ~b) among W words, -1 if none; clears it in a
+template <int W>
+__device__ __forceinline__ int pop_lowest(uint64_t *a) {
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    if (a[w]) {
+      int k = __builtin_ctzll(a[w]);
+      a[w] &= a[w] - 1;
+      return w * 64 + k;
+    }
+  }
+  return -1;
+}
+
+template <int W>
+__device__ __forceinline__ void clear_bit(uint64_t *s, int k) { s[k >> 6] &= ~(1ull << (k & 63)); }
+template <int W>
+__device__ __forceinline__ void set_bit(uint64_t *s, int k) { s[k >> 6] |= (1ull << (k & 63)); }
+
+// Phase of a+_p a_h acting on ket bits s (h occupied, p empty): each operator
+// contributes (-1)^(occupied below its mode) in the state it acts on.
+template <int W>
+__device__ __forceinline__ int sign_single(const uint64_t *s, int p, int h) {
+  uint64_t t[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) t[w] = s[w];
+  int e = count_below<W>(t, h);
+  clear_bit<W>(t, h);
+  e += count_below<W>(t, p);
+  return (e & 1) ? -1 : 1;
+}
+
+// Phase of a+_p1 a+_p2 a_h2 a_h1 on ket bits s (p1 < p2, h1 < h2).
+template <int W>
+__device__ __forceinline__ int sign_double(const uint64_t *s, int p1, int p2, int h1, int h2) {
+  uint64_t t[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) t[w] = s[w];
+  int e = count_below<W>(t, h1);
+  clear_bit<W>(t, h1);
+  e += count_below<W>(t, h2);
+  clear_bit<W>(t, h2);
+  e += count_below<W>(t, p2) + count_below<W>(t, p1);
+  return (e & 1) ? -1 : 1;
+}
+
+}  // namespace dev
+}  // namespace cib

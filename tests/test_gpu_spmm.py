@@ -1,0 +1,68 @@
+"""GPU parity of the symmetric SpMM Y = H X (cib_apply_H) against the oracle.
+
+Bar (Higham's bound for a dot product of length k): |Y - Y_ref| <= gamma_k
+|H||X| elementwise with gamma_k = k u / (1 - k u), k = 2 * (max stored row
+length) + 2, u = 2^-53 (float64) or 2^-24 (float32).  The float32 reference
+uses the oracle's float64 H rounded to float32 and the same float32 X, so the
+bound covers only the arithmetic.
+"""
+import numpy as np
+import pytest
+
+import cigen
+import oracle as O
+from tests.common import EPS32, EPS64, gpu_ctx, oracle_csr, oracle_tables
+
+pytestmark = pytest.mark.gpu
+
+CASES = ["sp1_n2_N4", "ab_n3_3p3_cut4"]
+
+
+def _gamma(k, u):
+    return k * u / (1 - k * u)
+
+
+@pytest.mark.parametrize("name", CASES)
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("nvec", [1, 3, 8, 13, 16, 24])
+def test_apply_H(name, dtype, nvec):
+    import torch
+    from paper_2110_10765_amd import cib
+    w = cigen.WORKLOADS[name]
+    ctx = gpu_ctx()
+    print("case", name, dtype, nvec, flush=True)
+    b = cib.build_basis(ctx, w.spec)
+    H = cib.build_H(ctx, b, oracle_tables(w.spec, w.seed), dtype)
+    rp, col, val = oracle_csr(w.spec, w.seed)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    rng = np.random.default_rng(nvec)
+    X = rng.standard_normal((b.dim, nvec))
+    if dtype == "f32":
+        X = X.astype(np.float32).astype(np.float64)
+        val = val.astype(np.float32).astype(np.float64)
+    Xd = torch.tensor(X, dtype=tdt, device="cuda:0")
+    # ragged leading dimension on the output
+    Yfull = torch.full((b.dim, nvec + 3), 7.0, dtype=tdt, device="cuda:0")
+    Yd = Yfull[:, :nvec]
+    cib.apply_H(ctx, H, Xd, Yd)
+    torch.cuda.synchronize()
+    Y = Yd.cpu().numpy().astype(np.float64)
+    assert torch.all(Yfull[:, nvec:] == 7.0)
+    Yref, absHX = O.spmm_half(rp, col, val, X)
+    k = 2 * int(np.diff(rp).max()) + 2
+    u = EPS64 if dtype == "f64" else EPS32
+    assert np.all(np.abs(Y - Yref) <= _gamma(k, u) * absHX + 1e-300)
+
+
+def test_apply_H_rejects_bad_shapes():
+    import torch
+    from paper_2110_10765_amd import cib
+    w = cigen.WORKLOADS["sp1_n2_N4"]
+    ctx = gpu_ctx()
+    b = cib.build_basis(ctx, w.spec)
+    H = cib.build_H(ctx, b, oracle_tables(w.spec, w.seed), "f64")
+    X = torch.zeros((b.dim, 4), dtype=torch.float64, device="cuda:0")
+    lib = cib.load()
+    assert lib.cib_apply_H(ctx.h, H.h, X.data_ptr(), 2, X.data_ptr(), 4, 4) == cib.CIB_E_INVALID
+    assert lib.cib_apply_H(ctx.h, H.h, X.data_ptr(), 4, X.data_ptr(), 4, 65) == cib.CIB_E_INVALID
+    assert lib.cib_apply_H(ctx.h, H.h, X.data_ptr(), 4, X.data_ptr(), 4, 0) == cib.CIB_E_INVALID
