@@ -305,12 +305,24 @@ cib_status cib_apply_H(cib_ctx *ctx, const cib_matrix *H, const void *X, int64_t
 
 }  // extern "C"
 
-// placeholders until the solver and the serving loop land
-extern "C" cib_status cib_lobpcg(cib_ctx *, const cib_matrix *, const cib_lobpcg_opts *, double *,
-                                 double *, int64_t, cib_lobpcg_info *) {
-  set_last_error("cib_lobpcg: not available in this build");
-  return CIB_E_INVALID;
+// ---------------------------------------------------------------- LOBPCG
+extern "C" cib_status cib_lobpcg(cib_ctx *ctx, const cib_matrix *H, const cib_lobpcg_opts *o,
+                                 double *evals, double *evecs, int64_t ld_evecs,
+                                 cib_lobpcg_info *info) {
+  cib_status st = CIB_OK;
+  cib_status rc = guarded([&] {
+    CIB_REQUIRE(ctx && H && o && evals, CIB_E_INVALID, "NULL argument");
+    CIB_REQUIRE(H->ctx == ctx, CIB_E_INVALID, "matrix belongs to another context");
+    BusyGuard busy(ctx);
+    DeviceGuard g(ctx->device);
+    st = lobpcg_solve(ctx, *H, *o, evals, evecs, ld_evecs, info);
+  });
+  if (rc != CIB_OK) return rc;
+  if (st == CIB_E_NOT_CONVERGED) set_last_error("LOBPCG reached max_iter before the tolerance");
+  return st;
 }
+
+// placeholder until the serving loop lands
 extern "C" cib_status cib_serve(cib_ctx *, const cib_request *, int32_t, const cib_serve_opts *,
                                 cib_result *) {
   set_last_error("cib_serve: not available in this build");

@@ -203,4 +203,7 @@ void build_matrix(cib_ctx *ctx, const cib_basis &b, const cib_interaction &it, c
 void spmm_sym(const cib_matrix &H, const void *X, int64_t ldx, void *Y, int64_t ldy, int nvec,
               hipStream_t s);
 
+cib_status lobpcg_solve(cib_ctx *ctx, const cib_matrix &H, const cib_lobpcg_opts &o, double *evals,
+                        double *evecs, int64_t ld_evecs, cib_lobpcg_info *info);
+
 }  // namespace cib

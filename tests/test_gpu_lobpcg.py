@@ -1,0 +1,100 @@
+"""GPU parity of the LOBPCG eigenvalues (cib_lobpcg) against the oracle.
+
+Bar (relative error |lam - lam_ref| / max(|lam_ref|, 1)):
+* float64 H: 1e-10 against LAPACK / ARPACK on the oracle's matrix;
+* float32 H (SpMM in float32, Rayleigh-Ritz in float64): 1e-6 against the
+  oracle's float64 eigenvalues.
+Eigenvectors are checked through the oracle's residual ||Hx - lam x|| /
+(max(|lam|,1) ||x||) and their orthonormality, never entry by entry (they are
+defined only up to sign and rotation within degenerate subspaces).
+"""
+import os
+
+import numpy as np
+import pytest
+
+import cigen
+import oracle as O
+from tests.common import golden, gpu_ctx, oracle_csr, oracle_tables
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _rel(a, b):
+    return np.abs(np.asarray(a) - np.asarray(b)) / np.maximum(np.abs(b), 1.0)
+
+
+def _solve(w, dtype, nev=None, block=None, **kw):
+    from paper_2110_10765_amd import cib
+    ctx = gpu_ctx()
+    print("case", w.name, dtype, flush=True)
+    b = cib.build_basis(ctx, w.spec)
+    H = cib.build_H(ctx, b, oracle_tables(w.spec, w.seed), dtype)
+    return cib.lobpcg(ctx, H, nev or w.nev, block=block or w.block, **kw)
+
+
+@pytest.mark.parametrize("name", ["sp1_n2_N4", "ab_n3_3p3_cut4"])
+def test_lobpcg_f64(name):
+    w = cigen.WORKLOADS[name]
+    g = golden(name)
+    ev, info, vec = _solve(w, "f64", want_vectors=True, max_iter=800)
+    assert info["status"] == 0, info
+    ref = np.asarray(g.get("evals_f64_lapack", g["evals_f64"]))[:w.nev]
+    assert _rel(ev, ref).max() <= 1e-10, (ev, ref)
+    X = vec.cpu().numpy()
+    assert np.abs(X.T @ X - np.eye(w.nev)).max() <= 1e-8
+    rp, col, val = oracle_csr(w.spec, w.seed)
+    assert O.residual_audit(rp, col, val, ev, X).max() <= 1e-8
+
+
+@pytest.mark.parametrize("name", ["sp1_n2_N4", "ab_n3_3p3_cut4"])
+def test_lobpcg_f32(name):
+    w = cigen.WORKLOADS[name]
+    g = golden(name)
+    ev, info, _ = _solve(w, "f32", max_iter=800)
+    assert info["status"] == 0, info
+    assert _rel(ev, np.asarray(g["evals_f64"])[:w.nev]).max() <= 1e-6
+
+
+@pytest.mark.parametrize("name,dtype", [("ab_n3_3p3_cut6", "f32"), ("ab_n5_4p4_cut4", "f32"),
+                                        ("ab_n3_3p3_cut6", "f64")])
+def test_lobpcg_full_size(name, dtype):
+    if not os.path.exists(os.path.join(GOLD, name + ".json")):
+        pytest.skip("stored oracle eigenvalues not generated")
+    w = cigen.WORKLOADS[name]
+    g = golden(name)
+    ev, info, _ = _solve(w, dtype, max_iter=1000)
+    assert info["status"] == 0, info
+    tol = 1e-6 if dtype == "f32" else 1e-10
+    assert _rel(ev, np.asarray(g["evals_f64"])[:w.nev]).max() <= tol, (ev, g["evals_f64"][:w.nev])
+
+
+def test_lobpcg_block_sizes_and_small_basis():
+    """block = nev, block = 16, and a basis only a few blocks wide."""
+    spec = cigen.BasisSpec.two(1, 2, 2, 1, 1, -1)
+    w = cigen.Workload("small", spec, 31, 3, 3, "f64")
+    b = O.Basis(spec)
+    H = O.dense_H(b, O.Interaction(b, oracle_tables(spec, 31)))
+    ref = O.eigs_dense(H, 6)
+    for nev, block in [(3, 3), (4, 8), (6, 16)]:
+        if 3 * block > b.D:
+            continue
+        ev, info, _ = _solve(w, "f64", nev=nev, block=block, max_iter=500)
+        assert info["status"] == 0
+        assert _rel(ev, ref[:nev]).max() <= 1e-10, (nev, block)
+
+
+def test_lobpcg_not_converged_and_invalid():
+    from paper_2110_10765_amd import cib
+    w = cigen.WORKLOADS["ab_n3_3p3_cut4"]
+    ev, info, _ = _solve(w, "f64", max_iter=1)
+    assert info["status"] == cib.CIB_E_NOT_CONVERGED
+    assert info["iters"] == 1 and np.all(np.isfinite(ev)) and np.all(info["resid"] > 0)
+    with pytest.raises(cib.CibError) as e:
+        _solve(w, "f64", nev=9, block=8)
+    assert e.value.code == cib.CIB_E_INVALID
+    tiny = cigen.Workload("t", cigen.BasisSpec.two(1, 1, 1, 1, 0, -1), 3, 2, 8, "f64")  # D = 12 < 24
+    with pytest.raises(cib.CibError) as e:
+        _solve(tiny, "f64")
+    assert e.value.code == cib.CIB_E_INVALID
