@@ -79,6 +79,16 @@ const char *cib_last_error(void);
 /* Device bytes currently held by the context's allocations (live, not cached). */
 cib_status cib_ctx_bytes(const cib_ctx *ctx, int64_t *live_bytes, int64_t *peak_bytes);
 
+/* Per-kernel device timing: when enabled, the library brackets every launch
+ * of its hot kernels with HIP events on the launching stream.  Query sums the
+ * elapsed times of all completed launches of one kernel since the last reset
+ * (it synchronises those events).  Kernel names: "tile_screen",
+ * "adjacency", "row_count", "scan", "row_fill", "spmm_sym", "gram",
+ * "rayleigh_ritz", "update".  Unknown names report zero launches. */
+cib_status cib_profile_enable(cib_ctx *ctx, int on);
+cib_status cib_profile_reset(cib_ctx *ctx);
+cib_status cib_profile_query(cib_ctx *ctx, const char *kernel, int64_t *launches, double *total_s);
+
 /* ---------------------------------------------------------------- basis --
  * Sec. 2: many-body states are antisymmetrised products of single-particle
  * states.  Single-particle orbitals of one species are harmonic-oscillator

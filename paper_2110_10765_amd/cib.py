@@ -35,6 +35,7 @@ STATUS_NAMES = {0: "CIB_OK", -1: "CIB_E_INVALID", -2: "CIB_E_NOMEM", -3: "CIB_E_
 # every symbol include/cib.h declares
 EXPORTS = [
     "cib_create", "cib_destroy", "cib_last_error", "cib_ctx_bytes",
+    "cib_profile_enable", "cib_profile_reset", "cib_profile_query",
     "cib_build_basis", "cib_basis_info", "cib_basis_export", "cib_basis_free",
     "cib_upload_interaction", "cib_interaction_free",
     "cib_build_H", "cib_build_H_resident", "cib_matrix_info", "cib_matrix_stats",
@@ -122,6 +123,9 @@ def load(path: str = LIB_PATH):
         "cib_destroy": ([vp], None),
         "cib_last_error": ([], ctypes.c_char_p),
         "cib_ctx_bytes": ([vp, P(i64), P(i64)], i32),
+        "cib_profile_enable": ([vp, ctypes.c_int], i32),
+        "cib_profile_reset": ([vp], i32),
+        "cib_profile_query": ([vp, ctypes.c_char_p, P(i64), P(ctypes.c_double)], i32),
         "cib_build_basis": ([vp, P(BasisSpecC), P(vp), P(i64)], i32),
         "cib_basis_info": ([vp, P(i64), P(i32), P(i32), P(i64)], i32),
         "cib_basis_export": ([vp, vp], i32),
@@ -241,6 +245,16 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def profile(self, on: bool = True):
+        _check(load().cib_profile_enable(self.h, int(on)))
+        _check(load().cib_profile_reset(self.h))
+
+    def kernel_time(self, name: str):
+        """(launches, total seconds) of one library kernel since profile()."""
+        n, t = ctypes.c_int64(), ctypes.c_double()
+        _check(load().cib_profile_query(self.h, name.encode(), ctypes.byref(n), ctypes.byref(t)))
+        return n.value, t.value
 
     def bytes(self):
         live, peak = ctypes.c_int64(), ctypes.c_int64()

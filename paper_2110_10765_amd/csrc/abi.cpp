@@ -6,7 +6,7 @@
 
 namespace cib {
 const char *last_error_cstr();
-cib_interaction *upload_interaction(cib_ctx *ctx, const cib_basis &b, const cib_tables &t);
+void profile_collect(cib_ctx *c);
 }  // namespace cib
 
 using namespace cib;
@@ -82,11 +82,46 @@ cib_status cib_create(int device, const cib_allocator *a, void *hip_stream, cib_
   });
 }
 
+cib_status cib_profile_enable(cib_ctx *ctx, int on) {
+  return guarded([&] {
+    CIB_REQUIRE(ctx, CIB_E_INVALID, "ctx is NULL");
+    ctx->profiling = on != 0;
+  });
+}
+
+cib_status cib_profile_reset(cib_ctx *ctx) {
+  return guarded([&] {
+    CIB_REQUIRE(ctx, CIB_E_INVALID, "ctx is NULL");
+    DeviceGuard g(ctx->device);
+    profile_collect(ctx);
+    ctx->kernel_totals.clear();
+  });
+}
+
+cib_status cib_profile_query(cib_ctx *ctx, const char *kernel, int64_t *launches, double *total_s) {
+  return guarded([&] {
+    CIB_REQUIRE(ctx && kernel, CIB_E_INVALID, "NULL argument");
+    DeviceGuard g(ctx->device);
+    profile_collect(ctx);
+    int64_t n = 0;
+    double t = 0.0;
+    for (int k = 0; k < K_NKERN; ++k)
+      if (std::strcmp(kernel, kKernelNames[k]) == 0) {
+        auto it = ctx->kernel_totals.find(k);
+        if (it != ctx->kernel_totals.end()) { n = it->second.first; t = it->second.second; }
+      }
+    if (launches) *launches = n;
+    if (total_s) *total_s = t;
+  });
+}
+
 void cib_destroy(cib_ctx *ctx) {
   if (!ctx) return;
   try {
     DeviceGuard g(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
+    profile_collect(ctx);
+    for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
     ctx->release_cache();
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
@@ -109,43 +144,8 @@ cib_status cib_build_basis(cib_ctx *ctx, const cib_basis_spec *spec, cib_basis *
     CIB_REQUIRE(ctx && spec && out, CIB_E_INVALID, "NULL argument");
     BusyGuard busy(ctx);
     DeviceGuard g(ctx->device);
-    std::unique_ptr<cib_basis> b(new cib_basis);
-    b->ctx = ctx;
-    make_plan(*spec, b->plan);
+    std::unique_ptr<cib_basis> b(make_basis(ctx, *spec, ctx->stream));
     const Plan &p = b->plan;
-    CIB_REQUIRE(p.D > 0, CIB_E_EMPTY_BASIS, "the spec admits no state");
-    CIB_REQUIRE(p.D < (int64_t(1) << 31), CIB_E_OVERFLOW, "basis dimension exceeds 2^31-1");
-    hipStream_t s = ctx->stream;
-    const int W = p.W, nA = p.nA(), nB = p.nB();
-    std::vector<uint64_t> soa((size_t)W * nA);
-    for (int k = 0; k < nA; ++k)
-      for (int w = 0; w < W; ++w) soa[(size_t)w * nA + k] = p.A.bits[(size_t)k * kMaxWords + w];
-    b->a_bits.reset(ctx, soa.size());
-    b->a_bits.upload(soa.data(), soa.size(), s);
-    std::vector<uint64_t> sob((size_t)W * nB);
-    for (int k = 0; k < nB; ++k)
-      for (int w = 0; w < W; ++w) sob[(size_t)w * nB + k] = p.B.bits[(size_t)k * kMaxWords + w];
-    b->b_bits.reset(ctx, sob.size());
-    b->b_bits.upload(sob.data(), sob.size(), s);
-    auto up32 = [&](DBuf<int32_t> &d, const std::vector<int32_t> &h) {
-      d.reset(ctx, std::max<size_t>(h.size(), 1));
-      d.upload(h.data(), h.size(), s);
-    };
-    up32(b->a_m2, p.A.m2);
-    up32(b->a_q, p.A.q);
-    up32(b->a_len, p.a_len);
-    up32(b->a_seg, p.a_seg);
-    up32(b->b_m2, p.B.m2);
-    up32(b->b_q, p.B.q);
-    up32(b->b_seg, p.b_seg);
-    up32(b->bseg_start, p.bseg_start);
-    b->a_off.reset(ctx, p.a_off.size());
-    b->a_off.upload(p.a_off.data(), p.a_off.size(), s);
-    b->row_a.reset(ctx, p.D);
-    b->row_p.reset(ctx, p.D);
-    b->words.reset(ctx, (size_t)(p.WA + p.WB) * p.D);
-    launch_expand_basis(*b, s);
-    CIB_HIP(hipStreamSynchronize(s));  // host staging vectors go out of scope
     if (dim) *dim = p.D;
     *out = b.release();
   });
@@ -194,7 +194,7 @@ cib_status cib_upload_interaction(cib_ctx *ctx, const cib_basis *b, const cib_ta
     CIB_REQUIRE(ctx && b && t && out, CIB_E_INVALID, "NULL argument");
     BusyGuard busy(ctx);
     DeviceGuard g(ctx->device);
-    *out = upload_interaction(ctx, *b, *t);
+    *out = upload_interaction(ctx, *b, *t, ctx->stream);
   });
 }
 
@@ -220,7 +220,7 @@ cib_status cib_build_H_resident(cib_ctx *ctx, const cib_basis *b, const cib_inte
     DeviceGuard g(ctx->device);
     std::unique_ptr<cib_matrix> H(new cib_matrix);
     H->ctx = ctx;
-    build_matrix(ctx, *b, *it, dt, *H);
+    build_matrix(ctx, *b, *it, dt, *H, ctx->stream, nullptr);
     if (nnz) *nnz = H->nnz;
     *out = H.release();
   });
@@ -322,9 +322,14 @@ extern "C" cib_status cib_lobpcg(cib_ctx *ctx, const cib_matrix *H, const cib_lo
   return st;
 }
 
-// placeholder until the serving loop lands
-extern "C" cib_status cib_serve(cib_ctx *, const cib_request *, int32_t, const cib_serve_opts *,
-                                cib_result *) {
-  set_last_error("cib_serve: not available in this build");
-  return CIB_E_INVALID;
+// ---------------------------------------------------------------- serve
+extern "C" cib_status cib_serve(cib_ctx *ctx, const cib_request *reqs, int32_t n,
+                                const cib_serve_opts *opts, cib_result *results) {
+  return guarded([&] {
+    CIB_REQUIRE(ctx && opts && n >= 0, CIB_E_INVALID, "bad argument");
+    CIB_REQUIRE(n == 0 || (reqs && results), CIB_E_INVALID, "NULL requests or results");
+    BusyGuard busy(ctx);
+    DeviceGuard g(ctx->device);
+    serve_run(ctx, reqs, n, *opts, results);
+  });
 }

@@ -15,6 +15,7 @@
 // lanes over tiles, ballot/scan compaction: the columns of a row come out in
 // ascending order without atomics (Sec. 2.2-2.3).
 #include <algorithm>
+#include <functional>
 
 #include "cib_internal.hpp"
 #include "device_common.hpp"
@@ -548,11 +549,11 @@ void launch_dab(const DevInter &it, double *dab, hipStream_t s) {
   CIB_HIP(hipGetLastError());
 }
 
-static int64_t read_i64(cib_ctx *ctx, const int64_t *dptr) {
-  int64_t *h = static_cast<int64_t *>(ctx->pinned_buf(sizeof(int64_t)));
-  CIB_HIP(hipMemcpyAsync(h, dptr, sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
-  CIB_HIP(hipStreamSynchronize(ctx->stream));
-  return *h;
+static int64_t read_i64(const int64_t *dptr, hipStream_t s) {
+  int64_t h = 0;
+  CIB_HIP(hipMemcpyAsync(&h, dptr, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  CIB_HIP(hipStreamSynchronize(s));
+  return h;
 }
 
 struct Events {
@@ -568,9 +569,8 @@ struct Events {
 
 template <int W>
 static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr, cib_dtype dt,
-                    cib_matrix &H) {
+                    cib_matrix &H, hipStream_t s, const std::function<void(int64_t)> &before_fill) {
   const Plan &p = b.plan;
-  hipStream_t s = ctx->stream;
   const DevInter it = itr.view();
   const int nA = p.nA(), nB = p.nB(), nseg = p.nseg();
   Events ev;
@@ -588,20 +588,20 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
   ta.nA = nA; ta.a_bits = b.a_bits.p; ta.a_m2 = b.a_m2.p; ta.a_len = b.a_len.p;
   ta.a_seg = b.a_seg.p; ta.a_off = b.a_off.p; ta.it = it; ta.tcnt = tcnt.p;
   const unsigned tblk = (unsigned)((nA + 3) / 4);
-  hipLaunchKernelGGL((k_tile_pass<W, false>), dim3(tblk), dim3(256), 0, s, ta);
+  { KTimer kt(ctx, K_TILE, s); hipLaunchKernelGGL((k_tile_pass<W, false>), dim3(tblk), dim3(256), 0, s, ta); }
   AdjArgs aa{};
   aa.nB = nB; aa.nseg = nseg; aa.b_bits = b.b_bits.p; aa.b_seg = b.b_seg.p;
   aa.bseg_start = b.bseg_start.p; aa.eB = eB.p; aa.it = it; aa.ls_cnt = ls_cnt.p; aa.l1_cnt = l1_cnt.p;
   const unsigned ablk = (unsigned)((nB + 3) / 4);
-  hipLaunchKernelGGL((k_adj_pass<W, false>), dim3(ablk), dim3(256), 0, s, aa);
+  { KTimer kt(ctx, K_ADJ, s); hipLaunchKernelGGL((k_adj_pass<W, false>), dim3(ablk), dim3(256), 0, s, aa); }
   CIB_HIP(hipGetLastError());
   launch_scan(tcnt.p, nA, t_ptr.p, scratch.p, s);
   launch_scan(ls_cnt.p, nB, ls_ptr.p, scratch.p, s);
   launch_scan(l1_cnt.p, (int64_t)nB * nseg, l1_seg.p, scratch.p, s);
   CIB_HIP(hipEventRecord(ev.e[1], s));
-  const int64_t n_tiles = read_i64(ctx, t_ptr.p + nA);
-  const int64_t n_ls = read_i64(ctx, ls_ptr.p + nB);
-  const int64_t n_l1 = read_i64(ctx, l1_seg.p + (int64_t)nB * nseg);
+  const int64_t n_tiles = read_i64(t_ptr.p + nA, s);
+  const int64_t n_ls = read_i64(ls_ptr.p + nB, s);
+  const int64_t n_l1 = read_i64(l1_seg.p + (int64_t)nB * nseg, s);
 
   // ---- filling passes of the two screens
   DBuf<int64_t> t_off(ctx, std::max<int64_t>(n_tiles, 1));
@@ -612,10 +612,10 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
   DBuf<double> ls_val(ctx, n_ls);
   CIB_HIP(hipEventRecord(ev.e[2], s));
   ta.t_ptr = t_ptr.p; ta.t_off = t_off.p; ta.t_len = t_len.p; ta.t_info = t_info.p; ta.t_val = t_val.p;
-  hipLaunchKernelGGL((k_tile_pass<W, true>), dim3(tblk), dim3(256), 0, s, ta);
+  { KTimer kt(ctx, K_TILE, s); hipLaunchKernelGGL((k_tile_pass<W, true>), dim3(tblk), dim3(256), 0, s, ta); }
   aa.ls_ptr = ls_ptr.p; aa.l1_seg = l1_seg.p; aa.ls_self = ls_self.p; aa.ls_pos = ls_pos.p;
   aa.ls_info = ls_info.p; aa.l1_pos = l1_pos.p; aa.l1_info = l1_info.p; aa.ls_val = ls_val.p;
-  hipLaunchKernelGGL((k_adj_pass<W, true>), dim3(ablk), dim3(256), 0, s, aa);
+  { KTimer kt(ctx, K_ADJ, s); hipLaunchKernelGGL((k_adj_pass<W, true>), dim3(ablk), dim3(256), 0, s, aa); }
   CIB_HIP(hipGetLastError());
   CIB_HIP(hipEventRecord(ev.e[3], s));
 
@@ -631,13 +631,14 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
   DBuf<int32_t> rcnt(ctx, p.D);
   ra.rcnt = rcnt.p;
   const unsigned rblk = (unsigned)((p.D + 3) / 4);
-  hipLaunchKernelGGL((k_row_pass<W, false, double>), dim3(rblk), dim3(256), 0, s, ra);
+  { KTimer kt(ctx, K_ROW_COUNT, s); hipLaunchKernelGGL((k_row_pass<W, false, double>), dim3(rblk), dim3(256), 0, s, ra); }
   CIB_HIP(hipGetLastError());
   CIB_HIP(hipEventRecord(ev.e[4], s));
   H.row_ptr.reset(ctx, p.D + 1);
-  launch_scan(rcnt.p, p.D, H.row_ptr.p, scratch.p, s);
+  { KTimer kt(ctx, K_SCAN, s); launch_scan(rcnt.p, p.D, H.row_ptr.p, scratch.p, s); }
   CIB_HIP(hipEventRecord(ev.e[5], s));
-  const int64_t nnz = read_i64(ctx, H.row_ptr.p + p.D);
+  const int64_t nnz = read_i64(H.row_ptr.p + p.D, s);
+  if (before_fill) before_fill(nnz);
   H.col.reset(ctx, std::max<int64_t>(nnz, 1));
   if (dt == CIB_F64) H.val64.reset(ctx, std::max<int64_t>(nnz, 1));
   else H.val32.reset(ctx, std::max<int64_t>(nnz, 1));
@@ -645,10 +646,13 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
   ra.col = H.col.p;
   ra.val = dt == CIB_F64 ? (void *)H.val64.p : (void *)H.val32.p;
   CIB_HIP(hipEventRecord(ev.e[6], s));
-  if (dt == CIB_F64)
-    hipLaunchKernelGGL((k_row_pass<W, true, double>), dim3(rblk), dim3(256), 0, s, ra);
-  else
-    hipLaunchKernelGGL((k_row_pass<W, true, float>), dim3(rblk), dim3(256), 0, s, ra);
+  {
+    KTimer kt(ctx, K_ROW_FILL, s);
+    if (dt == CIB_F64)
+      hipLaunchKernelGGL((k_row_pass<W, true, double>), dim3(rblk), dim3(256), 0, s, ra);
+    else
+      hipLaunchKernelGGL((k_row_pass<W, true, float>), dim3(rblk), dim3(256), 0, s, ra);
+  }
   CIB_HIP(hipGetLastError());
   CIB_HIP(hipEventRecord(ev.e[7], s));
   CIB_HIP(hipStreamSynchronize(s));
@@ -666,11 +670,11 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
 }
 
 void build_matrix(cib_ctx *ctx, const cib_basis &b, const cib_interaction &it, cib_dtype dt,
-                  cib_matrix &H) {
+                  cib_matrix &H, hipStream_t s, const std::function<void(int64_t)> &before_fill) {
   switch (b.plan.W) {
-    case 1: build_w<1>(ctx, b, it, dt, H); break;
-    case 2: build_w<2>(ctx, b, it, dt, H); break;
-    default: build_w<3>(ctx, b, it, dt, H); break;
+    case 1: build_w<1>(ctx, b, it, dt, H, s, before_fill); break;
+    case 2: build_w<2>(ctx, b, it, dt, H, s, before_fill); break;
+    default: build_w<3>(ctx, b, it, dt, H, s, before_fill); break;
   }
 }
 

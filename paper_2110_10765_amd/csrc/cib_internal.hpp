@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <cstring>
+#include <functional>
 #include <memory>
 #include <mutex>
 #include <stdexcept>
@@ -58,6 +59,13 @@ struct cib_ctx {
   void *pinned = nullptr;  // small pinned host staging buffer
   size_t pinned_bytes = 0;
 
+  // per-kernel event timing (cib_profile_*)
+  bool profiling = false;
+  struct Mark { int kernel; hipEvent_t a, b; };
+  std::vector<Mark> marks;
+  std::vector<hipEvent_t> event_pool;
+  std::unordered_map<int, std::pair<int64_t, double>> kernel_totals;
+
   void *alloc(size_t bytes);
   void free(void *p);
   void release_cache();
@@ -65,6 +73,20 @@ struct cib_ctx {
 };
 
 namespace cib {
+
+// Hot kernels known to the profiler.
+enum KernelId { K_TILE = 0, K_ADJ, K_ROW_COUNT, K_SCAN, K_ROW_FILL, K_SPMM, K_GRAM, K_RR, K_UPDATE, K_NKERN };
+extern const char *const kKernelNames[K_NKERN];
+
+// Brackets one launch with events when profiling is on (RAII).
+struct KTimer {
+  cib_ctx *ctx;
+  int k;
+  hipStream_t s;
+  hipEvent_t a = nullptr, b = nullptr;
+  KTimer(cib_ctx *c, int kernel, hipStream_t st);
+  ~KTimer();
+};
 
 // Typed device buffer owned through the context allocator.
 template <typename T>
@@ -196,12 +218,32 @@ void launch_dab(const DevInter &it, double *dab, hipStream_t s);
 size_t scan_scratch(int64_t n);
 void launch_scan(const int32_t *in, int64_t n, int64_t *out, int64_t *scratch, hipStream_t s);
 
-struct BuildWork;  // defined in build.hip
+// Build H on stream s.  before_fill(nnz) runs on the host once the nonzero
+// count is known and before the CSR arrays are allocated (it may block).
 void build_matrix(cib_ctx *ctx, const cib_basis &b, const cib_interaction &it, cib_dtype dt,
-                  cib_matrix &H);
+                  cib_matrix &H, hipStream_t s, const std::function<void(int64_t)> &before_fill);
+cib_basis *make_basis(cib_ctx *ctx, const cib_basis_spec &spec, hipStream_t s);
+cib_interaction *upload_interaction(cib_ctx *ctx, const cib_basis &b, const cib_tables &t,
+                                    hipStream_t s);
 
 void spmm_sym(const cib_matrix &H, const void *X, int64_t ldx, void *Y, int64_t ldy, int nvec,
               hipStream_t s);
+
+// Step-wise LOBPCG (used by the serving loop): all calls enqueue on the run's
+// stream; the status block (kStatusLen doubles: converged count, b relative
+// residuals, b Ritz values) is copied to host memory by lobpcg_copy_status.
+constexpr int kStatusLen = 1 + 2 * kMaxBlock;
+struct LobpcgRun;
+LobpcgRun *lobpcg_create(cib_ctx *ctx, const cib_matrix &H, const cib_lobpcg_opts &o, hipStream_t s);
+void lobpcg_start(LobpcgRun *r);
+void lobpcg_iterate(LobpcgRun *r);
+void lobpcg_copy_status(LobpcgRun *r, double *host);
+int lobpcg_iters(const LobpcgRun *r);
+void lobpcg_destroy(LobpcgRun *r);
+size_t lobpcg_bytes(int64_t D, int b, cib_dtype dt);
+
+cib_status serve_run(cib_ctx *ctx, const cib_request *reqs, int n, const cib_serve_opts &o,
+                     cib_result *results);
 
 cib_status lobpcg_solve(cib_ctx *ctx, const cib_matrix &H, const cib_lobpcg_opts &o, double *evals,
                         double *evecs, int64_t ld_evecs, cib_lobpcg_info *info);

@@ -495,23 +495,32 @@ __global__ void k_finish(int b, int nev, int nparts, const double *npart, const 
 // ------------------------------------------------------------ host driver
 static inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
-struct Lobpcg {
+struct LobpcgRun {
   cib_ctx *ctx;
   const cib_matrix &H;
   hipStream_t s;
   int64_t D;
-  int b, nev, ld, gram_blocks, upd_blocks;
+  int b, nev, ld, gram_blocks, upd_blocks, max_iter;
   int64_t gram_rows, upd_rows;
+  double tol;
+  cib_lobpcg_opts opts;
   DBuf<double> S, HS, diag, partial, C, lam, npart, status;
   DBuf<float> x32, y32;
   DBuf<int64_t> idx;
   DBuf<int32_t> flag;
-  double *status_h = nullptr;
+  int iters = 0;
   double t_spmm = 0.0;
   int64_t n_spmm = 0;
-  hipEvent_t ev0, ev1;
+  bool timing = false;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
 
-  Lobpcg(cib_ctx *c, const cib_matrix &h, int block, int ne) : ctx(c), H(h), s(c->stream), D(h.D), b(block), nev(ne) {
+  LobpcgRun(cib_ctx *c, const cib_matrix &h, const cib_lobpcg_opts &o, hipStream_t st, bool time_spmm)
+      : ctx(c), H(h), s(st), D(h.D), b(o.block), nev(o.nev), max_iter(o.max_iter), opts(o),
+        timing(time_spmm) {
+    CIB_REQUIRE(nev >= 1 && nev <= b && b <= kMaxBlock, CIB_E_INVALID, "need 1 <= nev <= block <= 16");
+    CIB_REQUIRE(3 * (int64_t)b <= H.D, CIB_E_INVALID, "need 3 * block <= D");
+    CIB_REQUIRE(o.max_iter >= 1, CIB_E_INVALID, "max_iter must be >= 1");
+    tol = o.tol > 0 ? o.tol : (H.dtype == CIB_F64 ? 1e-9 : 1e-6);
     ld = 3 * b;
     S.reset(ctx, (size_t)D * ld);
     HS.reset(ctx, (size_t)D * ld);
@@ -524,24 +533,26 @@ struct Lobpcg {
     C.reset(ctx, kNS * 2 * kMaxBlock);
     lam.reset(ctx, kMaxBlock);
     npart.reset(ctx, (size_t)upd_blocks * 2 * kMaxBlock);
-    status.reset(ctx, 1 + 2 * kMaxBlock);
+    status.reset(ctx, kStatusLen);
     idx.reset(ctx, kMaxBlock);
     flag.reset(ctx, 4);
     if (H.dtype == CIB_F32) {
       x32.reset(ctx, (size_t)D * b);
       y32.reset(ctx, (size_t)D * b);
     }
-    CIB_HIP(hipEventCreate(&ev0));
-    CIB_HIP(hipEventCreate(&ev1));
+    if (timing) {
+      CIB_HIP(hipEventCreate(&ev0));
+      CIB_HIP(hipEventCreate(&ev1));
+    }
   }
-  ~Lobpcg() {
-    (void)hipEventDestroy(ev0);
-    (void)hipEventDestroy(ev1);
+  ~LobpcgRun() {
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
   }
 
   // HS[:, slot] = H S[:, slot]
   void spmm(int slot, bool w32_ready) {
-    CIB_HIP(hipEventRecord(ev0, s));
+    if (timing) CIB_HIP(hipEventRecord(ev0, s));
     if (H.dtype == CIB_F64) {
       spmm_sym(H, S.p + slot * b, ld, HS.p + slot * b, ld, b, s);
     } else {
@@ -550,80 +561,111 @@ struct Lobpcg {
       spmm_sym(H, x32.p, b, y32.p, b, b, s);
       hipLaunchKernelGGL(k_widen, dim3(nblk(D * b)), dim3(256), 0, s, D, b, y32.p, HS.p + slot * b, ld);
     }
-    CIB_HIP(hipEventRecord(ev1, s));
+    if (timing) CIB_HIP(hipEventRecord(ev1, s));
     ++n_spmm;
   }
 
-  void rr_update(int ns, double tol) {
-    hipLaunchKernelGGL(k_gram, dim3(gram_blocks), dim3(256), 0, s, D, ns, ld, S.p, HS.p, gram_rows, partial.p);
+  void rr_update(int ns) {
+    { KTimer kt(ctx, K_GRAM, s); hipLaunchKernelGGL(k_gram, dim3(gram_blocks), dim3(256), 0, s, D, ns, ld, S.p, HS.p, gram_rows, partial.p); }
     RRArgs ra{ns, b, gram_blocks, partial.p, C.p, lam.p, flag.p, 1e-10};
-    hipLaunchKernelGGL(k_rayleigh_ritz, dim3(1), dim3(256), 0, s, ra);
+    { KTimer kt(ctx, K_RR, s); hipLaunchKernelGGL(k_rayleigh_ritz, dim3(1), dim3(256), 0, s, ra); }
     UpdArgs ua{D, b, ns, ld, S.p, HS.p, C.p, lam.p, diag.p, H.dtype == CIB_F32 ? x32.p : nullptr,
                npart.p, (int)upd_rows};
-    hipLaunchKernelGGL(k_update, dim3(upd_blocks), dim3(256), 0, s, ua);
+    { KTimer kt(ctx, K_UPDATE, s); hipLaunchKernelGGL(k_update, dim3(upd_blocks), dim3(256), 0, s, ua); }
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, s, b, nev, upd_blocks, npart.p, lam.p, tol, status.p);
     CIB_HIP(hipGetLastError());
   }
 
-  int read_status() {
-    CIB_HIP(hipMemcpyAsync(status_h, status.p, sizeof(double) * (1 + 2 * kMaxBlock), hipMemcpyDeviceToHost, s));
-    CIB_HIP(hipStreamSynchronize(s));
+  // diagonal, X0 and the Rayleigh-Ritz step on X0 alone
+  void start() {
+    if (H.dtype == CIB_F64)
+      hipLaunchKernelGGL(k_diag<double>, dim3(nblk(D)), dim3(256), 0, s, D, H.row_ptr.p, H.val64.p, diag.p);
+    else
+      hipLaunchKernelGGL(k_diag<float>, dim3(nblk(D)), dim3(256), 0, s, D, H.row_ptr.p, H.val32.p, diag.p);
+    if (opts.x0) {
+      hipLaunchKernelGGL(k_copy_x0, dim3(nblk(D * b)), dim3(256), 0, s, D, b, ld, opts.x0, S.p);
+    } else {
+      hipLaunchKernelGGL(k_select_smallest, dim3(1), dim3(1024), 0, s, D, diag.p, b, idx.p);
+      hipLaunchKernelGGL(k_init_x, dim3(nblk(D * b)), dim3(256), 0, s, D, b, ld, idx.p, opts.seed, S.p);
+    }
+    CIB_HIP(hipGetLastError());
+    spmm(0, false);
+    rr_update(b);
+  }
+
+  void iterate() {
+    ++iters;
+    spmm(1, H.dtype == CIB_F32);
+    rr_update(iters == 1 ? 2 * b : 3 * b);
+  }
+
+  void copy_status(double *host) {
+    CIB_HIP(hipMemcpyAsync(host, status.p, sizeof(double) * kStatusLen, hipMemcpyDeviceToHost, s));
+  }
+
+  void spmm_time_accumulate() {
+    if (!timing) return;
     float ms = 0.f;
     CIB_HIP(hipEventElapsedTime(&ms, ev0, ev1));
     t_spmm += ms * 1e-3;
-    return (int)status_h[0];
+  }
+
+  void copy_vectors(double *evecs, int64_t ld_evecs) {
+    hipLaunchKernelGGL(k_copy_cols, dim3(nblk(D * nev)), dim3(256), 0, s, D, nev, S.p, ld, evecs, ld_evecs);
+    CIB_HIP(hipGetLastError());
   }
 };
+
+size_t lobpcg_bytes(int64_t D, int b, cib_dtype dt) {
+  const int64_t gram_rows = std::max<int64_t>(256, (D + 2047) / 2048);
+  const int64_t gram_blocks = (D + gram_rows - 1) / gram_rows;
+  const int64_t upd_rows = std::max<int64_t>(64, (D + 4095) / 4096);
+  const int64_t upd_blocks = (D + upd_rows - 1) / upd_rows;
+  size_t n = (size_t)D * 3 * b * 8 * 2 + (size_t)D * 8 + (size_t)gram_blocks * kNS * 2 * kNS * 8 +
+             (size_t)upd_blocks * 2 * kMaxBlock * 8 + 64 * 1024;
+  if (dt == CIB_F32) n += (size_t)D * b * 4 * 2;
+  return n;
+}
+
+LobpcgRun *lobpcg_create(cib_ctx *ctx, const cib_matrix &H, const cib_lobpcg_opts &o, hipStream_t s) {
+  return new LobpcgRun(ctx, H, o, s, false);
+}
+void lobpcg_start(LobpcgRun *r) { r->start(); }
+void lobpcg_iterate(LobpcgRun *r) { r->iterate(); }
+void lobpcg_copy_status(LobpcgRun *r, double *host) { r->copy_status(host); }
+int lobpcg_iters(const LobpcgRun *r) { return r->iters; }
+void lobpcg_destroy(LobpcgRun *r) { delete r; }
 
 cib_status lobpcg_solve(cib_ctx *ctx, const cib_matrix &H, const cib_lobpcg_opts &o, double *evals,
                         double *evecs, int64_t ld_evecs, cib_lobpcg_info *info) {
   const auto t0 = std::chrono::steady_clock::now();
-  const int b = o.block, nev = o.nev;
-  CIB_REQUIRE(nev >= 1 && nev <= b && b <= kMaxBlock, CIB_E_INVALID, "need 1 <= nev <= block <= 16");
-  CIB_REQUIRE(3 * (int64_t)b <= H.D, CIB_E_INVALID, "need 3 * block <= D");
-  CIB_REQUIRE(o.max_iter >= 1, CIB_E_INVALID, "max_iter must be >= 1");
-  CIB_REQUIRE(!evecs || ld_evecs >= nev, CIB_E_INVALID, "ld_evecs < nev");
-  const double tol = o.tol > 0 ? o.tol : (H.dtype == CIB_F64 ? 1e-9 : 1e-6);
-  Lobpcg L(ctx, H, b, nev);
-  L.status_h = static_cast<double *>(ctx->pinned_buf(sizeof(double) * (1 + 2 * kMaxBlock)));
-  hipStream_t s = L.s;
-  const int64_t D = H.D;
-  if (H.dtype == CIB_F64)
-    hipLaunchKernelGGL(k_diag<double>, dim3(nblk(D)), dim3(256), 0, s, D, H.row_ptr.p, H.val64.p, L.diag.p);
-  else
-    hipLaunchKernelGGL(k_diag<float>, dim3(nblk(D)), dim3(256), 0, s, D, H.row_ptr.p, H.val32.p, L.diag.p);
-  if (o.x0) {
-    hipLaunchKernelGGL(k_copy_x0, dim3(nblk(D * b)), dim3(256), 0, s, D, b, L.ld, o.x0, L.S.p);
-  } else {
-    hipLaunchKernelGGL(k_select_smallest, dim3(1), dim3(1024), 0, s, D, L.diag.p, b, L.idx.p);
-    hipLaunchKernelGGL(k_init_x, dim3(nblk(D * b)), dim3(256), 0, s, D, b, L.ld, L.idx.p, o.seed, L.S.p);
+  CIB_REQUIRE(!evecs || ld_evecs >= o.nev, CIB_E_INVALID, "ld_evecs < nev");
+  LobpcgRun L(ctx, H, o, ctx->stream, true);
+  double *st = static_cast<double *>(ctx->pinned_buf(sizeof(double) * kStatusLen));
+  L.start();
+  L.copy_status(st);
+  CIB_HIP(hipStreamSynchronize(L.s));
+  L.spmm_time_accumulate();
+  int conv = (int)st[0];
+  while (conv < L.nev && L.iters < L.max_iter) {
+    L.iterate();
+    L.copy_status(st);
+    CIB_HIP(hipStreamSynchronize(L.s));
+    L.spmm_time_accumulate();
+    conv = (int)st[0];
   }
-  CIB_HIP(hipGetLastError());
-  // iteration 0: Rayleigh-Ritz on X0 alone
-  L.spmm(0, false);
-  L.rr_update(b, tol);
-  int conv = L.read_status();
-  int it = 0;
-  while (conv < nev && it < o.max_iter) {
-    ++it;
-    L.spmm(1, H.dtype == CIB_F32);
-    L.rr_update(it == 1 ? 2 * b : 3 * b, tol);
-    conv = L.read_status();
-  }
-  for (int k = 0; k < nev; ++k) evals[k] = L.status_h[1 + kMaxBlock + k];
-  if (evecs)
-    hipLaunchKernelGGL(k_copy_cols, dim3(nblk(D * nev)), dim3(256), 0, s, D, nev, L.S.p, L.ld, evecs, ld_evecs);
-  CIB_HIP(hipGetLastError());
-  CIB_HIP(hipStreamSynchronize(s));
+  for (int k = 0; k < L.nev; ++k) evals[k] = st[1 + kMaxBlock + k];
+  if (evecs) L.copy_vectors(evecs, ld_evecs);
+  CIB_HIP(hipStreamSynchronize(L.s));
   if (info) {
-    info->iters = it;
+    info->iters = L.iters;
     info->n_converged = conv;
-    for (int k = 0; k < 64; ++k) info->resid[k] = k < b ? L.status_h[1 + k] : 0.0;
+    for (int k = 0; k < 64; ++k) info->resid[k] = k < L.b ? st[1 + k] : 0.0;
     info->t_total_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     info->t_spmm_s = L.t_spmm;
     info->n_spmm = L.n_spmm;
   }
-  return conv >= nev ? CIB_OK : CIB_E_NOT_CONVERGED;
+  return conv >= L.nev ? CIB_OK : CIB_E_NOT_CONVERGED;
 }
 
 }  // namespace cib

@@ -42,7 +42,52 @@ static PairLayout pair_layout(const Orbs &o1, const Orbs &o2, bool same) {
   return L;
 }
 
-cib_interaction *upload_interaction(cib_ctx *ctx, const cib_basis &b, const cib_tables &t) {
+const char *const kKernelNames[K_NKERN] = {"tile_screen", "adjacency", "row_count", "scan",
+                                           "row_fill", "spmm_sym", "gram", "rayleigh_ritz", "update"};
+
+static hipEvent_t take_event(cib_ctx *c) {
+  if (!c->event_pool.empty()) {
+    hipEvent_t e = c->event_pool.back();
+    c->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  CIB_HIP(hipEventCreate(&e));
+  return e;
+}
+
+KTimer::KTimer(cib_ctx *c, int kernel, hipStream_t st) : ctx(c), k(kernel), s(st) {
+  if (!ctx || !ctx->profiling) return;
+  std::lock_guard<std::mutex> g(ctx->mu);
+  a = take_event(ctx);
+  b = take_event(ctx);
+  CIB_HIP(hipEventRecord(a, s));
+}
+
+KTimer::~KTimer() {
+  if (!a) return;
+  std::lock_guard<std::mutex> g(ctx->mu);
+  if (hipEventRecord(b, s) == hipSuccess) ctx->marks.push_back({k, a, b});
+}
+
+// Resolve completed marks into per-kernel totals (synchronises their events).
+void profile_collect(cib_ctx *c) {
+  std::lock_guard<std::mutex> g(c->mu);
+  for (auto &m : c->marks) {
+    float ms = 0.f;
+    if (hipEventSynchronize(m.b) == hipSuccess && hipEventElapsedTime(&ms, m.a, m.b) == hipSuccess) {
+      auto &t = c->kernel_totals[m.kernel];
+      t.first += 1;
+      t.second += ms * 1e-3;
+    }
+    c->event_pool.push_back(m.a);
+    c->event_pool.push_back(m.b);
+  }
+  c->marks.clear();
+}
+
+cib_interaction *upload_interaction(cib_ctx *ctx, const cib_basis &b, const cib_tables &t,
+                                    hipStream_t s) {
   const Plan &p = b.plan;
   CIB_REQUIRE(t.eps[0] && t.v_same[0], CIB_E_INVALID, "tables: eps[0] and v_same[0] required");
   if (p.ns == 2)
@@ -52,7 +97,6 @@ cib_interaction *upload_interaction(cib_ctx *ctx, const cib_basis &b, const cib_
   it->ctx = ctx;
   it->nA = p.oA.n_orb;
   it->nB = p.ns == 2 ? p.oB.n_orb : 0;
-  hipStream_t s = ctx->stream;
   auto up_layout = [&](const PairLayout &L, const double *v, DBuf<int32_t> &pidx, DBuf<int32_t> &vn,
                        DBuf<int64_t> &vbase, DBuf<double> &dv) {
     pidx.reset(ctx, L.pidx.size());
@@ -81,6 +125,47 @@ cib_interaction *upload_interaction(cib_ctx *ctx, const cib_basis &b, const cib_
   // host arrays are copied before returning
   CIB_HIP(hipStreamSynchronize(s));
   return it.release();
+}
+
+
+cib_basis *make_basis(cib_ctx *ctx, const cib_basis_spec &spec, hipStream_t s) {
+  std::unique_ptr<cib_basis> b(new cib_basis);
+  b->ctx = ctx;
+  make_plan(spec, b->plan);
+  const Plan &p = b->plan;
+  CIB_REQUIRE(p.D > 0, CIB_E_EMPTY_BASIS, "the spec admits no state");
+  CIB_REQUIRE(p.D < (int64_t(1) << 31), CIB_E_OVERFLOW, "basis dimension exceeds 2^31-1");
+  const int W = p.W, nA = p.nA(), nB = p.nB();
+  std::vector<uint64_t> soa((size_t)W * nA);
+  for (int k = 0; k < nA; ++k)
+    for (int w = 0; w < W; ++w) soa[(size_t)w * nA + k] = p.A.bits[(size_t)k * kMaxWords + w];
+  b->a_bits.reset(ctx, soa.size());
+  b->a_bits.upload(soa.data(), soa.size(), s);
+  std::vector<uint64_t> sob((size_t)W * nB);
+  for (int k = 0; k < nB; ++k)
+    for (int w = 0; w < W; ++w) sob[(size_t)w * nB + k] = p.B.bits[(size_t)k * kMaxWords + w];
+  b->b_bits.reset(ctx, sob.size());
+  b->b_bits.upload(sob.data(), sob.size(), s);
+  auto up32 = [&](DBuf<int32_t> &d, const std::vector<int32_t> &h) {
+    d.reset(ctx, std::max<size_t>(h.size(), 1));
+    d.upload(h.data(), h.size(), s);
+  };
+  up32(b->a_m2, p.A.m2);
+  up32(b->a_q, p.A.q);
+  up32(b->a_len, p.a_len);
+  up32(b->a_seg, p.a_seg);
+  up32(b->b_m2, p.B.m2);
+  up32(b->b_q, p.B.q);
+  up32(b->b_seg, p.b_seg);
+  up32(b->bseg_start, p.bseg_start);
+  b->a_off.reset(ctx, p.a_off.size());
+  b->a_off.upload(p.a_off.data(), p.a_off.size(), s);
+  b->row_a.reset(ctx, p.D);
+  b->row_p.reset(ctx, p.D);
+  b->words.reset(ctx, (size_t)(p.WA + p.WB) * p.D);
+  launch_expand_basis(*b, s);
+  CIB_HIP(hipStreamSynchronize(s));  // host staging vectors go out of scope
+  return b.release();
 }
 
 }  // namespace cib

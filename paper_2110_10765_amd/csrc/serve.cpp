@@ -1,0 +1,268 @@
+// Continuous-batching serving loop (cib_serve).
+//
+// Two host threads share one context:
+//   builder  takes requests in arrival order once they have arrived and a slot
+//            is free, builds the basis and the interaction tables, runs the
+//            counting passes of the H build, then waits until the request's
+//            whole device footprint (H, LOBPCG state, build scratch) fits the
+//            HBM budget, fills H and hands the request to the solver;
+//   solver   keeps every admitted request's H and LOBPCG state resident and,
+//            each step, enqueues one stage for every active request
+//            (initialisation for new ones, one LOBPCG iteration for the rest)
+//            on a pool of streams so their kernels overlap on the device,
+//            waits once, reads every status block from pinned memory, and
+//            retires converged requests (releasing their memory and budget).
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <thread>
+
+#include "cib_internal.hpp"
+
+namespace cib {
+
+namespace {
+
+using clk = std::chrono::steady_clock;
+
+struct Job {
+  int idx = 0;
+  const cib_request *req = nullptr;
+  cib_result *res = nullptr;
+  std::unique_ptr<cib_basis> basis;
+  std::unique_ptr<cib_interaction> inter;
+  std::unique_ptr<cib_matrix> H;
+  LobpcgRun *lp = nullptr;
+  size_t reserved = 0;
+  int stream = 0;
+  bool started = false;
+  double *status = nullptr;  // pinned host slot
+  ~Job() {
+    if (lp) lobpcg_destroy(lp);
+  }
+};
+
+struct Shared {
+  std::mutex mu;
+  std::condition_variable cv;
+  size_t budget = 0, in_use = 0;
+  int active = 0, max_active = 64;
+  std::deque<Job *> ready;
+  bool builder_done = false;
+  bool cancelled = false;
+};
+
+}  // namespace
+
+static size_t footprint(const cib_basis &b, int64_t nnz, cib_dtype dt, int block) {
+  const int64_t D = b.plan.D;
+  const size_t sv = dt == CIB_F64 ? 8 : 4;
+  size_t h = (size_t)nnz * (4 + sv) + 8 * (size_t)(D + 1);
+  return h + lobpcg_bytes(D, block, dt);
+}
+
+cib_status serve_run(cib_ctx *ctx, const cib_request *reqs, int n, const cib_serve_opts &o,
+                     cib_result *results) {
+  const auto t0 = clk::now();
+  auto now = [&] { return std::chrono::duration<double>(clk::now() - t0).count(); };
+  Shared sh;
+  sh.max_active = o.max_active > 0 ? o.max_active : 64;
+  const int nstreams = o.n_streams > 0 ? o.n_streams : 8;
+  if (o.hbm_budget_bytes) {
+    sh.budget = o.hbm_budget_bytes;
+  } else {
+    size_t fr = 0, tot = 0;
+    CIB_HIP(hipMemGetInfo(&fr, &tot));
+    sh.budget = (size_t)(0.9 * (double)fr);
+  }
+  const double deadline = o.deadline_s > 0 ? o.deadline_s : 1e300;
+
+  for (int i = 0; i < n; ++i) {
+    cib_result &r = results[i];
+    std::memset(&r, 0, sizeof(r));
+    r.id = reqs[i].id;
+    r.status = CIB_E_CANCELLED;
+    r.t_arrive = o.realtime ? reqs[i].arrival_s : 0.0;
+  }
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return reqs[a].arrival_s < reqs[b].arrival_s; });
+
+  std::vector<hipStream_t> streams(nstreams + 1, nullptr);
+  for (auto &st : streams) CIB_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+  hipStream_t bstream = streams[nstreams];
+  double *pinned = nullptr;
+  CIB_HIP(hipHostMalloc((void **)&pinned, sizeof(double) * kStatusLen * (size_t)sh.max_active,
+                        hipHostMallocDefault));
+  std::vector<int> free_slots;
+  for (int k = sh.max_active - 1; k >= 0; --k) free_slots.push_back(k);
+  std::string builder_error;
+  cib_status builder_status = CIB_OK;
+
+  // ------------------------------------------------------------ builder thread
+  std::thread builder([&] {
+    int dev = ctx->device;
+    (void)hipSetDevice(dev);
+    for (int k = 0; k < n; ++k) {
+      const int i = order[k];
+      const cib_request &q = reqs[i];
+      cib_result &res = results[i];
+      if (o.realtime) {
+        const double wait = q.arrival_s - now();
+        if (wait > 0) std::this_thread::sleep_for(std::chrono::duration<double>(wait));
+      }
+      {
+        std::unique_lock<std::mutex> lk(sh.mu);
+        sh.cv.wait(lk, [&] { return sh.active < sh.max_active || sh.cancelled; });
+        if (sh.cancelled) break;
+        ++sh.active;
+      }
+      if (now() > deadline) {
+        std::lock_guard<std::mutex> lk(sh.mu);
+        --sh.active;
+        sh.cv.notify_all();
+        continue;  // stays CIB_E_CANCELLED
+      }
+      res.t_admit = now();
+      std::unique_ptr<Job> job(new Job);
+      job->idx = i;
+      job->req = &q;
+      job->res = &res;
+      cib_status st = CIB_OK;
+      try {
+        CIB_REQUIRE(q.tables, CIB_E_INVALID, "request without tables");
+        CIB_REQUIRE(q.solve.x0 == nullptr, CIB_E_INVALID, "serving requests cannot pass x0");
+        CIB_REQUIRE(q.solve.nev >= 1 && q.solve.nev <= 16, CIB_E_INVALID, "nev must be in 1..16");
+        job->basis.reset(make_basis(ctx, q.basis, bstream));
+        res.dim = job->basis->plan.D;
+        CIB_REQUIRE(3 * (int64_t)q.solve.block <= res.dim, CIB_E_INVALID, "need 3 * block <= D");
+        job->inter.reset(upload_interaction(ctx, *job->basis, *q.tables, bstream));
+        job->H.reset(new cib_matrix);
+        job->H->ctx = ctx;
+        build_matrix(ctx, *job->basis, *job->inter, q.dtype, *job->H, bstream, [&](int64_t nnz) {
+          const size_t need = footprint(*job->basis, nnz, q.dtype, q.solve.block);
+          CIB_REQUIRE(need <= sh.budget, CIB_E_NOMEM, "request footprint exceeds the HBM budget");
+          std::unique_lock<std::mutex> lk(sh.mu);
+          sh.cv.wait(lk, [&] { return sh.in_use + need <= sh.budget || sh.cancelled; });
+          CIB_REQUIRE(!sh.cancelled, CIB_E_CANCELLED, "cancelled");
+          sh.in_use += need;
+          job->reserved = need;
+        });
+        res.nnz_half = job->H->nnz;
+        job->inter.reset();  // tables are no longer needed once H is built
+      } catch (const Error &e) {
+        st = e.code;
+        if (st == CIB_E_DEVICE) { builder_error = e.what(); builder_status = st; }
+      } catch (const std::exception &e) {
+        st = CIB_E_DEVICE;
+        builder_error = e.what();
+        builder_status = st;
+      }
+      if (st != CIB_OK) {
+        res.status = st;
+        res.t_done = now();
+        std::lock_guard<std::mutex> lk(sh.mu);
+        sh.in_use -= job->reserved;
+        --sh.active;
+        sh.cv.notify_all();
+        if (builder_status != CIB_OK) { sh.cancelled = true; break; }
+        continue;
+      }
+      std::lock_guard<std::mutex> lk(sh.mu);
+      sh.ready.push_back(job.release());
+      sh.cv.notify_all();
+    }
+    std::lock_guard<std::mutex> lk(sh.mu);
+    sh.builder_done = true;
+    sh.cv.notify_all();
+  });
+
+  // ------------------------------------------------------------ solver loop
+  std::vector<Job *> active;
+  int next_stream = 0;
+  cib_status loop_status = CIB_OK;
+  std::string loop_error;
+  try {
+    for (;;) {
+      {
+        std::unique_lock<std::mutex> lk(sh.mu);
+        if (active.empty())
+          sh.cv.wait(lk, [&] { return !sh.ready.empty() || sh.builder_done; });
+        while (!sh.ready.empty()) {
+          Job *j = sh.ready.front();
+          sh.ready.pop_front();
+          j->stream = next_stream;
+          next_stream = (next_stream + 1) % nstreams;
+          j->status = pinned + (size_t)free_slots.back() * kStatusLen;
+          free_slots.pop_back();
+          active.push_back(j);
+        }
+        if (active.empty() && sh.builder_done) break;
+      }
+      if (now() > deadline) break;
+      // enqueue one stage per active request
+      for (Job *j : active) {
+        hipStream_t s = streams[j->stream];
+        if (!j->started) {
+          cib_lobpcg_opts lo = j->req->solve;
+          j->lp = lobpcg_create(ctx, *j->H, lo, s);
+          lobpcg_start(j->lp);
+          j->started = true;
+        } else {
+          lobpcg_iterate(j->lp);
+        }
+        lobpcg_copy_status(j->lp, j->status);
+      }
+      for (int k = 0; k < nstreams; ++k) CIB_HIP(hipStreamSynchronize(streams[k]));
+      // retire
+      std::vector<Job *> keep;
+      for (Job *j : active) {
+        const int nev = j->req->solve.nev;
+        const int conv = (int)j->status[0];
+        const int it = lobpcg_iters(j->lp);
+        const bool done = conv >= nev || it >= j->req->solve.max_iter;
+        if (!done) { keep.push_back(j); continue; }
+        cib_result &r = *j->res;
+        r.status = conv >= nev ? CIB_OK : CIB_E_NOT_CONVERGED;
+        r.iters = it;
+        for (int k = 0; k < nev; ++k) {
+          r.resid[k] = j->status[1 + k];
+          r.evals[k] = j->status[1 + kMaxBlock + k];
+        }
+        r.t_done = now();
+        free_slots.push_back((int)((j->status - pinned) / kStatusLen));
+        const size_t rel = j->reserved;
+        delete j;
+        std::lock_guard<std::mutex> lk(sh.mu);
+        sh.in_use -= rel;
+        --sh.active;
+        sh.cv.notify_all();
+      }
+      active.swap(keep);
+    }
+  } catch (const Error &e) {
+    loop_status = e.code;
+    loop_error = e.what();
+  } catch (const std::exception &e) {
+    loop_status = CIB_E_DEVICE;
+    loop_error = e.what();
+  }
+  {
+    std::lock_guard<std::mutex> lk(sh.mu);
+    sh.cancelled = true;
+    sh.cv.notify_all();
+  }
+  builder.join();
+  for (auto &st : streams) (void)hipStreamSynchronize(st);
+  for (Job *j : active) delete j;
+  for (Job *j : sh.ready) delete j;
+  for (auto &st : streams) (void)hipStreamDestroy(st);
+  (void)hipHostFree(pinned);
+  if (loop_status != CIB_OK) throw Error(loop_status, loop_error);
+  if (builder_status != CIB_OK) throw Error(builder_status, builder_error);
+  return CIB_OK;
+}
+
+}  // namespace cib

@@ -60,6 +60,7 @@ static void spmm_t(const cib_matrix &H, const T *X, int64_t ldx, T *Y, int64_t l
   hipLaunchKernelGGL(k_zero<T>, dim3((unsigned)((nz + 255) / 256)), dim3(256), 0, s, Y, D, ldy, nvec);
   const unsigned nblk = (unsigned)((D + 3) / 4);
   for (int v0 = 0; v0 < nvec; v0 += 16) {
+    KTimer kt(H.ctx, K_SPMM, s);
     if (nvec - v0 <= 8)
       hipLaunchKernelGGL((k_spmm_sym<T, 8>), dim3(nblk), dim3(256), 0, s, D, H.row_ptr.p, H.col.p,
                          val, X, ldx, Y, ldy, nvec, v0);
