@@ -114,7 +114,7 @@ def serve_run(cib, ctx, cigen, dtype, n_req, budget=0):
         r = dict(r)
         r["tables"] = cigen.make_tables(r["spec"], r["seed"])
         r["dtype"] = dtype
-        r["tol"] = 1e-6
+        r["tol"] = 0.0   # library default per dtype
         reqs.append(r)
     t0 = time.perf_counter()
     res = cib.serve(ctx, reqs, hbm_budget_bytes=budget)
@@ -139,14 +139,14 @@ def cpu_baseline(cigen, name, seconds=15.0):
     rng = np.random.default_rng(0)
     n = 256
     total_nnz, total_t, cols_done = 0, 0.0, 0
-    while total_t < seconds and cols_done < b.D:
-        cols = rng.choice(b.D, size=min(n, b.D), replace=False)
+    while total_t < seconds:
+        cols = rng.integers(0, b.D, size=n)
         t0 = time.perf_counter()
         ptr, rows, vals = O.apply_columns(b, inter, cols)
         total_t += time.perf_counter() - t0
         total_nnz += int(ptr[-1])
         cols_done += len(cols)
-        n *= 2
+        n = min(2 * n, 1 << 16)
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     # nnz_full entries produced -> nnz_half-equivalent rate (each stored entry once)
     return {"value": total_nnz / total_t * 0.5 * (1 + 1.0 / max(1, total_nnz / cols_done)),
@@ -165,6 +165,10 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only copy 1 GiB five times (scale factor for the HBM byte counters)")
+    ap.add_argument("--spmm-only", default="",
+                    help="NAME:block:dtype -- only build H and run 10 SpMMs (for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU; --gpus %d is not supported (multi-GPU "
@@ -174,6 +178,28 @@ def main():
     import torch
     import cigen
     from paper_2110_10765_amd import cib
+
+    if args.calibrate_copy:
+        n = 1 << 27                          # 2^27 float64 = 1 GiB
+        src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        _sync()
+        print(json.dumps({"calibrate_copy_bytes_each_way": n * 8, "launches": 5}))
+        return
+    if args.spmm_only:
+        name, bb, dt = args.spmm_only.split(":")
+        wl = cigen.WORKLOADS[name]
+        ctx = cib.Context(0)
+        basis = cib.build_basis(ctx, wl.spec)
+        H = cib.build_H(ctx, basis, cigen.make_tables(wl.spec, wl.seed), dt)
+        t = measure_spmm(cib, ctx, H, int(bb), 10)
+        sv = 8 if dt == "f64" else 4
+        print(json.dumps({"workload": name, "dtype": dt, "block": int(bb), "D": H.dim,
+                          "nnz_half": H.nnz, "spmm_kernel_s": t,
+                          "algorithmic_bytes": _spmm_bytes(H.nnz, H.dim, int(bb), sv)}))
+        return
 
     w = cigen.WORKLOADS[args.workload]
     ctx = cib.Context(0)

@@ -84,7 +84,8 @@ cib_status cib_ctx_bytes(const cib_ctx *ctx, int64_t *live_bytes, int64_t *peak_
  * elapsed times of all completed launches of one kernel since the last reset
  * (it synchronises those events).  Kernel names: "tile_screen",
  * "adjacency", "row_count", "scan", "row_fill", "spmm_sym", "gram",
- * "rayleigh_ritz", "update".  Unknown names report zero launches. */
+ * "rayleigh_ritz", "update", "lower" (all passes of the lower triangle).
+ * Unknown names report zero launches. */
 cib_status cib_profile_enable(cib_ctx *ctx, int on);
 cib_status cib_profile_reset(cib_ctx *ctx);
 cib_status cib_profile_query(cib_ctx *ctx, const char *kernel, int64_t *launches, double *total_s);
@@ -165,7 +166,12 @@ void cib_interaction_free(cib_interaction *it);
  * differ in at most four orbitals (Sec. 2.1), whether or not its value is
  * zero.  Counting pass, counts -> offsets prefix sum, and a filling pass
  * (Fig. 1 steps 6-14; Sec. 2.2-2.3) with a deterministic in-row order.
- * One host synchronisation (the nonzero total sizes the allocation). */
+ * Host synchronisations: the screen totals and the nonzero total size the
+ * allocations.  The matrix also keeps the strictly lower triangle (built by
+ * the same passes over the transposed screens, bitwise the transpose for
+ * symmetric tables) because the SpMM reads both triangles instead of
+ * scattering the transposed half with atomics; cib_matrix_export returns
+ * only the upper half. */
 cib_status cib_build_H(cib_ctx *ctx, const cib_basis *basis, const cib_tables *t, cib_dtype dtype,
                        cib_matrix **out, int64_t *nnz_half);
 /* Same, with tables already on the device. */
@@ -178,9 +184,10 @@ typedef struct {
   double t_count_s;   /* per-row counting pass                           */
   double t_scan_s;    /* counts -> offsets                               */
   double t_fill_s;    /* per-row filling pass                            */
-  double t_total_s;   /* sum of the above                                */
+  double t_total_s;   /* sum of the above (the half-stored CSR)          */
   int64_t n_tiles;    /* A-configuration pairs kept by the screen        */
   int64_t n_adjacent; /* B-configuration pairs kept by the screen        */
+  double t_lower_s;   /* strictly lower triangle kept for the SpMM       */
 } cib_build_stats;
 
 cib_status cib_matrix_info(const cib_matrix *H, int64_t *dim, int64_t *nnz_half, cib_dtype *dtype);
@@ -209,7 +216,11 @@ cib_status cib_apply_H(cib_ctx *ctx, const cib_matrix *H, const void *X, int64_t
  * device; the SpMM runs in the matrix dtype.  Preconditioner: diagonal,
  * W = R / (diag(H) - lambda) with |diag - lambda| clamped below at 1e-2.
  * Converged when ||H x_k - lambda_k x_k|| <= tol * max(|lambda_k|, 1) for all
- * k < nev (tol <= 0: 1e-9 for float64 H, 1e-6 for float32 H).
+ * k < nev (tol <= 0: 1e-9 for float64 H; 1e-5 for float32 H, whose SpMM
+ * rounding floors the residual near 1e-6 while the eigenvalue error, quadratic
+ * in the residual, stays far below 1e-6).  Soft locking: a column whose
+ * residual met tol at the previous iteration gets W = 0, so it leaves the
+ * search space (its direction is dropped by the Cholesky) until it drifts out.
  * X0: unit vectors at the `block` smallest diagonal entries (ties: lower
  * index) plus 1e-3 * noise from a counter-based generator keyed by `seed`,
  * unless x0 (device, D x block float64 row-major) is given. */

@@ -72,7 +72,7 @@ class BuildStatsC(ctypes.Structure):
     _fields_ = [("t_screen_s", ctypes.c_double), ("t_count_s", ctypes.c_double),
                 ("t_scan_s", ctypes.c_double), ("t_fill_s", ctypes.c_double),
                 ("t_total_s", ctypes.c_double), ("n_tiles", ctypes.c_int64),
-                ("n_adjacent", ctypes.c_int64)]
+                ("n_adjacent", ctypes.c_int64), ("t_lower_s", ctypes.c_double)]
 
 
 class LobpcgOptsC(ctypes.Structure):
@@ -114,6 +114,11 @@ def load(path: str = LIB_PATH):
     global _LIB
     if _LIB is not None:
         return _LIB
+    # torch ships its own HIP/HSA runtime with the same sonames as /opt/rocm's;
+    # loading torch first makes libcib bind to that one runtime instead of
+    # bringing a second HIP + HSA runtime into the process (which then finds
+    # no device)
+    import torch  # noqa: F401
     if not os.path.exists(path):
         raise RuntimeError("libcib.so not found at %s: run `python -m paper_2110_10765_amd.build`" % path)
     lib = ctypes.CDLL(path)

@@ -116,8 +116,10 @@ __global__ void k_dab(DevInter it, double *dab) {
 }
 
 // ------------------------------------------------------------ tile screen
-// One wave per A configuration alpha; lanes over alpha' > alpha.  Kept: kA = 1,
-// or kA = 2 with equal 2M_A (a kA = 2 pair needs identical B configurations).
+// One wave per A configuration alpha; lanes over alpha' > alpha (or < alpha for
+// the lower triangle).  Kept: kA = 1, or kA = 2 with equal 2M_A (a kA = 2 pair
+// needs identical B configurations).  Tile data are computed with alpha as the
+// bra (row) and alpha' as the ket (column).
 struct TileArgs {
   int nA;
   const uint64_t *a_bits;
@@ -131,7 +133,7 @@ struct TileArgs {
   double *t_val;
 };
 
-template <int W, bool FILL>
+template <int W, bool FILL, bool LOWER>
 __global__ __launch_bounds__(256) void k_tile_pass(TileArgs g) {
   const int alpha = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6);
   if (alpha >= g.nA) return;
@@ -141,11 +143,12 @@ __global__ __launch_bounds__(256) void k_tile_pass(TileArgs g) {
   const int m = g.a_m2[alpha];
   int64_t out = FILL ? g.t_ptr[alpha] : 0;
   int cnt = 0;
-  for (int j0 = alpha + 1; j0 < g.nA; j0 += kWave) {
+  const int jb = LOWER ? 0 : alpha + 1, je = LOWER ? alpha : g.nA;
+  for (int j0 = jb; j0 < je; j0 += kWave) {
     const int j = j0 + lane;
     bool ok = false;
     uint64_t ca[W];
-    if (j < g.nA) {
+    if (j < je) {
       load_bits<W>(g.a_bits, g.nA, j, ca);
       const int d = popc_xor<W>(ra, ca);
       ok = d <= 2 || (d == 4 && g.a_m2[j] == m);
@@ -298,20 +301,162 @@ struct RowArgs {
   void *val;
 };
 
-// One wave per row i = (alpha, p).  Entries in column order: first the
-// diagonal A-block (Lsame of beta from beta itself on, positions < len(alpha)),
-// then the tiles alpha' > alpha in ascending order.
+// Diagonal A-block part of a row: Lsame(beta) entries [e0, e1) in position
+// order, kept while position < len(alpha) (a prefix).
 template <int W, bool FILL, typename T>
+__device__ __forceinline__ void row_diag(const RowArgs &g, int64_t e0, int64_t e1, int alpha,
+                                         int len_a, int64_t off_a, const uint64_t *ab,
+                                         const uint64_t *bb, int64_t out, int64_t &cnt) {
+  const int lane = lane_id();
+  T *val = static_cast<T *>(g.val);
+  for (int64_t k0 = e0; k0 < e1; k0 += kWave) {
+    const int64_t k = k0 + lane;
+    const bool valid = k < e1;
+    const bool ok = valid && g.ls_pos[k] < len_a;
+    const uint64_t m = ballot(ok);
+    if (FILL && ok) {
+      const int info = g.ls_info[k];
+      double v = g.ls_val[k];
+      const int kb = info & 3;
+      if (kb == 0) {  // diagonal: E_A + E_B + sum_{x in alpha, y in beta} V^AB_{xy,xy}
+        v += g.eA[alpha];
+        if (g.it.nB > 0) {
+          uint64_t t[W];
+#pragma unroll
+          for (int w = 0; w < W; ++w) t[w] = ab[w];
+          for (int x = pop_lowest<W>(t); x >= 0; x = pop_lowest<W>(t)) {
+            uint64_t u[W];
+#pragma unroll
+            for (int w = 0; w < W; ++w) u[w] = bb[w];
+            for (int y = pop_lowest<W>(u); y >= 0; y = pop_lowest<W>(u)) v += g.it.dab[x * g.it.nB + y];
+          }
+        }
+      } else if (kb == 1) {  // B single: + s_B sum_{x in alpha} V^AB_{(x,b),(x,d)}
+        const int b = (info >> 2) & 0xff, d = (info >> 10) & 0xff;
+        const double s = (info >> 18) & 1 ? -1.0 : 1.0;
+        double sum = 0.0;
+        uint64_t t[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) t[w] = ab[w];
+        for (int x = pop_lowest<W>(t); x >= 0; x = pop_lowest<W>(t)) sum += vab(g.it, x, b, x, d);
+        v += s * sum;
+      }
+      const int64_t o = out + cnt + (k - k0);
+      g.col[o] = (int32_t)(off_a + g.ls_pos[k]);
+      val[o] = (T)v;
+    }
+    cnt += __popcll(m);
+    if (m != ballot(valid)) break;
+  }
+}
+
+// Tile part of a row: tiles [t0, t1) in ascending alpha'.  Lanes over tiles;
+// a kA = 2 tile holds at most one entry (same B position), a kA = 1 tile the
+// prefix of beta's L1 list for the tile's 2M_B list with position < len.
+// kA = 1 entries are expanded over all lanes of the wave.
+template <int W, bool FILL, typename T>
+__device__ __forceinline__ void row_tiles(const RowArgs &g, int64_t t0, int64_t t1, int beta, int p,
+                                          const uint64_t *bb, int64_t out, int64_t &cnt) {
+  const int lane = lane_id();
+  T *val = static_cast<T *>(g.val);
+  const int64_t l1b = (int64_t)beta * g.nseg;
+  for (int64_t tb = t0; tb < t1; tb += kWave) {
+    const int64_t t = tb + lane;
+    int ne = 0, info = 0;
+    int64_t l0 = 0;
+    if (t < t1) {
+      info = g.t_info[t];
+      const int len = g.t_len[t];
+      if ((info & 3) == 2) {
+        ne = p < len;
+      } else {  // first entry of the sorted segment with position >= len
+        const int gt = (info >> 19) & 0x7f;
+        l0 = g.l1_seg[l1b + gt];
+        int64_t lo = l0, hi = g.l1_seg[l1b + gt + 1];
+        while (lo < hi) {
+          const int64_t mid = (lo + hi) >> 1;
+          if (g.l1_pos[mid] < len) lo = mid + 1; else hi = mid;
+        }
+        ne = (int)(lo - l0);
+      }
+    }
+    const int incl = wave_incl_scan(ne);
+    const int total = __shfl(incl, kWave - 1, kWave);
+    if (FILL) {
+      const int64_t o_lane = out + cnt + (incl - ne);
+      const bool two = (info & 3) == 2;
+      int64_t coff = 0;
+      double tv = 0.0;
+      if (ne) {
+        coff = g.t_off[t];
+        tv = g.t_val[t];
+      }
+      if (two && ne) {
+        g.col[o_lane] = (int32_t)(coff + p);
+        val[o_lane] = (T)tv;
+      }
+      // kA = 1 entries, spread over the lanes
+      const int n1 = two ? 0 : ne;
+      const int incl1 = wave_incl_scan(n1);
+      const int tot1 = __shfl(incl1, kWave - 1, kWave);
+      // every shuffle below runs with the whole wave active (uniform loop)
+      for (int k0 = 0; k0 < tot1; k0 += kWave) {
+        const int k = k0 + lane;
+        int lo = 0, hi = kWave - 1;  // owner: first lane with incl1 > k
+#pragma unroll
+        for (int step = 0; step < 6; ++step) {
+          const int mid = (lo + hi) >> 1;
+          const bool right = __shfl(incl1, mid, kWave) <= k;
+          lo = right ? mid + 1 : lo;
+          hi = right ? hi : mid;
+        }
+        const int own = lo;
+        const int q = k - (__shfl(incl1, own, kWave) - __shfl(n1, own, kWave));
+        const int oinfo = __shfl(info, own, kWave);
+        const int64_t ol0 = __shfl(l0, own, kWave);
+        const int64_t ocoff = __shfl(coff, own, kWave);
+        const double otv = __shfl(tv, own, kWave);
+        const int64_t oo = __shfl(o_lane, own, kWave);
+        if (k >= tot1) continue;
+        const int a = (oinfo >> 2) & 0xff, c = (oinfo >> 10) & 0xff;
+        const double sa = (oinfo >> 18) & 1 ? -1.0 : 1.0;
+        const int li = g.l1_info[ol0 + q];
+        double v;
+        if ((li & 3) == 0) {  // B unchanged: AA part + s_A sum_{y in beta} V^AB_{(a,y),(c,y)}
+          double sum = 0.0;
+          if (g.it.nB > 0) {
+            uint64_t u[W];
+#pragma unroll
+            for (int w = 0; w < W; ++w) u[w] = bb[w];
+            for (int y = pop_lowest<W>(u); y >= 0; y = pop_lowest<W>(u)) sum += vab(g.it, a, y, c, y);
+          }
+          v = otv + sa * sum;
+        } else {              // one A and one B orbital change
+          const int b = (li >> 2) & 0xff, d = (li >> 10) & 0xff;
+          const double sb = (li >> 18) & 1 ? -1.0 : 1.0;
+          v = sa * sb * vab(g.it, a, b, c, d);
+        }
+        g.col[oo + q] = (int32_t)(ocoff + g.l1_pos[ol0 + q]);
+        val[oo + q] = (T)v;
+      }
+    }
+    cnt += total;
+  }
+}
+
+// One wave per row i = (alpha, p).  Upper rows (j >= i): the diagonal A-block
+// from beta itself on (positions < len(alpha)), then tiles alpha' > alpha.
+// Lower rows (j < i): tiles alpha' < alpha, then the diagonal A-block entries
+// before beta.  Both lists come out in ascending column order.
+template <int W, bool FILL, typename T, bool LOWER>
 __global__ __launch_bounds__(256) void k_row_pass(RowArgs g) {
   const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
   const int64_t i = blk * (blockDim.x / kWave) + (threadIdx.x >> 6);
   if (i >= g.D) return;
-  const int lane = lane_id();
   const int alpha = g.row_a[i], p = g.row_p[i];
   const int beta = g.bseg_start[g.a_seg[alpha]] + p;
   const int len_a = g.a_len[alpha];
   const int64_t off_a = g.a_off[alpha];
-  T *val = static_cast<T *>(g.val);
   uint64_t ab[W], bb[W];
   if (FILL) {
     load_bits<W>(g.a_bits, g.nA, alpha, ab);
@@ -319,108 +464,14 @@ __global__ __launch_bounds__(256) void k_row_pass(RowArgs g) {
   }
   const int64_t out = FILL ? g.row_ptr[i] : 0;
   int64_t cnt = 0;
-
-  // diagonal A-block: Lsame entries from beta itself, a prefix by position
-  {
-    const int64_t e0 = g.ls_self[beta], e1 = g.ls_ptr[beta + 1];
-    for (int64_t k0 = e0; k0 < e1; k0 += kWave) {
-      const int64_t k = k0 + lane;
-      const bool valid = k < e1;
-      const bool ok = valid && g.ls_pos[k] < len_a;
-      const uint64_t m = ballot(ok);
-      if (FILL && ok) {
-        const int info = g.ls_info[k];
-        double v = g.ls_val[k];
-        const int kb = info & 3;
-        if (kb == 0) {  // diagonal: E_A + E_B + sum_{x in alpha, y in beta} V^AB_{xy,xy}
-          v += g.eA[alpha];
-          if (g.it.nB > 0) {
-            uint64_t t[W];
-#pragma unroll
-            for (int w = 0; w < W; ++w) t[w] = ab[w];
-            for (int x = pop_lowest<W>(t); x >= 0; x = pop_lowest<W>(t)) {
-              uint64_t u[W];
-#pragma unroll
-              for (int w = 0; w < W; ++w) u[w] = bb[w];
-              for (int y = pop_lowest<W>(u); y >= 0; y = pop_lowest<W>(u))
-                v += g.it.dab[x * g.it.nB + y];
-            }
-          }
-        } else if (kb == 1) {  // B single: + s_B sum_{x in alpha} V^AB_{(x,b),(x,d)}
-          const int b = (info >> 2) & 0xff, d = (info >> 10) & 0xff;
-          const double s = (info >> 18) & 1 ? -1.0 : 1.0;
-          double sum = 0.0;
-          uint64_t t[W];
-#pragma unroll
-          for (int w = 0; w < W; ++w) t[w] = ab[w];
-          for (int x = pop_lowest<W>(t); x >= 0; x = pop_lowest<W>(t)) sum += vab(g.it, x, b, x, d);
-          v += s * sum;
-        }
-        const int64_t o = out + (k - e0);
-        g.col[o] = (int32_t)(off_a + g.ls_pos[k]);
-        val[o] = (T)v;
-      }
-      cnt += __popcll(m);
-      if (m != ballot(valid)) break;
-    }
+  if (!LOWER) {
+    row_diag<W, FILL, T>(g, g.ls_self[beta], g.ls_ptr[beta + 1], alpha, len_a, off_a, ab, bb, out, cnt);
+    row_tiles<W, FILL, T>(g, g.t_ptr[alpha], g.t_ptr[alpha + 1], beta, p, bb, out, cnt);
+  } else {
+    row_tiles<W, FILL, T>(g, g.t_ptr[alpha], g.t_ptr[alpha + 1], beta, p, bb, out, cnt);
+    row_diag<W, FILL, T>(g, g.ls_ptr[beta], g.ls_self[beta], alpha, len_a, off_a, ab, bb, out, cnt);
   }
-
-  // tiles alpha' > alpha
-  const int64_t t0 = g.t_ptr[alpha], t1 = g.t_ptr[alpha + 1];
-  const int64_t l1b = (int64_t)beta * g.nseg;
-  for (int64_t tb = t0; tb < t1; tb += kWave) {
-    const int64_t t = tb + lane;
-    int ne = 0, info = 0, len = 0;
-    int64_t l0 = 0;
-    if (t < t1) {
-      info = g.t_info[t];
-      len = g.t_len[t];
-      if ((info & 3) == 2) {
-        ne = p < len;
-      } else {
-        const int gt = (info >> 19) & 0x7f;
-        l0 = g.l1_seg[l1b + gt];
-        const int64_t le = g.l1_seg[l1b + gt + 1];
-        while (l0 + ne < le && g.l1_pos[l0 + ne] < len) ++ne;
-      }
-    }
-    const int incl = wave_incl_scan(ne);
-    const int total = __shfl(incl, kWave - 1, kWave);
-    if (FILL && ne) {
-      int64_t o = out + cnt + (incl - ne);
-      const int64_t coff = g.t_off[t];
-      const double tv = g.t_val[t];
-      if ((info & 3) == 2) {
-        g.col[o] = (int32_t)(coff + p);
-        val[o] = (T)tv;
-      } else {
-        const int a = (info >> 2) & 0xff, c = (info >> 10) & 0xff;
-        const double sa = (info >> 18) & 1 ? -1.0 : 1.0;
-        for (int q = 0; q < ne; ++q, ++o) {
-          const int li = g.l1_info[l0 + q];
-          double v;
-          if ((li & 3) == 0) {  // B unchanged: AA part + s_A sum_{y in beta} V^AB_{(a,y),(c,y)}
-            double sum = 0.0;
-            if (g.it.nB > 0) {
-              uint64_t u[W];
-#pragma unroll
-              for (int w = 0; w < W; ++w) u[w] = bb[w];
-              for (int y = pop_lowest<W>(u); y >= 0; y = pop_lowest<W>(u)) sum += vab(g.it, a, y, c, y);
-            }
-            v = tv + sa * sum;
-          } else {              // one A and one B orbital change
-            const int b = (li >> 2) & 0xff, d = (li >> 10) & 0xff;
-            const double sb = (li >> 18) & 1 ? -1.0 : 1.0;
-            v = sa * sb * vab(g.it, a, b, c, d);
-          }
-          g.col[o] = (int32_t)(coff + g.l1_pos[l0 + q]);
-          val[o] = (T)v;
-        }
-      }
-    }
-    cnt += total;
-  }
-  if (!FILL && lane == 0) g.rcnt[i] = (int32_t)cnt;
+  if (!FILL && lane_id() == 0) g.rcnt[i] = (int32_t)cnt;
 }
 
 // ------------------------------------------------------------ exclusive scan
@@ -588,7 +639,7 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
   ta.nA = nA; ta.a_bits = b.a_bits.p; ta.a_m2 = b.a_m2.p; ta.a_len = b.a_len.p;
   ta.a_seg = b.a_seg.p; ta.a_off = b.a_off.p; ta.it = it; ta.tcnt = tcnt.p;
   const unsigned tblk = (unsigned)((nA + 3) / 4);
-  { KTimer kt(ctx, K_TILE, s); hipLaunchKernelGGL((k_tile_pass<W, false>), dim3(tblk), dim3(256), 0, s, ta); }
+  { KTimer kt(ctx, K_TILE, s); hipLaunchKernelGGL((k_tile_pass<W, false, false>), dim3(tblk), dim3(256), 0, s, ta); }
   AdjArgs aa{};
   aa.nB = nB; aa.nseg = nseg; aa.b_bits = b.b_bits.p; aa.b_seg = b.b_seg.p;
   aa.bseg_start = b.bseg_start.p; aa.eB = eB.p; aa.it = it; aa.ls_cnt = ls_cnt.p; aa.l1_cnt = l1_cnt.p;
@@ -612,7 +663,7 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
   DBuf<double> ls_val(ctx, n_ls);
   CIB_HIP(hipEventRecord(ev.e[2], s));
   ta.t_ptr = t_ptr.p; ta.t_off = t_off.p; ta.t_len = t_len.p; ta.t_info = t_info.p; ta.t_val = t_val.p;
-  { KTimer kt(ctx, K_TILE, s); hipLaunchKernelGGL((k_tile_pass<W, true>), dim3(tblk), dim3(256), 0, s, ta); }
+  { KTimer kt(ctx, K_TILE, s); hipLaunchKernelGGL((k_tile_pass<W, true, false>), dim3(tblk), dim3(256), 0, s, ta); }
   aa.ls_ptr = ls_ptr.p; aa.l1_seg = l1_seg.p; aa.ls_self = ls_self.p; aa.ls_pos = ls_pos.p;
   aa.ls_info = ls_info.p; aa.l1_pos = l1_pos.p; aa.l1_info = l1_info.p; aa.ls_val = ls_val.p;
   { KTimer kt(ctx, K_ADJ, s); hipLaunchKernelGGL((k_adj_pass<W, true>), dim3(ablk), dim3(256), 0, s, aa); }
@@ -631,7 +682,7 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
   DBuf<int32_t> rcnt(ctx, p.D);
   ra.rcnt = rcnt.p;
   const unsigned rblk = (unsigned)((p.D + 3) / 4);
-  { KTimer kt(ctx, K_ROW_COUNT, s); hipLaunchKernelGGL((k_row_pass<W, false, double>), dim3(rblk), dim3(256), 0, s, ra); }
+  { KTimer kt(ctx, K_ROW_COUNT, s); hipLaunchKernelGGL((k_row_pass<W, false, double, false>), dim3(rblk), dim3(256), 0, s, ra); }
   CIB_HIP(hipGetLastError());
   CIB_HIP(hipEventRecord(ev.e[4], s));
   H.row_ptr.reset(ctx, p.D + 1);
@@ -649,13 +700,48 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
   {
     KTimer kt(ctx, K_ROW_FILL, s);
     if (dt == CIB_F64)
-      hipLaunchKernelGGL((k_row_pass<W, true, double>), dim3(rblk), dim3(256), 0, s, ra);
+      hipLaunchKernelGGL((k_row_pass<W, true, double, false>), dim3(rblk), dim3(256), 0, s, ra);
     else
-      hipLaunchKernelGGL((k_row_pass<W, true, float>), dim3(rblk), dim3(256), 0, s, ra);
+      hipLaunchKernelGGL((k_row_pass<W, true, float, false>), dim3(rblk), dim3(256), 0, s, ra);
   }
   CIB_HIP(hipGetLastError());
   CIB_HIP(hipEventRecord(ev.e[7], s));
-  CIB_HIP(hipStreamSynchronize(s));
+
+  // ---- strictly lower triangle for the SpMM: the same passes with the lower
+  //      tile list (alpha' < alpha) and the diagonal-block entries before beta
+  {
+    KTimer kt(ctx, K_LOWER, s);
+    ta.tcnt = tcnt.p;
+    hipLaunchKernelGGL((k_tile_pass<W, false, true>), dim3(tblk), dim3(256), 0, s, ta);
+    DBuf<int64_t> tl_ptr(ctx, nA + 1);
+    launch_scan(tcnt.p, nA, tl_ptr.p, scratch.p, s);
+    const int64_t n_lt = read_i64(tl_ptr.p + nA, s);
+    DBuf<int64_t> tl_off(ctx, std::max<int64_t>(n_lt, 1));
+    DBuf<int32_t> tl_len(ctx, std::max<int64_t>(n_lt, 1)), tl_info(ctx, std::max<int64_t>(n_lt, 1));
+    DBuf<double> tl_val(ctx, std::max<int64_t>(n_lt, 1));
+    ta.t_ptr = tl_ptr.p; ta.t_off = tl_off.p; ta.t_len = tl_len.p; ta.t_info = tl_info.p; ta.t_val = tl_val.p;
+    hipLaunchKernelGGL((k_tile_pass<W, true, true>), dim3(tblk), dim3(256), 0, s, ta);
+    ra.t_ptr = tl_ptr.p; ra.t_off = tl_off.p; ra.t_len = tl_len.p; ra.t_info = tl_info.p; ra.t_val = tl_val.p;
+    hipLaunchKernelGGL((k_row_pass<W, false, double, true>), dim3(rblk), dim3(256), 0, s, ra);
+    H.lo_ptr.reset(ctx, p.D + 1);
+    launch_scan(rcnt.p, p.D, H.lo_ptr.p, scratch.p, s);
+    const int64_t nlo = read_i64(H.lo_ptr.p + p.D, s);
+    H.lo_col.reset(ctx, std::max<int64_t>(nlo, 1));
+    if (dt == CIB_F64) H.lo_val64.reset(ctx, std::max<int64_t>(nlo, 1));
+    else H.lo_val32.reset(ctx, std::max<int64_t>(nlo, 1));
+    ra.row_ptr = H.lo_ptr.p;
+    ra.col = H.lo_col.p;
+    ra.val = dt == CIB_F64 ? (void *)H.lo_val64.p : (void *)H.lo_val32.p;
+    CIB_HIP(hipEventRecord(ev.e[8], s));
+    if (dt == CIB_F64)
+      hipLaunchKernelGGL((k_row_pass<W, true, double, true>), dim3(rblk), dim3(256), 0, s, ra);
+    else
+      hipLaunchKernelGGL((k_row_pass<W, true, float, true>), dim3(rblk), dim3(256), 0, s, ra);
+    CIB_HIP(hipGetLastError());
+    CIB_HIP(hipEventRecord(ev.e[9], s));
+    CIB_HIP(hipStreamSynchronize(s));
+    H.nnz_lower = nlo;
+  }
 
   H.D = p.D;
   H.nnz = nnz;
@@ -665,6 +751,7 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
   H.stats.t_scan_s = ev.ms(4, 5);
   H.stats.t_fill_s = ev.ms(6, 7);
   H.stats.t_total_s = H.stats.t_screen_s + H.stats.t_count_s + H.stats.t_scan_s + H.stats.t_fill_s;
+  H.stats.t_lower_s = ev.ms(7, 9);
   H.stats.n_tiles = n_tiles;
   H.stats.n_adjacent = n_ls + n_l1;
 }

@@ -75,7 +75,7 @@ struct cib_ctx {
 namespace cib {
 
 // Hot kernels known to the profiler.
-enum KernelId { K_TILE = 0, K_ADJ, K_ROW_COUNT, K_SCAN, K_ROW_FILL, K_SPMM, K_GRAM, K_RR, K_UPDATE, K_NKERN };
+enum KernelId { K_TILE = 0, K_ADJ, K_ROW_COUNT, K_SCAN, K_ROW_FILL, K_SPMM, K_GRAM, K_RR, K_UPDATE, K_LOWER, K_NKERN };
 extern const char *const kKernelNames[K_NKERN];
 
 // Brackets one launch with events when profiling is on (RAII).
@@ -201,7 +201,14 @@ struct cib_matrix {
   cib::DBuf<int32_t> col;
   cib::DBuf<double> val64;
   cib::DBuf<float> val32;
+  // strictly lower triangle (transposed copy) read by the SpMM
+  int64_t nnz_lower = 0;
+  cib::DBuf<int64_t> lo_ptr;
+  cib::DBuf<int32_t> lo_col;
+  cib::DBuf<double> lo_val64;
+  cib::DBuf<float> lo_val32;
   cib_build_stats stats{};
+  const void *lo_val() const { return dtype == CIB_F64 ? (const void *)lo_val64.p : (const void *)lo_val32.p; }
   const void *val() const { return dtype == CIB_F64 ? (const void *)val64.p : (const void *)val32.p; }
 };
 

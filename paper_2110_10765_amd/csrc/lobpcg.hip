@@ -6,12 +6,16 @@
 // Per iteration: W <- H W (SpMM in the matrix dtype), partial Gram matrices
 // S^T S and S^T HS over row chunks, one workgroup that reduces them and does
 // the Rayleigh-Ritz step in float64 (scaled Cholesky of S^T S with dropping
-// of dependent directions, reduced matrix, parallel cyclic Jacobi), then a
+// of dependent directions, reduced matrix, Householder tridiagonalisation,
+// multisection for the wanted eigenvalues, twisted-factorisation
+// eigenvectors), then a
 // row-parallel update X, P, HX, HP <- S C, HS C, the residual R = HX - X L,
 // its norms and the preconditioned W = R / (diag(H) - lambda).
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 
 #include "cib_internal.hpp"
 #include "device_common.hpp"
@@ -109,49 +113,107 @@ __global__ __launch_bounds__(256) void k_copy_cols(int64_t D, int n, const doubl
 
 // ------------------------------------------------------------ Gram matrices
 // partial[blk] = sum over the block's rows of S_i^T [S_i, HS_i] for the first
-// ns columns: an ns x 2ns matrix (left half S^T S, right half S^T HS).
+// ns columns: an ns x 2ns matrix (left half S^T S, right half S^T HS).  Rows
+// are staged through LDS in chunks; each thread keeps a 6 x 6 register tile
+// of the output; when the output needs fewer than 256 threads, several thread
+// groups take alternate rows and are summed at the end in a fixed order.
 constexpr int kGramRows = 32;
+constexpr int kGT = 6;
 
 __global__ __launch_bounds__(256) void k_gram(int64_t D, int ns, int ld, const double *__restrict__ S,
                                               const double *__restrict__ HS, int64_t rows_per_blk,
                                               double *__restrict__ partial) {
-  __shared__ double ts[kGramRows][kNS + 1];
-  __shared__ double th[kGramRows][kNS + 1];
+  __shared__ double buf[kNS * 2 * kNS];
+  const int tid = threadIdx.x;
+  const int w2 = 2 * ns, nout = ns * w2;
+  const int nti = (ns + kGT - 1) / kGT, ntj = (w2 + kGT - 1) / kGT;
+  const int T = nti * ntj;
+  const int groups = max(1, (int)blockDim.x / T);
+  const int grp = tid / T, loc = tid % T;
+  const bool worker = grp < groups;
+  const int i0 = (loc / ntj) * kGT, j0 = (loc % ntj) * kGT;
+  double acc[kGT][kGT];
+#pragma unroll
+  for (int a = 0; a < kGT; ++a)
+#pragma unroll
+    for (int c = 0; c < kGT; ++c) acc[a][c] = 0.0;
   const int64_t r0 = (int64_t)blockIdx.x * rows_per_blk;
   const int64_t r1 = min(D, r0 + rows_per_blk);
-  const int nout = ns * 2 * ns;
-  double acc[18];
-#pragma unroll
-  for (int q = 0; q < 18; ++q) acc[q] = 0.0;
   for (int64_t rb = r0; rb < r1; rb += kGramRows) {
     const int nr = (int)min<int64_t>(kGramRows, r1 - rb);
-    for (int k = threadIdx.x; k < kGramRows * ns; k += blockDim.x) {
-      const int r = k / ns, c = k % ns;
-      const bool in = r < nr;
-      ts[r][c] = in ? S[(rb + r) * ld + c] : 0.0;
-      th[r][c] = in ? HS[(rb + r) * ld + c] : 0.0;
+    for (int k = tid; k < nr * w2; k += blockDim.x) {
+      const int r = k / w2, c = k % w2;
+      buf[k] = c < ns ? S[(rb + r) * ld + c] : HS[(rb + r) * ld + (c - ns)];
     }
     __syncthreads();
+    if (worker)
+      for (int r = grp; r < nr; r += groups) {
+        const double *row = buf + r * w2;
+        double xi[kGT], xj[kGT];
 #pragma unroll
-    for (int q = 0; q < 18; ++q) {
-      const int e = threadIdx.x + q * 256;
-      if (e < nout) {
-        const int i = e / (2 * ns), j = e % (2 * ns);
-        double a = acc[q];
-        if (j < ns) {
-          for (int r = 0; r < kGramRows; ++r) a += ts[r][i] * ts[r][j];
-        } else {
-          for (int r = 0; r < kGramRows; ++r) a += ts[r][i] * th[r][j - ns];
-        }
-        acc[q] = a;
+        for (int a = 0; a < kGT; ++a) xi[a] = row[i0 + a];
+#pragma unroll
+        for (int c = 0; c < kGT; ++c) xj[c] = row[j0 + c];
+#pragma unroll
+        for (int a = 0; a < kGT; ++a)
+#pragma unroll
+          for (int c = 0; c < kGT; ++c) acc[a][c] += xi[a] * xj[c];
       }
-    }
     __syncthreads();
   }
+  // fixed-order sum of the thread groups in LDS
+  for (int q = 0; q < groups; ++q) {
+    if (worker && grp == q)
 #pragma unroll
-  for (int q = 0; q < 18; ++q) {
-    const int e = threadIdx.x + q * 256;
-    if (e < nout) partial[(int64_t)blockIdx.x * nout + e] = acc[q];
+      for (int a = 0; a < kGT; ++a)
+#pragma unroll
+        for (int c = 0; c < kGT; ++c) {
+          const int i = i0 + a, j = j0 + c;
+          if (i < ns && j < w2) buf[i * w2 + j] = (q == 0 ? 0.0 : buf[i * w2 + j]) + acc[a][c];
+        }
+    __syncthreads();
+  }
+  for (int e = tid; e < nout; e += blockDim.x) partial[(int64_t)blockIdx.x * nout + e] = buf[e];
+}
+
+// out[e] = sum over the nparts partial matrices, in a fixed order
+__global__ __launch_bounds__(256) void k_gram_reduce(int nout, int nparts, const double *__restrict__ partial,
+                                                     double *__restrict__ out) {
+  __shared__ double red[256];
+  const int e = blockIdx.x * 64 + (threadIdx.x & 63), slice = threadIdx.x >> 6;
+  double s = 0.0;
+  if (e < nout)
+    for (int q = slice; q < nparts; q += 4) s += partial[(int64_t)q * nout + e];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  if (slice == 0 && e < nout) out[e] = (red[threadIdx.x] + red[threadIdx.x + 64]) + (red[threadIdx.x + 128] + red[threadIdx.x + 192]);
+}
+
+// Gershgorin lower bound of H: min_i (H_ii - sum_{j != i} |H_ij|), both halves.
+template <typename T>
+__global__ __launch_bounds__(256) void k_gersh_rows(int64_t D, const int64_t *rp, const T *val, const int64_t *lrp,
+                                                    const T *lval, double *out) {
+  const int64_t i = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x >> 6);
+  if (i >= D) return;
+  const int lane = lane_id();
+  double sum = 0.0;
+  for (int64_t k = rp[i] + 1 + lane; k < rp[i + 1]; k += kWave) sum += fabs((double)val[k]);
+  for (int64_t k = lrp[i] + lane; k < lrp[i + 1]; k += kWave) sum += fabs((double)lval[k]);
+  sum = wave_sum(sum);
+  if (lane == 0) out[i] = (double)val[rp[i]] - sum;
+}
+
+__global__ __launch_bounds__(1024) void k_min(int64_t n, const double *in, double *out) {
+  __shared__ double red[1024 / kWave];
+  double m = INFINITY;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) m = fmin(m, in[i]);
+  for (int d = kWave / 2; d > 0; d >>= 1) m = fmin(m, __shfl_xor(m, d, kWave));
+  if (lane_id() == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = red[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) r = fmin(r, red[w]);
+    out[0] = r;
   }
 }
 
@@ -161,123 +223,56 @@ struct RRArgs {
   const double *partial;
   double *C;        // ns x 2b: [Cx | Cp]
   double *lam;      // b
-  int32_t *flag;    // [0]: rank of the search space
+  int32_t *flag;    // [0]: rank of the search space, [1]: fallback taken
   double drop_tol;
+  const double *hlow;  // lower bound of the spectrum of H (Gershgorin)
 };
 
-// Parallel cyclic Jacobi on the r x r symmetric matrix A (LDS, ld kLd);
-// V receives the eigenvectors (columns).  Round-robin ordering: in each round
-// the r/2 rotations touch disjoint index pairs, so each 2x2 block of A is
-// transformed by one thread.
-__device__ void jacobi_eig(double (*A)[kLd], double (*V)[kLd], int r, double *cs, int *pq,
-                           double *red) {
-  const int tid = threadIdx.x, nt = blockDim.x;
-  const int m = r + (r & 1);
-  for (int k = tid; k < r * r; k += nt) V[k / r][k % r] = (k / r == k % r) ? 1.0 : 0.0;
-  __syncthreads();
-  for (int sweep = 0; sweep < 40; ++sweep) {
-    // off-diagonal and total Frobenius norms
-    double off = 0.0, tot = 0.0;
-    for (int k = tid; k < r * r; k += nt) {
-      const double a = A[k / r][k % r];
-      tot += a * a;
-      if (k / r != k % r) off += a * a;
-    }
-    off = wave_sum(off);
-    tot = wave_sum(tot);
-    if (lane_id() == 0) { red[2 * (tid >> 6)] = off; red[2 * (tid >> 6) + 1] = tot; }
-    __syncthreads();
-    double so = 0.0, st = 0.0;
-    for (int w = 0; w < nt / kWave; ++w) { so += red[2 * w]; st += red[2 * w + 1]; }
-    __syncthreads();
-    if (so <= 1e-32 * st || so == 0.0) break;
-    for (int rd = 0; rd < m - 1; ++rd) {
-      // pairs of this round
-      for (int k = tid; k < m / 2; k += nt) {
-        int p, q;
-        if (k == 0) { p = 0; q = 1 + rd % (m - 1); }
-        else {
-          p = 1 + ((rd - k) % (m - 1) + (m - 1)) % (m - 1);
-          q = 1 + (rd + k) % (m - 1);
-        }
-        if (p > q) { const int t = p; p = q; q = t; }
-        double c = 1.0, s = 0.0;
-        if (q < r) {
-          const double apq = A[p][q];
-          if (apq != 0.0) {
-            const double tau = (A[q][q] - A[p][p]) / (2.0 * apq);
-            const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-            c = 1.0 / sqrt(1.0 + t * t);
-            s = t * c;
-          }
-        }
-        pq[2 * k] = p;
-        pq[2 * k + 1] = q;
-        cs[2 * k] = c;
-        cs[2 * k + 1] = s;
-      }
-      __syncthreads();
-      // A <- J^T A J, one 2x2 block (pair k1 rows, pair k2 columns) per item
-      const int h = m / 2;
-      for (int k = tid; k < h * h; k += nt) {
-        const int k1 = k / h, k2 = k % h;
-        const int p1 = pq[2 * k1], q1 = pq[2 * k1 + 1], p2 = pq[2 * k2], q2 = pq[2 * k2 + 1];
-        if (q1 >= r || q2 >= r) {
-          // a dummy index (odd r): rotate only the real one of each pair
-          if (q1 >= r && q2 >= r) {
-            // p1 and p2 are real, nothing rotates
-          } else if (q1 >= r) {  // rows p1 only, columns (p2, q2)
-            const double c2 = cs[2 * k2], s2 = cs[2 * k2 + 1];
-            const double a = A[p1][p2], bq = A[p1][q2];
-            A[p1][p2] = c2 * a - s2 * bq;
-            A[p1][q2] = s2 * a + c2 * bq;
-          } else {               // rows (p1, q1), column p2 only
-            const double c1 = cs[2 * k1], s1 = cs[2 * k1 + 1];
-            const double a = A[p1][p2], bq = A[q1][p2];
-            A[p1][p2] = c1 * a - s1 * bq;
-            A[q1][p2] = s1 * a + c1 * bq;
-          }
-          continue;
-        }
-        const double c1 = cs[2 * k1], s1 = cs[2 * k1 + 1], c2 = cs[2 * k2], s2 = cs[2 * k2 + 1];
-        const double app = A[p1][p2], apq = A[p1][q2], aqp = A[q1][p2], aqq = A[q1][q2];
-        // rows: new_p = c1 row_p - s1 row_q ; new_q = s1 row_p + c1 row_q
-        const double bpp = c1 * app - s1 * aqp, bpq = c1 * apq - s1 * aqq;
-        const double bqp = s1 * app + c1 * aqp, bqq = s1 * apq + c1 * aqq;
-        // columns: new_p = c2 col_p - s2 col_q ; new_q = s2 col_p + c2 col_q
-        A[p1][p2] = c2 * bpp - s2 * bpq;
-        A[p1][q2] = s2 * bpp + c2 * bpq;
-        A[q1][p2] = c2 * bqp - s2 * bqq;
-        A[q1][q2] = s2 * bqp + c2 * bqq;
-      }
-      // V <- V J
-      for (int k = tid; k < r * h; k += nt) {
-        const int i = k / h, kk = k % h;
-        const int p = pq[2 * kk], q = pq[2 * kk + 1];
-        if (q >= r) continue;
-        const double c = cs[2 * kk], s = cs[2 * kk + 1];
-        const double vp = V[i][p], vq = V[i][q];
-        V[i][p] = c * vp - s * vq;
-        V[i][q] = s * vp + c * vq;
-      }
-      __syncthreads();
-    }
+// Number of eigenvalues of the symmetric tridiagonal (d, e2 = e^2) below x
+// (Sturm sequence of the LDL^T pivots).
+__device__ __forceinline__ int sturm_count(const double *d, const double *e2, int n, double x,
+                                           double pivmin) {
+  double q = d[0] - x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  int c = q <= 0.0;
+  for (int i = 1; i < n; ++i) {
+    q = d[i] - x - e2[i - 1] / q;
+    if (fabs(q) < pivmin) q = -pivmin;
+    c += q <= 0.0;
   }
+  return c;
 }
 
+// One workgroup.  (1) reduce the partial Gram matrices; (2) scale S^T S and
+// S^T H S to unit diagonal; (3) Cholesky S^T S = L L^T dropping columns whose
+// residual pivot falls below drop_tol (directions already spanned); (4) Z =
+// L^-1 and the reduced matrix M = Z (S^T H S) Z^T on the r kept columns;
+// (5) Householder reduction of M to tridiagonal form; (6) the lowest b
+// eigenvalues by multisection of Sturm counts; (7) their eigenvectors from
+// twisted LDL^T / UDU^T factorisations, re-orthogonalised inside clusters;
+// (8) back to M's basis with the Householder reflectors; (9) coefficients
+// C_x = scale * Z^T y and C_p = C_x with the X rows zeroed (P = W C_W + P C_P).
 __global__ __launch_bounds__(256) void k_rayleigh_ritz(RRArgs g) {
-  __shared__ double G[kNS][kLd], Hm[kNS][kLd], V[kNS][kLd];
-  __shared__ double scale[kNS], cs[kNS], red[16], theta[kNS];
-  __shared__ int keep[kNS], kidx[kNS], pq[kNS], order[kNS];
-  __shared__ int rank_s;
-  const int ns = g.ns, b = g.b, tid = threadIdx.x, nt = blockDim.x;
-  const int nout = ns * 2 * ns;
-  // 1. reduce the partial Gram matrices (fixed order: deterministic)
+  __shared__ double G[kNS][kLd], Hm[kNS][kLd], Z[kNS][kLd];
+  __shared__ double scale[kNS], dd[kNS], ee[kNS], e2[kNS], beta[kNS], vv[kNS], pp[kNS];
+  __shared__ double theta[kMaxBlock];
+  __shared__ int keep[kNS], kidx[kNS];
+  __shared__ int rank_s, retry_s;
+  const int ns_full = g.ns, b = g.b, tid = threadIdx.x, nt = blockDim.x;
+  const int nout = ns_full * 2 * ns_full;
+  int ns = ns_full, r = 0, nb = 0;
+  double drop_tol = g.drop_tol, tnorm = 0.0, pivmin = 0.0;
+  for (int attempt = 0; attempt < 2; ++attempt) {
+  // 1. reduce the partial Gram matrices (fixed order: deterministic); a
+  //    retry keeps only the first ns columns ([X W]) of the same matrices
   for (int e = tid; e < nout; e += nt) {
     double s = 0.0;
     for (int q = 0; q < g.nparts; ++q) s += g.partial[(int64_t)q * nout + e];
-    const int i = e / (2 * ns), j = e % (2 * ns);
-    if (j < ns) G[i][j] = s; else Hm[i][j - ns] = s;
+    const int i = e / (2 * ns_full), j = e % (2 * ns_full);
+    if (i < ns) {
+      if (j < ns) G[i][j] = s;
+      else if (j >= ns_full && j - ns_full < ns) Hm[i][j - ns_full] = s;
+    }
   }
   __syncthreads();
   // 2. symmetrise, scale to unit diagonal
@@ -297,25 +292,22 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz(RRArgs g) {
     }
   }
   __syncthreads();
-  // 3. right-looking Cholesky of G (lower, in place) with dropping of columns
-  //    whose residual diagonal falls below drop_tol (dependent directions)
+  // 3. right-looking Cholesky with dropping
   for (int k = 0; k < ns; ++k) {
-    if (tid == 0) {
-      const double piv = G[k][k];
-      keep[k] = (scale[k] > 0.0 && piv > g.drop_tol) ? 1 : 0;
-      G[k][k] = keep[k] ? sqrt(piv) : 0.0;
-    }
-    __syncthreads();
-    const double lkk = G[k][k];
-    for (int i = k + 1 + tid; i < ns; i += nt) G[i][k] = keep[k] ? G[i][k] / lkk : 0.0;
-    __syncthreads();
-    if (keep[k]) {
-      const int m = ns - k - 1;
+    const double piv = G[k][k];
+    const bool kk = scale[k] > 0.0 && piv > drop_tol;   // every thread decides the same
+    const double lkk = kk ? sqrt(piv) : 0.0;
+    const int m = ns - k - 1;
+    // column k and the trailing update in one phase: element (i, j) of the
+    // trailing block uses the old G[i][k], G[j][k], which nobody writes here
+    if (kk)
       for (int e = tid; e < m * m; e += nt) {
         const int i = k + 1 + e / m, j = k + 1 + e % m;
-        if (j <= i) G[i][j] -= G[i][k] * G[j][k];
+        if (j <= i) G[i][j] -= G[i][k] * G[j][k] / piv;
       }
-    }
+    __syncthreads();
+    for (int i = k + 1 + tid; i < ns; i += nt) G[i][k] = kk ? G[i][k] / lkk : 0.0;
+    if (tid == 0) { G[k][k] = lkk; keep[k] = kk; }
     __syncthreads();
   }
   if (tid == 0) {
@@ -324,28 +316,35 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz(RRArgs g) {
     rank_s = r;
   }
   __syncthreads();
-  const int r = rank_s;
-  // 4. reduced matrix M = L^-1 Hm L^-T over the kept indices.
-  //    Z = L^-1 Hm: thread j solves for column j into V (forward substitution).
-  for (int j = tid; j < r; j += nt) {
-    const int cj = kidx[j];
-    for (int a = 0; a < r; ++a) {
-      const int ka = kidx[a];
-      double s = Hm[ka][cj];
-      for (int q = 0; q < a; ++q) s -= G[ka][kidx[q]] * V[q][j];
-      V[a][j] = s / G[ka][ka];
+  r = rank_s;
+  // 4a. Z = L^-1 (compressed r x r, lower triangular), row by row
+  for (int a = 0; a < r; ++a) {
+    const int ka = kidx[a];
+    for (int j = tid; j < r; j += nt) {
+      double v = 0.0;
+      if (j <= a) {
+        double s = a == j ? 1.0 : 0.0;
+        for (int q = j; q < a; ++q) s -= G[ka][kidx[q]] * Z[q][j];
+        v = s / G[ka][ka];
+      }
+      Z[a][j] = v;
     }
+    __syncthreads();
+  }
+  // 4b. T1 = Hm_c Z^T into G (L is no longer needed), then M = Z T1 into Hm
+  for (int e = tid; e < r * r; e += nt) {
+    const int a = e / r, q = e % r;
+    const int ka = kidx[a];
+    double s = 0.0;
+    for (int t = 0; t <= q; ++t) s += Hm[ka][kidx[t]] * Z[q][t];
+    G[a][q] = s;
   }
   __syncthreads();
-  //    M = L^-1 Z^T: column j has right-hand side row j of Z; written into Hm
-  //    (no longer needed) in compressed indices.
-  for (int j = tid; j < r; j += nt) {
-    for (int a = 0; a < r; ++a) {
-      const int ka = kidx[a];
-      double s = V[j][a];
-      for (int q = 0; q < a; ++q) s -= G[ka][kidx[q]] * Hm[q][j];
-      Hm[a][j] = s / G[ka][ka];
-    }
+  for (int e = tid; e < r * r; e += nt) {
+    const int p = e / r, q = e % r;
+    double s = 0.0;
+    for (int a = 0; a <= p; ++a) s += Z[p][a] * G[a][q];
+    Hm[p][q] = s;
   }
   __syncthreads();
   for (int e = tid; e < r * r; e += nt) {
@@ -357,45 +356,213 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz(RRArgs g) {
     }
   }
   __syncthreads();
-  // 5. eigen-decomposition of M
-  jacobi_eig(Hm, V, r, cs, pq, red);
+  // 5. Householder tridiagonalisation of M (r x r in Hm); the reflector of
+  //    step k is kept in column k below the subdiagonal, its scale in beta[k]
+  for (int k = 0; k + 2 < r; ++k) {
+    const int m = r - k - 1;
+    double sigma = 0.0;
+    for (int i = k + 1; i < r; ++i) sigma += Hm[i][k] * Hm[i][k];
+    const double x0 = Hm[k + 1][k];
+    const double tail = sigma - x0 * x0;
+    const bool refl = tail > 1e-300;
+    const double alpha = refl ? -copysign(sqrt(sigma), x0) : x0;
+    const double bk = refl ? 2.0 / (tail + (x0 - alpha) * (x0 - alpha)) : 0.0;
+    for (int i = k + 1 + tid; i < r; i += nt) {
+      double acc = 0.0;
+      for (int j = k + 1; j < r; ++j) {
+        const double vj = j == k + 1 ? x0 - alpha : Hm[j][k];
+        acc += Hm[i][j] * vj;
+      }
+      pp[i] = bk * acc;
+      vv[i] = i == k + 1 ? x0 - alpha : Hm[i][k];
+    }
+    __syncthreads();
+    double K = 0.0;
+    for (int i = k + 1; i < r; ++i) K += vv[i] * pp[i];
+    K *= 0.5 * bk;
+    for (int e = tid; e < m * m; e += nt) {
+      const int i = k + 1 + e / m, j = k + 1 + e % m;
+      const double wi = pp[i] - K * vv[i], wj = pp[j] - K * vv[j];
+      Hm[i][j] -= vv[i] * wj + wi * vv[j];
+    }
+    for (int i = k + 1 + tid; i < r; i += nt) Hm[i][k] = vv[i];
+    if (tid == 0) { beta[k] = bk; ee[k] = alpha; }
+    __syncthreads();
+  }
+  for (int i = tid; i < r; i += nt) {
+    dd[i] = Hm[i][i];
+    if (i == r - 2) ee[i] = Hm[r - 1][r - 2];
+  }
   __syncthreads();
-  // 6. ascending order of the Ritz values
-  for (int a = tid; a < r; a += nt) theta[a] = Hm[a][a];
+  for (int i = tid; i + 1 < r; i += nt) e2[i] = ee[i] * ee[i];
   __syncthreads();
+  // 6. lowest nb eigenvalues: 16 threads per eigenvalue, 16 rounds of
+  //    17-way multisection of the Gershgorin interval
+  nb = b < r ? b : r;
+  double gl = 1e300, gu = -1e300, emax = 0.0;
+  for (int i = 0; i < r; ++i) {
+    const double rad = (i > 0 ? fabs(ee[i - 1]) : 0.0) + (i + 1 < r ? fabs(ee[i]) : 0.0);
+    gl = fmin(gl, dd[i] - rad);
+    gu = fmax(gu, dd[i] + rad);
+    if (i + 1 < r) emax = fmax(emax, e2[i]);
+  }
+  tnorm = fmax(fabs(gl), fabs(gu));
+  pivmin = fmax(1e-300, 2.2e-308 * fmax(emax, 1.0));
+  gl -= 2.2e-16 * tnorm * 4 + pivmin;
+  gu += 2.2e-16 * tnorm * 4 + pivmin;
+  {
+    const int grp = tid >> 4, t = tid & 15;
+    double lo = gl, hi = gu;
+    for (int round = 0; round < 16; ++round) {
+      const double x = lo + (t + 1) * (hi - lo) * (1.0 / 17.0);
+      const bool above = grp < nb ? sturm_count(dd, e2, r, x, pivmin) > grp : true;
+      const uint64_t m = __ballot(above);
+      const unsigned gm = (unsigned)((m >> ((tid & 63) & ~15)) & 0xffffu);
+      const int first = __builtin_ctz(gm | 0x10000u);  // first sub-point with count > grp
+      const double nlo = first == 0 ? lo : lo + first * (hi - lo) * (1.0 / 17.0);
+      const double nhi = first == 16 ? hi : lo + (first + 1) * (hi - lo) * (1.0 / 17.0);
+      lo = nlo;
+      hi = nhi;
+    }
+    if (t == 0 && grp < nb) theta[grp] = 0.5 * (lo + hi);
+  }
+  __syncthreads();
+  // a Ritz value below the spectrum of H means a numerically dependent
+  // direction spoiled the reduced matrix: redo without P and a looser drop
   if (tid == 0) {
-    for (int a = 0; a < r; ++a) order[a] = a;
-    for (int a = 1; a < r; ++a) {
-      const int t = order[a];
-      const double vt = theta[t];
-      int q = a - 1;
-      while (q >= 0 && theta[order[q]] > vt) { order[q + 1] = order[q]; --q; }
-      order[q + 1] = t;
-    }
-    g.flag[0] = r;
+    const double lowb = g.hlow ? g.hlow[0] : -INFINITY;
+    retry_s = attempt == 0 && nb > 0 &&
+              (!(theta[0] == theta[0]) || theta[0] < lowb - 1e-6 * fmax(1.0, fabs(lowb)));
   }
   __syncthreads();
-  // 7. coefficients: C_x[:, c] = scale * L^-T y_c (back substitution into
-  //    Hm[.][c]), dropped rows 0; C_p = C_x with the X rows zeroed.
-  for (int c = tid; c < b; c += nt) {
-    const int oc = c < r ? order[c] : 0;
-    for (int a = r - 1; a >= 0; --a) {
-      double s = c < r ? V[a][oc] : 0.0;
-      for (int q = a + 1; q < r; ++q) s -= G[kidx[q]][kidx[a]] * Hm[q][c];
-      Hm[a][c] = s / G[kidx[a]][kidx[a]];
-    }
-    for (int k = 0; k < ns; ++k) {
-      g.C[k * 2 * b + c] = 0.0;
-      g.C[k * 2 * b + b + c] = 0.0;
-    }
-    for (int a = 0; a < r; ++a) {
-      const int k = kidx[a];
-      const double v = c < r ? Hm[a][c] * scale[k] : 0.0;
-      g.C[k * 2 * b + c] = v;
-      g.C[k * 2 * b + b + c] = k < b ? 0.0 : v;
-    }
-    g.lam[c] = c < r ? theta[oc] : 0.0;
+  if (!retry_s) break;
+  ns = min(ns_full, 2 * b);
+  drop_tol = fmax(drop_tol * 1e4, 1e-6);
+  if (tid == 0) g.flag[1] = 1;
+  __syncthreads();
   }
+  // 7. eigenvectors of the tridiagonal by twisted factorisation (one thread
+  //    each); workspace and vectors in G (free after step 4b):
+  //    rows [0, kNS) cols [0, 16): Y; rows [0,kNS) cols [16, 32): D+; [32, 48): D-
+  if (tid < nb) {
+    const int c = tid;
+    const double th = theta[c];
+    double *Y = &G[0][0];
+    auto Yr = [&](int i) -> double & { return G[i][c]; };
+    auto Dp = [&](int i) -> double & { return G[i][16 + c]; };
+    auto Dm = [&](int i) -> double & { return G[i][32 + c]; };
+    (void)Y;
+    Dp(0) = dd[0] - th;
+    for (int i = 0; i + 1 < r; ++i) {
+      double q = Dp(i);
+      if (fabs(q) < pivmin) q = -pivmin;
+      Dp(i + 1) = dd[i + 1] - th - e2[i] / q;
+    }
+    Dm(r - 1) = dd[r - 1] - th;
+    for (int i = r - 2; i >= 0; --i) {
+      double q = Dm(i + 1);
+      if (fabs(q) < pivmin) q = -pivmin;
+      Dm(i) = dd[i] - th - e2[i] / q;
+    }
+    int tw = 0;
+    double best = 1e300;
+    for (int i = 0; i < r; ++i) {
+      const double gam = fabs(Dp(i) + Dm(i) - (dd[i] - th));
+      if (gam < best) { best = gam; tw = i; }
+    }
+    // outward recurrences from the twist; a pivot is kept away from zero
+    // (|q| >= 1e-280 (1 + |e|)) and the partial vector is rescaled whenever an
+    // entry passes 1e10, so a nearly split matrix cannot overflow
+    Yr(tw) = 1.0;
+    for (int i = tw - 1; i >= 0; --i) {
+      double q = Dp(i);
+      const double qmin = 1e-280 * (1.0 + fabs(ee[i]));
+      if (fabs(q) < qmin) q = q < 0 ? -qmin : qmin;
+      Yr(i) = -(ee[i] / q) * Yr(i + 1);
+      if (fabs(Yr(i)) > 1e10) {
+        const double sc = 1.0 / fabs(Yr(i));
+        for (int j = i; j <= tw; ++j) Yr(j) *= sc;
+      }
+    }
+    for (int i = tw + 1; i < r; ++i) {
+      double q = Dm(i);
+      const double qmin = 1e-280 * (1.0 + fabs(ee[i - 1]));
+      if (fabs(q) < qmin) q = q < 0 ? -qmin : qmin;
+      Yr(i) = -(ee[i - 1] / q) * Yr(i - 1);
+      if (fabs(Yr(i)) > 1e10) {
+        const double sc = 1.0 / fabs(Yr(i));
+        for (int j = 0; j <= i; ++j) Yr(j) *= sc;
+      }
+    }
+    double nrm = 0.0;
+    for (int i = 0; i < r; ++i) nrm += Yr(i) * Yr(i);
+    if (!(nrm > 0.0) || !(nrm < INFINITY)) {  // last resort: the twist's unit vector
+      for (int i = 0; i < r; ++i) Yr(i) = i == tw ? 1.0 : 0.0;
+      nrm = 1.0;
+    }
+    nrm = 1.0 / sqrt(nrm);
+    for (int i = 0; i < r; ++i) Yr(i) *= nrm;
+  }
+  __syncthreads();
+  // re-orthogonalise inside clusters of close eigenvalues (wave 0, in order)
+  if (tid < kWave) {
+    const double cl = 1e-5 * fmax(tnorm, 1e-300);
+    for (int c = 1; c < nb; ++c) {
+      bool any = false;
+      for (int j = 0; j < c; ++j) {
+        if (fabs(theta[c] - theta[j]) > cl) continue;
+        any = true;
+        double dot = 0.0;
+        for (int i = tid; i < r; i += kWave) dot += G[i][c] * G[i][j];
+        dot = wave_sum(dot);
+        for (int i = tid; i < r; i += kWave) G[i][c] -= dot * G[i][j];
+      }
+      if (any) {
+        double nrm = 0.0;
+        for (int i = tid; i < r; i += kWave) nrm += G[i][c] * G[i][c];
+        nrm = wave_sum(nrm);
+        nrm = 1.0 / sqrt(nrm);
+        for (int i = tid; i < r; i += kWave) G[i][c] *= nrm;
+      }
+    }
+  }
+  __syncthreads();
+  // 8. y <- Q y with the reflectors (last one first); 16 lanes per column,
+  //    each lane owning rows i = t mod 16 (no cross-lane memory hazards)
+  {
+    const int c = tid >> 4, t = tid & 15;
+    for (int k = r - 3; k >= 0; --k) {
+      const double bk = beta[k];
+      if (bk == 0.0) continue;
+      double dot = 0.0;
+      if (c < nb)
+        for (int i = k + 1 + t; i < r; i += 16) dot += Hm[i][k] * G[i][c];
+#pragma unroll
+      for (int o = 8; o > 0; o >>= 1) dot += __shfl_xor(dot, o, kWave);
+      if (c < nb)
+        for (int i = k + 1 + t; i < r; i += 16) G[i][c] -= bk * dot * Hm[i][k];
+    }
+  }
+  __syncthreads();
+  // 9. coefficients in S's columns
+  if (tid == 0) g.flag[0] = r;
+  for (int e = tid; e < ns_full * b; e += nt) {
+    const int k = e / b, c = e % b;
+    g.C[k * 2 * b + c] = 0.0;
+    g.C[k * 2 * b + b + c] = 0.0;
+  }
+  __syncthreads();
+  for (int e = tid; e < r * b; e += nt) {
+    const int a = e / b, c = e % b;
+    const int k = kidx[a];
+    double v = 0.0;
+    if (c < nb)
+      for (int q = a; q < r; ++q) v += Z[q][a] * G[q][c];
+    v *= scale[k];
+    g.C[k * 2 * b + c] = v;
+    g.C[k * 2 * b + b + c] = k < b ? 0.0 : v;
+  }
+  for (int c = tid; c < b; c += nt) g.lam[c] = c < nb ? theta[c] : 0.0;
 }
 
 // ------------------------------------------------------------ update
@@ -407,6 +574,7 @@ struct UpdArgs {
   float *w32;             // optional float32 copy of W (dense D x b)
   double *npart;          // per block: b residual sums, b |x|^2 sums
   int rows_per_blk;
+  const int32_t *locked;  // per column: converged at the previous check (W = 0)
 };
 
 // Threads (row, column c).  All reads of a row precede the barrier, all writes
@@ -447,7 +615,7 @@ __global__ __launch_bounds__(256) void k_update(UpdArgs g) {
       const double res = hx - lam[c] * x;
       double den = g.diag[i] - lam[c];
       if (fabs(den) < 1e-2) den = den < 0 ? -1e-2 : 1e-2;
-      const double w = res / den;
+      const double w = g.locked[c] ? 0.0 : res / den;   // soft locking
       double *s = g.S + i * ld;
       double *h = g.HS + i * ld;
       s[c] = x;
@@ -471,7 +639,7 @@ __global__ __launch_bounds__(256) void k_update(UpdArgs g) {
 
 // Relative residual norms and the count of converged leading pairs.
 __global__ void k_finish(int b, int nev, int nparts, const double *npart, const double *lam, double tol,
-                         double *status) {
+                         double *status, int32_t *locked) {
   __shared__ double rs[kMaxBlock], xs[kMaxBlock];
   const int c = threadIdx.x;
   if (c < b) {
@@ -482,6 +650,7 @@ __global__ void k_finish(int b, int nev, int nparts, const double *npart, const 
     }
     rs[c] = sqrt(a) / (fmax(fabs(lam[c]), 1.0) * sqrt(fmax(x, 1e-300)));
     xs[c] = lam[c];
+    locked[c] = rs[c] <= tol;
   }
   __syncthreads();
   if (c == 0) {
@@ -495,6 +664,13 @@ __global__ void k_finish(int b, int nev, int nparts, const double *npart, const 
 // ------------------------------------------------------------ host driver
 static inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
+// rows per Gram block: about 512 blocks, a multiple of the staging chunk
+static int64_t gram_rows_for(int64_t D) {
+  int64_t r = (D + 511) / 512;
+  r = (r + kGramRows - 1) / kGramRows * kGramRows;
+  return std::max<int64_t>(kGramRows, r);
+}
+
 struct LobpcgRun {
   cib_ctx *ctx;
   const cib_matrix &H;
@@ -504,10 +680,10 @@ struct LobpcgRun {
   int64_t gram_rows, upd_rows;
   double tol;
   cib_lobpcg_opts opts;
-  DBuf<double> S, HS, diag, partial, C, lam, npart, status;
+  DBuf<double> S, HS, diag, partial, gram, C, lam, npart, status, hlow;
   DBuf<float> x32, y32;
   DBuf<int64_t> idx;
-  DBuf<int32_t> flag;
+  DBuf<int32_t> flag, locked;
   int iters = 0;
   double t_spmm = 0.0;
   int64_t n_spmm = 0;
@@ -520,22 +696,25 @@ struct LobpcgRun {
     CIB_REQUIRE(nev >= 1 && nev <= b && b <= kMaxBlock, CIB_E_INVALID, "need 1 <= nev <= block <= 16");
     CIB_REQUIRE(3 * (int64_t)b <= H.D, CIB_E_INVALID, "need 3 * block <= D");
     CIB_REQUIRE(o.max_iter >= 1, CIB_E_INVALID, "max_iter must be >= 1");
-    tol = o.tol > 0 ? o.tol : (H.dtype == CIB_F64 ? 1e-9 : 1e-6);
+    tol = o.tol > 0 ? o.tol : (H.dtype == CIB_F64 ? 1e-9 : 1e-5);
     ld = 3 * b;
     S.reset(ctx, (size_t)D * ld);
     HS.reset(ctx, (size_t)D * ld);
     diag.reset(ctx, D);
-    gram_rows = std::max<int64_t>(256, (D + 2047) / 2048);
+    gram_rows = gram_rows_for(D);
     gram_blocks = (int)((D + gram_rows - 1) / gram_rows);
     upd_rows = std::max<int64_t>(64, (D + 4095) / 4096);
     upd_blocks = (int)((D + upd_rows - 1) / upd_rows);
     partial.reset(ctx, (size_t)gram_blocks * kNS * 2 * kNS);
+    gram.reset(ctx, (size_t)kNS * 2 * kNS);
+    hlow.reset(ctx, 1);
     C.reset(ctx, kNS * 2 * kMaxBlock);
     lam.reset(ctx, kMaxBlock);
     npart.reset(ctx, (size_t)upd_blocks * 2 * kMaxBlock);
     status.reset(ctx, kStatusLen);
     idx.reset(ctx, kMaxBlock);
     flag.reset(ctx, 4);
+    locked.reset(ctx, kMaxBlock);
     if (H.dtype == CIB_F32) {
       x32.reset(ctx, (size_t)D * b);
       y32.reset(ctx, (size_t)D * b);
@@ -566,22 +745,36 @@ struct LobpcgRun {
   }
 
   void rr_update(int ns) {
-    { KTimer kt(ctx, K_GRAM, s); hipLaunchKernelGGL(k_gram, dim3(gram_blocks), dim3(256), 0, s, D, ns, ld, S.p, HS.p, gram_rows, partial.p); }
-    RRArgs ra{ns, b, gram_blocks, partial.p, C.p, lam.p, flag.p, 1e-10};
+    {
+      KTimer kt(ctx, K_GRAM, s);
+      hipLaunchKernelGGL(k_gram, dim3(gram_blocks), dim3(256), 0, s, D, ns, ld, S.p, HS.p, gram_rows, partial.p);
+      const int nout = ns * 2 * ns;
+      hipLaunchKernelGGL(k_gram_reduce, dim3((nout + 63) / 64), dim3(256), 0, s, nout, gram_blocks, partial.p, gram.p);
+    }
+    RRArgs ra{ns, b, 1, gram.p, C.p, lam.p, flag.p, H.dtype == CIB_F64 ? 1e-10 : 1e-7, hlow.p};
     { KTimer kt(ctx, K_RR, s); hipLaunchKernelGGL(k_rayleigh_ritz, dim3(1), dim3(256), 0, s, ra); }
     UpdArgs ua{D, b, ns, ld, S.p, HS.p, C.p, lam.p, diag.p, H.dtype == CIB_F32 ? x32.p : nullptr,
-               npart.p, (int)upd_rows};
+               npart.p, (int)upd_rows, locked.p};
     { KTimer kt(ctx, K_UPDATE, s); hipLaunchKernelGGL(k_update, dim3(upd_blocks), dim3(256), 0, s, ua); }
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, s, b, nev, upd_blocks, npart.p, lam.p, tol, status.p);
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, s, b, nev, upd_blocks, npart.p, lam.p, tol, status.p, locked.p);
     CIB_HIP(hipGetLastError());
   }
 
-  // diagonal, X0 and the Rayleigh-Ritz step on X0 alone
+  // diagonal, spectrum bound, X0 and the Rayleigh-Ritz step on X0 alone
   void start() {
-    if (H.dtype == CIB_F64)
+    CIB_HIP(hipMemsetAsync(flag.p, 0, sizeof(int32_t) * 4, s));
+    CIB_HIP(hipMemsetAsync(locked.p, 0, sizeof(int32_t) * kMaxBlock, s));
+    const unsigned rb = (unsigned)((D + 3) / 4);
+    if (H.dtype == CIB_F64) {
       hipLaunchKernelGGL(k_diag<double>, dim3(nblk(D)), dim3(256), 0, s, D, H.row_ptr.p, H.val64.p, diag.p);
-    else
+      hipLaunchKernelGGL(k_gersh_rows<double>, dim3(rb), dim3(256), 0, s, D, H.row_ptr.p, H.val64.p,
+                         H.lo_ptr.p, H.lo_val64.p, HS.p);
+    } else {
       hipLaunchKernelGGL(k_diag<float>, dim3(nblk(D)), dim3(256), 0, s, D, H.row_ptr.p, H.val32.p, diag.p);
+      hipLaunchKernelGGL(k_gersh_rows<float>, dim3(rb), dim3(256), 0, s, D, H.row_ptr.p, H.val32.p,
+                         H.lo_ptr.p, H.lo_val32.p, HS.p);
+    }
+    hipLaunchKernelGGL(k_min, dim3(1), dim3(1024), 0, s, D, HS.p, hlow.p);   // HS is scratch here
     if (opts.x0) {
       hipLaunchKernelGGL(k_copy_x0, dim3(nblk(D * b)), dim3(256), 0, s, D, b, ld, opts.x0, S.p);
     } else {
@@ -617,7 +810,7 @@ struct LobpcgRun {
 };
 
 size_t lobpcg_bytes(int64_t D, int b, cib_dtype dt) {
-  const int64_t gram_rows = std::max<int64_t>(256, (D + 2047) / 2048);
+  const int64_t gram_rows = gram_rows_for(D);
   const int64_t gram_blocks = (D + gram_rows - 1) / gram_rows;
   const int64_t upd_rows = std::max<int64_t>(64, (D + 4095) / 4096);
   const int64_t upd_blocks = (D + upd_rows - 1) / upd_rows;
@@ -646,13 +839,33 @@ cib_status lobpcg_solve(cib_ctx *ctx, const cib_matrix &H, const cib_lobpcg_opts
   L.copy_status(st);
   CIB_HIP(hipStreamSynchronize(L.s));
   L.spmm_time_accumulate();
+  // CIB_DEBUG_DUMP=<file>: on a non-finite status, write the last reduced Gram
+  // matrices, coefficients and Ritz values (float64, raw) for offline analysis
+  auto dump = [&](int ns) {
+    const char *path = std::getenv("CIB_DEBUG_DUMP");
+    if (!path) return;
+    std::vector<double> h(kNS * 2 * kNS + kNS * 2 * kMaxBlock + kMaxBlock + 4, 0.0);
+    h[0] = ns; h[1] = L.b; h[2] = L.iters;
+    CIB_HIP(hipMemcpy(h.data() + 4, L.gram.p, sizeof(double) * ns * 2 * ns, hipMemcpyDeviceToHost));
+    CIB_HIP(hipMemcpy(h.data() + 4 + kNS * 2 * kNS, L.C.p, sizeof(double) * kNS * 2 * kMaxBlock, hipMemcpyDeviceToHost));
+    if (FILE *f = std::fopen(path, "wb")) { std::fwrite(h.data(), sizeof(double), h.size(), f); std::fclose(f); }
+  };
+  auto finite = [&] {
+    for (int k = 0; k < L.b; ++k)
+      if (!std::isfinite(st[1 + k]) || !std::isfinite(st[1 + kMaxBlock + k])) return false;
+    return true;
+  };
   int conv = (int)st[0];
+  if (!finite()) dump(L.b);
+  CIB_REQUIRE(finite(), CIB_E_DEVICE, "LOBPCG produced non-finite Ritz values");
   while (conv < L.nev && L.iters < L.max_iter) {
     L.iterate();
     L.copy_status(st);
     CIB_HIP(hipStreamSynchronize(L.s));
     L.spmm_time_accumulate();
     conv = (int)st[0];
+    if (!finite()) dump(L.iters == 1 ? 2 * L.b : 3 * L.b);
+    CIB_REQUIRE(finite(), CIB_E_DEVICE, "LOBPCG produced non-finite Ritz values");
   }
   for (int k = 0; k < L.nev; ++k) evals[k] = st[1 + kMaxBlock + k];
   if (evecs) L.copy_vectors(evecs, ld_evecs);

@@ -43,7 +43,8 @@ static PairLayout pair_layout(const Orbs &o1, const Orbs &o2, bool same) {
 }
 
 const char *const kKernelNames[K_NKERN] = {"tile_screen", "adjacency", "row_count", "scan",
-                                           "row_fill", "spmm_sym", "gram", "rayleigh_ritz", "update"};
+                                           "row_fill", "spmm_sym", "gram", "rayleigh_ritz", "update",
+                                           "lower"};
 
 static hipEvent_t take_event(cib_ctx *c) {
   if (!c->event_pool.empty()) {

@@ -58,7 +58,8 @@ struct Shared {
 static size_t footprint(const cib_basis &b, int64_t nnz, cib_dtype dt, int block) {
   const int64_t D = b.plan.D;
   const size_t sv = dt == CIB_F64 ? 8 : 4;
-  size_t h = (size_t)nnz * (4 + sv) + 8 * (size_t)(D + 1);
+  // upper half + strictly lower copy
+  size_t h = (size_t)(2 * nnz - D) * (4 + sv) + 16 * (size_t)(D + 1);
   return h + lobpcg_bytes(D, block, dt);
 }
 

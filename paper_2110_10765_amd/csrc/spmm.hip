@@ -1,54 +1,70 @@
-// Symmetric SpMM Y = H X from the half-stored CSR (upper triangle with the
-// diagonal): y_i += sum_{j>=i} H_ij x_j (row gather) and y_j += H_ij x_i for
-// j > i (transposed half, device atomics).  Sec. 2: sparse matrix-matrix
-// products of the eigensolver; Fig. 2 line 5 ("FMA of H_ij with the i-th row
-// and j-th column vector elements").
+// Symmetric SpMM Y = H X (Sec. 2: sparse matrix-matrix products of the
+// eigensolver; Fig. 2 line 5, "FMA of H_ij with the i-th row and j-th column
+// vector elements").  Row i gathers its upper half (the half-stored CSR,
+// j >= i) and its strictly lower half (the transposed copy the build keeps),
+// so every output row is written once by one wave: no atomics, no zeroing,
+// and a fixed summation order (deterministic).
 //
 // Layout: X, Y row-major (D x nvec, leading dimensions ldx / ldy), so one
 // vector row is one contiguous run of 8 or 16 values.  A wave handles one
 // row; its 64 lanes are E = 64 / B entry slots times B vector columns, so a
-// gather of x_j and an atomic update of y_j are each one contiguous segment.
+// gather of x_j is one contiguous segment, and each lane keeps U entries in
+// flight.
 #include "cib_internal.hpp"
 #include "device_common.hpp"
 
 namespace cib {
 using namespace dev;
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_zero(T *Y, int64_t D, int64_t ldy, int nvec) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t r = k / nvec, c = k % nvec;
-  if (r < D) Y[r * ldy + c] = T(0);
+template <typename T, int B, int U>
+__device__ __forceinline__ T row_dot(int64_t k0, int64_t k1, const int32_t *__restrict__ col,
+                                     const T *__restrict__ val, const T *__restrict__ X, int64_t ldx,
+                                     int vc, bool cv, int e) {
+  constexpr int E = kWave / B;
+  T acc = T(0);
+  int64_t k = k0 + e;
+  for (; k + (U - 1) * E < k1; k += U * E) {
+    int32_t j[U];
+    T h[U], x[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      j[u] = col[k + u * E];
+      h[u] = val[k + u * E];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) x[u] = cv ? X[(int64_t)j[u] * ldx + vc] : T(0);
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc += h[u] * x[u];
+  }
+  for (; k < k1; k += E) {
+    const int32_t j = col[k];
+    const T h = val[k];
+    acc += h * (cv ? X[(int64_t)j * ldx + vc] : T(0));
+  }
+  return acc;
 }
 
 template <typename T, int B>
 __global__ __launch_bounds__(256) void k_spmm_sym(int64_t D, const int64_t *__restrict__ rp,
                                                   const int32_t *__restrict__ col,
                                                   const T *__restrict__ val,
-                                                  const T *__restrict__ X, int64_t ldx, T *Y,
+                                                  const int64_t *__restrict__ lrp,
+                                                  const int32_t *__restrict__ lcol,
+                                                  const T *__restrict__ lval,
+                                                  const T *__restrict__ X, int64_t ldx, T *__restrict__ Y,
                                                   int64_t ldy, int nvec, int v0) {
-  constexpr int E = kWave / B;
   const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
   const int64_t i = blk * (blockDim.x / kWave) + (threadIdx.x >> 6);
   if (i >= D) return;
   const int lane = lane_id();
   const int e = lane / B, c = lane % B;
-  const bool cv = c < nvec - v0 && c < B;
+  const bool cv = c < nvec - v0;
   const int vc = v0 + c;
-  const T xi = cv ? X[i * ldx + vc] : T(0);
-  T acc = T(0);
-  const int64_t k1 = rp[i + 1];
-  for (int64_t k = rp[i] + e; k < k1; k += E) {
-    const int32_t j = col[k];
-    const T h = val[k];
-    if (cv) {
-      acc += h * X[(int64_t)j * ldx + vc];
-      if (j != i) unsafeAtomicAdd(&Y[(int64_t)j * ldy + vc], h * xi);
-    }
-  }
+  T acc = row_dot<T, B, 4>(lrp[i], lrp[i + 1], lcol, lval, X, ldx, vc, cv, e);
+  acc += row_dot<T, B, 4>(rp[i], rp[i + 1], col, val, X, ldx, vc, cv, e);
 #pragma unroll
   for (int s = kWave / 2; s >= B; s >>= 1) acc += __shfl_down(acc, s, kWave);
-  if (e == 0 && cv) unsafeAtomicAdd(&Y[i * ldy + vc], acc);
+  if (e == 0 && cv) Y[i * ldy + vc] = acc;
 }
 
 template <typename T>
@@ -56,17 +72,16 @@ static void spmm_t(const cib_matrix &H, const T *X, int64_t ldx, T *Y, int64_t l
                    hipStream_t s) {
   const int64_t D = H.D;
   const T *val = static_cast<const T *>(H.val());
-  const int64_t nz = D * nvec;
-  hipLaunchKernelGGL(k_zero<T>, dim3((unsigned)((nz + 255) / 256)), dim3(256), 0, s, Y, D, ldy, nvec);
+  const T *lval = static_cast<const T *>(H.lo_val());
   const unsigned nblk = (unsigned)((D + 3) / 4);
   for (int v0 = 0; v0 < nvec; v0 += 16) {
     KTimer kt(H.ctx, K_SPMM, s);
     if (nvec - v0 <= 8)
       hipLaunchKernelGGL((k_spmm_sym<T, 8>), dim3(nblk), dim3(256), 0, s, D, H.row_ptr.p, H.col.p,
-                         val, X, ldx, Y, ldy, nvec, v0);
+                         val, H.lo_ptr.p, H.lo_col.p, lval, X, ldx, Y, ldy, nvec, v0);
     else
       hipLaunchKernelGGL((k_spmm_sym<T, 16>), dim3(nblk), dim3(256), 0, s, D, H.row_ptr.p,
-                         H.col.p, val, X, ldx, Y, ldy, nvec, v0);
+                         H.col.p, val, H.lo_ptr.p, H.lo_col.p, lval, X, ldx, Y, ldy, nvec, v0);
   }
   CIB_HIP(hipGetLastError());
 }
