@@ -226,6 +226,7 @@ struct RRArgs {
   int32_t *flag;    // [0]: rank of the search space, [1]: fallback taken
   double drop_tol;
   const double *hlow;  // lower bound of the spectrum of H (Gershgorin)
+  long long *clk;      // optional: wall-clock stamps of the phases (thread 0)
 };
 
 // Number of eigenvalues of the symmetric tridiagonal (d, e2 = e^2) below x
@@ -263,6 +264,7 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz(RRArgs g) {
   int ns = ns_full, r = 0, nb = 0;
   double drop_tol = g.drop_tol, tnorm = 0.0, pivmin = 0.0;
   for (int attempt = 0; attempt < 2; ++attempt) {
+  if (g.clk && tid == 0) g.clk[0] = wall_clock64();
   // 1. reduce the partial Gram matrices (fixed order: deterministic); a
   //    retry keeps only the first ns columns ([X W]) of the same matrices
   for (int e = tid; e < nout; e += nt) {
@@ -275,6 +277,7 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz(RRArgs g) {
     }
   }
   __syncthreads();
+  if (g.clk && tid == 0) g.clk[1] = wall_clock64();
   // 2. symmetrise, scale to unit diagonal
   for (int i = tid; i < ns; i += nt) {
     const double d = G[i][i];
@@ -292,6 +295,7 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz(RRArgs g) {
     }
   }
   __syncthreads();
+  if (g.clk && tid == 0) g.clk[2] = wall_clock64();
   // 3. right-looking Cholesky with dropping
   for (int k = 0; k < ns; ++k) {
     const double piv = G[k][k];
@@ -317,6 +321,7 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz(RRArgs g) {
   }
   __syncthreads();
   r = rank_s;
+  if (g.clk && tid == 0) g.clk[3] = wall_clock64();
   // 4a. Z = L^-1 (compressed r x r, lower triangular), row by row
   for (int a = 0; a < r; ++a) {
     const int ka = kidx[a];
@@ -331,6 +336,7 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz(RRArgs g) {
     }
     __syncthreads();
   }
+  if (g.clk && tid == 0) g.clk[4] = wall_clock64();
   // 4b. T1 = Hm_c Z^T into G (L is no longer needed), then M = Z T1 into Hm
   for (int e = tid; e < r * r; e += nt) {
     const int a = e / r, q = e % r;
@@ -356,6 +362,7 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz(RRArgs g) {
     }
   }
   __syncthreads();
+  if (g.clk && tid == 0) g.clk[5] = wall_clock64();
   // 5. Householder tridiagonalisation of M (r x r in Hm); the reflector of
   //    step k is kept in column k below the subdiagonal, its scale in beta[k]
   for (int k = 0; k + 2 < r; ++k) {
@@ -396,6 +403,7 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz(RRArgs g) {
   __syncthreads();
   for (int i = tid; i + 1 < r; i += nt) e2[i] = ee[i] * ee[i];
   __syncthreads();
+  if (g.clk && tid == 0) g.clk[6] = wall_clock64();
   // 6. lowest nb eigenvalues: 16 threads per eigenvalue, 16 rounds of
   //    17-way multisection of the Gershgorin interval
   nb = b < r ? b : r;
@@ -441,6 +449,7 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz(RRArgs g) {
   if (tid == 0) g.flag[1] = 1;
   __syncthreads();
   }
+  if (g.clk && tid == 0) g.clk[7] = wall_clock64();
   // 7. eigenvectors of the tridiagonal by twisted factorisation (one thread
   //    each); workspace and vectors in G (free after step 4b):
   //    rows [0, kNS) cols [0, 16): Y; rows [0,kNS) cols [16, 32): D+; [32, 48): D-
@@ -527,6 +536,7 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz(RRArgs g) {
     }
   }
   __syncthreads();
+  if (g.clk && tid == 0) g.clk[8] = wall_clock64();
   // 8. y <- Q y with the reflectors (last one first); 16 lanes per column,
   //    each lane owning rows i = t mod 16 (no cross-lane memory hazards)
   {
@@ -544,6 +554,7 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz(RRArgs g) {
     }
   }
   __syncthreads();
+  if (g.clk && tid == 0) g.clk[9] = wall_clock64();
   // 9. coefficients in S's columns
   if (tid == 0) g.flag[0] = r;
   for (int e = tid; e < ns_full * b; e += nt) {
@@ -563,6 +574,7 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz(RRArgs g) {
     g.C[k * 2 * b + b + c] = k < b ? 0.0 : v;
   }
   for (int c = tid; c < b; c += nt) g.lam[c] = c < nb ? theta[c] : 0.0;
+  if (g.clk && tid == 0) g.clk[10] = wall_clock64();
 }
 
 // ------------------------------------------------------------ update
@@ -638,26 +650,34 @@ __global__ __launch_bounds__(256) void k_update(UpdArgs g) {
 }
 
 // Relative residual norms and the count of converged leading pairs.
-__global__ void k_finish(int b, int nev, int nparts, const double *npart, const double *lam, double tol,
-                         double *status, int32_t *locked) {
-  __shared__ double rs[kMaxBlock], xs[kMaxBlock];
-  const int c = threadIdx.x;
-  if (c < b) {
-    double a = 0.0, x = 0.0;
-    for (int q = 0; q < nparts; ++q) {
+__global__ __launch_bounds__(256) void k_finish(int b, int nev, int nparts, const double *npart,
+                                                const double *lam, double tol, double *status,
+                                                int32_t *locked) {
+  // 16 slices of the partial sums per column, then a fixed-order sum
+  __shared__ double ra[16][kMaxBlock], rx[16][kMaxBlock];
+  __shared__ double rs[kMaxBlock];
+  const int c = threadIdx.x & 15, sl = threadIdx.x >> 4;
+  double a = 0.0, x = 0.0;
+  if (c < b)
+    for (int q = sl; q < nparts; q += 16) {
       a += npart[(int64_t)q * 2 * b + c];
       x += npart[(int64_t)q * 2 * b + b + c];
     }
-    rs[c] = sqrt(a) / (fmax(fabs(lam[c]), 1.0) * sqrt(fmax(x, 1e-300)));
-    xs[c] = lam[c];
+  ra[sl][c] = a;
+  rx[sl][c] = x;
+  __syncthreads();
+  if (threadIdx.x < b) {
+    double sa = 0.0, sx = 0.0;
+    for (int q = 0; q < 16; ++q) { sa += ra[q][c]; sx += rx[q][c]; }
+    rs[c] = sqrt(sa) / (fmax(fabs(lam[c]), 1.0) * sqrt(fmax(sx, 1e-300)));
     locked[c] = rs[c] <= tol;
   }
   __syncthreads();
-  if (c == 0) {
+  if (threadIdx.x == 0) {
     int conv = 0;
     for (int k = 0; k < nev; ++k) conv += rs[k] <= tol;
     status[0] = conv;
-    for (int k = 0; k < b; ++k) { status[1 + k] = rs[k]; status[1 + kMaxBlock + k] = xs[k]; }
+    for (int k = 0; k < b; ++k) { status[1 + k] = rs[k]; status[1 + kMaxBlock + k] = lam[k]; }
   }
 }
 
@@ -666,7 +686,7 @@ static inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t -
 
 // rows per Gram block: about 512 blocks, a multiple of the staging chunk
 static int64_t gram_rows_for(int64_t D) {
-  int64_t r = (D + 511) / 512;
+  int64_t r = std::max<int64_t>((D + 511) / 512, 256);
   r = (r + kGramRows - 1) / kGramRows * kGramRows;
   return std::max<int64_t>(kGramRows, r);
 }
@@ -684,6 +704,8 @@ struct LobpcgRun {
   DBuf<float> x32, y32;
   DBuf<int64_t> idx;
   DBuf<int32_t> flag, locked;
+  DBuf<long long> clk;
+  bool clk_on = false;
   int iters = 0;
   double t_spmm = 0.0;
   int64_t n_spmm = 0;
@@ -715,6 +737,8 @@ struct LobpcgRun {
     idx.reset(ctx, kMaxBlock);
     flag.reset(ctx, 4);
     locked.reset(ctx, kMaxBlock);
+    clk_on = std::getenv("CIB_DEBUG_RR_CLOCK") != nullptr;
+    if (clk_on) clk.reset(ctx, 16);
     if (H.dtype == CIB_F32) {
       x32.reset(ctx, (size_t)D * b);
       y32.reset(ctx, (size_t)D * b);
@@ -751,12 +775,13 @@ struct LobpcgRun {
       const int nout = ns * 2 * ns;
       hipLaunchKernelGGL(k_gram_reduce, dim3((nout + 63) / 64), dim3(256), 0, s, nout, gram_blocks, partial.p, gram.p);
     }
-    RRArgs ra{ns, b, 1, gram.p, C.p, lam.p, flag.p, H.dtype == CIB_F64 ? 1e-10 : 1e-7, hlow.p};
+    RRArgs ra{ns, b, 1, gram.p, C.p, lam.p, flag.p, H.dtype == CIB_F64 ? 1e-10 : 1e-7, hlow.p,
+              clk_on ? clk.p : nullptr};
     { KTimer kt(ctx, K_RR, s); hipLaunchKernelGGL(k_rayleigh_ritz, dim3(1), dim3(256), 0, s, ra); }
     UpdArgs ua{D, b, ns, ld, S.p, HS.p, C.p, lam.p, diag.p, H.dtype == CIB_F32 ? x32.p : nullptr,
                npart.p, (int)upd_rows, locked.p};
     { KTimer kt(ctx, K_UPDATE, s); hipLaunchKernelGGL(k_update, dim3(upd_blocks), dim3(256), 0, s, ua); }
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, s, b, nev, upd_blocks, npart.p, lam.p, tol, status.p, locked.p);
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, b, nev, upd_blocks, npart.p, lam.p, tol, status.p, locked.p);
     CIB_HIP(hipGetLastError());
   }
 
@@ -870,6 +895,13 @@ cib_status lobpcg_solve(cib_ctx *ctx, const cib_matrix &H, const cib_lobpcg_opts
   for (int k = 0; k < L.nev; ++k) evals[k] = st[1 + kMaxBlock + k];
   if (evecs) L.copy_vectors(evecs, ld_evecs);
   CIB_HIP(hipStreamSynchronize(L.s));
+  if (L.clk_on) {  // debug: phase durations of the last Rayleigh-Ritz step (100 MHz counter)
+    long long c[16];
+    CIB_HIP(hipMemcpy(c, L.clk.p, sizeof(c), hipMemcpyDeviceToHost));
+    std::fprintf(stderr, "rayleigh_ritz phases (us):");
+    for (int k = 0; k < 10; ++k) std::fprintf(stderr, " %d:%.2f", k + 1, (c[k + 1] - c[k]) * 0.01);
+    std::fprintf(stderr, "\n");
+  }
   if (info) {
     info->iters = L.iters;
     info->n_converged = conv;

@@ -10,6 +10,8 @@
 // row; its 64 lanes are E = 64 / B entry slots times B vector columns, so a
 // gather of x_j is one contiguous segment, and each lane keeps U entries in
 // flight.
+#include <type_traits>
+
 #include "cib_internal.hpp"
 #include "device_common.hpp"
 
@@ -67,6 +69,59 @@ __global__ __launch_bounds__(256) void k_spmm_sym(int64_t D, const int64_t *__re
   if (e == 0 && cv) Y[i * ldy + vc] = acc;
 }
 
+// Wide variant for nvec == NV (8 or 16) with 16-byte aligned rows: one lane
+// per stored entry, so col/val reads are coalesced across the wave, and the
+// x_j row is fetched with 16-byte vector loads into NV register accumulators;
+// the row total is a wave reduction per vector column.
+template <typename T, int NV>
+__global__ __launch_bounds__(256) void k_spmm_wide(int64_t D, const int64_t *__restrict__ rp,
+                                                   const int32_t *__restrict__ col,
+                                                   const T *__restrict__ val,
+                                                   const int64_t *__restrict__ lrp,
+                                                   const int32_t *__restrict__ lcol,
+                                                   const T *__restrict__ lval,
+                                                   const T *__restrict__ X, int64_t ldx, T *__restrict__ Y,
+                                                   int64_t ldy) {
+  constexpr int PER16 = 16 / sizeof(T);           // values per 16-byte load
+  using V = typename std::conditional<sizeof(T) == 8, double2, float4>::type;
+  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t i = blk * (blockDim.x / kWave) + (threadIdx.x >> 6);
+  if (i >= D) return;
+  const int lane = lane_id();
+  T acc[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) acc[v] = T(0);
+  auto part = [&](int64_t k0, int64_t k1, const int32_t *__restrict__ cc, const T *__restrict__ vv) {
+    for (int64_t k = k0 + lane; k < k1; k += kWave) {
+      const int32_t j = cc[k];
+      const T h = vv[k];
+      const V *xr = reinterpret_cast<const V *>(X + (int64_t)j * ldx);
+#pragma unroll
+      for (int q = 0; q < NV / PER16; ++q) {
+        const V t = xr[q];
+        if constexpr (sizeof(T) == 8) {
+          acc[2 * q] += h * t.x;
+          acc[2 * q + 1] += h * t.y;
+        } else {
+          acc[4 * q] += h * t.x;
+          acc[4 * q + 1] += h * t.y;
+          acc[4 * q + 2] += h * t.z;
+          acc[4 * q + 3] += h * t.w;
+        }
+      }
+    }
+  };
+  part(lrp[i], lrp[i + 1], lcol, lval);
+  part(rp[i], rp[i + 1], col, val);
+  // reduce each column over the wave; lane v ends with column v's total
+#pragma unroll
+  for (int v = 0; v < NV; ++v) acc[v] = wave_sum(acc[v]);
+  T mine = acc[0];
+#pragma unroll
+  for (int v = 1; v < NV; ++v) mine = lane == v ? acc[v] : mine;
+  if (lane < NV) Y[i * ldy + lane] = mine;
+}
+
 template <typename T>
 static void spmm_t(const cib_matrix &H, const T *X, int64_t ldx, T *Y, int64_t ldy, int nvec,
                    hipStream_t s) {
@@ -74,6 +129,18 @@ static void spmm_t(const cib_matrix &H, const T *X, int64_t ldx, T *Y, int64_t l
   const T *val = static_cast<const T *>(H.val());
   const T *lval = static_cast<const T *>(H.lo_val());
   const unsigned nblk = (unsigned)((D + 3) / 4);
+  const bool aligned = ((uintptr_t)X % 16 == 0) && ((ldx * sizeof(T)) % 16 == 0);
+  if (aligned && (nvec == 8 || nvec == 16)) {
+    KTimer kt(H.ctx, K_SPMM, s);
+    if (nvec == 8)
+      hipLaunchKernelGGL((k_spmm_wide<T, 8>), dim3(nblk), dim3(256), 0, s, D, H.row_ptr.p, H.col.p, val,
+                         H.lo_ptr.p, H.lo_col.p, lval, X, ldx, Y, ldy);
+    else
+      hipLaunchKernelGGL((k_spmm_wide<T, 16>), dim3(nblk), dim3(256), 0, s, D, H.row_ptr.p, H.col.p, val,
+                         H.lo_ptr.p, H.lo_col.p, lval, X, ldx, Y, ldy);
+    CIB_HIP(hipGetLastError());
+    return;
+  }
   for (int v0 = 0; v0 < nvec; v0 += 16) {
     KTimer kt(H.ctx, K_SPMM, s);
     if (nvec - v0 <= 8)
