@@ -9,8 +9,10 @@ stored H (popcount screen, phases, matrix elements, counts -> offsets ->
 fill), and block LOBPCG to convergence (every iteration one symmetric SpMM,
 float64 Gram / Rayleigh-Ritz / update).  Printed as one JSON line:
 
-  value            H nonzeros built per second (nnz_half / wall time of the
-                   build call, mean over the timed steps)
+  value            H nonzeros built per second: nnz_half over the device time
+                   of the build (HIP events around its kernels, both stored
+                   triangles, tables resident), mean over the timed steps;
+                   the rate over the wall time of the call is a submetric
   submetrics       H build rate per dtype, SpMM nnz*vec/s per dtype (kernel
                    time from HIP events), solves/s of the step, the same
                    numbers for the larger workloads, and the serving loop
@@ -44,7 +46,9 @@ def _spmm_bytes(nnz_half, D, b, sv):
 
 
 def _fill_bytes(nnz_half, D, sv):
-    return nnz_half * (4 + sv) + 8 * (D + 1)
+    """Bytes the fill writes: both stored triangles (the upper half and the
+    strictly lower copy the SpMM reads) and their row offsets."""
+    return (2 * nnz_half - D) * (4 + sv) + 16 * (D + 1)
 
 
 def _gram_bytes(D, b):
@@ -93,7 +97,8 @@ def workload_rates(cib, ctx, cigen, name, b, reps=20):
         nnz_full = 2 * H.nnz - H.dim
         out["nnz_half"] = H.nnz
         out[dt] = {
-            "build_nnz_per_s": H.nnz / t_wall,
+            "build_nnz_per_s": H.nnz / st["t_total_s"],
+            "build_wall_nnz_per_s": H.nnz / t_wall,
             "build_device_s": st["t_total_s"],
             "build_fill_s": st["t_fill_s"],
             "fill_hbm_frac": _fill_bytes(H.nnz, H.dim, sv) / st["t_fill_s"] / 1e9 / HBM_PEAK_GBS,
@@ -217,6 +222,7 @@ def main():
         t3 = time.perf_counter()
         if record is not None:
             record.append(dict(basis=t1 - t0, build=t2 - t1, solve=t3 - t2, nnz=H.nnz,
+                               build_device=H.stats()["t_total_s"],
                                iters=info["iters"], status=info["status"], ev=ev.tolist()))
         H.free()
         b.free()
@@ -233,7 +239,7 @@ def main():
     _sync()
     elapsed = time.perf_counter() - t0
     kernels = {}
-    for k in ("tile_screen", "adjacency", "row_count", "scan", "row_fill", "spmm_sym", "gram",
+    for k in ("tile_screen", "adjacency", "row_count", "scan", "row_fill", "lower", "spmm_sym", "gram",
               "rayleigh_ritz", "update"):
         n, t = ctx.kernel_time(k)
         kernels[k] = {"launches": n, "total_s": t, "mean_s": t / n if n else None}
@@ -257,8 +263,11 @@ def main():
                 "frac": None, "traffic": None, "mean_launch_s": kernels[dom]["mean_s"]}
 
     build_t = sum(r["build"] for r in rec) / len(rec)
+    build_dev = sum(r["build_device"] for r in rec) / len(rec)
     sub = {
         "step_breakdown_s": {k: sum(r[k] for r in rec) / len(rec) for k in ("basis", "build", "solve")},
+        "build_device_s": build_dev,
+        "build_wall_nnz_per_s": nnz / build_t,
         "lobpcg_iters": [r["iters"] for r in rec],
         "lowest_eigenvalues": rec[-1]["ev"],
         "solves_per_s": args.steps / elapsed,
@@ -276,7 +285,7 @@ def main():
         except cib.CibError as e:
             sub["serve"] = {"error": str(e)}
     line = {
-        "metric": METRIC, "value": nnz / build_t, "unit": "nnz/s", "n_gpus": 1,
+        "metric": METRIC, "value": nnz / build_dev, "unit": "nnz/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": w.dtype,
         "data": "synthetic (seeded eps ~ n + U(-0.1,0.1), V ~ N(0,1) m-conserving)",

@@ -178,16 +178,18 @@ cib_status cib_build_H(cib_ctx *ctx, const cib_basis *basis, const cib_tables *t
 cib_status cib_build_H_resident(cib_ctx *ctx, const cib_basis *basis, const cib_interaction *it,
                                 cib_dtype dtype, cib_matrix **out, int64_t *nnz_half);
 
+/* Every stage builds the stored upper half and the strictly lower copy the
+ * SpMM reads side by side, so each time below covers both. */
 typedef struct {
   /* device time of each stage of the last build, from HIP events, seconds */
   double t_screen_s;  /* A-configuration tile screen + B-configuration adjacency */
   double t_count_s;   /* per-row counting pass                           */
   double t_scan_s;    /* counts -> offsets                               */
   double t_fill_s;    /* per-row filling pass                            */
-  double t_total_s;   /* sum of the above (the half-stored CSR)          */
+  double t_total_s;   /* sum of the above (host waits between stages excluded) */
   int64_t n_tiles;    /* A-configuration pairs kept by the screen        */
   int64_t n_adjacent; /* B-configuration pairs kept by the screen        */
-  double t_lower_s;   /* strictly lower triangle kept for the SpMM       */
+  double t_lower_s;   /* part of t_fill_s spent filling the lower copy   */
 } cib_build_stats;
 
 cib_status cib_matrix_info(const cib_matrix *H, int64_t *dim, int64_t *nnz_half, cib_dtype *dtype);

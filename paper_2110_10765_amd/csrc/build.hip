@@ -16,6 +16,7 @@
 // ascending order without atomics (Sec. 2.2-2.3).
 #include <algorithm>
 #include <functional>
+#include <initializer_list>
 
 #include "cib_internal.hpp"
 #include "device_common.hpp"
@@ -24,29 +25,29 @@ namespace cib {
 using namespace dev;
 
 // ------------------------------------------------------------ table access
-// V_{(a,b),(c,d)} for valid pairs of the blocked layout; 0 across 2M blocks.
-__device__ __forceinline__ double v_pair(const int32_t *pidx, int n2, const int64_t *vbase,
-                                         const int32_t *vn, const double *v, int a, int b, int c,
-                                         int d) {
+// V_{(a,b),(c,d)} from the blocked layout; 0 across 2M blocks and for pairs
+// the layout does not store.  The three table reads are independent, so the
+// value costs two dependent memory accesses.
+__device__ __forceinline__ double v_pair(const int32_t *pidx, const int64_t *prow, int n2,
+                                         const double *v, int a, int b, int c, int d) {
   const int pk = pidx[a * n2 + b], qk = pidx[c * n2 + d];
-  const int blk = pk >> 16;
-  if (blk != (qk >> 16)) return 0.0;
-  return v[vbase[blk] + (int64_t)(pk & 0xffff) * vn[blk] + (qk & 0xffff)];
+  const int64_t rb = prow[a * n2 + b];
+  if ((pk | qk) < 0 || (pk >> 16) != (qk >> 16)) return 0.0;
+  return v[rb + (qk & 0xffff)];
 }
 
 // Antisymmetrised same-species element Vbar_{(a,x),(c,x)}: V stored for
 // ordered pairs, one sign flip per pair that has to be reordered.
-__device__ __forceinline__ double vbar_same(const int32_t *pidx, int n, const int64_t *vbase,
-                                            const int32_t *vn, const double *v, int a, int x,
-                                            int c) {
+__device__ __forceinline__ double vbar_same(const int32_t *pidx, const int64_t *prow, int n,
+                                            const double *v, int a, int x, int c) {
   int s = 1, p0 = a, p1 = x, q0 = c, q1 = x;
   if (a > x) { p0 = x; p1 = a; s = -s; }
   if (c > x) { q0 = x; q1 = c; s = -s; }
-  return s * v_pair(pidx, n, vbase, vn, v, p0, p1, q0, q1);
+  return s * v_pair(pidx, prow, n, v, p0, p1, q0, q1);
 }
 
 __device__ __forceinline__ double vab(const DevInter &it, int a, int b, int c, int d) {
-  return v_pair(it.pidxAB, it.nB, it.vbaseAB, it.vnAB, it.vAB, a, b, c, d);
+  return v_pair(it.pidxAB, it.prowAB, it.nB, it.vAB, a, b, c, d);
 }
 
 template <int W>
@@ -86,9 +87,9 @@ __global__ __launch_bounds__(256) void k_expand_basis(int64_t D, int nA, int nB,
 template <int W>
 __global__ __launch_bounds__(256) void k_config_energy(int n, const uint64_t *__restrict__ bits,
                                                        const double *__restrict__ eps,
-                                                       const int32_t *pidx, int norb,
-                                                       const int64_t *vbase, const int32_t *vn,
-                                                       const double *v, double *__restrict__ e) {
+                                                       const int32_t *pidx, const int64_t *prow,
+                                                       int norb, const double *v,
+                                                       double *__restrict__ e) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   uint64_t s[W];
@@ -103,7 +104,7 @@ __global__ __launch_bounds__(256) void k_config_energy(int n, const uint64_t *__
 #pragma unroll
     for (int w = 0; w < W; ++w) u[w] = t[w];
     for (int b = pop_lowest<W>(u); b >= 0; b = pop_lowest<W>(u))
-      acc += v_pair(pidx, norb, vbase, vn, v, a, b, a, b);
+      acc += v_pair(pidx, prow, norb, v, a, b, a, b);
   }
   e[k] = acc;
 }
@@ -173,12 +174,12 @@ __global__ __launch_bounds__(256) void k_tile_pass(TileArgs g) {
         const int s = sign_single<W>(ca, p1, h1);
         double sum = 0.0;
         for (int x = pop_lowest<W>(common); x >= 0; x = pop_lowest<W>(common))
-          sum += vbar_same(g.it.pidxA, g.it.nA, g.it.vbaseA, g.it.vnA, g.it.vA, p1, x, h1);
+          sum += vbar_same(g.it.pidxA, g.it.prowA, g.it.nA, g.it.vA, p1, x, h1);
         val = s * sum;
         info = 1 | (p1 << 2) | (h1 << 10) | ((s < 0) << 18) | (g.a_seg[j] << 19);
       } else {       // kA = 2
         const int s = sign_double<W>(ca, p1, p2, h1, h2);
-        val = s * v_pair(g.it.pidxA, g.it.nA, g.it.vbaseA, g.it.vnA, g.it.vA, p1, p2, h1, h2);
+        val = s * v_pair(g.it.pidxA, g.it.prowA, g.it.nA, g.it.vA, p1, p2, h1, h2);
         info = 2;
       }
       g.t_info[o] = info;
@@ -249,13 +250,13 @@ __global__ __launch_bounds__(256) void k_adj_pass(AdjArgs g) {
           if (in_ls) {
             double sum = 0.0;
             for (int y = pop_lowest<W>(common); y >= 0; y = pop_lowest<W>(common))
-              sum += vbar_same(g.it.pidxB, g.it.nB, g.it.vbaseB, g.it.vnB, g.it.vB, p1, y, h1);
+              sum += vbar_same(g.it.pidxB, g.it.prowB, g.it.nB, g.it.vB, p1, y, h1);
             val = s * sum;
           }
         } else {
           s = sign_double<W>(cb, p1, p2, h1, h2);
           info = 2;
-          val = s * v_pair(g.it.pidxB, g.it.nB, g.it.vbaseB, g.it.vnB, g.it.vB, p1, p2, h1, h2);
+          val = s * v_pair(g.it.pidxB, g.it.prowB, g.it.nB, g.it.vB, p1, p2, h1, h2);
         }
         if (in_ls) {
           const int64_t o = ls0 + c_ls + mask_rank(m_ls);
@@ -575,10 +576,10 @@ template <int W>
 static void energy_w(const cib_basis &b, const DevInter &it, double *eA, double *eB, hipStream_t s) {
   const Plan &p = b.plan;
   hipLaunchKernelGGL(k_config_energy<W>, dim3((p.nA() + 255) / 256), dim3(256), 0, s, p.nA(),
-                     b.a_bits.p, it.epsA, it.pidxA, it.nA, it.vbaseA, it.vnA, it.vA, eA);
+                     b.a_bits.p, it.epsA, it.pidxA, it.prowA, it.nA, it.vA, eA);
   if (it.nB > 0)
     hipLaunchKernelGGL(k_config_energy<W>, dim3((p.nB() + 255) / 256), dim3(256), 0, s, p.nB(),
-                       b.b_bits.p, it.epsB, it.pidxB, it.nB, it.vbaseB, it.vnB, it.vB, eB);
+                       b.b_bits.p, it.epsB, it.pidxB, it.prowB, it.nB, it.vB, eB);
   else
     CIB_HIP(hipMemsetAsync(eB, 0, sizeof(double) * p.nB(), s));
 }
@@ -600,15 +601,29 @@ void launch_dab(const DevInter &it, double *dab, hipStream_t s) {
   CIB_HIP(hipGetLastError());
 }
 
-static int64_t read_i64(const int64_t *dptr, hipStream_t s) {
-  int64_t h = 0;
-  CIB_HIP(hipMemcpyAsync(&h, dptr, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+// Copies up to 4 device int64 values (the totals of several scans) into one
+// small device array, so the host reads them with a single synchronisation.
+struct Gather4 {
+  const int64_t *src[4];
+};
+__global__ void k_gather_i64(Gather4 g, int n, int64_t *out) {
+  const int t = threadIdx.x;
+  if (t < n) out[t] = *g.src[t];
+}
+
+static void read_totals(std::initializer_list<const int64_t *> src, int64_t *scratch, int64_t *host,
+                        hipStream_t s) {
+  Gather4 g{};
+  int n = 0;
+  for (const int64_t *q : src) g.src[n++] = q;
+  hipLaunchKernelGGL(k_gather_i64, dim3(1), dim3(64), 0, s, g, n, scratch);
+  CIB_HIP(hipGetLastError());
+  CIB_HIP(hipMemcpyAsync(host, scratch, sizeof(int64_t) * n, hipMemcpyDeviceToHost, s));
   CIB_HIP(hipStreamSynchronize(s));
-  return h;
 }
 
 struct Events {
-  hipEvent_t e[10];
+  hipEvent_t e[9];
   Events() { for (auto &x : e) CIB_HIP(hipEventCreate(&x)); }
   ~Events() { for (auto &x : e) (void)hipEventDestroy(x); }
   double ms(int a, int b) {
@@ -618,6 +633,9 @@ struct Events {
   }
 };
 
+// The upper half (the product) and the strictly lower copy (read by the
+// SpMM) are built by the same passes side by side, so the host waits twice:
+// once for the sizes of the screens' lists, once for the two nonzero counts.
 template <int W>
 static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr, cib_dtype dt,
                     cib_matrix &H, hipStream_t s, const std::function<void(int64_t)> &before_fill) {
@@ -630,16 +648,22 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
   DBuf<double> eA(ctx, nA), eB(ctx, nB);
   launch_substate_energy(b, it, eA.p, eB.p, s);
 
-  // ---- counting passes of the two screens
-  DBuf<int32_t> tcnt(ctx, nA), ls_cnt(ctx, nB), l1_cnt(ctx, (size_t)nB * nseg);
-  DBuf<int64_t> t_ptr(ctx, nA + 1), ls_ptr(ctx, nB + 1), l1_seg(ctx, (size_t)nB * nseg + 1);
+  // ---- counting passes of the two screens (tiles of both triangles)
+  DBuf<int32_t> tcnt(ctx, nA), tlcnt(ctx, nA), ls_cnt(ctx, nB), l1_cnt(ctx, (size_t)nB * nseg);
+  DBuf<int64_t> t_ptr(ctx, nA + 1), tl_ptr(ctx, nA + 1), ls_ptr(ctx, nB + 1), l1_seg(ctx, (size_t)nB * nseg + 1);
   const int64_t nscr = std::max(scan_scratch(p.D), scan_scratch((int64_t)nB * nseg));
-  DBuf<int64_t> scratch(ctx, nscr);
+  DBuf<int64_t> scratch(ctx, nscr), totals(ctx, 4);
   TileArgs ta{};
   ta.nA = nA; ta.a_bits = b.a_bits.p; ta.a_m2 = b.a_m2.p; ta.a_len = b.a_len.p;
   ta.a_seg = b.a_seg.p; ta.a_off = b.a_off.p; ta.it = it; ta.tcnt = tcnt.p;
+  TileArgs tl = ta;
+  tl.tcnt = tlcnt.p;
   const unsigned tblk = (unsigned)((nA + 3) / 4);
-  { KTimer kt(ctx, K_TILE, s); hipLaunchKernelGGL((k_tile_pass<W, false, false>), dim3(tblk), dim3(256), 0, s, ta); }
+  {
+    KTimer kt(ctx, K_TILE, s);
+    hipLaunchKernelGGL((k_tile_pass<W, false, false>), dim3(tblk), dim3(256), 0, s, ta);
+    hipLaunchKernelGGL((k_tile_pass<W, false, true>), dim3(tblk), dim3(256), 0, s, tl);
+  }
   AdjArgs aa{};
   aa.nB = nB; aa.nseg = nseg; aa.b_bits = b.b_bits.p; aa.b_seg = b.b_seg.p;
   aa.bseg_start = b.bseg_start.p; aa.eB = eB.p; aa.it = it; aa.ls_cnt = ls_cnt.p; aa.l1_cnt = l1_cnt.p;
@@ -647,30 +671,38 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
   { KTimer kt(ctx, K_ADJ, s); hipLaunchKernelGGL((k_adj_pass<W, false>), dim3(ablk), dim3(256), 0, s, aa); }
   CIB_HIP(hipGetLastError());
   launch_scan(tcnt.p, nA, t_ptr.p, scratch.p, s);
+  launch_scan(tlcnt.p, nA, tl_ptr.p, scratch.p, s);
   launch_scan(ls_cnt.p, nB, ls_ptr.p, scratch.p, s);
   launch_scan(l1_cnt.p, (int64_t)nB * nseg, l1_seg.p, scratch.p, s);
   CIB_HIP(hipEventRecord(ev.e[1], s));
-  const int64_t n_tiles = read_i64(t_ptr.p + nA, s);
-  const int64_t n_ls = read_i64(ls_ptr.p + nB, s);
-  const int64_t n_l1 = read_i64(l1_seg.p + (int64_t)nB * nseg, s);
+  int64_t n4[4];
+  read_totals({t_ptr.p + nA, tl_ptr.p + nA, ls_ptr.p + nB, l1_seg.p + (int64_t)nB * nseg}, totals.p, n4, s);
+  const int64_t n_tiles = n4[0], n_lt = n4[1], n_ls = n4[2], n_l1 = n4[3];
 
   // ---- filling passes of the two screens
-  DBuf<int64_t> t_off(ctx, std::max<int64_t>(n_tiles, 1));
-  DBuf<int32_t> t_len(ctx, std::max<int64_t>(n_tiles, 1)), t_info(ctx, std::max<int64_t>(n_tiles, 1));
-  DBuf<double> t_val(ctx, std::max<int64_t>(n_tiles, 1));
+  auto at_least1 = [](int64_t n) { return (size_t)std::max<int64_t>(n, 1); };
+  DBuf<int64_t> t_off(ctx, at_least1(n_tiles)), tl_off(ctx, at_least1(n_lt));
+  DBuf<int32_t> t_len(ctx, at_least1(n_tiles)), t_info(ctx, at_least1(n_tiles));
+  DBuf<int32_t> tl_len(ctx, at_least1(n_lt)), tl_info(ctx, at_least1(n_lt));
+  DBuf<double> t_val(ctx, at_least1(n_tiles)), tl_val(ctx, at_least1(n_lt));
   DBuf<int32_t> ls_self(ctx, nB), ls_pos(ctx, n_ls), ls_info(ctx, n_ls), l1_pos(ctx, n_l1),
       l1_info(ctx, n_l1);
   DBuf<double> ls_val(ctx, n_ls);
   CIB_HIP(hipEventRecord(ev.e[2], s));
   ta.t_ptr = t_ptr.p; ta.t_off = t_off.p; ta.t_len = t_len.p; ta.t_info = t_info.p; ta.t_val = t_val.p;
-  { KTimer kt(ctx, K_TILE, s); hipLaunchKernelGGL((k_tile_pass<W, true, false>), dim3(tblk), dim3(256), 0, s, ta); }
+  tl.t_ptr = tl_ptr.p; tl.t_off = tl_off.p; tl.t_len = tl_len.p; tl.t_info = tl_info.p; tl.t_val = tl_val.p;
+  {
+    KTimer kt(ctx, K_TILE, s);
+    hipLaunchKernelGGL((k_tile_pass<W, true, false>), dim3(tblk), dim3(256), 0, s, ta);
+    hipLaunchKernelGGL((k_tile_pass<W, true, true>), dim3(tblk), dim3(256), 0, s, tl);
+  }
   aa.ls_ptr = ls_ptr.p; aa.l1_seg = l1_seg.p; aa.ls_self = ls_self.p; aa.ls_pos = ls_pos.p;
   aa.ls_info = ls_info.p; aa.l1_pos = l1_pos.p; aa.l1_info = l1_info.p; aa.ls_val = ls_val.p;
   { KTimer kt(ctx, K_ADJ, s); hipLaunchKernelGGL((k_adj_pass<W, true>), dim3(ablk), dim3(256), 0, s, aa); }
   CIB_HIP(hipGetLastError());
   CIB_HIP(hipEventRecord(ev.e[3], s));
 
-  // ---- per-row counting pass, offsets, filling pass
+  // ---- per-row counting passes (both triangles), offsets
   RowArgs ra{};
   ra.D = p.D; ra.nA = nA; ra.nB = nB; ra.nseg = nseg;
   ra.row_a = b.row_a.p; ra.row_p = b.row_p.p; ra.a_seg = b.a_seg.p; ra.a_len = b.a_len.p;
@@ -679,23 +711,48 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
   ra.t_val = t_val.p; ra.ls_ptr = ls_ptr.p; ra.l1_seg = l1_seg.p; ra.ls_self = ls_self.p;
   ra.ls_pos = ls_pos.p; ra.ls_info = ls_info.p; ra.l1_pos = l1_pos.p; ra.l1_info = l1_info.p;
   ra.ls_val = ls_val.p; ra.it = it;
-  DBuf<int32_t> rcnt(ctx, p.D);
+  DBuf<int32_t> rcnt(ctx, p.D), rlcnt(ctx, p.D);
   ra.rcnt = rcnt.p;
+  RowArgs rl = ra;
+  rl.t_ptr = tl_ptr.p; rl.t_off = tl_off.p; rl.t_len = tl_len.p; rl.t_info = tl_info.p; rl.t_val = tl_val.p;
+  rl.rcnt = rlcnt.p;
   const unsigned rblk = (unsigned)((p.D + 3) / 4);
-  { KTimer kt(ctx, K_ROW_COUNT, s); hipLaunchKernelGGL((k_row_pass<W, false, double, false>), dim3(rblk), dim3(256), 0, s, ra); }
+  {
+    KTimer kt(ctx, K_ROW_COUNT, s);
+    hipLaunchKernelGGL((k_row_pass<W, false, double, false>), dim3(rblk), dim3(256), 0, s, ra);
+    hipLaunchKernelGGL((k_row_pass<W, false, double, true>), dim3(rblk), dim3(256), 0, s, rl);
+  }
   CIB_HIP(hipGetLastError());
   CIB_HIP(hipEventRecord(ev.e[4], s));
   H.row_ptr.reset(ctx, p.D + 1);
-  { KTimer kt(ctx, K_SCAN, s); launch_scan(rcnt.p, p.D, H.row_ptr.p, scratch.p, s); }
+  H.lo_ptr.reset(ctx, p.D + 1);
+  {
+    KTimer kt(ctx, K_SCAN, s);
+    launch_scan(rcnt.p, p.D, H.row_ptr.p, scratch.p, s);
+    launch_scan(rlcnt.p, p.D, H.lo_ptr.p, scratch.p, s);
+  }
   CIB_HIP(hipEventRecord(ev.e[5], s));
-  const int64_t nnz = read_i64(H.row_ptr.p + p.D, s);
+  int64_t n2[2];
+  read_totals({H.row_ptr.p + p.D, H.lo_ptr.p + p.D}, totals.p, n2, s);
+  const int64_t nnz = n2[0], nlo = n2[1];
   if (before_fill) before_fill(nnz);
-  H.col.reset(ctx, std::max<int64_t>(nnz, 1));
-  if (dt == CIB_F64) H.val64.reset(ctx, std::max<int64_t>(nnz, 1));
-  else H.val32.reset(ctx, std::max<int64_t>(nnz, 1));
+
+  // ---- filling passes
+  H.col.reset(ctx, at_least1(nnz));
+  H.lo_col.reset(ctx, at_least1(nlo));
+  if (dt == CIB_F64) {
+    H.val64.reset(ctx, at_least1(nnz));
+    H.lo_val64.reset(ctx, at_least1(nlo));
+  } else {
+    H.val32.reset(ctx, at_least1(nnz));
+    H.lo_val32.reset(ctx, at_least1(nlo));
+  }
   ra.row_ptr = H.row_ptr.p;
   ra.col = H.col.p;
   ra.val = dt == CIB_F64 ? (void *)H.val64.p : (void *)H.val32.p;
+  rl.row_ptr = H.lo_ptr.p;
+  rl.col = H.lo_col.p;
+  rl.val = dt == CIB_F64 ? (void *)H.lo_val64.p : (void *)H.lo_val32.p;
   CIB_HIP(hipEventRecord(ev.e[6], s));
   {
     KTimer kt(ctx, K_ROW_FILL, s);
@@ -704,54 +761,28 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
     else
       hipLaunchKernelGGL((k_row_pass<W, true, float, false>), dim3(rblk), dim3(256), 0, s, ra);
   }
-  CIB_HIP(hipGetLastError());
   CIB_HIP(hipEventRecord(ev.e[7], s));
-
-  // ---- strictly lower triangle for the SpMM: the same passes with the lower
-  //      tile list (alpha' < alpha) and the diagonal-block entries before beta
   {
     KTimer kt(ctx, K_LOWER, s);
-    ta.tcnt = tcnt.p;
-    hipLaunchKernelGGL((k_tile_pass<W, false, true>), dim3(tblk), dim3(256), 0, s, ta);
-    DBuf<int64_t> tl_ptr(ctx, nA + 1);
-    launch_scan(tcnt.p, nA, tl_ptr.p, scratch.p, s);
-    const int64_t n_lt = read_i64(tl_ptr.p + nA, s);
-    DBuf<int64_t> tl_off(ctx, std::max<int64_t>(n_lt, 1));
-    DBuf<int32_t> tl_len(ctx, std::max<int64_t>(n_lt, 1)), tl_info(ctx, std::max<int64_t>(n_lt, 1));
-    DBuf<double> tl_val(ctx, std::max<int64_t>(n_lt, 1));
-    ta.t_ptr = tl_ptr.p; ta.t_off = tl_off.p; ta.t_len = tl_len.p; ta.t_info = tl_info.p; ta.t_val = tl_val.p;
-    hipLaunchKernelGGL((k_tile_pass<W, true, true>), dim3(tblk), dim3(256), 0, s, ta);
-    ra.t_ptr = tl_ptr.p; ra.t_off = tl_off.p; ra.t_len = tl_len.p; ra.t_info = tl_info.p; ra.t_val = tl_val.p;
-    hipLaunchKernelGGL((k_row_pass<W, false, double, true>), dim3(rblk), dim3(256), 0, s, ra);
-    H.lo_ptr.reset(ctx, p.D + 1);
-    launch_scan(rcnt.p, p.D, H.lo_ptr.p, scratch.p, s);
-    const int64_t nlo = read_i64(H.lo_ptr.p + p.D, s);
-    H.lo_col.reset(ctx, std::max<int64_t>(nlo, 1));
-    if (dt == CIB_F64) H.lo_val64.reset(ctx, std::max<int64_t>(nlo, 1));
-    else H.lo_val32.reset(ctx, std::max<int64_t>(nlo, 1));
-    ra.row_ptr = H.lo_ptr.p;
-    ra.col = H.lo_col.p;
-    ra.val = dt == CIB_F64 ? (void *)H.lo_val64.p : (void *)H.lo_val32.p;
-    CIB_HIP(hipEventRecord(ev.e[8], s));
     if (dt == CIB_F64)
-      hipLaunchKernelGGL((k_row_pass<W, true, double, true>), dim3(rblk), dim3(256), 0, s, ra);
+      hipLaunchKernelGGL((k_row_pass<W, true, double, true>), dim3(rblk), dim3(256), 0, s, rl);
     else
-      hipLaunchKernelGGL((k_row_pass<W, true, float, true>), dim3(rblk), dim3(256), 0, s, ra);
-    CIB_HIP(hipGetLastError());
-    CIB_HIP(hipEventRecord(ev.e[9], s));
-    CIB_HIP(hipStreamSynchronize(s));
-    H.nnz_lower = nlo;
+      hipLaunchKernelGGL((k_row_pass<W, true, float, true>), dim3(rblk), dim3(256), 0, s, rl);
   }
+  CIB_HIP(hipGetLastError());
+  CIB_HIP(hipEventRecord(ev.e[8], s));
+  CIB_HIP(hipStreamSynchronize(s));
 
   H.D = p.D;
   H.nnz = nnz;
+  H.nnz_lower = nlo;
   H.dtype = dt;
   H.stats.t_screen_s = ev.ms(0, 1) + ev.ms(2, 3);
   H.stats.t_count_s = ev.ms(3, 4);
   H.stats.t_scan_s = ev.ms(4, 5);
-  H.stats.t_fill_s = ev.ms(6, 7);
+  H.stats.t_fill_s = ev.ms(6, 8);
   H.stats.t_total_s = H.stats.t_screen_s + H.stats.t_count_s + H.stats.t_scan_s + H.stats.t_fill_s;
-  H.stats.t_lower_s = ev.ms(7, 9);
+  H.stats.t_lower_s = ev.ms(7, 8);
   H.stats.n_tiles = n_tiles;
   H.stats.n_adjacent = n_ls + n_l1;
 }

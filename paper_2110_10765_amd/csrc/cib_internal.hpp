@@ -159,15 +159,12 @@ void make_plan(const cib_basis_spec &s, Plan &p);
 struct DevInter {
   int nA = 0, nB = 0;
   const double *epsA = nullptr, *epsB = nullptr;
-  const int32_t *pidxA = nullptr, *vnA = nullptr;
-  const int64_t *vbaseA = nullptr;
-  const double *vA = nullptr;
-  const int32_t *pidxB = nullptr, *vnB = nullptr;
-  const int64_t *vbaseB = nullptr;
-  const double *vB = nullptr;
-  const int32_t *pidxAB = nullptr, *vnAB = nullptr;
-  const int64_t *vbaseAB = nullptr;
-  const double *vAB = nullptr;
+  // per ordered orbital pair p = a * n2 + b of each table: pidx[p] = 2M-block
+  // << 16 | index in the block (-1: not a stored pair), prow[p] = offset of
+  // the pair's row of its block in v
+  const int32_t *pidxA = nullptr, *pidxB = nullptr, *pidxAB = nullptr;
+  const int64_t *prowA = nullptr, *prowB = nullptr, *prowAB = nullptr;
+  const double *vA = nullptr, *vB = nullptr, *vAB = nullptr;
   const double *dab = nullptr;  // nA * nB: V^AB_{(x,y),(x,y)}
 };
 
@@ -188,8 +185,8 @@ struct cib_interaction {
   cib_ctx *ctx = nullptr;
   int nA = 0, nB = 0;
   cib::DBuf<double> epsA, epsB, vA, vB, vAB, dab;
-  cib::DBuf<int32_t> pidxA, vnA, pidxB, vnB, pidxAB, vnAB;
-  cib::DBuf<int64_t> vbaseA, vbaseB, vbaseAB;
+  cib::DBuf<int32_t> pidxA, pidxB, pidxAB;
+  cib::DBuf<int64_t> prowA, prowB, prowAB;
   cib::DevInter view() const;
 };
 

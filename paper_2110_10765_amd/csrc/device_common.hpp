@@ -19,6 +19,15 @@ __device__ __forceinline__ int mask_rank(uint64_t m) {
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 
+// Orders LDS accesses between the lanes of one wave: LDS instructions of a
+// wave execute in issue order, so only compiler code motion has to be
+// stopped (no workgroup barrier).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Inclusive and exclusive wave-wide prefix sums.
 template <typename T>
 __device__ __forceinline__ T wave_incl_scan(T v) {
@@ -70,24 +79,39 @@ __device__ __forceinline__ int count_below(const uint64_t *s, int k) {
   return c;
 }
 
-// index of the lowest set bit of (a & ~b) among W words, -1 if none; clears it in a
+// index of the lowest set bit among W words, -1 if none; clears it in a
+// (straight-line over the words, so they stay in registers)
 template <int W>
 __device__ __forceinline__ int pop_lowest(uint64_t *a) {
+  int res = -1;
+  bool found = false;
 #pragma unroll
   for (int w = 0; w < W; ++w) {
-    if (a[w]) {
-      int k = __builtin_ctzll(a[w]);
-      a[w] &= a[w] - 1;
-      return w * 64 + k;
-    }
+    const bool here = !found && a[w] != 0ull;
+    const int k = __builtin_ctzll(a[w] | (here ? 0ull : 1ull));
+    res = here ? w * 64 + k : res;
+    a[w] = here ? (a[w] & (a[w] - 1ull)) : a[w];
+    found = found || here;
   }
-  return -1;
+  return res;
 }
 
+// (every word is touched with a constant index, so the words stay in
+// registers: a variable index would put the array in scratch memory)
 template <int W>
-__device__ __forceinline__ void clear_bit(uint64_t *s, int k) { s[k >> 6] &= ~(1ull << (k & 63)); }
+__device__ __forceinline__ void clear_bit(uint64_t *s, int k) {
+  const int kw = k >> 6;
+  const uint64_t m = 1ull << (k & 63);
+#pragma unroll
+  for (int w = 0; w < W; ++w) s[w] &= w == kw ? ~m : ~0ull;
+}
 template <int W>
-__device__ __forceinline__ void set_bit(uint64_t *s, int k) { s[k >> 6] |= (1ull << (k & 63)); }
+__device__ __forceinline__ void set_bit(uint64_t *s, int k) {
+  const int kw = k >> 6;
+  const uint64_t m = 1ull << (k & 63);
+#pragma unroll
+  for (int w = 0; w < W; ++w) s[w] |= w == kw ? m : 0ull;
+}
 
 // Phase of a+_p a_h acting on ket bits s (h occupied, p empty): each operator
 // contributes (-1)^(occupied below its mode) in the state it acts on.

@@ -229,6 +229,15 @@ struct RRArgs {
   long long *clk;      // optional: wall-clock stamps of the phases (thread 0)
 };
 
+// 1 / q from the hardware reciprocal refined by one Newton step (within an
+// ulp or two of the quotient; a Sturm count only needs the pivots' signs to
+// be those of a slightly perturbed matrix).
+__device__ __forceinline__ double recip(double q) {
+  double r = __builtin_amdgcn_rcp(q);
+  const double e = fma(-q, r, 1.0);
+  return fma(r, e, r);
+}
+
 // Number of eigenvalues of the symmetric tridiagonal (d, e2 = e^2) below x
 // (Sturm sequence of the LDL^T pivots).
 __device__ __forceinline__ int sturm_count(const double *d, const double *e2, int n, double x,
@@ -236,8 +245,9 @@ __device__ __forceinline__ int sturm_count(const double *d, const double *e2, in
   double q = d[0] - x;
   if (fabs(q) < pivmin) q = -pivmin;
   int c = q <= 0.0;
+#pragma unroll 4
   for (int i = 1; i < n; ++i) {
-    q = d[i] - x - e2[i - 1] / q;
+    q = (d[i] - x) - e2[i - 1] * recip(q);
     if (fabs(q) < pivmin) q = -pivmin;
     c += q <= 0.0;
   }
@@ -255,7 +265,7 @@ __device__ __forceinline__ int sturm_count(const double *d, const double *e2, in
 // C_x = scale * Z^T y and C_p = C_x with the X rows zeroed (P = W C_W + P C_P).
 __global__ __launch_bounds__(256) void k_rayleigh_ritz(RRArgs g) {
   __shared__ double G[kNS][kLd], Hm[kNS][kLd], Z[kNS][kLd];
-  __shared__ double scale[kNS], dd[kNS], ee[kNS], e2[kNS], beta[kNS], vv[kNS], pp[kNS];
+  __shared__ double scale[kNS], dd[kNS], ee[kNS], e2[kNS], beta[kNS], vv[kNS], pp[kNS], dinv[kNS];
   __shared__ double theta[kMaxBlock];
   __shared__ int keep[kNS], kidx[kNS];
   __shared__ int rank_s, retry_s;
@@ -296,46 +306,58 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz(RRArgs g) {
   }
   __syncthreads();
   if (g.clk && tid == 0) g.clk[2] = wall_clock64();
-  // 3. right-looking Cholesky with dropping
-  for (int k = 0; k < ns; ++k) {
-    const double piv = G[k][k];
-    const bool kk = scale[k] > 0.0 && piv > drop_tol;   // every thread decides the same
-    const double lkk = kk ? sqrt(piv) : 0.0;
-    const int m = ns - k - 1;
-    // column k and the trailing update in one phase: element (i, j) of the
-    // trailing block uses the old G[i][k], G[j][k], which nobody writes here
-    if (kk)
-      for (int e = tid; e < m * m; e += nt) {
-        const int i = k + 1 + e / m, j = k + 1 + e % m;
-        if (j <= i) G[i][j] -= G[i][k] * G[j][k] / piv;
+  // 3. right-looking Cholesky with dropping, on wave 0 with one lane per row
+  //    (the steps are sequential; LDS traffic between lanes needs no barrier)
+  if (tid < kWave) {
+    const int i = tid;
+    for (int k = 0; k < ns; ++k) {
+      const double piv = G[k][k];
+      const bool kk = scale[k] > 0.0 && piv > drop_tol;   // every lane decides the same
+      const double lkk = kk ? sqrt(piv) : 0.0;
+      const double ilkk = kk ? 1.0 / lkk : 0.0;
+      double lik = 0.0;
+      if (i > k && i < ns) {
+        lik = G[i][k] * ilkk;
+        G[i][k] = lik;
       }
-    __syncthreads();
-    for (int i = k + 1 + tid; i < ns; i += nt) G[i][k] = kk ? G[i][k] / lkk : 0.0;
-    if (tid == 0) { G[k][k] = lkk; keep[k] = kk; }
-    __syncthreads();
-  }
-  if (tid == 0) {
-    int r = 0;
-    for (int k = 0; k < ns; ++k) if (keep[k]) kidx[r++] = k;
-    rank_s = r;
+      if (i == k) {
+        G[k][k] = lkk;
+        keep[k] = kk;
+      }
+      wave_lds_sync();
+      if (kk && i > k && i < ns)
+        for (int j = k + 1; j <= i; ++j) G[i][j] -= lik * G[j][k];
+      wave_lds_sync();
+    }
+    const bool kp = i < ns && keep[i];
+    const uint64_t km = __ballot(kp);
+    if (kp) kidx[mask_rank(km)] = i;
+    if (i == 0) rank_s = (int)__popcll(km);
+    wave_lds_sync();
+    // 4a. Z = L^-1 on the kept columns (compressed r x r, lower
+    //     triangular): lane j solves for column j by forward substitution
+    const int rr = rank_s;
+    if (i < rr) dinv[i] = 1.0 / G[kidx[i]][kidx[i]];
+    wave_lds_sync();
+    if (i < rr) {
+      for (int a = 0; a < i; ++a) Z[a][i] = 0.0;
+      Z[i][i] = dinv[i];
+      for (int a = i + 1; a < rr; ++a) {
+        const int ka = kidx[a];
+        double s0 = 0.0, s1 = 0.0;
+        int q = i;
+        for (; q + 1 < a; q += 2) {
+          s0 += G[ka][kidx[q]] * Z[q][i];
+          s1 += G[ka][kidx[q + 1]] * Z[q + 1][i];
+        }
+        if (q < a) s0 += G[ka][kidx[q]] * Z[q][i];
+        Z[a][i] = -(s0 + s1) * dinv[a];
+      }
+    }
   }
   __syncthreads();
   r = rank_s;
   if (g.clk && tid == 0) g.clk[3] = wall_clock64();
-  // 4a. Z = L^-1 (compressed r x r, lower triangular), row by row
-  for (int a = 0; a < r; ++a) {
-    const int ka = kidx[a];
-    for (int j = tid; j < r; j += nt) {
-      double v = 0.0;
-      if (j <= a) {
-        double s = a == j ? 1.0 : 0.0;
-        for (int q = j; q < a; ++q) s -= G[ka][kidx[q]] * Z[q][j];
-        v = s / G[ka][ka];
-      }
-      Z[a][j] = v;
-    }
-    __syncthreads();
-  }
   if (g.clk && tid == 0) g.clk[4] = wall_clock64();
   // 4b. T1 = Hm_c Z^T into G (L is no longer needed), then M = Z T1 into Hm
   for (int e = tid; e < r * r; e += nt) {
@@ -363,39 +385,50 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz(RRArgs g) {
   }
   __syncthreads();
   if (g.clk && tid == 0) g.clk[5] = wall_clock64();
-  // 5. Householder tridiagonalisation of M (r x r in Hm); the reflector of
-  //    step k is kept in column k below the subdiagonal, its scale in beta[k]
-  for (int k = 0; k + 2 < r; ++k) {
-    const int m = r - k - 1;
-    double sigma = 0.0;
-    for (int i = k + 1; i < r; ++i) sigma += Hm[i][k] * Hm[i][k];
-    const double x0 = Hm[k + 1][k];
-    const double tail = sigma - x0 * x0;
-    const bool refl = tail > 1e-300;
-    const double alpha = refl ? -copysign(sqrt(sigma), x0) : x0;
-    const double bk = refl ? 2.0 / (tail + (x0 - alpha) * (x0 - alpha)) : 0.0;
-    for (int i = k + 1 + tid; i < r; i += nt) {
-      double acc = 0.0;
-      for (int j = k + 1; j < r; ++j) {
-        const double vj = j == k + 1 ? x0 - alpha : Hm[j][k];
-        acc += Hm[i][j] * vj;
+  // 5. Householder tridiagonalisation of M (r x r in Hm) on wave 0, one lane
+  //    per row; the reflector of step k is kept in column k below the
+  //    subdiagonal, its scale in beta[k]
+  if (tid < kWave) {
+    const int i = tid;
+    const bool row = i < r;
+    for (int k = 0; k + 2 < r; ++k) {
+      const bool act = row && i > k;
+      const double xi = act ? Hm[i][k] : 0.0;
+      const double sigma = wave_sum(xi * xi);
+      const double x0 = Hm[k + 1][k];
+      const double tail = sigma - x0 * x0;
+      const bool refl = tail > 1e-300;
+      const double alpha = refl ? -copysign(sqrt(sigma), x0) : x0;
+      const double bk = refl ? 2.0 / (tail + (x0 - alpha) * (x0 - alpha)) : 0.0;
+      const double vi = i == k + 1 ? x0 - alpha : xi;
+      if (i < kNS) vv[i] = vi;
+      wave_lds_sync();
+      double acc0 = 0.0, acc1 = 0.0;
+      if (act) {
+        int j = k + 1;
+        for (; j + 1 < r; j += 2) {
+          acc0 += Hm[i][j] * vv[j];
+          acc1 += Hm[i][j + 1] * vv[j + 1];
+        }
+        if (j < r) acc0 += Hm[i][j] * vv[j];
       }
-      pp[i] = bk * acc;
-      vv[i] = i == k + 1 ? x0 - alpha : Hm[i][k];
+      const double pi = bk * (acc0 + acc1);
+      const double K = 0.5 * bk * wave_sum(vi * pi);
+      const double wi = pi - K * vi;
+      if (i < kNS) pp[i] = wi;
+      wave_lds_sync();
+      if (act) {
+        for (int j = k + 1; j < r; ++j) Hm[i][j] -= vi * pp[j] + wi * vv[j];
+        Hm[i][k] = vi;
+      }
+      if (i == 0) {
+        beta[k] = bk;
+        ee[k] = alpha;
+      }
+      wave_lds_sync();
     }
-    __syncthreads();
-    double K = 0.0;
-    for (int i = k + 1; i < r; ++i) K += vv[i] * pp[i];
-    K *= 0.5 * bk;
-    for (int e = tid; e < m * m; e += nt) {
-      const int i = k + 1 + e / m, j = k + 1 + e % m;
-      const double wi = pp[i] - K * vv[i], wj = pp[j] - K * vv[j];
-      Hm[i][j] -= vv[i] * wj + wi * vv[j];
-    }
-    for (int i = k + 1 + tid; i < r; i += nt) Hm[i][k] = vv[i];
-    if (tid == 0) { beta[k] = bk; ee[k] = alpha; }
-    __syncthreads();
   }
+  __syncthreads();
   for (int i = tid; i < r; i += nt) {
     dd[i] = Hm[i][i];
     if (i == r - 2) ee[i] = Hm[r - 1][r - 2];
@@ -404,7 +437,7 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz(RRArgs g) {
   for (int i = tid; i + 1 < r; i += nt) e2[i] = ee[i] * ee[i];
   __syncthreads();
   if (g.clk && tid == 0) g.clk[6] = wall_clock64();
-  // 6. lowest nb eigenvalues: 16 threads per eigenvalue, 16 rounds of
+  // 6. lowest nb eigenvalues: 16 threads per eigenvalue, 14 rounds of
   //    17-way multisection of the Gershgorin interval
   nb = b < r ? b : r;
   double gl = 1e300, gu = -1e300, emax = 0.0;
@@ -421,7 +454,7 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz(RRArgs g) {
   {
     const int grp = tid >> 4, t = tid & 15;
     double lo = gl, hi = gu;
-    for (int round = 0; round < 16; ++round) {
+    for (int round = 0; round < 14; ++round) {
       const double x = lo + (t + 1) * (hi - lo) * (1.0 / 17.0);
       const bool above = grp < nb ? sturm_count(dd, e2, r, x, pivmin) > grp : true;
       const uint64_t m = __ballot(above);

@@ -15,8 +15,8 @@ DevInter cib_interaction_view(const cib_interaction &t);
 // Pair layout of the blocked tables: blocks by 2M_pair ascending, pairs
 // lexicographic inside a block.  pidx[a * n2 + b] = block << 16 | index.
 struct PairLayout {
-  std::vector<int32_t> pidx, vn;
-  std::vector<int64_t> vbase;
+  std::vector<int32_t> pidx;   // per ordered pair: block << 16 | index, -1 if not stored
+  std::vector<int64_t> prow;   // per ordered pair: offset of its row in the blocked table
   int64_t total = 0;
 };
 
@@ -25,20 +25,22 @@ static PairLayout pair_layout(const Orbs &o1, const Orbs &o2, bool same) {
   for (int a = 0; a < o1.n_orb; ++a)
     for (int b = same ? a + 1 : 0; b < o2.n_orb; ++b) blocks[o1.twom[a] + o2.twom[b]].push_back({a, b});
   PairLayout L;
-  L.pidx.assign((size_t)std::max(1, o1.n_orb * o2.n_orb), -1);
+  const size_t npair = (size_t)std::max(1, o1.n_orb * o2.n_orb);
+  L.pidx.assign(npair, -1);
+  L.prow.assign(npair, 0);
   int blk = 0;
   for (auto &kv : blocks) {
     auto &prs = kv.second;
     std::sort(prs.begin(), prs.end());
     CIB_REQUIRE(prs.size() < 65536, CIB_E_OVERFLOW, "pair block too large");
-    for (size_t i = 0; i < prs.size(); ++i)
-      L.pidx[(size_t)prs[i].first * o2.n_orb + prs[i].second] = (blk << 16) | (int32_t)i;
-    L.vbase.push_back(L.total);
-    L.vn.push_back((int32_t)prs.size());
+    for (size_t i = 0; i < prs.size(); ++i) {
+      const size_t q = (size_t)prs[i].first * o2.n_orb + prs[i].second;
+      L.pidx[q] = (blk << 16) | (int32_t)i;
+      L.prow[q] = L.total + (int64_t)i * (int64_t)prs.size();
+    }
     L.total += (int64_t)prs.size() * (int64_t)prs.size();
     ++blk;
   }
-  if (L.vbase.empty()) { L.vbase.push_back(0); L.vn.push_back(0); }
   return L;
 }
 
@@ -98,28 +100,26 @@ cib_interaction *upload_interaction(cib_ctx *ctx, const cib_basis &b, const cib_
   it->ctx = ctx;
   it->nA = p.oA.n_orb;
   it->nB = p.ns == 2 ? p.oB.n_orb : 0;
-  auto up_layout = [&](const PairLayout &L, const double *v, DBuf<int32_t> &pidx, DBuf<int32_t> &vn,
-                       DBuf<int64_t> &vbase, DBuf<double> &dv) {
+  auto up_layout = [&](const PairLayout &L, const double *v, DBuf<int32_t> &pidx, DBuf<int64_t> &prow,
+                       DBuf<double> &dv) {
     pidx.reset(ctx, L.pidx.size());
     pidx.upload(L.pidx.data(), L.pidx.size(), s);
-    vn.reset(ctx, L.vn.size());
-    vn.upload(L.vn.data(), L.vn.size(), s);
-    vbase.reset(ctx, L.vbase.size());
-    vbase.upload(L.vbase.data(), L.vbase.size(), s);
+    prow.reset(ctx, L.prow.size());
+    prow.upload(L.prow.data(), L.prow.size(), s);
     dv.reset(ctx, std::max<int64_t>(L.total, 1));
     dv.upload(v, (size_t)L.total, s);
   };
   it->epsA.reset(ctx, it->nA);
   it->epsA.upload(t.eps[0], it->nA, s);
   PairLayout LA = pair_layout(p.oA, p.oA, true);
-  up_layout(LA, t.v_same[0], it->pidxA, it->vnA, it->vbaseA, it->vA);
+  up_layout(LA, t.v_same[0], it->pidxA, it->prowA, it->vA);
   if (p.ns == 2) {
     it->epsB.reset(ctx, it->nB);
     it->epsB.upload(t.eps[1], it->nB, s);
     PairLayout LB = pair_layout(p.oB, p.oB, true);
-    up_layout(LB, t.v_same[1], it->pidxB, it->vnB, it->vbaseB, it->vB);
+    up_layout(LB, t.v_same[1], it->pidxB, it->prowB, it->vB);
     PairLayout LAB = pair_layout(p.oA, p.oB, false);
-    up_layout(LAB, t.v_ab, it->pidxAB, it->vnAB, it->vbaseAB, it->vAB);
+    up_layout(LAB, t.v_ab, it->pidxAB, it->prowAB, it->vAB);
     it->dab.reset(ctx, (size_t)it->nA * it->nB);
     launch_dab(it->view(), it->dab.p, s);
   }
@@ -175,9 +175,9 @@ cib::DevInter cib_interaction::view() const {
   cib::DevInter v;
   v.nA = nA; v.nB = nB;
   v.epsA = epsA.p; v.epsB = epsB.p;
-  v.pidxA = pidxA.p; v.vnA = vnA.p; v.vbaseA = vbaseA.p; v.vA = vA.p;
-  v.pidxB = pidxB.p; v.vnB = vnB.p; v.vbaseB = vbaseB.p; v.vB = vB.p;
-  v.pidxAB = pidxAB.p; v.vnAB = vnAB.p; v.vbaseAB = vbaseAB.p; v.vAB = vAB.p;
+  v.pidxA = pidxA.p; v.prowA = prowA.p; v.vA = vA.p;
+  v.pidxB = pidxB.p; v.prowB = prowB.p; v.vB = vB.p;
+  v.pidxAB = pidxAB.p; v.prowAB = prowAB.p; v.vAB = vAB.p;
   v.dab = dab.p;
   return v;
 }

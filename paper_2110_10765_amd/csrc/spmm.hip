@@ -1,15 +1,12 @@
 // Symmetric SpMM Y = H X (Sec. 2: sparse matrix-matrix products of the
-// eigensolver; Fig. 2 line 5, "FMA of H_ij with the i-th row and j-th column
-// vector elements").  Row i gathers its upper half (the half-stored CSR,
-// j >= i) and its strictly lower half (the transposed copy the build keeps),
-// so every output row is written once by one wave: no atomics, no zeroing,
-// and a fixed summation order (deterministic).
+// eigensolver; Fig. 2, the FMA of H_ij with the vector elements of row j).
+// Row i gathers its upper half (the half-stored CSR, j >= i) and its
+// strictly lower half (the transposed copy the build keeps), so every output
+// row is produced by gathers only: no atomics, no zeroing, and a fixed
+// summation order (deterministic).
 //
 // Layout: X, Y row-major (D x nvec, leading dimensions ldx / ldy), so one
-// vector row is one contiguous run of 8 or 16 values.  A wave handles one
-// row; its 64 lanes are E = 64 / B entry slots times B vector columns, so a
-// gather of x_j is one contiguous segment, and each lane keeps U entries in
-// flight.
+// vector row is one contiguous run of nvec values.
 #include <type_traits>
 
 #include "cib_internal.hpp"
@@ -18,6 +15,9 @@
 namespace cib {
 using namespace dev;
 
+// ------------------------------------------------------------ general path
+// Any nvec, any alignment: a wave per row, 64 / B entry slots times B vector
+// columns, so a gather of x_j is one contiguous segment.
 template <typename T, int B, int U>
 __device__ __forceinline__ T row_dot(int64_t k0, int64_t k1, const int32_t *__restrict__ col,
                                      const T *__restrict__ val, const T *__restrict__ X, int64_t ldx,
@@ -69,59 +69,134 @@ __global__ __launch_bounds__(256) void k_spmm_sym(int64_t D, const int64_t *__re
   if (e == 0 && cv) Y[i * ldy + vc] = acc;
 }
 
-// Wide variant for nvec == NV (8 or 16) with 16-byte aligned rows: one lane
-// per stored entry, so col/val reads are coalesced across the wave, and the
-// x_j row is fetched with 16-byte vector loads into NV register accumulators;
-// the row total is a wave reduction per vector column.
-template <typename T, int NV>
-__global__ __launch_bounds__(256) void k_spmm_wide(int64_t D, const int64_t *__restrict__ rp,
-                                                   const int32_t *__restrict__ col,
-                                                   const T *__restrict__ val,
-                                                   const int64_t *__restrict__ lrp,
-                                                   const int32_t *__restrict__ lcol,
-                                                   const T *__restrict__ lval,
-                                                   const T *__restrict__ X, int64_t ldx, T *__restrict__ Y,
-                                                   int64_t ldy) {
-  constexpr int PER16 = 16 / sizeof(T);           // values per 16-byte load
-  using V = typename std::conditional<sizeof(T) == 8, double2, float4>::type;
-  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
-  const int64_t i = blk * (blockDim.x / kWave) + (threadIdx.x >> 6);
-  if (i >= D) return;
-  const int lane = lane_id();
-  T acc[NV];
+// ------------------------------------------------------------ vector path
+// Butterfly reduce-scatter of N accumulators over the lane bits M, M/2, ...,
+// G (the entry-slot bits): each exchange halves the values a lane keeps, so
+// N values cost N - 1 + (remaining steps) shuffles instead of N per step.
+template <typename T, int N, int M, int G>
+struct Bfly {
+  __device__ __forceinline__ static void run(T *acc, int lane) {
+    if constexpr (M >= G) {
+      if constexpr (N > 1) {
+        const bool up = lane & M;
 #pragma unroll
-  for (int v = 0; v < NV; ++v) acc[v] = T(0);
-  auto part = [&](int64_t k0, int64_t k1, const int32_t *__restrict__ cc, const T *__restrict__ vv) {
-    for (int64_t k = k0 + lane; k < k1; k += kWave) {
-      const int32_t j = cc[k];
-      const T h = vv[k];
-      const V *xr = reinterpret_cast<const V *>(X + (int64_t)j * ldx);
-#pragma unroll
-      for (int q = 0; q < NV / PER16; ++q) {
-        const V t = xr[q];
-        if constexpr (sizeof(T) == 8) {
-          acc[2 * q] += h * t.x;
-          acc[2 * q + 1] += h * t.y;
-        } else {
-          acc[4 * q] += h * t.x;
-          acc[4 * q + 1] += h * t.y;
-          acc[4 * q + 2] += h * t.z;
-          acc[4 * q + 3] += h * t.w;
+        for (int k = 0; k < N / 2; ++k) {
+          const T keep = up ? acc[N / 2 + k] : acc[k];
+          const T send = up ? acc[k] : acc[N / 2 + k];
+          acc[k] = keep + __shfl_xor(send, M, kWave);
         }
+        Bfly<T, N / 2, M / 2, G>::run(acc, lane);
+      } else {
+        acc[0] += __shfl_xor(acc[0], M, kWave);
+        Bfly<T, 1, M / 2, G>::run(acc, lane);
       }
     }
+  }
+};
+
+struct VecArgs {
+  int64_t D;
+  const int64_t *rp;
+  const int32_t *col;
+  const void *val;
+  const int64_t *lrp;
+  const int32_t *lcol;
+  const void *lval;
+  const void *X;
+  int64_t ldx;
+  void *Y;
+  int64_t ldy;
+};
+
+// nvec == NV (8 or 16) with 16-byte aligned rows of X.  One wave per row.
+// The wave reads 64 consecutive entries of the row (lower part, then upper
+// part) with one coalesced load of col and of val; the entries are handed to groups of G lanes by
+// lane permutes, and each group gathers the NV values of x_j with one
+// 16-byte load per lane.  The col/val loads of the next step are issued
+// behind the gathers of the current one, so a step costs one memory round
+// trip.  Columns are reduced over the entry slots at the end with a
+// butterfly.
+//
+// The limit here is the number of L1 misses in flight per CU, not HBM:
+// every entry gathers a row of X that is rarely in L1.  Splitting the
+// columns into chunks, one per XCD, so that X stays in L2, and streaming
+// col/val with non-temporal loads were both measured slower.
+template <typename T, int NV>
+__global__ __launch_bounds__(256) void k_spmm_vec(const VecArgs a) {
+  constexpr int PER16 = 16 / sizeof(T);  // values per 16-byte load
+  constexpr int G = NV / PER16;          // lanes per entry
+  constexpr int E = kWave / G;           // entries per gather instruction
+  using V = typename std::conditional<sizeof(T) == 8, double2, float4>::type;
+  const int32_t *__restrict__ col = a.col;
+  const int32_t *__restrict__ lcol = a.lcol;
+  const T *__restrict__ val = static_cast<const T *>(a.val);
+  const T *__restrict__ lval = static_cast<const T *>(a.lval);
+  const T *__restrict__ X = static_cast<const T *>(a.X);
+  const int64_t i = xcd_block(blockIdx.x, gridDim.x) * (blockDim.x / kWave) + (threadIdx.x >> 6);
+  if (i >= a.D) return;
+  const int lane = lane_id();
+  const int e = lane / G, g = lane % G;
+  const int64_t lb = a.lrp[i], ub = a.rp[i];
+  const int nl = (int)(a.lrp[i + 1] - lb);
+  const int n = nl + (int)(a.rp[i + 1] - ub);
+  // Loads are issued unconditionally (out-of-range lanes read a valid
+  // address and discard it): loads under branches would make the compiler
+  // wait for every outstanding load, the prefetch included.
+  auto fetch = [&](int p, int32_t &j, T &h) {
+    const bool ok = p < n;
+    const bool lo = p < nl;
+    const int64_t k = !ok ? ub : lo ? lb + p : ub + (p - nl);
+    const int32_t *cp = ok && lo ? lcol : col;
+    const T *vp = ok && lo ? lval : val;
+    const int32_t jj = cp[k];
+    const T hh = vp[k];
+    j = ok ? jj : -1;
+    h = ok ? hh : T(0);
   };
-  part(lrp[i], lrp[i + 1], lcol, lval);
-  part(rp[i], rp[i + 1], col, val);
-  // reduce each column over the wave; lane v ends with column v's total
+  T acc[PER16];
 #pragma unroll
-  for (int v = 0; v < NV; ++v) acc[v] = wave_sum(acc[v]);
-  T mine = acc[0];
+  for (int t = 0; t < PER16; ++t) acc[t] = T(0);
+  int32_t jn;
+  T hn;
+  fetch(lane, jn, hn);
+  for (int p0 = 0; p0 < n; p0 += kWave) {
+    const int32_t jc = jn;
+    const T hc = hn;
+    V x[G];
 #pragma unroll
-  for (int v = 1; v < NV; ++v) mine = lane == v ? acc[v] : mine;
-  if (lane < NV) Y[i * ldy + lane] = mine;
+    for (int u = 0; u < G; ++u) {
+      const int32_t j = __shfl(jc, u * E + e, kWave);
+      x[u] = reinterpret_cast<const V *>(X + (int64_t)(j < 0 ? i : j) * a.ldx)[g];
+    }
+    fetch(p0 + kWave + lane, jn, hn);
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      // lane permutes first, with every lane active: a permute reading a
+      // lane that has branched off returns garbage
+      const T h = __shfl(hc, u * E + e, kWave);
+      const bool used = __shfl(jc, u * E + e, kWave) >= 0;
+      // an unused slot has j < 0 and h == 0; skip it so a non-finite x_i
+      // cannot leak in
+      if (!used) continue;
+      if constexpr (sizeof(T) == 8) {
+        acc[0] += h * x[u].x;
+        acc[1] += h * x[u].y;
+      } else {
+        acc[0] += h * x[u].x;
+        acc[1] += h * x[u].y;
+        acc[2] += h * x[u].z;
+        acc[3] += h * x[u].w;
+      }
+    }
+  }
+  Bfly<T, PER16, kWave / 2, G>::run(acc, lane);
+  // after the exchanges, lane bits above log2(64 / PER16) select the column
+  constexpr int SEL = kWave / PER16;
+  T *Y = static_cast<T *>(a.Y);
+  if ((lane & (SEL - 1) & ~(G - 1)) == 0) Y[i * a.ldy + g * PER16 + ((lane / SEL) & (PER16 - 1))] = acc[0];
 }
 
+// ------------------------------------------------------------ host side
 template <typename T>
 static void spmm_t(const cib_matrix &H, const T *X, int64_t ldx, T *Y, int64_t ldy, int nvec,
                    hipStream_t s) {
@@ -131,13 +206,10 @@ static void spmm_t(const cib_matrix &H, const T *X, int64_t ldx, T *Y, int64_t l
   const unsigned nblk = (unsigned)((D + 3) / 4);
   const bool aligned = ((uintptr_t)X % 16 == 0) && ((ldx * sizeof(T)) % 16 == 0);
   if (aligned && (nvec == 8 || nvec == 16)) {
+    const VecArgs a{D, H.row_ptr.p, H.col.p, val, H.lo_ptr.p, H.lo_col.p, lval, X, ldx, Y, ldy};
     KTimer kt(H.ctx, K_SPMM, s);
-    if (nvec == 8)
-      hipLaunchKernelGGL((k_spmm_wide<T, 8>), dim3(nblk), dim3(256), 0, s, D, H.row_ptr.p, H.col.p, val,
-                         H.lo_ptr.p, H.lo_col.p, lval, X, ldx, Y, ldy);
-    else
-      hipLaunchKernelGGL((k_spmm_wide<T, 16>), dim3(nblk), dim3(256), 0, s, D, H.row_ptr.p, H.col.p, val,
-                         H.lo_ptr.p, H.lo_col.p, lval, X, ldx, Y, ldy);
+    if (nvec == 8) hipLaunchKernelGGL((k_spmm_vec<T, 8>), dim3(nblk), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_spmm_vec<T, 16>), dim3(nblk), dim3(256), 0, s, a);
     CIB_HIP(hipGetLastError());
     return;
   }

@@ -1,5 +1,12 @@
 """GPU parity of the symmetric SpMM Y = H X (cib_apply_H) against the oracle.
 
+Small workloads are compared in full; at the full sizes (D = 198,912 and
+173,624) sampled output rows are compared with rows of H that the oracle
+computes one by one (the image H|Phi_i> by operator application, a column
+of H and by symmetry its row), in the layouts the eigensolver uses: float64
+X as the middle third of a row-interleaved [X | W | P] block, float32 X
+dense.
+
 Bar (Higham's bound for a dot product of length k): |Y - Y_ref| <= gamma_k
 |H||X| elementwise with gamma_k = k u / (1 - k u), k = 2 * (max stored row
 length) + 2, u = 2^-53 (float64) or 2^-24 (float32).  The float32 reference
@@ -11,7 +18,7 @@ import pytest
 
 import cigen
 import oracle as O
-from tests.common import EPS32, EPS64, gpu_ctx, oracle_csr, oracle_tables
+from tests.common import EPS32, EPS64, gpu_ctx, oracle_basis, oracle_csr, oracle_tables
 
 pytestmark = pytest.mark.gpu
 
@@ -66,3 +73,49 @@ def test_apply_H_rejects_bad_shapes():
     assert lib.cib_apply_H(ctx.h, H.h, X.data_ptr(), 2, X.data_ptr(), 4, 4) == cib.CIB_E_INVALID
     assert lib.cib_apply_H(ctx.h, H.h, X.data_ptr(), 4, X.data_ptr(), 4, 65) == cib.CIB_E_INVALID
     assert lib.cib_apply_H(ctx.h, H.h, X.data_ptr(), 4, X.data_ptr(), 4, 0) == cib.CIB_E_INVALID
+
+
+@pytest.mark.parametrize("name,nvec", [("ab_n3_3p3_cut6", 16), ("ab_n5_4p4_cut4", 8)])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_apply_H_full_size_sampled_rows(name, nvec, dtype):
+    """Full size, the solver's layouts; 64 sampled rows against the oracle.
+    The bound adds two rounding units per term for the matrix values
+    themselves (the device's float64 values agree with the oracle's to a
+    few ulps, and float32 values are those rounded once more)."""
+    import torch
+    from paper_2110_10765_amd import cib
+    w = cigen.WORKLOADS[name]
+    ctx = gpu_ctx()
+    print("case", name, dtype, nvec, flush=True)
+    b = cib.build_basis(ctx, w.spec)
+    tables = oracle_tables(w.spec, w.seed)
+    H = cib.build_H(ctx, b, tables, dtype)
+    D = b.dim
+    rng = np.random.default_rng(11)
+    X = rng.standard_normal((D, nvec))
+    if dtype == "f64":
+        S = torch.full((D, 3 * nvec), 5.0, dtype=torch.float64, device="cuda:0")
+        S[:, nvec:2 * nvec] = torch.tensor(X, dtype=torch.float64, device="cuda:0")
+        Yfull = torch.full((D, 3 * nvec), 7.0, dtype=torch.float64, device="cuda:0")
+        Xd, Yd = S[:, nvec:2 * nvec], Yfull[:, nvec:2 * nvec]
+    else:
+        X = X.astype(np.float32).astype(np.float64)
+        Xd = torch.tensor(X, dtype=torch.float32, device="cuda:0")
+        Yfull = None
+        Yd = torch.empty_like(Xd)
+    cib.apply_H(ctx, H, Xd, Yd)
+    torch.cuda.synchronize()
+    Y = Yd.cpu().numpy().astype(np.float64)
+    if Yfull is not None:
+        rest = torch.cat([Yfull[:, :nvec], Yfull[:, 2 * nvec:]], dim=1)
+        assert torch.all(rest == 7.0)
+    sample = np.unique(np.concatenate([[0, 1, D // 2, D - 2, D - 1], rng.integers(0, D, 59)]))
+    ob = oracle_basis(w.spec)
+    ptr, rows, vals = O.apply_columns(ob, O.Interaction(ob, tables), sample)
+    u = EPS64 if dtype == "f64" else EPS32
+    for c, i in enumerate(sample):
+        rr, vv = rows[ptr[c]:ptr[c + 1]], vals[ptr[c]:ptr[c + 1]]
+        yref = vv @ X[rr]
+        absHX = np.abs(vv) @ np.abs(X[rr])
+        k = len(rr) + 2
+        assert np.all(np.abs(Y[i] - yref) <= _gamma(k, u) * absHX + 1e-300), (i, Y[i], yref)
