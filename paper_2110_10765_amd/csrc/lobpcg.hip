@@ -114,21 +114,27 @@ __global__ __launch_bounds__(256) void k_copy_cols(int64_t D, int n, const doubl
 // ------------------------------------------------------------ Gram matrices
 // partial[blk] = sum over the block's rows of S_i^T [S_i, HS_i] for the first
 // ns columns: an ns x 2ns matrix (left half S^T S, right half S^T HS).  Rows
-// are staged through LDS in chunks; each thread keeps a 6 x 6 register tile
-// of the output; when the output needs fewer than 256 threads, several thread
-// groups take alternate rows and are summed at the end in a fixed order.
+// are staged through LDS in chunks of kGramRows; the next chunk is loaded
+// into registers while the current one is multiplied, so HBM latency hides
+// behind the FMAs.  Each thread keeps a 6 x 6 register tile of the output;
+// when the output needs fewer than 256 threads, several thread groups take
+// alternate rows and are summed at the end in a fixed order.
 constexpr int kGramRows = 32;
 constexpr int kGT = 6;
+constexpr int kGramStage = 2 * kNS / 8;   // staged values per thread: 8 threads per row
 
 __global__ __launch_bounds__(256) void k_gram(int64_t D, int ns, int ld, const double *__restrict__ S,
                                               const double *__restrict__ HS, int64_t rows_per_blk,
                                               double *__restrict__ partial) {
-  __shared__ double buf[kNS * 2 * kNS];
+  // row chunks, then (groups / 2) ns x 2ns tiles of the group tree; both
+  // fit in kNS * 2kNS doubles (groups * ns * 2ns <= 2 * 256 * 36)
+  __shared__ double buf[(kGramRows > kNS ? kGramRows : kNS) * 2 * kNS];
   const int tid = threadIdx.x;
   const int w2 = 2 * ns, nout = ns * w2;
   const int nti = (ns + kGT - 1) / kGT, ntj = (w2 + kGT - 1) / kGT;
   const int T = nti * ntj;
-  const int groups = max(1, (int)blockDim.x / T);
+  int groups = max(1, (int)blockDim.x / T);
+  while (groups & (groups - 1)) groups &= groups - 1;   // a power of two for the tree
   const int grp = tid / T, loc = tid % T;
   const bool worker = grp < groups;
   const int i0 = (loc / ntj) * kGT, j0 = (loc % ntj) * kGT;
@@ -139,21 +145,38 @@ __global__ __launch_bounds__(256) void k_gram(int64_t D, int ns, int ld, const d
     for (int c = 0; c < kGT; ++c) acc[a][c] = 0.0;
   const int64_t r0 = (int64_t)blockIdx.x * rows_per_blk;
   const int64_t r1 = min(D, r0 + rows_per_blk);
+  // staging: thread (row sr, lane sc of 8) holds columns sc, sc + 8, ...
+  double stage[kGramStage];
+  const int sr = tid >> 3, sc = tid & 7;
+  auto fetch = [&](int64_t rb) {
+    const int64_t row = rb + sr;
+    const bool ok = row < r1;
+    const double *srow = S + (ok ? row : r0) * ld, *hrow = HS + (ok ? row : r0) * ld;
+#pragma unroll
+    for (int t = 0; t < kGramStage; ++t) {
+      const int c = sc + 8 * t;
+      stage[t] = 0.0;
+      if (ok && c < w2) stage[t] = c < ns ? srow[c] : hrow[c - ns];
+    }
+  };
+  if (r0 < r1) fetch(r0);
   for (int64_t rb = r0; rb < r1; rb += kGramRows) {
     const int nr = (int)min<int64_t>(kGramRows, r1 - rb);
-    for (int k = tid; k < nr * w2; k += blockDim.x) {
-      const int r = k / w2, c = k % w2;
-      buf[k] = c < ns ? S[(rb + r) * ld + c] : HS[(rb + r) * ld + (c - ns)];
+#pragma unroll
+    for (int t = 0; t < kGramStage; ++t) {
+      const int c = sc + 8 * t;
+      if (c < w2) buf[sr * w2 + c] = stage[t];
     }
     __syncthreads();
+    if (rb + kGramRows < r1) fetch(rb + kGramRows);
     if (worker)
       for (int r = grp; r < nr; r += groups) {
         const double *row = buf + r * w2;
         double xi[kGT], xj[kGT];
 #pragma unroll
-        for (int a = 0; a < kGT; ++a) xi[a] = row[i0 + a];
+        for (int a = 0; a < kGT; ++a) xi[a] = row[min(i0 + a, w2 - 1)];
 #pragma unroll
-        for (int c = 0; c < kGT; ++c) xj[c] = row[j0 + c];
+        for (int c = 0; c < kGT; ++c) xj[c] = row[min(j0 + c, w2 - 1)];
 #pragma unroll
         for (int a = 0; a < kGT; ++a)
 #pragma unroll
@@ -161,32 +184,59 @@ __global__ __launch_bounds__(256) void k_gram(int64_t D, int ns, int ld, const d
       }
     __syncthreads();
   }
-  // fixed-order sum of the thread groups in LDS
-  for (int q = 0; q < groups; ++q) {
-    if (worker && grp == q)
+  // pairwise tree over the thread groups (a power of two) in LDS, fixed
+  // order: at each level the upper half of the groups hands its tiles to
+  // the lower half
+  for (int half = groups >> 1; half >= 1; half >>= 1) {
+    if (worker && grp >= half && grp < 2 * half)
 #pragma unroll
       for (int a = 0; a < kGT; ++a)
 #pragma unroll
         for (int c = 0; c < kGT; ++c) {
           const int i = i0 + a, j = j0 + c;
-          if (i < ns && j < w2) buf[i * w2 + j] = (q == 0 ? 0.0 : buf[i * w2 + j]) + acc[a][c];
+          if (i < ns && j < w2) buf[(grp - half) * nout + i * w2 + j] = acc[a][c];
+        }
+    __syncthreads();
+    if (worker && grp < half)
+#pragma unroll
+      for (int a = 0; a < kGT; ++a)
+#pragma unroll
+        for (int c = 0; c < kGT; ++c) {
+          const int i = i0 + a, j = j0 + c;
+          if (i < ns && j < w2) acc[a][c] += buf[grp * nout + i * w2 + j];
         }
     __syncthreads();
   }
-  for (int e = tid; e < nout; e += blockDim.x) partial[(int64_t)blockIdx.x * nout + e] = buf[e];
+  if (worker && grp == 0)
+#pragma unroll
+    for (int a = 0; a < kGT; ++a)
+#pragma unroll
+      for (int c = 0; c < kGT; ++c) {
+        const int i = i0 + a, j = j0 + c;
+        if (i < ns && j < w2) partial[(int64_t)blockIdx.x * nout + i * w2 + j] = acc[a][c];
+      }
 }
 
-// out[e] = sum over the nparts partial matrices, in a fixed order
-__global__ __launch_bounds__(256) void k_gram_reduce(int nout, int nparts, const double *__restrict__ partial,
-                                                     double *__restrict__ out) {
-  __shared__ double red[256];
-  const int e = blockIdx.x * 64 + (threadIdx.x & 63), slice = threadIdx.x >> 6;
-  double s = 0.0;
-  if (e < nout)
-    for (int q = slice; q < nparts; q += 4) s += partial[(int64_t)q * nout + e];
-  red[threadIdx.x] = s;
-  __syncthreads();
-  if (slice == 0 && e < nout) out[e] = (red[threadIdx.x] + red[threadIdx.x + 64]) + (red[threadIdx.x + 128] + red[threadIdx.x + 192]);
+// out[g][e] = sum of in[q][e] over the parts q of group g (grid.y = groups of
+// `per` consecutive parts), in a fixed order.  One thread per output element
+// (coalesced); all loads of a group are in flight together.  The Gram
+// reduction runs it twice: groups of 32 partial matrices, then the group sums.
+__global__ __launch_bounds__(256) void k_sum_parts(int nout, int nparts, int per, const double *__restrict__ in,
+                                                   double *__restrict__ out) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nout) return;
+  const int q0 = blockIdx.y * per, q1 = min(nparts, q0 + per);
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  int q = q0;
+  for (; q + 8 <= q1; q += 8) {
+    double v[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) v[t] = in[(int64_t)(q + t) * nout + e];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) acc[t & 3] += v[t];
+  }
+  for (; q < q1; ++q) acc[q & 3] += in[(int64_t)q * nout + e];
+  out[(int64_t)blockIdx.y * nout + e] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
 }
 
 // Gershgorin lower bound of H: min_i (H_ii - sum_{j != i} |H_ij|), both halves.
@@ -229,35 +279,59 @@ struct RRArgs {
   long long *clk;      // optional: wall-clock stamps of the phases (thread 0)
 };
 
-// 1 / q from the hardware reciprocal refined by one Newton step (within an
-// ulp or two of the quotient; a Sturm count only needs the pivots' signs to
-// be those of a slightly perturbed matrix).
-__device__ __forceinline__ double recip(double q) {
-  double r = __builtin_amdgcn_rcp(q);
-  const double e = fma(-q, r, 1.0);
-  return fma(r, e, r);
+__device__ __forceinline__ uint32_t sign_word(double v) {
+  return (uint32_t)(__builtin_bit_cast(uint64_t, v) >> 32);
 }
 
-// Number of eigenvalues of the symmetric tridiagonal (d, e2 = e^2) below x
-// (Sturm sequence of the LDL^T pivots).
-__device__ __forceinline__ int sturm_count(const double *d, const double *e2, int n, double x,
-                                           double pivmin) {
-  double q = d[0] - x;
-  if (fabs(q) < pivmin) q = -pivmin;
-  int c = q <= 0.0;
-#pragma unroll 4
-  for (int i = 1; i < n; ++i) {
-    q = (d[i] - x) - e2[i - 1] * recip(q);
-    if (fabs(q) < pivmin) q = -pivmin;
-    c += q <= 0.0;
+// Number of eigenvalues of the symmetric tridiagonal (d, e2 = e^2) below x:
+// the sign changes of p_0 = 1, p_i = (d_i - x) p_{i-1} - e2_{i-1} p_{i-2}
+// (the characteristic polynomials of the leading blocks), which are the
+// negative pivots q_i = p_i / p_{i-1} of T - x I = L D L^T.  A zero p_i is
+// replaced by a tiny value of the sign opposite to p_{i-1} (a pivot of -0).
+// No division: one dependent FMA per step, and the sign changes are counted
+// from the sign bits.  p is rescaled by a power of two (exact) when it leaves
+// [2^-500, 2^500].  Steps past n are padded with d - x = 1, e2 = 0, which
+// repeat p and add no sign change.
+__device__ __forceinline__ int sturm_count(const double *d, const double *e2, int n, double x) {
+  double pm = 1.0;
+  double p = d[0] - x;
+  p = p == 0.0 ? -0x1p-600 : p;
+  uint32_t c = sign_word(p) >> 31;
+  for (int i0 = 1; i0 < n; i0 += 8) {
+    double dv[8], ev[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int i = min(i0 + t, n - 1);
+      const bool in = i0 + t < n;
+      const double di = d[i], ei = e2[i - 1];
+      dv[t] = in ? di - x : 1.0;
+      ev[t] = in ? ei : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      // (the replacement depends on p only, so it is off the dependent chain)
+      const double rep = copysign(fmax(0x1p-600 * fabs(p), 0x1p-1000), -p);
+      double pn = fma(dv[t], p, -ev[t] * pm);
+      pn = pn == 0.0 ? rep : pn;
+      c += (sign_word(pn) ^ sign_word(p)) >> 31;
+      pm = p;
+      p = pn;
+    }
+    const double m = fmax(fabs(p), fabs(pm));
+    if (m > 0x1p500 || m < 0x1p-500) {
+      const double sc = ldexp(1.0, min(max(-ilogb(m), -1000), 1000));
+      p *= sc;
+      pm *= sc;
+    }
   }
-  return c;
+  return (int)c;
 }
 
 // One workgroup.  (1) reduce the partial Gram matrices; (2) scale S^T S and
 // S^T H S to unit diagonal; (3) Cholesky S^T S = L L^T dropping columns whose
-// residual pivot falls below drop_tol (directions already spanned); (4) Z =
-// L^-1 and the reduced matrix M = Z (S^T H S) Z^T on the r kept columns;
+// residual pivot falls below drop_tol (directions already spanned); (4) the
+// kept rows and columns compacted, Z = L^-1 and the reduced matrix
+// M = Z (S^T H S) Z^T;
 // (5) Householder reduction of M to tridiagonal form; (6) the lowest b
 // eigenvalues by multisection of Sturm counts; (7) their eigenvectors from
 // twisted LDL^T / UDU^T factorisations, re-orthogonalised inside clusters;
@@ -313,8 +387,11 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz(RRArgs g) {
     for (int k = 0; k < ns; ++k) {
       const double piv = G[k][k];
       const bool kk = scale[k] > 0.0 && piv > drop_tol;   // every lane decides the same
-      const double lkk = kk ? sqrt(piv) : 0.0;
-      const double ilkk = kk ? 1.0 / lkk : 0.0;
+      // 1/sqrt(piv) from the hardware estimate and one Newton step
+      double y = __builtin_amdgcn_rsq(kk ? piv : 1.0);
+      y = y * fma(-0.5 * (kk ? piv : 1.0) * y, y, 1.5);
+      const double ilkk = kk ? y : 0.0;
+      const double lkk = kk ? piv * y : 0.0;
       double lik = 0.0;
       if (i > k && i < ns) {
         lik = G[i][k] * ilkk;
@@ -325,54 +402,122 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz(RRArgs g) {
         keep[k] = kk;
       }
       wave_lds_sync();
-      if (kk && i > k && i < ns)
-        for (int j = k + 1; j <= i; ++j) G[i][j] -= lik * G[j][k];
+      if (kk && i > k && i < ns) {
+        // all reads of a batch before its writes: one LDS round trip per 8
+        for (int j0 = k + 1; j0 <= i; j0 += 8) {
+          double cv[8], rv[8];
+#pragma unroll
+          for (int t = 0; t < 8; ++t) {
+            const int j = min(j0 + t, i);
+            cv[t] = G[j][k];
+            rv[t] = G[i][j];
+          }
+#pragma unroll
+          for (int t = 0; t < 8; ++t)
+            if (j0 + t <= i) G[i][j0 + t] = rv[t] - lik * cv[t];
+        }
+      }
       wave_lds_sync();
     }
+    if (g.clk && i == 0) g.clk[3] = wall_clock64();
     const bool kp = i < ns && keep[i];
     const uint64_t km = __ballot(kp);
     if (kp) kidx[mask_rank(km)] = i;
     if (i == 0) rank_s = (int)__popcll(km);
     wave_lds_sync();
-    // 4a. Z = L^-1 on the kept columns (compressed r x r, lower
-    //     triangular): lane j solves for column j by forward substitution
+    // 4a. compact L (G) and S^T H S (Hm) to the kept rows and columns, in
+    //     place: kidx increases, so every source lies at or after its
+    //     target in both indices, and a batch's loads precede its stores
     const int rr = rank_s;
-    if (i < rr) dinv[i] = 1.0 / G[kidx[i]][kidx[i]];
+    if (rr < ns && i < rr) {
+      const int ka = kidx[i];
+      for (int q0 = 0; q0 < rr; q0 += 8) {
+        double lv[8], hv[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          const int kq = kidx[min(q0 + t, rr - 1)];
+          lv[t] = G[ka][kq];
+          hv[t] = Hm[ka][kq];
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+          if (q0 + t < rr) {
+            G[i][q0 + t] = lv[t];
+            Hm[i][q0 + t] = hv[t];
+          }
+      }
+    }
+    wave_lds_sync();
+    // 4b. Z = L^-1 (r x r, lower triangular): lane j solves for column j by
+    //     forward substitution
+    if (i < rr) dinv[i] = 1.0 / G[i][i];
     wave_lds_sync();
     if (i < rr) {
       for (int a = 0; a < i; ++a) Z[a][i] = 0.0;
       Z[i][i] = dinv[i];
       for (int a = i + 1; a < rr; ++a) {
-        const int ka = kidx[a];
         double s0 = 0.0, s1 = 0.0;
-        int q = i;
-        for (; q + 1 < a; q += 2) {
-          s0 += G[ka][kidx[q]] * Z[q][i];
-          s1 += G[ka][kidx[q + 1]] * Z[q + 1][i];
+        for (int q0 = i; q0 < a; q0 += 8) {
+          double lv[8], zv[8];
+#pragma unroll
+          for (int t = 0; t < 8; ++t) {
+            const int q = min(q0 + t, a - 1);
+            lv[t] = G[a][q];
+            zv[t] = Z[q][i];
+          }
+#pragma unroll
+          for (int t = 0; t < 8; t += 2) {
+            if (q0 + t < a) s0 += lv[t] * zv[t];
+            if (q0 + t + 1 < a) s1 += lv[t + 1] * zv[t + 1];
+          }
         }
-        if (q < a) s0 += G[ka][kidx[q]] * Z[q][i];
         Z[a][i] = -(s0 + s1) * dinv[a];
       }
     }
   }
   __syncthreads();
   r = rank_s;
-  if (g.clk && tid == 0) g.clk[3] = wall_clock64();
   if (g.clk && tid == 0) g.clk[4] = wall_clock64();
-  // 4b. T1 = Hm_c Z^T into G (L is no longer needed), then M = Z T1 into Hm
+  // 4c. T1 = Hm Z^T into G (L is no longer needed), then M = Z T1 into Hm
+  //     (dots of up to 48 terms, 8 table reads in flight)
   for (int e = tid; e < r * r; e += nt) {
     const int a = e / r, q = e % r;
-    const int ka = kidx[a];
-    double s = 0.0;
-    for (int t = 0; t <= q; ++t) s += Hm[ka][kidx[t]] * Z[q][t];
-    G[a][q] = s;
+    double s0 = 0.0, s1 = 0.0;
+    for (int t0 = 0; t0 <= q; t0 += 8) {
+      double hv[8], zv[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int tt = min(t0 + t, q);
+        hv[t] = Hm[a][tt];
+        zv[t] = Z[q][tt];
+      }
+#pragma unroll
+      for (int t = 0; t < 8; t += 2) {
+        if (t0 + t <= q) s0 += hv[t] * zv[t];
+        if (t0 + t + 1 <= q) s1 += hv[t + 1] * zv[t + 1];
+      }
+    }
+    G[a][q] = s0 + s1;
   }
   __syncthreads();
   for (int e = tid; e < r * r; e += nt) {
     const int p = e / r, q = e % r;
-    double s = 0.0;
-    for (int a = 0; a <= p; ++a) s += Z[p][a] * G[a][q];
-    Hm[p][q] = s;
+    double s0 = 0.0, s1 = 0.0;
+    for (int a0 = 0; a0 <= p; a0 += 8) {
+      double zv[8], tv[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int a = min(a0 + t, p);
+        zv[t] = Z[p][a];
+        tv[t] = G[a][q];
+      }
+#pragma unroll
+      for (int t = 0; t < 8; t += 2) {
+        if (a0 + t <= p) s0 += zv[t] * tv[t];
+        if (a0 + t + 1 <= p) s1 += zv[t + 1] * tv[t + 1];
+      }
+    }
+    Hm[p][q] = s0 + s1;
   }
   __syncthreads();
   for (int e = tid; e < r * r; e += nt) {
@@ -394,7 +539,7 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz(RRArgs g) {
     for (int k = 0; k + 2 < r; ++k) {
       const bool act = row && i > k;
       const double xi = act ? Hm[i][k] : 0.0;
-      const double sigma = wave_sum(xi * xi);
+      const double sigma = wave_sum_dpp(xi * xi);
       const double x0 = Hm[k + 1][k];
       const double tail = sigma - x0 * x0;
       const bool refl = tail > 1e-300;
@@ -405,20 +550,40 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz(RRArgs g) {
       wave_lds_sync();
       double acc0 = 0.0, acc1 = 0.0;
       if (act) {
-        int j = k + 1;
-        for (; j + 1 < r; j += 2) {
-          acc0 += Hm[i][j] * vv[j];
-          acc1 += Hm[i][j + 1] * vv[j + 1];
+        for (int j0 = k + 1; j0 < r; j0 += 8) {
+          double hv[8], xv[8];
+#pragma unroll
+          for (int t = 0; t < 8; ++t) {
+            const int j = min(j0 + t, r - 1);
+            hv[t] = Hm[i][j];
+            xv[t] = vv[j];
+          }
+#pragma unroll
+          for (int t = 0; t < 8; t += 2) {
+            if (j0 + t < r) acc0 += hv[t] * xv[t];
+            if (j0 + t + 1 < r) acc1 += hv[t + 1] * xv[t + 1];
+          }
         }
-        if (j < r) acc0 += Hm[i][j] * vv[j];
       }
       const double pi = bk * (acc0 + acc1);
-      const double K = 0.5 * bk * wave_sum(vi * pi);
+      const double K = 0.5 * bk * wave_sum_dpp(vi * pi);
       const double wi = pi - K * vi;
       if (i < kNS) pp[i] = wi;
       wave_lds_sync();
       if (act) {
-        for (int j = k + 1; j < r; ++j) Hm[i][j] -= vi * pp[j] + wi * vv[j];
+        for (int j0 = k + 1; j0 < r; j0 += 8) {
+          double hv[8], wv[8], xv[8];
+#pragma unroll
+          for (int t = 0; t < 8; ++t) {
+            const int j = min(j0 + t, r - 1);
+            hv[t] = Hm[i][j];
+            wv[t] = pp[j];
+            xv[t] = vv[j];
+          }
+#pragma unroll
+          for (int t = 0; t < 8; ++t)
+            if (j0 + t < r) Hm[i][j0 + t] = hv[t] - (vi * wv[t] + wi * xv[t]);
+        }
         Hm[i][k] = vi;
       }
       if (i == 0) {
@@ -437,8 +602,9 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz(RRArgs g) {
   for (int i = tid; i + 1 < r; i += nt) e2[i] = ee[i] * ee[i];
   __syncthreads();
   if (g.clk && tid == 0) g.clk[6] = wall_clock64();
-  // 6. lowest nb eigenvalues: 16 threads per eigenvalue, 14 rounds of
-  //    17-way multisection of the Gershgorin interval
+  // 6. lowest nb eigenvalues by multisection of the Gershgorin interval:
+  //    gsz threads per eigenvalue (32 when nb <= 8, else 16), each round
+  //    cutting the interval into gsz + 1 parts, until (gsz + 1)^rounds > 2^53
   nb = b < r ? b : r;
   double gl = 1e300, gu = -1e300, emax = 0.0;
   for (int i = 0; i < r; ++i) {
@@ -451,22 +617,27 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz(RRArgs g) {
   pivmin = fmax(1e-300, 2.2e-308 * fmax(emax, 1.0));
   gl -= 2.2e-16 * tnorm * 4 + pivmin;
   gu += 2.2e-16 * tnorm * 4 + pivmin;
+  if (g.clk && tid == 0) g.clk[11] = wall_clock64();
   {
-    const int grp = tid >> 4, t = tid & 15;
+    const int gsz = nb <= 8 ? 32 : 16;
+    const int rounds = gsz == 32 ? 11 : 14;
+    const double inv = 1.0 / (gsz + 1);
+    const int grp = tid / gsz, t = tid % gsz;
     double lo = gl, hi = gu;
-    for (int round = 0; round < 14; ++round) {
-      const double x = lo + (t + 1) * (hi - lo) * (1.0 / 17.0);
-      const bool above = grp < nb ? sturm_count(dd, e2, r, x, pivmin) > grp : true;
+    for (int round = 0; round < rounds; ++round) {
+      const double x = lo + (t + 1) * (hi - lo) * inv;
+      const bool above = grp < nb ? sturm_count(dd, e2, r, x) > grp : true;
       const uint64_t m = __ballot(above);
-      const unsigned gm = (unsigned)((m >> ((tid & 63) & ~15)) & 0xffffu);
-      const int first = __builtin_ctz(gm | 0x10000u);  // first sub-point with count > grp
-      const double nlo = first == 0 ? lo : lo + first * (hi - lo) * (1.0 / 17.0);
-      const double nhi = first == 16 ? hi : lo + (first + 1) * (hi - lo) * (1.0 / 17.0);
+      const uint64_t gm = (m >> ((tid & 63) & ~(gsz - 1))) & ((1ull << gsz) - 1ull);
+      const int first = __builtin_ctzll(gm | (1ull << gsz));  // first sub-point with count > grp
+      const double nlo = first == 0 ? lo : lo + first * (hi - lo) * inv;
+      const double nhi = first == gsz ? hi : lo + (first + 1) * (hi - lo) * inv;
       lo = nlo;
       hi = nhi;
     }
     if (t == 0 && grp < nb) theta[grp] = 0.5 * (lo + hi);
   }
+  if (g.clk && tid == 0) g.clk[12] = wall_clock64();
   __syncthreads();
   // a Ritz value below the spectrum of H means a numerically dependent
   // direction spoiled the reduced matrix: redo without P and a looser drop
@@ -494,17 +665,22 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz(RRArgs g) {
     auto Dp = [&](int i) -> double & { return G[i][16 + c]; };
     auto Dm = [&](int i) -> double & { return G[i][32 + c]; };
     (void)Y;
-    Dp(0) = dd[0] - th;
+    // the pivots are carried in registers and only stored for later
+    double qc = dd[0] - th;
+    Dp(0) = qc;
     for (int i = 0; i + 1 < r; ++i) {
-      double q = Dp(i);
+      double q = qc;
       if (fabs(q) < pivmin) q = -pivmin;
-      Dp(i + 1) = dd[i + 1] - th - e2[i] / q;
+      qc = dd[i + 1] - th - e2[i] / q;
+      Dp(i + 1) = qc;
     }
-    Dm(r - 1) = dd[r - 1] - th;
+    qc = dd[r - 1] - th;
+    Dm(r - 1) = qc;
     for (int i = r - 2; i >= 0; --i) {
-      double q = Dm(i + 1);
+      double q = qc;
       if (fabs(q) < pivmin) q = -pivmin;
-      Dm(i) = dd[i] - th - e2[i] / q;
+      qc = dd[i] - th - e2[i] / q;
+      Dm(i) = qc;
     }
     int tw = 0;
     double best = 1e300;
@@ -516,24 +692,30 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz(RRArgs g) {
     // (|q| >= 1e-280 (1 + |e|)) and the partial vector is rescaled whenever an
     // entry passes 1e10, so a nearly split matrix cannot overflow
     Yr(tw) = 1.0;
+    double yc = 1.0;
     for (int i = tw - 1; i >= 0; --i) {
       double q = Dp(i);
       const double qmin = 1e-280 * (1.0 + fabs(ee[i]));
       if (fabs(q) < qmin) q = q < 0 ? -qmin : qmin;
-      Yr(i) = -(ee[i] / q) * Yr(i + 1);
-      if (fabs(Yr(i)) > 1e10) {
-        const double sc = 1.0 / fabs(Yr(i));
+      yc = -(ee[i] / q) * yc;
+      Yr(i) = yc;
+      if (fabs(yc) > 1e10) {
+        const double sc = 1.0 / fabs(yc);
         for (int j = i; j <= tw; ++j) Yr(j) *= sc;
+        yc *= sc;
       }
     }
+    yc = 1.0;
     for (int i = tw + 1; i < r; ++i) {
       double q = Dm(i);
       const double qmin = 1e-280 * (1.0 + fabs(ee[i - 1]));
       if (fabs(q) < qmin) q = q < 0 ? -qmin : qmin;
-      Yr(i) = -(ee[i - 1] / q) * Yr(i - 1);
-      if (fabs(Yr(i)) > 1e10) {
-        const double sc = 1.0 / fabs(Yr(i));
+      yc = -(ee[i - 1] / q) * yc;
+      Yr(i) = yc;
+      if (fabs(yc) > 1e10) {
+        const double sc = 1.0 / fabs(yc);
         for (int j = 0; j <= i; ++j) Yr(j) *= sc;
+        yc *= sc;
       }
     }
     double nrm = 0.0;
@@ -601,7 +783,18 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz(RRArgs g) {
     const int k = kidx[a];
     double v = 0.0;
     if (c < nb)
-      for (int q = a; q < r; ++q) v += Z[q][a] * G[q][c];
+      for (int q0 = a; q0 < r; q0 += 8) {
+        double zv[8], yv[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          const int q = min(q0 + t, r - 1);
+          zv[t] = Z[q][a];
+          yv[t] = G[q][c];
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+          if (q0 + t < r) v += zv[t] * yv[t];
+      }
     v *= scale[k];
     g.C[k * 2 * b + c] = v;
     g.C[k * 2 * b + b + c] = k < b ? 0.0 : v;
@@ -718,10 +911,13 @@ __global__ __launch_bounds__(256) void k_finish(int b, int nev, int nparts, cons
 static inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
 // rows per Gram block: about 512 blocks, a multiple of the staging chunk
+constexpr int kSumGroup = 32;  // partial Gram matrices added per thread in the first pass
+
+// rows per Gram workgroup: about one workgroup per CU, each streaming its
+// slab chunk after chunk (loads of the next chunk overlap the FMAs)
 static int64_t gram_rows_for(int64_t D) {
-  int64_t r = std::max<int64_t>((D + 511) / 512, 256);
-  r = (r + kGramRows - 1) / kGramRows * kGramRows;
-  return std::max<int64_t>(kGramRows, r);
+  int64_t r = std::max<int64_t>((D + 255) / 256, kGramRows);
+  return (r + kGramRows - 1) / kGramRows * kGramRows;
 }
 
 struct LobpcgRun {
@@ -733,7 +929,7 @@ struct LobpcgRun {
   int64_t gram_rows, upd_rows;
   double tol;
   cib_lobpcg_opts opts;
-  DBuf<double> S, HS, diag, partial, gram, C, lam, npart, status, hlow;
+  DBuf<double> S, HS, diag, partial, partial2, gram, C, lam, npart, status, hlow;
   DBuf<float> x32, y32;
   DBuf<int64_t> idx;
   DBuf<int32_t> flag, locked;
@@ -761,6 +957,7 @@ struct LobpcgRun {
     upd_rows = std::max<int64_t>(64, (D + 4095) / 4096);
     upd_blocks = (int)((D + upd_rows - 1) / upd_rows);
     partial.reset(ctx, (size_t)gram_blocks * kNS * 2 * kNS);
+    partial2.reset(ctx, (size_t)((gram_blocks + kSumGroup - 1) / kSumGroup) * kNS * 2 * kNS);
     gram.reset(ctx, (size_t)kNS * 2 * kNS);
     hlow.reset(ctx, 1);
     C.reset(ctx, kNS * 2 * kMaxBlock);
@@ -806,7 +1003,11 @@ struct LobpcgRun {
       KTimer kt(ctx, K_GRAM, s);
       hipLaunchKernelGGL(k_gram, dim3(gram_blocks), dim3(256), 0, s, D, ns, ld, S.p, HS.p, gram_rows, partial.p);
       const int nout = ns * 2 * ns;
-      hipLaunchKernelGGL(k_gram_reduce, dim3((nout + 63) / 64), dim3(256), 0, s, nout, gram_blocks, partial.p, gram.p);
+      const int groups = (gram_blocks + kSumGroup - 1) / kSumGroup;
+      hipLaunchKernelGGL(k_sum_parts, dim3((nout + 255) / 256, groups), dim3(256), 0, s, nout, gram_blocks,
+                         kSumGroup, partial.p, partial2.p);
+      hipLaunchKernelGGL(k_sum_parts, dim3((nout + 255) / 256, 1), dim3(256), 0, s, nout, groups, groups,
+                         partial2.p, gram.p);
     }
     RRArgs ra{ns, b, 1, gram.p, C.p, lam.p, flag.p, H.dtype == CIB_F64 ? 1e-10 : 1e-7, hlow.p,
               clk_on ? clk.p : nullptr};
@@ -872,7 +1073,8 @@ size_t lobpcg_bytes(int64_t D, int b, cib_dtype dt) {
   const int64_t gram_blocks = (D + gram_rows - 1) / gram_rows;
   const int64_t upd_rows = std::max<int64_t>(64, (D + 4095) / 4096);
   const int64_t upd_blocks = (D + upd_rows - 1) / upd_rows;
-  size_t n = (size_t)D * 3 * b * 8 * 2 + (size_t)D * 8 + (size_t)gram_blocks * kNS * 2 * kNS * 8 +
+  const int64_t groups = (gram_blocks + kSumGroup - 1) / kSumGroup;
+  size_t n = (size_t)D * 3 * b * 8 * 2 + (size_t)D * 8 + (size_t)(gram_blocks + groups) * kNS * 2 * kNS * 8 +
              (size_t)upd_blocks * 2 * kMaxBlock * 8 + 64 * 1024;
   if (dt == CIB_F32) n += (size_t)D * b * 4 * 2;
   return n;
@@ -933,7 +1135,8 @@ cib_status lobpcg_solve(cib_ctx *ctx, const cib_matrix &H, const cib_lobpcg_opts
     CIB_HIP(hipMemcpy(c, L.clk.p, sizeof(c), hipMemcpyDeviceToHost));
     std::fprintf(stderr, "rayleigh_ritz phases (us):");
     for (int k = 0; k < 10; ++k) std::fprintf(stderr, " %d:%.2f", k + 1, (c[k + 1] - c[k]) * 0.01);
-    std::fprintf(stderr, "\n");
+    std::fprintf(stderr, " | 7a:%.2f 7b:%.2f 7c:%.2f\n", (c[11] - c[6]) * 0.01, (c[12] - c[11]) * 0.01,
+                 (c[7] - c[12]) * 0.01);
   }
   if (info) {
     info->iters = L.iters;

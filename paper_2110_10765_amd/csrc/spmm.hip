@@ -106,6 +106,7 @@ struct VecArgs {
   int64_t ldx;
   void *Y;
   int64_t ldy;
+  int xcd;  // 1: each XCD takes one contiguous range of rows
 };
 
 // nvec == NV (8 or 16) with 16-byte aligned rows of X.  One wave per row.
@@ -132,7 +133,8 @@ __global__ __launch_bounds__(256) void k_spmm_vec(const VecArgs a) {
   const T *__restrict__ val = static_cast<const T *>(a.val);
   const T *__restrict__ lval = static_cast<const T *>(a.lval);
   const T *__restrict__ X = static_cast<const T *>(a.X);
-  const int64_t i = xcd_block(blockIdx.x, gridDim.x) * (blockDim.x / kWave) + (threadIdx.x >> 6);
+  const int64_t blk = a.xcd ? xcd_block(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+  const int64_t i = blk * (blockDim.x / kWave) + (threadIdx.x >> 6);
   if (i >= a.D) return;
   const int lane = lane_id();
   const int e = lane / G, g = lane % G;
@@ -206,7 +208,12 @@ static void spmm_t(const cib_matrix &H, const T *X, int64_t ldx, T *Y, int64_t l
   const unsigned nblk = (unsigned)((D + 3) / 4);
   const bool aligned = ((uintptr_t)X % 16 == 0) && ((ldx * sizeof(T)) % 16 == 0);
   if (aligned && (nvec == 8 || nvec == 16)) {
-    const VecArgs a{D, H.row_ptr.p, H.col.p, val, H.lo_ptr.p, H.lo_col.p, lval, X, ldx, Y, ldy};
+    // Row order: when the span of X the gathers touch is large (float64 rows
+    // inside the eigensolver's [X | W | P] block at D ~ 2e5) contiguous row
+    // ranges per XCD measured 7-11% faster (L2 reuse); otherwise plain order
+    // is 6-12% faster (rows of very different lengths balance better).
+    const bool xcd = (double)D * (double)ldx * sizeof(T) > 16.0 * (1 << 20);
+    const VecArgs a{D, H.row_ptr.p, H.col.p, val, H.lo_ptr.p, H.lo_col.p, lval, X, ldx, Y, ldy, xcd ? 1 : 0};
     KTimer kt(H.ctx, K_SPMM, s);
     if (nvec == 8) hipLaunchKernelGGL((k_spmm_vec<T, 8>), dim3(nblk), dim3(256), 0, s, a);
     else hipLaunchKernelGGL((k_spmm_vec<T, 16>), dim3(nblk), dim3(256), 0, s, a);
