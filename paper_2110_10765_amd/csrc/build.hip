@@ -123,28 +123,41 @@ __global__ void k_dab(DevInter it, double *dab) {
 // bra (row) and alpha' as the ket (column).
 struct TileArgs {
   int nA;
+  int nchunk;             // candidate chunks per configuration (units = nA * nchunk)
   const uint64_t *a_bits;
   const int32_t *a_m2, *a_len, *a_seg;
   const int64_t *a_off;
   DevInter it;
-  int32_t *tcnt;          // count pass
-  const int64_t *t_ptr;   // fill pass
+  int32_t *tcnt;          // count pass: per unit
+  const int64_t *t_ptr;   // fill pass: per unit
   int64_t *t_off;
   int32_t *t_len, *t_info;
   double *t_val;
 };
 
+constexpr int kTileChunk = 256;   // candidate configurations per wave
+
+// One wave per unit (alpha, chunk): candidates alpha' in the chunk's range of
+// kTileChunk configurations, restricted to alpha' > alpha (upper) or
+// alpha' < alpha (LOWER).  Units are laid out alpha-major, so the scan of
+// the per-unit counts lists each alpha's tiles in ascending alpha'.
 template <int W, bool FILL, bool LOWER>
 __global__ __launch_bounds__(256) void k_tile_pass(TileArgs g) {
-  const int alpha = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6);
-  if (alpha >= g.nA) return;
+  const int64_t unit = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+  if (unit >= (int64_t)g.nA * g.nchunk) return;
+  const int alpha = (int)(unit / g.nchunk), chunk = (int)(unit % g.nchunk);
   const int lane = lane_id();
+  const int jb = max(chunk * kTileChunk, LOWER ? 0 : alpha + 1);
+  const int je = min((chunk + 1) * kTileChunk, LOWER ? alpha : g.nA);
+  if (jb >= je) {
+    if (!FILL && lane == 0) g.tcnt[unit] = 0;
+    return;
+  }
   uint64_t ra[W];
   load_bits<W>(g.a_bits, g.nA, alpha, ra);
   const int m = g.a_m2[alpha];
-  int64_t out = FILL ? g.t_ptr[alpha] : 0;
+  int64_t out = FILL ? g.t_ptr[unit] : 0;
   int cnt = 0;
-  const int jb = LOWER ? 0 : alpha + 1, je = LOWER ? alpha : g.nA;
   for (int j0 = jb; j0 < je; j0 += kWave) {
     const int j = j0 + lane;
     bool ok = false;
@@ -187,17 +200,19 @@ __global__ __launch_bounds__(256) void k_tile_pass(TileArgs g) {
     }
     cnt += __popcll(msk);
   }
-  if (!FILL && lane == 0) g.tcnt[alpha] = cnt;
+  if (!FILL && lane == 0) g.tcnt[unit] = cnt;
 }
 
 // ------------------------------------------------------------ B adjacency
-// One wave per B configuration beta.  Lsame(beta): beta' in beta's own 2M_B
+// One wave per unit (beta, segment h).  Lsame(beta): beta' in beta's own 2M_B
 // list with popcount <= 4, ascending position; carries the B-only value part.
 // L1(beta): beta' in any list with popcount <= 2, grouped by list, ascending.
+// A list whose 2M_B differs from beta's by more than one orbital change can
+// shift it (max_dm) holds no L1 entry and is not scanned.
 struct AdjArgs {
-  int nB, nseg;
+  int nB, nseg, max_dm;
   const uint64_t *b_bits;
-  const int32_t *b_seg, *bseg_start;
+  const int32_t *b_seg, *b_m2, *bseg_start;
   const double *eB;
   DevInter it;
   int32_t *ls_cnt, *l1_cnt;           // count pass
@@ -208,76 +223,80 @@ struct AdjArgs {
 
 template <int W, bool FILL>
 __global__ __launch_bounds__(256) void k_adj_pass(AdjArgs g) {
-  const int beta = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6);
-  if (beta >= g.nB) return;
+  const int64_t unit = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+  if (unit >= (int64_t)g.nB * g.nseg) return;
+  const int beta = (int)(unit / g.nseg), h = (int)(unit % g.nseg);
   const int lane = lane_id();
+  const int gs = g.b_seg[beta];
+  const int lo = g.bseg_start[h], hi = g.bseg_start[h + 1];
+  const bool own = h == gs;
+  if (!own && (hi <= lo || abs(g.b_m2[lo] - g.b_m2[beta]) > g.max_dm)) {
+    if (!FILL && lane == 0) g.l1_cnt[unit] = 0;
+    return;
+  }
   uint64_t rb[W];
   load_bits<W>(g.b_bits, g.nB, beta, rb);
-  const int gs = g.b_seg[beta];
-  for (int h = 0; h < g.nseg; ++h) {
-    const int lo = g.bseg_start[h], hi = g.bseg_start[h + 1];
-    int c_ls = 0, c_l1 = 0;
-    const int64_t ls0 = FILL && h == gs ? g.ls_ptr[beta] : 0;
-    const int64_t l10 = FILL ? g.l1_seg[(int64_t)beta * g.nseg + h] : 0;
-    for (int j0 = lo; j0 < hi; j0 += kWave) {
-      const int j = j0 + lane;
-      int d = 99;
-      uint64_t cb[W];
-      if (j < hi) {
-        load_bits<W>(g.b_bits, g.nB, j, cb);
-        d = popc_xor<W>(rb, cb);
-      }
-      const bool in_ls = h == gs && d <= 4;
-      const bool in_l1 = d <= 2;
-      const uint64_t m_ls = ballot(in_ls), m_l1 = ballot(in_l1);
-      if (FILL && (in_ls || in_l1)) {
-        uint64_t part[W], hole[W], common[W];
+  int c_ls = 0, c_l1 = 0;
+  const int64_t ls0 = FILL && own ? g.ls_ptr[beta] : 0;
+  const int64_t l10 = FILL ? g.l1_seg[unit] : 0;
+  for (int j0 = lo; j0 < hi; j0 += kWave) {
+    const int j = j0 + lane;
+    int d = 99;
+    uint64_t cb[W];
+    if (j < hi) {
+      load_bits<W>(g.b_bits, g.nB, j, cb);
+      d = popc_xor<W>(rb, cb);
+    }
+    const bool in_ls = own && d <= 4;
+    const bool in_l1 = d <= 2;
+    const uint64_t m_ls = ballot(in_ls), m_l1 = ballot(in_l1);
+    if (FILL && (in_ls || in_l1)) {
+      uint64_t part[W], hole[W], common[W];
 #pragma unroll
-        for (int w = 0; w < W; ++w) {
-          part[w] = rb[w] & ~cb[w];
-          hole[w] = cb[w] & ~rb[w];
-          common[w] = rb[w] & cb[w];
-        }
-        const int p1 = pop_lowest<W>(part), h1 = pop_lowest<W>(hole);
-        const int p2 = pop_lowest<W>(part), h2 = pop_lowest<W>(hole);
-        int info = 0, s = 1;
-        double val = 0.0;
-        if (d == 0) {
-          val = g.eB[beta];
-        } else if (d == 2) {
-          s = sign_single<W>(cb, p1, h1);
-          info = 1 | (p1 << 2) | (h1 << 10) | ((s < 0) << 18);
-          if (in_ls) {
-            double sum = 0.0;
-            for (int y = pop_lowest<W>(common); y >= 0; y = pop_lowest<W>(common))
-              sum += vbar_same(g.it.pidxB, g.it.prowB, g.it.nB, g.it.vB, p1, y, h1);
-            val = s * sum;
-          }
-        } else {
-          s = sign_double<W>(cb, p1, p2, h1, h2);
-          info = 2;
-          val = s * v_pair(g.it.pidxB, g.it.prowB, g.it.nB, g.it.vB, p1, p2, h1, h2);
-        }
-        if (in_ls) {
-          const int64_t o = ls0 + c_ls + mask_rank(m_ls);
-          g.ls_pos[o] = j - lo;
-          g.ls_info[o] = info;
-          g.ls_val[o] = val;
-          if (d == 0) g.ls_self[beta] = (int32_t)o;
-        }
-        if (in_l1) {
-          const int64_t o = l10 + c_l1 + mask_rank(m_l1);
-          g.l1_pos[o] = j - lo;
-          g.l1_info[o] = info;
-        }
+      for (int w = 0; w < W; ++w) {
+        part[w] = rb[w] & ~cb[w];
+        hole[w] = cb[w] & ~rb[w];
+        common[w] = rb[w] & cb[w];
       }
-      c_ls += __popcll(m_ls);
-      c_l1 += __popcll(m_l1);
+      const int p1 = pop_lowest<W>(part), h1 = pop_lowest<W>(hole);
+      const int p2 = pop_lowest<W>(part), h2 = pop_lowest<W>(hole);
+      int info = 0, sg = 1;
+      double val = 0.0;
+      if (d == 0) {
+        val = g.eB[beta];
+      } else if (d == 2) {
+        sg = sign_single<W>(cb, p1, h1);
+        info = 1 | (p1 << 2) | (h1 << 10) | ((sg < 0) << 18);
+        if (in_ls) {
+          double sum = 0.0;
+          for (int y = pop_lowest<W>(common); y >= 0; y = pop_lowest<W>(common))
+            sum += vbar_same(g.it.pidxB, g.it.prowB, g.it.nB, g.it.vB, p1, y, h1);
+          val = sg * sum;
+        }
+      } else {
+        sg = sign_double<W>(cb, p1, p2, h1, h2);
+        info = 2;
+        val = sg * v_pair(g.it.pidxB, g.it.prowB, g.it.nB, g.it.vB, p1, p2, h1, h2);
+      }
+      if (in_ls) {
+        const int64_t o = ls0 + c_ls + mask_rank(m_ls);
+        g.ls_pos[o] = j - lo;
+        g.ls_info[o] = info;
+        g.ls_val[o] = val;
+        if (d == 0) g.ls_self[beta] = (int32_t)o;
+      }
+      if (in_l1) {
+        const int64_t o = l10 + c_l1 + mask_rank(m_l1);
+        g.l1_pos[o] = j - lo;
+        g.l1_info[o] = info;
+      }
     }
-    if (!FILL && lane == 0) {
-      g.l1_cnt[(int64_t)beta * g.nseg + h] = c_l1;
-      if (h == gs) g.ls_cnt[beta] = c_ls;
-    }
+    c_ls += __popcll(m_ls);
+    c_l1 += __popcll(m_l1);
+  }
+  if (!FILL && lane == 0) {
+    g.l1_cnt[unit] = c_l1;
+    if (own) g.ls_cnt[beta] = c_ls;
   }
 }
 
@@ -289,7 +308,8 @@ struct RowArgs {
   const int64_t *a_off;
   const uint64_t *a_bits, *b_bits;
   const double *eA;
-  const int64_t *t_ptr, *t_off;
+  const int64_t *t_ptr, *t_off;   // t_ptr per tile unit: alpha's tiles at [alpha * tstride, (alpha + 1) * tstride]
+  int tstride;
   const int32_t *t_len, *t_info;
   const double *t_val;
   const int64_t *ls_ptr, *l1_seg;
@@ -351,16 +371,30 @@ __device__ __forceinline__ void row_diag(const RowArgs &g, int64_t e0, int64_t e
   }
 }
 
+// beta's L1 list as one row pass sees it: either staged in LDS (segment
+// offsets relative to the list's start) or read from global memory.
+constexpr int kL1Stage = 512;   // entries of one configuration's L1 list kept in LDS
+
+template <bool ST>
+struct L1View {
+  const int32_t *seg32;   // ST: nseg + 1 offsets relative to the list start
+  const int64_t *seg64;   // !ST: absolute offsets of beta's segments
+  const int32_t *pos, *info;
+  __device__ __forceinline__ int64_t seg(int h) const {
+    if constexpr (ST) return seg32[h];
+    else return seg64[h];
+  }
+};
+
 // Tile part of a row: tiles [t0, t1) in ascending alpha'.  Lanes over tiles;
 // a kA = 2 tile holds at most one entry (same B position), a kA = 1 tile the
 // prefix of beta's L1 list for the tile's 2M_B list with position < len.
 // kA = 1 entries are expanded over all lanes of the wave.
-template <int W, bool FILL, typename T>
-__device__ __forceinline__ void row_tiles(const RowArgs &g, int64_t t0, int64_t t1, int beta, int p,
-                                          const uint64_t *bb, int64_t out, int64_t &cnt) {
+template <int W, bool FILL, typename T, bool ST>
+__device__ __forceinline__ void row_tiles(const RowArgs &g, int64_t t0, int64_t t1, int p, const uint64_t *bb,
+                                          int64_t out, int64_t &cnt, const L1View<ST> &L) {
   const int lane = lane_id();
   T *val = static_cast<T *>(g.val);
-  const int64_t l1b = (int64_t)beta * g.nseg;
   for (int64_t tb = t0; tb < t1; tb += kWave) {
     const int64_t t = tb + lane;
     int ne = 0, info = 0;
@@ -372,16 +406,16 @@ __device__ __forceinline__ void row_tiles(const RowArgs &g, int64_t t0, int64_t 
         ne = p < len;
       } else {  // first entry of the sorted segment with position >= len
         const int gt = (info >> 19) & 0x7f;
-        l0 = g.l1_seg[l1b + gt];
-        int64_t lo = l0, hi = g.l1_seg[l1b + gt + 1];
+        l0 = L.seg(gt);
+        int64_t lo = l0, hi = L.seg(gt + 1);
         while (lo < hi) {
           const int64_t mid = (lo + hi) >> 1;
-          if (g.l1_pos[mid] < len) lo = mid + 1; else hi = mid;
+          if (L.pos[mid] < len) lo = mid + 1; else hi = mid;
         }
         ne = (int)(lo - l0);
       }
     }
-    const int incl = wave_incl_scan(ne);
+    const int incl = wave_incl_scan_dpp(ne);
     const int total = __shfl(incl, kWave - 1, kWave);
     if (FILL) {
       const int64_t o_lane = out + cnt + (incl - ne);
@@ -398,7 +432,7 @@ __device__ __forceinline__ void row_tiles(const RowArgs &g, int64_t t0, int64_t 
       }
       // kA = 1 entries, spread over the lanes
       const int n1 = two ? 0 : ne;
-      const int incl1 = wave_incl_scan(n1);
+      const int incl1 = wave_incl_scan_dpp(n1);
       const int tot1 = __shfl(incl1, kWave - 1, kWave);
       // every shuffle below runs with the whole wave active (uniform loop)
       for (int k0 = 0; k0 < tot1; k0 += kWave) {
@@ -421,7 +455,8 @@ __device__ __forceinline__ void row_tiles(const RowArgs &g, int64_t t0, int64_t 
         if (k >= tot1) continue;
         const int a = (oinfo >> 2) & 0xff, c = (oinfo >> 10) & 0xff;
         const double sa = (oinfo >> 18) & 1 ? -1.0 : 1.0;
-        const int li = g.l1_info[ol0 + q];
+        const int li = L.info[ol0 + q];
+        const int lp = L.pos[ol0 + q];
         double v;
         if ((li & 3) == 0) {  // B unchanged: AA part + s_A sum_{y in beta} V^AB_{(a,y),(c,y)}
           double sum = 0.0;
@@ -437,7 +472,7 @@ __device__ __forceinline__ void row_tiles(const RowArgs &g, int64_t t0, int64_t 
           const double sb = (li >> 18) & 1 ? -1.0 : 1.0;
           v = sa * sb * vab(g.it, a, b, c, d);
         }
-        g.col[oo + q] = (int32_t)(ocoff + g.l1_pos[ol0 + q]);
+        g.col[oo + q] = (int32_t)(ocoff + lp);
         val[oo + q] = (T)v;
       }
     }
@@ -448,14 +483,18 @@ __device__ __forceinline__ void row_tiles(const RowArgs &g, int64_t t0, int64_t 
 // One wave per row i = (alpha, p).  Upper rows (j >= i): the diagonal A-block
 // from beta itself on (positions < len(alpha)), then tiles alpha' > alpha.
 // Lower rows (j < i): tiles alpha' < alpha, then the diagonal A-block entries
-// before beta.  Both lists come out in ascending column order.
+// before beta.  Both lists come out in ascending column order.  beta's L1
+// list (at most a few hundred entries for these bases) is first copied to
+// LDS, so the per-tile binary searches and the expansion read it there.
 template <int W, bool FILL, typename T, bool LOWER>
 __global__ __launch_bounds__(256) void k_row_pass(RowArgs g) {
+  __shared__ int32_t s_pos[4][kL1Stage], s_info[4][FILL ? kL1Stage : 1], s_seg[4][kMaxSeg + 2];
   // plain block order: rows of very different lengths sit in runs, and
   // giving each XCD one contiguous range of rows (for L2 locality of the
   // tile lists) measured 30-40% slower from the imbalance between XCDs
   const int64_t i = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x >> 6);
   if (i >= g.D) return;
+  const int wv = threadIdx.x >> 6, lane = lane_id();
   const int alpha = g.row_a[i], p = g.row_p[i];
   const int beta = g.bseg_start[g.a_seg[alpha]] + p;
   const int len_a = g.a_len[alpha];
@@ -466,15 +505,37 @@ __global__ __launch_bounds__(256) void k_row_pass(RowArgs g) {
     load_bits<W>(g.b_bits, g.nB, beta, bb);
   }
   const int64_t out = FILL ? g.row_ptr[i] : 0;
+  const int64_t l1b = (int64_t)beta * g.nseg;
+  const int64_t base = g.l1_seg[l1b];
+  const int64_t n1 = g.l1_seg[l1b + g.nseg] - base;
   int64_t cnt = 0;
-  if (!LOWER) {
-    row_diag<W, FILL, T>(g, g.ls_self[beta], g.ls_ptr[beta + 1], alpha, len_a, off_a, ab, bb, out, cnt);
-    row_tiles<W, FILL, T>(g, g.t_ptr[alpha], g.t_ptr[alpha + 1], beta, p, bb, out, cnt);
+  const int64_t t0 = g.t_ptr[(int64_t)alpha * g.tstride], t1 = g.t_ptr[(int64_t)(alpha + 1) * g.tstride];
+  if (n1 <= kL1Stage && g.nseg <= kMaxSeg + 1) {
+    for (int64_t k = lane; k < n1; k += kWave) {
+      s_pos[wv][k] = g.l1_pos[base + k];
+      if (FILL) s_info[wv][k] = g.l1_info[base + k];
+    }
+    for (int h = lane; h <= g.nseg; h += kWave) s_seg[wv][h] = (int32_t)(g.l1_seg[l1b + h] - base);
+    wave_lds_sync();
+    const L1View<true> L{s_seg[wv], nullptr, s_pos[wv], FILL ? s_info[wv] : nullptr};
+    if (!LOWER) {
+      row_diag<W, FILL, T>(g, g.ls_self[beta], g.ls_ptr[beta + 1], alpha, len_a, off_a, ab, bb, out, cnt);
+      row_tiles<W, FILL, T, true>(g, t0, t1, p, bb, out, cnt, L);
+    } else {
+      row_tiles<W, FILL, T, true>(g, t0, t1, p, bb, out, cnt, L);
+      row_diag<W, FILL, T>(g, g.ls_ptr[beta], g.ls_self[beta], alpha, len_a, off_a, ab, bb, out, cnt);
+    }
   } else {
-    row_tiles<W, FILL, T>(g, g.t_ptr[alpha], g.t_ptr[alpha + 1], beta, p, bb, out, cnt);
-    row_diag<W, FILL, T>(g, g.ls_ptr[beta], g.ls_self[beta], alpha, len_a, off_a, ab, bb, out, cnt);
+    const L1View<false> L{nullptr, g.l1_seg + l1b, g.l1_pos, g.l1_info};
+    if (!LOWER) {
+      row_diag<W, FILL, T>(g, g.ls_self[beta], g.ls_ptr[beta + 1], alpha, len_a, off_a, ab, bb, out, cnt);
+      row_tiles<W, FILL, T, false>(g, t0, t1, p, bb, out, cnt, L);
+    } else {
+      row_tiles<W, FILL, T, false>(g, t0, t1, p, bb, out, cnt, L);
+      row_diag<W, FILL, T>(g, g.ls_ptr[beta], g.ls_self[beta], alpha, len_a, off_a, ab, bb, out, cnt);
+    }
   }
-  if (!FILL && lane_id() == 0) g.rcnt[i] = (int32_t)cnt;
+  if (!FILL && lane == 0) g.rcnt[i] = (int32_t)cnt;
 }
 
 // ------------------------------------------------------------ exclusive scan
@@ -495,13 +556,33 @@ __device__ int64_t block_excl_scan(int64_t v, int64_t *lds, int64_t &total) {
   return wbase + incl - v;
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const int32_t *in, int64_t n,
-                                                              int64_t *bsum) {
+// Several independent exclusive scans in one set of three launches: the
+// tiles of all arrays form one grid (block -> array through blk0), the
+// per-tile totals of each array are scanned by one block per array, and the
+// down-sweep writes every array's offsets and its total.
+struct ScanSet {
+  int n_arrays;
+  const int32_t *in[kScanArrays];
+  int64_t *out[kScanArrays];
+  int64_t n[kScanArrays];
+  int64_t blk0[kScanArrays + 1];   // first tile of each array; blk0[n_arrays] = all tiles
+};
+
+__device__ __forceinline__ int scan_array_of(const ScanSet &S, int64_t b) {
+  int k = 0;
+  while (k + 1 < S.n_arrays && b >= S.blk0[k + 1]) ++k;
+  return k;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(ScanSet S, int64_t *bsum) {
   __shared__ int64_t lds[kScanThreads / kWave];
-  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  const int k = scan_array_of(S, blockIdx.x);
+  const int32_t *in = S.in[k];
+  const int64_t n = S.n[k];
+  const int64_t base = (blockIdx.x - S.blk0[k]) * kScanTile;
   int64_t s = 0;
-  for (int k = 0; k < kScanItems; ++k) {
-    const int64_t idx = base + (int64_t)k * kScanThreads + threadIdx.x;
+  for (int t = 0; t < kScanItems; ++t) {
+    const int64_t idx = base + (int64_t)t * kScanThreads + threadIdx.x;
     if (idx < n) s += in[idx];
   }
   int64_t total;
@@ -509,49 +590,71 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const int32_t *in,
   if (threadIdx.x == 0) bsum[blockIdx.x] = total;
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_top(int64_t *bsum, int64_t nb) {
+// one block per array: exclusive scan of its tile totals, in place; the
+// array's total goes to bsum[blk0[n_arrays] + k]
+__global__ __launch_bounds__(kScanThreads) void k_scan_top(ScanSet S, int64_t *bsum) {
   __shared__ int64_t lds[kScanThreads / kWave];
+  const int k = blockIdx.x;
+  const int64_t b0 = S.blk0[k], nb = S.blk0[k + 1] - b0;
   int64_t carry = 0;
   for (int64_t c0 = 0; c0 < nb; c0 += kScanThreads) {
     const int64_t idx = c0 + threadIdx.x;
-    const int64_t v = idx < nb ? bsum[idx] : 0;
+    const int64_t v = idx < nb ? bsum[b0 + idx] : 0;
     int64_t total;
     const int64_t ex = block_excl_scan(v, lds, total);
-    if (idx < nb) bsum[idx] = carry + ex;
+    if (idx < nb) bsum[b0 + idx] = carry + ex;
     carry += total;
   }
-  if (threadIdx.x == 0) bsum[nb] = carry;
+  if (threadIdx.x == 0) bsum[S.blk0[S.n_arrays] + k] = carry;
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_down(const int32_t *in, int64_t n,
-                                                            const int64_t *boff, int64_t *out) {
+__global__ __launch_bounds__(kScanThreads) void k_scan_down(ScanSet S, const int64_t *bsum) {
   __shared__ int64_t lds[kScanThreads / kWave];
-  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  const int k = scan_array_of(S, blockIdx.x);
+  const int32_t *in = S.in[k];
+  int64_t *out = S.out[k];
+  const int64_t n = S.n[k];
+  const int64_t lb = blockIdx.x - S.blk0[k];
+  const int64_t base = lb * kScanTile + (int64_t)threadIdx.x * kScanItems;
   int32_t v[kScanItems];
   int64_t s = 0;
 #pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    v[k] = base + k < n ? in[base + k] : 0;
-    s += v[k];
+  for (int t = 0; t < kScanItems; ++t) {
+    v[t] = base + t < n ? in[base + t] : 0;
+    s += v[t];
   }
   int64_t total;
-  int64_t run = boff[blockIdx.x] + block_excl_scan(s, lds, total);
+  int64_t run = bsum[blockIdx.x] + block_excl_scan(s, lds, total);
 #pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    if (base + k < n) out[base + k] = run;
-    run += v[k];
+  for (int t = 0; t < kScanItems; ++t) {
+    if (base + t < n) out[base + t] = run;
+    run += v[t];
   }
-  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = boff[gridDim.x];
+  if (blockIdx.x == S.blk0[k + 1] - 1 && threadIdx.x == 0) out[n] = bsum[S.blk0[S.n_arrays] + k];
 }
 
-size_t scan_scratch(int64_t n) { return (size_t)((n + kScanTile - 1) / kScanTile + 2); }
+size_t scan_scratch(const std::vector<int64_t> &ns) {
+  size_t t = 0;
+  for (int64_t n : ns) t += (size_t)std::max<int64_t>(1, (n + kScanTile - 1) / kScanTile);
+  return t + ns.size();
+}
 
-void launch_scan(const int32_t *in, int64_t n, int64_t *out, int64_t *scratch, hipStream_t s) {
-  const int64_t nb = std::max<int64_t>(1, (n + kScanTile - 1) / kScanTile);
-  hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, n, scratch);
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, s, scratch, nb);
-  hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, n,
-                     (const int64_t *)scratch, out);
+void launch_scans(const std::vector<ScanJob> &jobs, int64_t *scratch, hipStream_t s) {
+  CIB_REQUIRE(!jobs.empty() && jobs.size() <= (size_t)kScanArrays, CIB_E_INVALID, "scan batch size");
+  ScanSet S{};
+  S.n_arrays = (int)jobs.size();
+  int64_t nb = 0;
+  for (int k = 0; k < S.n_arrays; ++k) {
+    S.in[k] = jobs[k].in;
+    S.out[k] = jobs[k].out;
+    S.n[k] = jobs[k].n;
+    S.blk0[k] = nb;
+    nb += std::max<int64_t>(1, (jobs[k].n + kScanTile - 1) / kScanTile);
+  }
+  S.blk0[S.n_arrays] = nb;
+  hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, S, scratch);
+  hipLaunchKernelGGL(k_scan_top, dim3((unsigned)S.n_arrays), dim3(kScanThreads), 0, s, S, scratch);
+  hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kScanThreads), 0, s, S, (const int64_t *)scratch);
   CIB_HIP(hipGetLastError());
 }
 
@@ -651,34 +754,39 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
   launch_substate_energy(b, it, eA.p, eB.p, s);
 
   // ---- counting passes of the two screens (tiles of both triangles)
-  DBuf<int32_t> tcnt(ctx, nA), tlcnt(ctx, nA), ls_cnt(ctx, nB), l1_cnt(ctx, (size_t)nB * nseg);
-  DBuf<int64_t> t_ptr(ctx, nA + 1), tl_ptr(ctx, nA + 1), ls_ptr(ctx, nB + 1), l1_seg(ctx, (size_t)nB * nseg + 1);
-  const int64_t nscr = std::max(scan_scratch(p.D), scan_scratch((int64_t)nB * nseg));
+  const int nchunk = (nA + kTileChunk - 1) / kTileChunk;
+  const int64_t nunit = (int64_t)nA * nchunk;
+  DBuf<int32_t> tcnt(ctx, nunit), tlcnt(ctx, nunit), ls_cnt(ctx, nB), l1_cnt(ctx, (size_t)nB * nseg);
+  DBuf<int64_t> t_ptr(ctx, nunit + 1), tl_ptr(ctx, nunit + 1), ls_ptr(ctx, nB + 1), l1_seg(ctx, (size_t)nB * nseg + 1);
+  const int64_t nscr = std::max(scan_scratch({nunit, nunit, nB, (int64_t)nB * nseg}), scan_scratch({p.D, p.D}));
   DBuf<int64_t> scratch(ctx, nscr), totals(ctx, 4);
   TileArgs ta{};
-  ta.nA = nA; ta.a_bits = b.a_bits.p; ta.a_m2 = b.a_m2.p; ta.a_len = b.a_len.p;
+  ta.nA = nA; ta.nchunk = nchunk; ta.a_bits = b.a_bits.p; ta.a_m2 = b.a_m2.p; ta.a_len = b.a_len.p;
   ta.a_seg = b.a_seg.p; ta.a_off = b.a_off.p; ta.it = it; ta.tcnt = tcnt.p;
   TileArgs tl = ta;
   tl.tcnt = tlcnt.p;
-  const unsigned tblk = (unsigned)((nA + 3) / 4);
+  const unsigned tblk = (unsigned)((nunit + 3) / 4);
   {
     KTimer kt(ctx, K_TILE, s);
     hipLaunchKernelGGL((k_tile_pass<W, false, false>), dim3(tblk), dim3(256), 0, s, ta);
     hipLaunchKernelGGL((k_tile_pass<W, false, true>), dim3(tblk), dim3(256), 0, s, tl);
   }
   AdjArgs aa{};
-  aa.nB = nB; aa.nseg = nseg; aa.b_bits = b.b_bits.p; aa.b_seg = b.b_seg.p;
+  aa.nB = nB; aa.nseg = nseg; aa.b_bits = b.b_bits.p; aa.b_seg = b.b_seg.p; aa.b_m2 = b.b_m2.p;
   aa.bseg_start = b.bseg_start.p; aa.eB = eB.p; aa.it = it; aa.ls_cnt = ls_cnt.p; aa.l1_cnt = l1_cnt.p;
-  const unsigned ablk = (unsigned)((nB + 3) / 4);
+  aa.max_dm = 0;
+  if (p.ns == 2 && !p.oB.twom.empty())
+    aa.max_dm = *std::max_element(p.oB.twom.begin(), p.oB.twom.end()) -
+                *std::min_element(p.oB.twom.begin(), p.oB.twom.end());
+  const unsigned ablk = (unsigned)(((int64_t)nB * nseg + 3) / 4);
   { KTimer kt(ctx, K_ADJ, s); hipLaunchKernelGGL((k_adj_pass<W, false>), dim3(ablk), dim3(256), 0, s, aa); }
   CIB_HIP(hipGetLastError());
-  launch_scan(tcnt.p, nA, t_ptr.p, scratch.p, s);
-  launch_scan(tlcnt.p, nA, tl_ptr.p, scratch.p, s);
-  launch_scan(ls_cnt.p, nB, ls_ptr.p, scratch.p, s);
-  launch_scan(l1_cnt.p, (int64_t)nB * nseg, l1_seg.p, scratch.p, s);
+  launch_scans({{tcnt.p, nunit, t_ptr.p}, {tlcnt.p, nunit, tl_ptr.p}, {ls_cnt.p, nB, ls_ptr.p},
+                {l1_cnt.p, (int64_t)nB * nseg, l1_seg.p}},
+               scratch.p, s);
   CIB_HIP(hipEventRecord(ev.e[1], s));
   int64_t n4[4];
-  read_totals({t_ptr.p + nA, tl_ptr.p + nA, ls_ptr.p + nB, l1_seg.p + (int64_t)nB * nseg}, totals.p, n4, s);
+  read_totals({t_ptr.p + nunit, tl_ptr.p + nunit, ls_ptr.p + nB, l1_seg.p + (int64_t)nB * nseg}, totals.p, n4, s);
   const int64_t n_tiles = n4[0], n_lt = n4[1], n_ls = n4[2], n_l1 = n4[3];
 
   // ---- filling passes of the two screens
@@ -709,7 +817,7 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
   ra.D = p.D; ra.nA = nA; ra.nB = nB; ra.nseg = nseg;
   ra.row_a = b.row_a.p; ra.row_p = b.row_p.p; ra.a_seg = b.a_seg.p; ra.a_len = b.a_len.p;
   ra.bseg_start = b.bseg_start.p; ra.a_off = b.a_off.p; ra.a_bits = b.a_bits.p; ra.b_bits = b.b_bits.p;
-  ra.eA = eA.p; ra.t_ptr = t_ptr.p; ra.t_off = t_off.p; ra.t_len = t_len.p; ra.t_info = t_info.p;
+  ra.eA = eA.p; ra.t_ptr = t_ptr.p; ra.tstride = nchunk; ra.t_off = t_off.p; ra.t_len = t_len.p; ra.t_info = t_info.p;
   ra.t_val = t_val.p; ra.ls_ptr = ls_ptr.p; ra.l1_seg = l1_seg.p; ra.ls_self = ls_self.p;
   ra.ls_pos = ls_pos.p; ra.ls_info = ls_info.p; ra.l1_pos = l1_pos.p; ra.l1_info = l1_info.p;
   ra.ls_val = ls_val.p; ra.it = it;
@@ -730,8 +838,7 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
   H.lo_ptr.reset(ctx, p.D + 1);
   {
     KTimer kt(ctx, K_SCAN, s);
-    launch_scan(rcnt.p, p.D, H.row_ptr.p, scratch.p, s);
-    launch_scan(rlcnt.p, p.D, H.lo_ptr.p, scratch.p, s);
+    launch_scans({{rcnt.p, p.D, H.row_ptr.p}, {rlcnt.p, p.D, H.lo_ptr.p}}, scratch.p, s);
   }
   CIB_HIP(hipEventRecord(ev.e[5], s));
   int64_t n2[2];

@@ -218,9 +218,17 @@ void launch_substate_energy(const cib_basis &b, const DevInter &it, double *eA, 
                             hipStream_t s);
 void launch_dab(const DevInter &it, double *dab, hipStream_t s);
 
-// exclusive scan of n int32 counts into n+1 int64 offsets; scratch >= scan_scratch(n)
-size_t scan_scratch(int64_t n);
-void launch_scan(const int32_t *in, int64_t n, int64_t *out, int64_t *scratch, hipStream_t s);
+// Exclusive scans of int32 counts into int64 offsets (n + 1 values each, the
+// last one the total), up to kScanArrays independent arrays per call;
+// scratch >= scan_scratch(sizes) int64 values.
+constexpr int kScanArrays = 4;
+struct ScanJob {
+  const int32_t *in;
+  int64_t n;
+  int64_t *out;
+};
+size_t scan_scratch(const std::vector<int64_t> &ns);
+void launch_scans(const std::vector<ScanJob> &jobs, int64_t *scratch, hipStream_t s);
 
 // Build H on stream s.  before_fill(nnz) runs on the host once the nonzero
 // count is known and before the CSR arrays are allocated (it may block).
