@@ -727,6 +727,22 @@ static void read_totals(std::initializer_list<const int64_t *> src, int64_t *scr
   CIB_HIP(hipStreamSynchronize(s));
 }
 
+// out[x] = first row i with rp[i] + lrp[i] >= x / 8 of all stored entries
+// (both triangles), x = 0 .. 8: row ranges of equal work for the 8 XCDs.
+__global__ void k_xcd_rows(int64_t D, const int64_t *rp, const int64_t *lrp, int64_t *out) {
+  const int x = threadIdx.x;
+  if (x > 8) return;
+  const int64_t total = rp[D] + lrp[D];
+  const int64_t target = x == 8 ? total + 1 : (total / 8) * x + (total % 8) * x / 8;
+  int64_t lo = 0, hi = D;
+  while (lo < hi) {
+    const int64_t m = (lo + hi) >> 1;
+    if (rp[m] + lrp[m] < target) lo = m + 1;
+    else hi = m;
+  }
+  out[x] = x == 8 ? D : lo;
+}
+
 struct Events {
   hipEvent_t e[9];
   Events() { for (auto &x : e) CIB_HIP(hipEventCreate(&x)); }
@@ -880,6 +896,10 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
   }
   CIB_HIP(hipGetLastError());
   CIB_HIP(hipEventRecord(ev.e[8], s));
+  DBuf<int64_t> xr(ctx, 9);
+  hipLaunchKernelGGL(k_xcd_rows, dim3(1), dim3(64), 0, s, p.D, H.row_ptr.p, H.lo_ptr.p, xr.p);
+  CIB_HIP(hipGetLastError());
+  CIB_HIP(hipMemcpyAsync(H.xcd_rows, xr.p, sizeof(H.xcd_rows), hipMemcpyDeviceToHost, s));
   CIB_HIP(hipStreamSynchronize(s));
 
   H.D = p.D;

@@ -205,6 +205,8 @@ struct cib_matrix {
   cib::DBuf<double> lo_val64;
   cib::DBuf<float> lo_val32;
   cib_build_stats stats{};
+  // row ranges of equal stored entries (both triangles), one per XCD
+  int64_t xcd_rows[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   const void *lo_val() const { return dtype == CIB_F64 ? (const void *)lo_val64.p : (const void *)lo_val32.p; }
   const void *val() const { return dtype == CIB_F64 ? (const void *)val64.p : (const void *)val32.p; }
 };
