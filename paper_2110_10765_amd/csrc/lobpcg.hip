@@ -355,7 +355,8 @@ __device__ __forceinline__ int sturm_count(const double *d, const double *e2, in
 // C_x = scale * Z^T y and C_p = C_x with the X rows zeroed (P = W C_W + P C_P).
 __global__ __launch_bounds__(256) void k_rayleigh_ritz(RRArgs g) {
   __shared__ double G[kNS][kLd], Hm[kNS][kLd], Z[kNS][kLd];
-  __shared__ double scale[kNS], dd[kNS], ee[kNS], e2[kNS], beta[kNS], vv[kNS], pp[kNS], dinv[kNS];
+  __shared__ double scale[kNS], dd[kNS], ee[kNS], e2[kNS], beta[kNS], dinv[kNS];
+  __shared__ double pw[4][kNS];
   __shared__ double theta[kMaxBlock];
   __shared__ int keep[kNS], kidx[kNS];
   __shared__ int rank_s, retry_s;
@@ -396,10 +397,15 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz(RRArgs g) {
   }
   __syncthreads();
   if (g.clk && tid == 0) g.clk[2] = wall_clock64();
-  // 3. right-looking Cholesky with dropping, on wave 0 with one lane per row
-  //    (the steps are sequential; LDS traffic between lanes needs no barrier)
-  if (tid < kWave) {
-    const int i = tid;
+  // 3. right-looking Cholesky with dropping.  Lane i of every wave owns row
+  //    i; the trailing update of step k is split over the waves by column
+  //    (wave w takes columns k + 1 + w, k + 1 + w + nw, ...), and column k of
+  //    L reaches the other lanes through lane reads.  Every wave reads the
+  //    unscaled column k in step k, so wave 0 writes the scaled column back
+  //    one step later.
+  {
+    const int i = tid & (kWave - 1), wv = tid >> 6, nw = nt >> 6;
+    double lprev = 0.0, dprev = 0.0;
     for (int k = 0; k < ns; ++k) {
       const double piv = G[k][k];
       const bool kk = scale[k] > 0.0 && piv > drop_tol;   // every lane decides the same
@@ -408,33 +414,30 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz(RRArgs g) {
       y = y * fma(-0.5 * (kk ? piv : 1.0) * y, y, 1.5);
       const double ilkk = kk ? y : 0.0;
       const double lkk = kk ? piv * y : 0.0;
-      double lik = 0.0;
-      if (i > k && i < ns) {
-        lik = G[i][k] * ilkk;
-        G[i][k] = lik;
+      const double lik = (i > k && i < ns) ? G[i][k] * ilkk : 0.0;
+      if (wv == 0 && k > 0) {   // column k - 1 of L, read by nobody in this step
+        if (i > k - 1 && i < ns) G[i][k - 1] = lprev;
+        if (i == k - 1) G[i][i] = dprev;
       }
-      if (i == k) {
-        G[k][k] = lkk;
-        keep[k] = kk;
-      }
-      wave_lds_sync();
-      if (kk && i > k && i < ns) {
-        // all reads of a batch before its writes: one LDS round trip per 8
-        for (int j0 = k + 1; j0 <= i; j0 += 8) {
-          double cv[8], rv[8];
-#pragma unroll
-          for (int t = 0; t < 8; ++t) {
-            const int j = min(j0 + t, i);
-            cv[t] = G[j][k];
-            rv[t] = G[i][j];
-          }
-#pragma unroll
-          for (int t = 0; t < 8; ++t)
-            if (j0 + t <= i) G[i][j0 + t] = rv[t] - lik * cv[t];
+      if (tid == 0) keep[k] = kk;
+      if (kk) {
+        for (int j = k + 1 + wv; j < ns; j += nw) {
+          const double ljk = readlane_f64(lik, j);
+          if (i >= j && i < ns) G[i][j] -= lik * ljk;
         }
       }
-      wave_lds_sync();
+      lprev = lik;
+      dprev = lkk;
+      __syncthreads();
     }
+    if (wv == 0 && ns > 0) {
+      if (i > ns - 1 && i < ns) G[i][ns - 1] = lprev;
+      if (i == ns - 1) G[i][i] = dprev;
+    }
+    __syncthreads();
+  }
+  if (tid < kWave) {
+    const int i = tid;
     if (g.clk && i == 0) g.clk[3] = wall_clock64();
     const bool kp = i < ns && keep[i];
     const uint64_t km = __ballot(kp);
@@ -546,11 +549,15 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz(RRArgs g) {
   }
   __syncthreads();
   if (g.clk && tid == 0) g.clk[5] = wall_clock64();
-  // 5. Householder tridiagonalisation of M (r x r in Hm) on wave 0, one lane
-  //    per row; the reflector of step k is kept in column k below the
-  //    subdiagonal, its scale in beta[k]
-  if (tid < kWave) {
-    const int i = tid;
+  // 5. Householder tridiagonalisation of M (r x r in Hm).  Lane i of every
+  //    wave owns row i and computes the reflector redundantly (DPP sums, so
+  //    every wave gets the same bits); the product with the trailing block
+  //    and the rank-2 update are split over the waves by column ranges, and
+  //    the partial products are combined in LDS in wave order.  The
+  //    reflector of step k is kept in column k below the subdiagonal, its
+  //    scale in beta[k].
+  {
+    const int i = tid & (kWave - 1), wv = tid >> 6;
     const bool row = i < r;
     for (int k = 0; k + 2 < r; ++k) {
       const bool act = row && i > k;
@@ -562,54 +569,31 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz(RRArgs g) {
       const double alpha = refl ? -copysign(sqrt(sigma), x0) : x0;
       const double bk = refl ? 2.0 / (tail + (x0 - alpha) * (x0 - alpha)) : 0.0;
       const double vi = i == k + 1 ? x0 - alpha : xi;
-      if (i < kNS) vv[i] = vi;
-      wave_lds_sync();
-      double acc0 = 0.0, acc1 = 0.0;
-      if (act) {
-        for (int j0 = k + 1; j0 < r; j0 += 8) {
-          double hv[8], xv[8];
-#pragma unroll
-          for (int t = 0; t < 8; ++t) {
-            const int j = min(j0 + t, r - 1);
-            hv[t] = Hm[i][j];
-            xv[t] = vv[j];
-          }
-#pragma unroll
-          for (int t = 0; t < 8; t += 2) {
-            if (j0 + t < r) acc0 += hv[t] * xv[t];
-            if (j0 + t + 1 < r) acc1 += hv[t + 1] * xv[t + 1];
-          }
-        }
+      const int m = r - k - 1;
+      const int q = (m + 3) / 4;
+      const int j0 = k + 1 + wv * q, j1 = min(r, j0 + q);
+      double acc = 0.0;
+      for (int j = j0; j < j1; ++j) {
+        const double vj = readlane_f64(vi, j);
+        if (act) acc += Hm[i][j] * vj;
       }
-      const double pi = bk * (acc0 + acc1);
+      if (i < kNS) pw[wv][i] = acc;
+      __syncthreads();
+      const double pi = i < kNS ? bk * ((pw[0][i] + pw[1][i]) + (pw[2][i] + pw[3][i])) : 0.0;
       const double K = 0.5 * bk * wave_sum_dpp(vi * pi);
       const double wi = pi - K * vi;
-      if (i < kNS) pp[i] = wi;
-      wave_lds_sync();
-      if (act) {
-        for (int j0 = k + 1; j0 < r; j0 += 8) {
-          double hv[8], wv[8], xv[8];
-#pragma unroll
-          for (int t = 0; t < 8; ++t) {
-            const int j = min(j0 + t, r - 1);
-            hv[t] = Hm[i][j];
-            wv[t] = pp[j];
-            xv[t] = vv[j];
-          }
-#pragma unroll
-          for (int t = 0; t < 8; ++t)
-            if (j0 + t < r) Hm[i][j0 + t] = hv[t] - (vi * wv[t] + wi * xv[t]);
-        }
-        Hm[i][k] = vi;
+      for (int j = j0; j < j1; ++j) {
+        const double vj = readlane_f64(vi, j), wj = readlane_f64(wi, j);
+        if (act) Hm[i][j] -= vi * wj + wi * vj;
       }
-      if (i == 0) {
+      if (wv == 0 && act) Hm[i][k] = vi;
+      if (tid == 0) {
         beta[k] = bk;
         ee[k] = alpha;
       }
-      wave_lds_sync();
+      __syncthreads();
     }
   }
-  __syncthreads();
   for (int i = tid; i < r; i += nt) {
     dd[i] = Hm[i][i];
     if (i == r - 2) ee[i] = Hm[r - 1][r - 2];
