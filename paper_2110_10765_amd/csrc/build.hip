@@ -116,6 +116,79 @@ __global__ void k_dab(DevInter it, double *dab) {
   dab[k] = vab(it, x, y, x, y);
 }
 
+// One thread per entry of the transition table: find the entry's block, its
+// A transition (row) and B transition (column), read V^AB from the blocked
+// pair table.
+__global__ void k_build_vt(DevInter it, const VtBlock *blk, int nblk, const int32_t *atr,
+                           const int32_t *btr, int64_t total, double *vt) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  int g = 0;
+  while (g + 1 < nblk && blk[g + 1].base <= e) ++g;
+  const VtBlock B = blk[g];
+  const int64_t r = e - B.base;
+  const int32_t ta = atr[B.a0 + (int)(r / B.nb)], tb = btr[B.b0 + (int)(r % B.nb)];
+  vt[e] = vab(it, ta >> 16, tb >> 16, ta & 0xffff, tb & 0xffff);
+}
+
+// V^AB_{(a,b),(c,d)} through the transition table (row base of a <- c from
+// the tile, column of b <- d from the B adjacency entry).
+__device__ __forceinline__ double vt_at(const DevInter &it, int32_t rb, int32_t col) { return it.vt[rb + col]; }
+
+// Sum of f(k) over the set bits k of s (at most 64 * W), in ascending k, with
+// the table reads of four terms issued before their additions.  Skipped terms
+// are not added, so the result equals the plain ascending loop bit for bit.
+template <int W, typename F>
+__device__ __forceinline__ double sum_over_bits(const uint64_t *s, F f) {
+  uint64_t t[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) t[w] = s[w];
+  double sum = 0.0;
+  for (;;) {
+    const int k0 = pop_lowest<W>(t), k1 = pop_lowest<W>(t), k2 = pop_lowest<W>(t), k3 = pop_lowest<W>(t);
+    const double v0 = k0 >= 0 ? f(k0) : 0.0, v1 = k1 >= 0 ? f(k1) : 0.0;
+    const double v2 = k2 >= 0 ? f(k2) : 0.0, v3 = k3 >= 0 ? f(k3) : 0.0;
+    if (k0 >= 0) sum += v0;
+    if (k1 >= 0) sum += v1;
+    if (k2 >= 0) sum += v2;
+    if (k3 < 0) break;
+    sum += v3;
+  }
+  return sum;
+}
+
+// Diagonal element of every state, E_A(alpha) + E_B(beta) + sum over the
+// occupied pairs (x in alpha, y in beta) of V^AB_{(x,y),(x,y)}; one thread
+// per state, added in the order the row pass used to add them.
+template <int W>
+__global__ __launch_bounds__(256) void k_state_diag(int64_t D, const int32_t *__restrict__ row_a,
+                                                    const int32_t *__restrict__ row_p,
+                                                    const int32_t *__restrict__ a_seg,
+                                                    const int32_t *__restrict__ bseg_start,
+                                                    const uint64_t *__restrict__ a_bits, int nA,
+                                                    const uint64_t *__restrict__ b_bits, int nB,
+                                                    const double *__restrict__ eA, const double *__restrict__ eB,
+                                                    DevInter it, double *__restrict__ diag) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= D) return;
+  const int alpha = row_a[i];
+  const int beta = bseg_start[a_seg[alpha]] + row_p[i];
+  double v = eB[beta];
+  v += eA[alpha];
+  if (it.nB > 0) {
+    uint64_t ab[W], bb[W];
+    load_bits<W>(a_bits, nA, alpha, ab);
+    load_bits<W>(b_bits, nB, beta, bb);
+    for (int x = pop_lowest<W>(ab); x >= 0; x = pop_lowest<W>(ab)) {
+      uint64_t u[W];
+#pragma unroll
+      for (int w = 0; w < W; ++w) u[w] = bb[w];
+      for (int y = pop_lowest<W>(u); y >= 0; y = pop_lowest<W>(u)) v += it.dab[x * it.nB + y];
+    }
+  }
+  diag[i] = v;
+}
+
 // ------------------------------------------------------------ tile screen
 // One wave per A configuration alpha; lanes over alpha' > alpha (or < alpha for
 // the lower triangle).  Kept: kA = 1, or kA = 2 with equal 2M_A (a kA = 2 pair
@@ -131,7 +204,7 @@ struct TileArgs {
   int32_t *tcnt;          // count pass: per unit
   const int64_t *t_ptr;   // fill pass: per unit
   int64_t *t_off;
-  int32_t *t_len, *t_info;
+  int32_t *t_len, *t_info, *t_rb;
   double *t_val;
 };
 
@@ -143,7 +216,7 @@ constexpr int kTileChunk = 256;   // candidate configurations per wave
 // the per-unit counts lists each alpha's tiles in ascending alpha'.
 template <int W, bool FILL, bool LOWER>
 __global__ __launch_bounds__(256) void k_tile_pass(TileArgs g) {
-  const int64_t unit = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+  const int64_t unit = blockIdx.x * (int64_t)(blockDim.x / kWave) + uni((int)(threadIdx.x >> 6));
   if (unit >= (int64_t)g.nA * g.nchunk) return;
   const int alpha = (int)(unit / g.nchunk), chunk = (int)(unit % g.nchunk);
   const int lane = lane_id();
@@ -155,8 +228,10 @@ __global__ __launch_bounds__(256) void k_tile_pass(TileArgs g) {
   }
   uint64_t ra[W];
   load_bits<W>(g.a_bits, g.nA, alpha, ra);
-  const int m = g.a_m2[alpha];
-  int64_t out = FILL ? g.t_ptr[unit] : 0;
+#pragma unroll
+  for (int w = 0; w < W; ++w) ra[w] = uni(ra[w]);
+  const int m = uni(g.a_m2[alpha]);
+  int64_t out = FILL ? uni(g.t_ptr[unit]) : 0;
   int cnt = 0;
   for (int j0 = jb; j0 < je; j0 += kWave) {
     const int j = j0 + lane;
@@ -190,6 +265,7 @@ __global__ __launch_bounds__(256) void k_tile_pass(TileArgs g) {
           sum += vbar_same(g.it.pidxA, g.it.prowA, g.it.nA, g.it.vA, p1, x, h1);
         val = s * sum;
         info = 1 | (p1 << 2) | (h1 << 10) | ((s < 0) << 18) | (g.a_seg[j] << 19);
+        g.t_rb[o] = g.it.arb ? g.it.arb[p1 * g.it.nA + h1] : 0;
       } else {       // kA = 2
         const int s = sign_double<W>(ca, p1, p2, h1, h2);
         val = s * v_pair(g.it.pidxA, g.it.prowA, g.it.nA, g.it.vA, p1, p2, h1, h2);
@@ -208,7 +284,9 @@ __global__ __launch_bounds__(256) void k_tile_pass(TileArgs g) {
 // list with popcount <= 4, ascending position; carries the B-only value part.
 // L1(beta): beta' in any list with popcount <= 2, grouped by list, ascending.
 // A list whose 2M_B differs from beta's by more than one orbital change can
-// shift it (max_dm) holds no L1 entry and is not scanned.
+// shift it (max_dm) holds no L1 entry and is not scanned.  Entry info:
+// orbitals changed (0, 1, 2) | phase bit << 2 | (one change b <- d) the column
+// of b <- d in the V^AB transition table << 3.
 struct AdjArgs {
   int nB, nseg, max_dm;
   const uint64_t *b_bits;
@@ -223,12 +301,12 @@ struct AdjArgs {
 
 template <int W, bool FILL>
 __global__ __launch_bounds__(256) void k_adj_pass(AdjArgs g) {
-  const int64_t unit = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+  const int64_t unit = blockIdx.x * (int64_t)(blockDim.x / kWave) + uni((int)(threadIdx.x >> 6));
   if (unit >= (int64_t)g.nB * g.nseg) return;
   const int beta = (int)(unit / g.nseg), h = (int)(unit % g.nseg);
   const int lane = lane_id();
-  const int gs = g.b_seg[beta];
-  const int lo = g.bseg_start[h], hi = g.bseg_start[h + 1];
+  const int gs = uni(g.b_seg[beta]);
+  const int lo = uni(g.bseg_start[h]), hi = uni(g.bseg_start[h + 1]);
   const bool own = h == gs;
   if (!own && (hi <= lo || abs(g.b_m2[lo] - g.b_m2[beta]) > g.max_dm)) {
     if (!FILL && lane == 0) g.l1_cnt[unit] = 0;
@@ -236,9 +314,11 @@ __global__ __launch_bounds__(256) void k_adj_pass(AdjArgs g) {
   }
   uint64_t rb[W];
   load_bits<W>(g.b_bits, g.nB, beta, rb);
+#pragma unroll
+  for (int w = 0; w < W; ++w) rb[w] = uni(rb[w]);
   int c_ls = 0, c_l1 = 0;
-  const int64_t ls0 = FILL && own ? g.ls_ptr[beta] : 0;
-  const int64_t l10 = FILL ? g.l1_seg[unit] : 0;
+  const int64_t ls0 = FILL && own ? uni(g.ls_ptr[beta]) : 0;
+  const int64_t l10 = FILL ? uni(g.l1_seg[unit]) : 0;
   for (int j0 = lo; j0 < hi; j0 += kWave) {
     const int j = j0 + lane;
     int d = 99;
@@ -266,7 +346,7 @@ __global__ __launch_bounds__(256) void k_adj_pass(AdjArgs g) {
         val = g.eB[beta];
       } else if (d == 2) {
         sg = sign_single<W>(cb, p1, h1);
-        info = 1 | (p1 << 2) | (h1 << 10) | ((sg < 0) << 18);
+        info = 1 | ((sg < 0) << 2) | ((g.it.bcol ? g.it.bcol[p1 * g.it.nB + h1] : 0) << 3);
         if (in_ls) {
           double sum = 0.0;
           for (int y = pop_lowest<W>(common); y >= 0; y = pop_lowest<W>(common))
@@ -310,11 +390,12 @@ struct RowArgs {
   const double *eA;
   const int64_t *t_ptr, *t_off;   // t_ptr per tile unit: alpha's tiles at [alpha * tstride, (alpha + 1) * tstride]
   int tstride;
-  const int32_t *t_len, *t_info;
+  const int32_t *t_len, *t_info, *t_rb;
   const double *t_val;
   const int64_t *ls_ptr, *l1_seg;
   const int32_t *ls_self, *ls_pos, *ls_info, *l1_pos, *l1_info;
   const double *ls_val;
+  const double *diag;       // fill pass: diagonal element of every state
   DevInter it;
   int32_t *rcnt;            // count pass
   const int64_t *row_ptr;   // fill pass
@@ -325,7 +406,7 @@ struct RowArgs {
 // Diagonal A-block part of a row: Lsame(beta) entries [e0, e1) in position
 // order, kept while position < len(alpha) (a prefix).
 template <int W, bool FILL, typename T>
-__device__ __forceinline__ void row_diag(const RowArgs &g, int64_t e0, int64_t e1, int alpha,
+__device__ __forceinline__ void row_diag(const RowArgs &g, int64_t i, int64_t e0, int64_t e1, int alpha,
                                          int len_a, int64_t off_a, const uint64_t *ab,
                                          const uint64_t *bb, int64_t out, int64_t &cnt) {
   const int lane = lane_id();
@@ -340,27 +421,11 @@ __device__ __forceinline__ void row_diag(const RowArgs &g, int64_t e0, int64_t e
       double v = g.ls_val[k];
       const int kb = info & 3;
       if (kb == 0) {  // diagonal: E_A + E_B + sum_{x in alpha, y in beta} V^AB_{xy,xy}
-        v += g.eA[alpha];
-        if (g.it.nB > 0) {
-          uint64_t t[W];
-#pragma unroll
-          for (int w = 0; w < W; ++w) t[w] = ab[w];
-          for (int x = pop_lowest<W>(t); x >= 0; x = pop_lowest<W>(t)) {
-            uint64_t u[W];
-#pragma unroll
-            for (int w = 0; w < W; ++w) u[w] = bb[w];
-            for (int y = pop_lowest<W>(u); y >= 0; y = pop_lowest<W>(u)) v += g.it.dab[x * g.it.nB + y];
-          }
-        }
+        v = g.diag[i];
       } else if (kb == 1) {  // B single: + s_B sum_{x in alpha} V^AB_{(x,b),(x,d)}
-        const int b = (info >> 2) & 0xff, d = (info >> 10) & 0xff;
-        const double s = (info >> 18) & 1 ? -1.0 : 1.0;
-        double sum = 0.0;
-        uint64_t t[W];
-#pragma unroll
-        for (int w = 0; w < W; ++w) t[w] = ab[w];
-        for (int x = pop_lowest<W>(t); x >= 0; x = pop_lowest<W>(t)) sum += vab(g.it, x, b, x, d);
-        v += s * sum;
+        const int32_t bc = info >> 3;
+        const double s = (info >> 2) & 1 ? -1.0 : 1.0;
+        v += s * sum_over_bits<W>(ab, [&](int x) { return vt_at(g.it, g.it.arb[x * g.it.nA + x], bc); });
       }
       const int64_t o = out + cnt + (k - k0);
       g.col[o] = (int32_t)(off_a + g.ls_pos[k]);
@@ -379,10 +444,11 @@ template <bool ST>
 struct L1View {
   const int32_t *seg32;   // ST: nseg + 1 offsets relative to the list start
   const int64_t *seg64;   // !ST: absolute offsets of beta's segments
-  const int32_t *pos, *info;
-  __device__ __forceinline__ int64_t seg(int h) const {
+  int64_t base;           // !ST: absolute offset of the list start
+  const int32_t *pos, *info;   // indexed relative to the list start
+  __device__ __forceinline__ int seg(int h) const {
     if constexpr (ST) return seg32[h];
-    else return seg64[h];
+    else return (int)(seg64[h] - base);
   }
 };
 
@@ -392,13 +458,12 @@ struct L1View {
 // kA = 1 entries are expanded over all lanes of the wave.
 template <int W, bool FILL, typename T, bool ST>
 __device__ __forceinline__ void row_tiles(const RowArgs &g, int64_t t0, int64_t t1, int p, const uint64_t *bb,
-                                          int64_t out, int64_t &cnt, const L1View<ST> &L) {
+                                          int64_t out, int64_t &cnt, const L1View<ST> &L, int32_t *mark) {
   const int lane = lane_id();
   T *val = static_cast<T *>(g.val);
   for (int64_t tb = t0; tb < t1; tb += kWave) {
     const int64_t t = tb + lane;
-    int ne = 0, info = 0;
-    int64_t l0 = 0;
+    int ne = 0, info = 0, l0 = 0;
     if (t < t1) {
       info = g.t_info[t];
       const int len = g.t_len[t];
@@ -407,73 +472,71 @@ __device__ __forceinline__ void row_tiles(const RowArgs &g, int64_t t0, int64_t 
       } else {  // first entry of the sorted segment with position >= len
         const int gt = (info >> 19) & 0x7f;
         l0 = L.seg(gt);
-        int64_t lo = l0, hi = L.seg(gt + 1);
+        int lo = l0, hi = L.seg(gt + 1);
         while (lo < hi) {
-          const int64_t mid = (lo + hi) >> 1;
+          const int mid = (lo + hi) >> 1;
           if (L.pos[mid] < len) lo = mid + 1; else hi = mid;
         }
-        ne = (int)(lo - l0);
+        ne = lo - l0;
       }
     }
     const int incl = wave_incl_scan_dpp(ne);
-    const int total = __shfl(incl, kWave - 1, kWave);
+    const int total = __builtin_amdgcn_readlane(incl, kWave - 1);
     if (FILL) {
-      const int64_t o_lane = out + cnt + (incl - ne);
+      const int orel = incl - ne;   // lane's first output, relative to out + cnt
       const bool two = (info & 3) == 2;
-      int64_t coff = 0;
+      int32_t coff = 0, rb = 0;
       double tv = 0.0;
       if (ne) {
-        coff = g.t_off[t];
+        coff = (int32_t)g.t_off[t];
         tv = g.t_val[t];
       }
       if (two && ne) {
-        g.col[o_lane] = (int32_t)(coff + p);
-        val[o_lane] = (T)tv;
+        g.col[out + cnt + orel] = coff + p;
+        val[out + cnt + orel] = (T)tv;
       }
+      if (!two && ne) rb = g.t_rb[t];
       // kA = 1 entries, spread over the lanes
       const int n1 = two ? 0 : ne;
       const int incl1 = wave_incl_scan_dpp(n1);
-      const int tot1 = __shfl(incl1, kWave - 1, kWave);
-      // every shuffle below runs with the whole wave active (uniform loop)
+      const int tot1 = __builtin_amdgcn_readlane(incl1, kWave - 1);
+      const int st1 = incl1 - n1;
+      // Window of 64 entries: each tile marks the slot where its entries
+      // start (lane + 1), a prefix maximum spreads the marks, the owner of
+      // the slot before the window covers the slots ahead of the first mark.
+      // Every shuffle below runs with the whole wave active (uniform loop).
+      int carry = 0;
       for (int k0 = 0; k0 < tot1; k0 += kWave) {
         const int k = k0 + lane;
-        int lo = 0, hi = kWave - 1;  // owner: first lane with incl1 > k
-#pragma unroll
-        for (int step = 0; step < 6; ++step) {
-          const int mid = (lo + hi) >> 1;
-          const bool right = __shfl(incl1, mid, kWave) <= k;
-          lo = right ? mid + 1 : lo;
-          hi = right ? hi : mid;
-        }
-        const int own = lo;
-        const int q = k - (__shfl(incl1, own, kWave) - __shfl(n1, own, kWave));
+        mark[lane] = 0;
+        wave_lds_sync();
+        if (n1 > 0 && st1 >= k0 && st1 < k0 + kWave) mark[st1 - k0] = lane + 1;
+        wave_lds_sync();
+        const int own = max(wave_incl_max_dpp(mark[lane]), carry) - 1;
+        wave_lds_sync();
+        carry = __builtin_amdgcn_readlane(own + 1, kWave - 1);
+        const int q = k - __shfl(st1, own, kWave);
         const int oinfo = __shfl(info, own, kWave);
-        const int64_t ol0 = __shfl(l0, own, kWave);
-        const int64_t ocoff = __shfl(coff, own, kWave);
-        const double otv = __shfl(tv, own, kWave);
-        const int64_t oo = __shfl(o_lane, own, kWave);
+        const int ol0 = __shfl(l0, own, kWave);
+        const int ocoff = __shfl(coff, own, kWave);
+        const int orb = __shfl(rb, own, kWave);
+        const int oo = __shfl(orel, own, kWave);
         if (k >= tot1) continue;
-        const int a = (oinfo >> 2) & 0xff, c = (oinfo >> 10) & 0xff;
         const double sa = (oinfo >> 18) & 1 ? -1.0 : 1.0;
         const int li = L.info[ol0 + q];
         const int lp = L.pos[ol0 + q];
         double v;
         if ((li & 3) == 0) {  // B unchanged: AA part + s_A sum_{y in beta} V^AB_{(a,y),(c,y)}
           double sum = 0.0;
-          if (g.it.nB > 0) {
-            uint64_t u[W];
-#pragma unroll
-            for (int w = 0; w < W; ++w) u[w] = bb[w];
-            for (int y = pop_lowest<W>(u); y >= 0; y = pop_lowest<W>(u)) sum += vab(g.it, a, y, c, y);
-          }
-          v = otv + sa * sum;
+          if (g.it.nB > 0)
+            sum = sum_over_bits<W>(bb, [&](int y) { return vt_at(g.it, orb, g.it.bcol[y * g.it.nB + y]); });
+          v = g.t_val[tb + own] + sa * sum;
         } else {              // one A and one B orbital change
-          const int b = (li >> 2) & 0xff, d = (li >> 10) & 0xff;
-          const double sb = (li >> 18) & 1 ? -1.0 : 1.0;
-          v = sa * sb * vab(g.it, a, b, c, d);
+          const double sb = (li >> 2) & 1 ? -1.0 : 1.0;
+          v = sa * sb * vt_at(g.it, orb, li >> 3);
         }
-        g.col[oo + q] = (int32_t)(ocoff + lp);
-        val[oo + q] = (T)v;
+        g.col[out + cnt + oo + q] = ocoff + lp;
+        val[out + cnt + oo + q] = (T)v;
       }
     }
     cnt += total;
@@ -486,30 +549,37 @@ __device__ __forceinline__ void row_tiles(const RowArgs &g, int64_t t0, int64_t 
 // before beta.  Both lists come out in ascending column order.  beta's L1
 // list (at most a few hundred entries for these bases) is first copied to
 // LDS, so the per-tile binary searches and the expansion read it there.
+// Eight waves per SIMD (the most the hardware holds) are asked for
+// explicitly: the pass waits on chains of dependent reads, and the scalar
+// registers the compiler would otherwise keep cap it at seven (measured 12%
+// slower).
 template <int W, bool FILL, typename T, bool LOWER>
-__global__ __launch_bounds__(256) void k_row_pass(RowArgs g) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_row_pass(RowArgs g) {
   __shared__ int32_t s_pos[4][kL1Stage], s_info[4][FILL ? kL1Stage : 1], s_seg[4][kMaxSeg + 2];
+  __shared__ int32_t s_mark[4][FILL ? kWave : 1];
   // plain block order: rows of very different lengths sit in runs, and
   // giving each XCD one contiguous range of rows (for L2 locality of the
   // tile lists) measured 30-40% slower from the imbalance between XCDs
-  const int64_t i = (int64_t)blockIdx.x * (blockDim.x / kWave) + (threadIdx.x >> 6);
+  const int wv = uni((int)(threadIdx.x >> 6)), lane = lane_id();
+  const int64_t i = (int64_t)blockIdx.x * (blockDim.x / kWave) + wv;
   if (i >= g.D) return;
-  const int wv = threadIdx.x >> 6, lane = lane_id();
-  const int alpha = g.row_a[i], p = g.row_p[i];
-  const int beta = g.bseg_start[g.a_seg[alpha]] + p;
-  const int len_a = g.a_len[alpha];
-  const int64_t off_a = g.a_off[alpha];
+  const int alpha = uni(g.row_a[i]), p = uni(g.row_p[i]);
+  const int beta = uni(g.bseg_start[g.a_seg[alpha]] + p);
+  const int len_a = uni(g.a_len[alpha]);
+  const int64_t off_a = uni(g.a_off[alpha]);
   uint64_t ab[W], bb[W];
   if (FILL) {
+    // (kept in vector registers: the table reads in the per-entry sums over
+    // these bits then go through the vector memory path)
     load_bits<W>(g.a_bits, g.nA, alpha, ab);
     load_bits<W>(g.b_bits, g.nB, beta, bb);
   }
-  const int64_t out = FILL ? g.row_ptr[i] : 0;
+  const int64_t out = FILL ? uni(g.row_ptr[i]) : 0;
   const int64_t l1b = (int64_t)beta * g.nseg;
-  const int64_t base = g.l1_seg[l1b];
-  const int64_t n1 = g.l1_seg[l1b + g.nseg] - base;
+  const int64_t base = uni(g.l1_seg[l1b]);
+  const int64_t n1 = uni(g.l1_seg[l1b + g.nseg]) - base;
   int64_t cnt = 0;
-  const int64_t t0 = g.t_ptr[(int64_t)alpha * g.tstride], t1 = g.t_ptr[(int64_t)(alpha + 1) * g.tstride];
+  const int64_t t0 = uni(g.t_ptr[(int64_t)alpha * g.tstride]), t1 = uni(g.t_ptr[(int64_t)(alpha + 1) * g.tstride]);
   if (n1 <= kL1Stage && g.nseg <= kMaxSeg + 1) {
     for (int64_t k = lane; k < n1; k += kWave) {
       s_pos[wv][k] = g.l1_pos[base + k];
@@ -517,22 +587,22 @@ __global__ __launch_bounds__(256) void k_row_pass(RowArgs g) {
     }
     for (int h = lane; h <= g.nseg; h += kWave) s_seg[wv][h] = (int32_t)(g.l1_seg[l1b + h] - base);
     wave_lds_sync();
-    const L1View<true> L{s_seg[wv], nullptr, s_pos[wv], FILL ? s_info[wv] : nullptr};
+    const L1View<true> L{s_seg[wv], nullptr, 0, s_pos[wv], FILL ? s_info[wv] : nullptr};
     if (!LOWER) {
-      row_diag<W, FILL, T>(g, g.ls_self[beta], g.ls_ptr[beta + 1], alpha, len_a, off_a, ab, bb, out, cnt);
-      row_tiles<W, FILL, T, true>(g, t0, t1, p, bb, out, cnt, L);
+      row_diag<W, FILL, T>(g, i, uni((int64_t)g.ls_self[beta]), uni(g.ls_ptr[beta + 1]), alpha, len_a, off_a, ab, bb, out, cnt);
+      row_tiles<W, FILL, T, true>(g, t0, t1, p, bb, out, cnt, L, s_mark[wv]);
     } else {
-      row_tiles<W, FILL, T, true>(g, t0, t1, p, bb, out, cnt, L);
-      row_diag<W, FILL, T>(g, g.ls_ptr[beta], g.ls_self[beta], alpha, len_a, off_a, ab, bb, out, cnt);
+      row_tiles<W, FILL, T, true>(g, t0, t1, p, bb, out, cnt, L, s_mark[wv]);
+      row_diag<W, FILL, T>(g, i, uni(g.ls_ptr[beta]), uni((int64_t)g.ls_self[beta]), alpha, len_a, off_a, ab, bb, out, cnt);
     }
   } else {
-    const L1View<false> L{nullptr, g.l1_seg + l1b, g.l1_pos, g.l1_info};
+    const L1View<false> L{nullptr, g.l1_seg + l1b, base, g.l1_pos + base, FILL ? g.l1_info + base : nullptr};
     if (!LOWER) {
-      row_diag<W, FILL, T>(g, g.ls_self[beta], g.ls_ptr[beta + 1], alpha, len_a, off_a, ab, bb, out, cnt);
-      row_tiles<W, FILL, T, false>(g, t0, t1, p, bb, out, cnt, L);
+      row_diag<W, FILL, T>(g, i, uni((int64_t)g.ls_self[beta]), uni(g.ls_ptr[beta + 1]), alpha, len_a, off_a, ab, bb, out, cnt);
+      row_tiles<W, FILL, T, false>(g, t0, t1, p, bb, out, cnt, L, s_mark[wv]);
     } else {
-      row_tiles<W, FILL, T, false>(g, t0, t1, p, bb, out, cnt, L);
-      row_diag<W, FILL, T>(g, g.ls_ptr[beta], g.ls_self[beta], alpha, len_a, off_a, ab, bb, out, cnt);
+      row_tiles<W, FILL, T, false>(g, t0, t1, p, bb, out, cnt, L, s_mark[wv]);
+      row_diag<W, FILL, T>(g, i, uni(g.ls_ptr[beta]), uni((int64_t)g.ls_self[beta]), alpha, len_a, off_a, ab, bb, out, cnt);
     }
   }
   if (!FILL && lane == 0) g.rcnt[i] = (int32_t)cnt;
@@ -699,6 +769,14 @@ void launch_substate_energy(const cib_basis &b, const DevInter &it, double *eA, 
   CIB_HIP(hipGetLastError());
 }
 
+void launch_build_vt(const DevInter &it, const VtBlock *blocks, int nblk, const int32_t *atr,
+                     const int32_t *btr, int64_t total, double *vt, hipStream_t s) {
+  if (total == 0 || nblk == 0) return;
+  hipLaunchKernelGGL(k_build_vt, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, it, blocks, nblk,
+                     atr, btr, total, vt);
+  CIB_HIP(hipGetLastError());
+}
+
 void launch_dab(const DevInter &it, double *dab, hipStream_t s) {
   const int n = it.nA * it.nB;
   if (n == 0) return;
@@ -810,13 +888,16 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
   DBuf<int64_t> t_off(ctx, at_least1(n_tiles)), tl_off(ctx, at_least1(n_lt));
   DBuf<int32_t> t_len(ctx, at_least1(n_tiles)), t_info(ctx, at_least1(n_tiles));
   DBuf<int32_t> tl_len(ctx, at_least1(n_lt)), tl_info(ctx, at_least1(n_lt));
+  DBuf<int32_t> t_rb(ctx, at_least1(n_tiles)), tl_rb(ctx, at_least1(n_lt));
   DBuf<double> t_val(ctx, at_least1(n_tiles)), tl_val(ctx, at_least1(n_lt));
   DBuf<int32_t> ls_self(ctx, nB), ls_pos(ctx, n_ls), ls_info(ctx, n_ls), l1_pos(ctx, n_l1),
       l1_info(ctx, n_l1);
   DBuf<double> ls_val(ctx, n_ls);
   CIB_HIP(hipEventRecord(ev.e[2], s));
   ta.t_ptr = t_ptr.p; ta.t_off = t_off.p; ta.t_len = t_len.p; ta.t_info = t_info.p; ta.t_val = t_val.p;
+  ta.t_rb = t_rb.p;
   tl.t_ptr = tl_ptr.p; tl.t_off = tl_off.p; tl.t_len = tl_len.p; tl.t_info = tl_info.p; tl.t_val = tl_val.p;
+  tl.t_rb = tl_rb.p;
   {
     KTimer kt(ctx, K_TILE, s);
     hipLaunchKernelGGL((k_tile_pass<W, true, false>), dim3(tblk), dim3(256), 0, s, ta);
@@ -834,20 +915,27 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
   ra.row_a = b.row_a.p; ra.row_p = b.row_p.p; ra.a_seg = b.a_seg.p; ra.a_len = b.a_len.p;
   ra.bseg_start = b.bseg_start.p; ra.a_off = b.a_off.p; ra.a_bits = b.a_bits.p; ra.b_bits = b.b_bits.p;
   ra.eA = eA.p; ra.t_ptr = t_ptr.p; ra.tstride = nchunk; ra.t_off = t_off.p; ra.t_len = t_len.p; ra.t_info = t_info.p;
-  ra.t_val = t_val.p; ra.ls_ptr = ls_ptr.p; ra.l1_seg = l1_seg.p; ra.ls_self = ls_self.p;
+  ra.t_val = t_val.p; ra.t_rb = t_rb.p; ra.ls_ptr = ls_ptr.p; ra.l1_seg = l1_seg.p; ra.ls_self = ls_self.p;
   ra.ls_pos = ls_pos.p; ra.ls_info = ls_info.p; ra.l1_pos = l1_pos.p; ra.l1_info = l1_info.p;
   ra.ls_val = ls_val.p; ra.it = it;
   DBuf<int32_t> rcnt(ctx, p.D), rlcnt(ctx, p.D);
   ra.rcnt = rcnt.p;
   RowArgs rl = ra;
   rl.t_ptr = tl_ptr.p; rl.t_off = tl_off.p; rl.t_len = tl_len.p; rl.t_info = tl_info.p; rl.t_val = tl_val.p;
+  rl.t_rb = tl_rb.p;
   rl.rcnt = rlcnt.p;
   const unsigned rblk = (unsigned)((p.D + 3) / 4);
+  DBuf<double> diag(ctx, p.D);
   {
     KTimer kt(ctx, K_ROW_COUNT, s);
     hipLaunchKernelGGL((k_row_pass<W, false, double, false>), dim3(rblk), dim3(256), 0, s, ra);
     hipLaunchKernelGGL((k_row_pass<W, false, double, true>), dim3(rblk), dim3(256), 0, s, rl);
+    hipLaunchKernelGGL((k_state_diag<W>), dim3((unsigned)((p.D + 255) / 256)), dim3(256), 0, s, p.D,
+                       b.row_a.p, b.row_p.p, b.a_seg.p, b.bseg_start.p, b.a_bits.p, nA, b.b_bits.p, nB,
+                       eA.p, eB.p, it, diag.p);
   }
+  ra.diag = diag.p;
+  rl.diag = diag.p;
   CIB_HIP(hipGetLastError());
   CIB_HIP(hipEventRecord(ev.e[4], s));
   H.row_ptr.reset(ctx, p.D + 1);

@@ -166,6 +166,13 @@ struct DevInter {
   const int64_t *prowA = nullptr, *prowB = nullptr, *prowAB = nullptr;
   const double *vA = nullptr, *vB = nullptr, *vAB = nullptr;
   const double *dab = nullptr;  // nA * nB: V^AB_{(x,y),(x,y)}
+  // V^AB by orbital transitions: rows are the A transitions (a <- c), columns
+  // the B transitions (b <- d), one dense block per 2m_a - 2m_c = -(2m_b - 2m_d),
+  // so that V^AB_{(a,b),(c,d)} = vt[arb[a * nA + c] + bcol[b * nB + d]]: the
+  // tile supplies the row base, the B adjacency entry the column, and the
+  // value costs one memory access.
+  const double *vt = nullptr;
+  const int32_t *arb = nullptr, *bcol = nullptr;
 };
 
 }  // namespace cib
@@ -184,8 +191,8 @@ struct cib_basis {
 struct cib_interaction {
   cib_ctx *ctx = nullptr;
   int nA = 0, nB = 0;
-  cib::DBuf<double> epsA, epsB, vA, vB, vAB, dab;
-  cib::DBuf<int32_t> pidxA, pidxB, pidxAB;
+  cib::DBuf<double> epsA, epsB, vA, vB, vAB, dab, vt;
+  cib::DBuf<int32_t> pidxA, pidxB, pidxAB, arb, bcol;
   cib::DBuf<int64_t> prowA, prowB, prowAB;
   cib::DevInter view() const;
 };
@@ -219,6 +226,15 @@ void launch_expand_basis(const cib_basis &b, hipStream_t s);
 void launch_substate_energy(const cib_basis &b, const DevInter &it, double *eA, double *eB,
                             hipStream_t s);
 void launch_dab(const DevInter &it, double *dab, hipStream_t s);
+// Transition blocks of vt: block g holds rows [a0, a0 + na) of the A
+// transition list and columns [b0, b0 + nb) of the B transition list (each
+// entry a << 16 | c), stored row-major from vt offset base.
+struct VtBlock {
+  int64_t base;
+  int32_t a0, na, b0, nb;
+};
+void launch_build_vt(const DevInter &it, const VtBlock *blocks, int nblk, const int32_t *atr,
+                     const int32_t *btr, int64_t total, double *vt, hipStream_t s);
 
 // Exclusive scans of int32 counts into int64 offsets (n + 1 values each, the
 // last one the total), up to kScanArrays independent arrays per call;

@@ -19,6 +19,19 @@ __device__ __forceinline__ int mask_rank(uint64_t m) {
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 
+// A value equal in all lanes of the wave, moved to a scalar register.  The
+// compiler treats anything derived from threadIdx.x as varying per lane, also
+// threadIdx.x / 64, so per-wave indices and what is loaded through them would
+// otherwise be computed lane by lane in vector registers.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uni(int64_t v) {
+  const uint64_t u = (uint64_t)v;
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(u >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ uint64_t uni(uint64_t v) { return (uint64_t)uni((int64_t)v); }
+
 // Lane permutation within rows of 16 lanes through DPP (no LDS round trip).
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v) {
@@ -65,6 +78,19 @@ __device__ __forceinline__ int wave_incl_scan_dpp(int v) {
   v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xF, true);  // row_shr:8
   v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false); // row_bcast:15 -> rows 1, 3
   v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xC, 0xF, false); // row_bcast:31 -> rows 2, 3
+  return v;
+}
+
+// Inclusive prefix maximum of a non-negative int over the 64 lanes through
+// DPP (all lanes active; lanes shifted in from outside a row read 0, the
+// identity for non-negative values).
+__device__ __forceinline__ int wave_incl_max_dpp(int v) {
+  v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x111, 0xF, 0xF, true));   // row_shr:1
+  v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x112, 0xF, 0xF, true));   // row_shr:2
+  v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, true));   // row_shr:4
+  v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xF, true));   // row_shr:8
+  v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false));  // row_bcast:15 -> rows 1, 3
+  v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x143, 0xC, 0xF, false));  // row_bcast:31 -> rows 2, 3
   return v;
 }
 

@@ -44,6 +44,51 @@ static PairLayout pair_layout(const Orbs &o1, const Orbs &o2, bool same) {
   return L;
 }
 
+// Transition layout of V^AB: A transitions (a <- c, a == c included) grouped
+// by 2m_a - 2m_c, B transitions (b <- d) by 2m_b - 2m_d, both groups in
+// lexicographic order.  Block for difference k: the A group k against the B
+// group -k (the only B transitions that conserve the total 2M), row-major.
+struct TransLayout {
+  std::vector<int32_t> atr, btr;     // (a << 16 | c) and (b << 16 | d), group by group
+  std::vector<int32_t> arb, bcol;    // per ordered orbital pair: row base, column index
+  std::vector<VtBlock> blocks;
+  int64_t total = 0;
+};
+
+static TransLayout trans_layout(const Orbs &oa, const Orbs &ob) {
+  std::map<int, std::vector<int32_t>> ga, gb;
+  for (int a = 0; a < oa.n_orb; ++a)
+    for (int c = 0; c < oa.n_orb; ++c) ga[oa.twom[a] - oa.twom[c]].push_back((a << 16) | c);
+  for (int b = 0; b < ob.n_orb; ++b)
+    for (int d = 0; d < ob.n_orb; ++d) gb[ob.twom[b] - ob.twom[d]].push_back((b << 16) | d);
+  TransLayout T;
+  T.arb.assign((size_t)oa.n_orb * oa.n_orb, 0);
+  T.bcol.assign((size_t)ob.n_orb * ob.n_orb, 0);
+  std::map<int, int32_t> boff;
+  for (auto &kv : gb) {
+    boff[kv.first] = (int32_t)T.btr.size();
+    for (size_t j = 0; j < kv.second.size(); ++j) {
+      const int32_t e = kv.second[j];
+      T.bcol[(size_t)(e >> 16) * ob.n_orb + (e & 0xffff)] = (int32_t)j;
+      T.btr.push_back(e);
+    }
+  }
+  for (auto &kv : ga) {
+    const auto bit = gb.find(-kv.first);
+    const int32_t nb = bit == gb.end() ? 0 : (int32_t)bit->second.size();
+    VtBlock B{T.total, (int32_t)T.atr.size(), (int32_t)kv.second.size(), nb ? boff[-kv.first] : 0, nb};
+    for (size_t i = 0; i < kv.second.size(); ++i) {
+      const int32_t e = kv.second[i];
+      T.arb[(size_t)(e >> 16) * oa.n_orb + (e & 0xffff)] = (int32_t)(T.total + (int64_t)i * nb);
+      T.atr.push_back(e);
+    }
+    T.total += (int64_t)B.na * nb;
+    CIB_REQUIRE(T.total < (int64_t(1) << 31), CIB_E_OVERFLOW, "transition table exceeds 2^31 entries");
+    if (nb) T.blocks.push_back(B);
+  }
+  return T;
+}
+
 const char *const kKernelNames[K_NKERN] = {"tile_screen", "adjacency", "row_count", "scan",
                                            "row_fill", "spmm_sym", "gram", "rayleigh_ritz", "update",
                                            "lower"};
@@ -122,6 +167,24 @@ cib_interaction *upload_interaction(cib_ctx *ctx, const cib_basis &b, const cib_
     up_layout(LAB, t.v_ab, it->pidxAB, it->prowAB, it->vAB);
     it->dab.reset(ctx, (size_t)it->nA * it->nB);
     launch_dab(it->view(), it->dab.p, s);
+    // V^AB re-laid out by orbital transitions (one access per matrix entry)
+    TransLayout T = trans_layout(p.oA, p.oB);
+    DBuf<int32_t> atr(ctx, std::max<size_t>(T.atr.size(), 1)), btr(ctx, std::max<size_t>(T.btr.size(), 1));
+    DBuf<VtBlock> blk(ctx, std::max<size_t>(T.blocks.size(), 1));
+    atr.upload(T.atr.data(), T.atr.size(), s);
+    btr.upload(T.btr.data(), T.btr.size(), s);
+    blk.upload(T.blocks.data(), T.blocks.size(), s);
+    it->arb.reset(ctx, T.arb.size());
+    it->arb.upload(T.arb.data(), T.arb.size(), s);
+    it->bcol.reset(ctx, T.bcol.size());
+    it->bcol.upload(T.bcol.data(), T.bcol.size(), s);
+    it->vt.reset(ctx, (size_t)std::max<int64_t>(T.total, 1));
+    launch_build_vt(it->view(), blk.p, (int)T.blocks.size(), atr.p, btr.p, T.total, it->vt.p, s);
+    CIB_HIP(hipStreamSynchronize(s));
+    // the blocked pair tables are not read after this point
+    it->vAB.release();
+    it->pidxAB.release();
+    it->prowAB.release();
   }
   // host arrays are copied before returning
   CIB_HIP(hipStreamSynchronize(s));
@@ -179,6 +242,7 @@ cib::DevInter cib_interaction::view() const {
   v.pidxB = pidxB.p; v.prowB = prowB.p; v.vB = vB.p;
   v.pidxAB = pidxAB.p; v.prowAB = prowAB.p; v.vAB = vAB.p;
   v.dab = dab.p;
+  v.vt = vt.p; v.arb = arb.p; v.bcol = bcol.p;
   return v;
 }
 
