@@ -137,13 +137,13 @@ __global__ __launch_bounds__(256) void k_spmm_vec(const VecArgs a) {
   // workgroups go to the 8 XCDs round-robin; XCD x (block mod 8) walks its
   // own range of rows, the ranges holding equal numbers of stored entries
   const int x = blockIdx.x & 7;
-  const int64_t i = a.xr[x] + (int64_t)(blockIdx.x >> 3) * (blockDim.x / kWave) + uni((int)(threadIdx.x >> 6));
+  const int64_t i = a.xr[x] + (int64_t)(blockIdx.x >> 3) * (blockDim.x / kWave) + (threadIdx.x >> 6);
   if (i >= a.xr[x + 1]) return;
   const int lane = lane_id();
   const int e = lane / G, g = lane % G;
-  const int64_t lb = uni(a.lrp[i]), ub = uni(a.rp[i]);
-  const int nl = uni((int)(a.lrp[i + 1] - lb));
-  const int n = uni(nl + (int)(a.rp[i + 1] - ub));
+  const int64_t lb = a.lrp[i], ub = a.rp[i];
+  const int nl = (int)(a.lrp[i + 1] - lb);
+  const int n = nl + (int)(a.rp[i + 1] - ub);
   // Loads are issued unconditionally (out-of-range lanes read a valid
   // address and discard it): loads under branches would make the compiler
   // wait for every outstanding load, the prefetch included.
