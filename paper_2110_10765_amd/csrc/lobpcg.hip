@@ -129,108 +129,111 @@ __global__ __launch_bounds__(256) void k_copy_cols(int64_t D, int n, const doubl
 
 // ------------------------------------------------------------ Gram matrices
 // partial[blk] = sum over the block's rows of S_i^T [S_i, HS_i] for the first
-// ns columns: an ns x 2ns matrix (left half S^T S, right half S^T HS).  Rows
-// are staged through LDS in chunks of kGramRows; the next chunk is loaded
-// into registers while the current one is multiplied, so HBM latency hides
-// behind the FMAs.  Each thread keeps a 6 x 6 register tile of the output;
-// when the output needs fewer than 256 threads, several thread groups take
-// alternate rows and are summed at the end in a fixed order.
-constexpr int kGramRows = 32;
-constexpr int kGT = 6;
-constexpr int kGramStage = 2 * kNS / 8;   // staged values per thread: 8 threads per row
+// ns columns: an ns x 2ns matrix (left half S^T S, right half S^T HS).  This
+// is a dense contraction over the rows, done on the float64 matrix cores:
+// v_mfma_f64_16x16x4f64 multiplies a 16 x 4 by a 4 x 16 block.  Four
+// consecutive rows form one step; lane l holds row (l / 16), column
+// 16 t + (l % 16) of tile t, which is at once the lane's element of the left
+// operand (S^T, 16 x 4) and of the right operand (S or HS, 4 x 16), so the
+// rows go from global memory straight into the operands (coalesced 128-byte
+// row pieces, no LDS).  Output tile (ti, tj): lane l, element v holds row
+// 16 ti + 4 v + (l / 16), column 16 tj + (l % 16) (checked on the device).
+// S^T S is symmetric: only its tiles ti <= tj are formed and mirrored.  The
+// four waves of a workgroup take alternate steps (the next step's rows load
+// during the current one) and are summed in LDS in wave order.  The matrix
+// cores are the limit here: measured about 36 TFLOP/s for this instruction.
+constexpr int kGramSteps = 4;   // rows per matrix-core step
+constexpr int kGramPad = 48;    // doubles allocated past the last row of S and HS
+typedef double dbl4 __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(256) void k_gram(int64_t D, int ns, int ld, const double *__restrict__ S,
-                                              const double *__restrict__ HS, int64_t rows_per_blk,
-                                              double *__restrict__ partial) {
-  // row chunks, then (groups / 2) ns x 2ns tiles of the group tree; both
-  // fit in kNS * 2kNS doubles (groups * ns * 2ns <= 2 * 256 * 36)
-  __shared__ double buf[(kGramRows > kNS ? kGramRows : kNS) * 2 * kNS];
-  const int tid = threadIdx.x;
-  const int w2 = 2 * ns, nout = ns * w2;
-  const int nti = (ns + kGT - 1) / kGT, ntj = (w2 + kGT - 1) / kGT;
-  const int T = nti * ntj;
-  int groups = max(1, (int)blockDim.x / T);
-  while (groups & (groups - 1)) groups &= groups - 1;   // a power of two for the tree
-  const int grp = tid / T, loc = tid % T;
-  const bool worker = grp < groups;
-  const int i0 = (loc / ntj) * kGT, j0 = (loc % ntj) * kGT;
-  double acc[kGT][kGT];
-#pragma unroll
-  for (int a = 0; a < kGT; ++a)
-#pragma unroll
-    for (int c = 0; c < kGT; ++c) acc[a][c] = 0.0;
+template <int T>   // 16-column tiles per side: ns <= 16 T
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_gram(
+    int64_t D, int ns, int ld, const double *__restrict__ S, const double *__restrict__ HS,
+    int64_t rows_per_blk, double *__restrict__ partial) {
+  constexpr int NG = T * (T + 1) / 2;   // upper tiles of S^T S
+  __shared__ double red[kNS * 2 * kNS];
+  const int wv = uni((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
+  const int kr = lane >> 4, kc = lane & 15;
+  const int w2 = 2 * ns;
   const int64_t r0 = (int64_t)blockIdx.x * rows_per_blk;
   const int64_t r1 = min(D, r0 + rows_per_blk);
-  // staging: thread (row sr, lane sc of 8) holds columns sc, sc + 8, ...
-  double stage[kGramStage];
-  const int sr = tid >> 3, sc = tid & 7;
-  auto fetch = [&](int64_t rb) {
-    const int64_t row = rb + sr;
-    const bool ok = row < r1;
-    const double *srow = S + (ok ? row : r0) * ld, *hrow = HS + (ok ? row : r0) * ld;
+  dbl4 ag[NG], ah[T][T];
 #pragma unroll
-    for (int t = 0; t < kGramStage; ++t) {
-      const int c = sc + 8 * t;
-      stage[t] = 0.0;
-      if (ok && c < w2) stage[t] = c < ns ? srow[c] : hrow[c - ns];
+  for (int a = 0; a < NG; ++a) ag[a] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int a = 0; a < T; ++a)
+#pragma unroll
+    for (int c = 0; c < T; ++c) ah[a][c] = dbl4{0.0, 0.0, 0.0, 0.0};
+  // loads from a valid address in every lane, then select: a load under a
+  // branch would make the compiler wait for the prefetch as well.  Columns
+  // up to 16 T - 1 are read unclamped (S and HS carry kGramPad doubles of
+  // padding past the last row), so the tiles of a row sit at fixed offsets.
+  auto fetch = [&](int64_t rb, double (&xs)[T], double (&xh)[T]) {
+    const int64_t row = rb + kr;
+    const bool rok = row < r1;
+    const double *sp = S + (rok ? row : r0) * ld + kc, *hp = HS + (rok ? row : r0) * ld + kc;
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const bool ok = rok && 16 * t + kc < ns;
+      const double vs = sp[16 * t], vh = hp[16 * t];
+      xs[t] = ok ? vs : 0.0;
+      xh[t] = ok ? vh : 0.0;
     }
   };
-  if (r0 < r1) fetch(r0);
-  for (int64_t rb = r0; rb < r1; rb += kGramRows) {
-    const int nr = (int)min<int64_t>(kGramRows, r1 - rb);
+  constexpr int kStride = 4 * kGramSteps;   // rows per round of the four waves
+  double xs[T], xh[T], ys[T], yh[T];
+  int64_t rb = r0 + (int64_t)wv * kGramSteps;
+  fetch(rb, xs, xh);
+  for (; rb < r1; rb += kStride) {
+    fetch(rb + kStride, ys, yh);   // rows past the slab load as 0
+    int g = 0;
 #pragma unroll
-    for (int t = 0; t < kGramStage; ++t) {
-      const int c = sc + 8 * t;
-      if (c < w2) buf[sr * w2 + c] = stage[t];
+    for (int a = 0; a < T; ++a) {
+#pragma unroll
+      for (int c = a; c < T; ++c, ++g) ag[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(xs[a], xs[c], ag[g], 0, 0, 0);
+#pragma unroll
+      for (int c = 0; c < T; ++c) ah[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(xs[a], xh[c], ah[a][c], 0, 0, 0);
+    }
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      xs[t] = ys[t];
+      xh[t] = yh[t];
+    }
+  }
+  // waves in order: wave 0 stores, waves 1-3 add
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    if (wv == w) {
+      auto put = [&](int i, int j, double v) {
+        if (w == 0) red[i * w2 + j] = v;
+        else red[i * w2 + j] += v;
+      };
+      int g = 0;
+#pragma unroll
+      for (int a = 0; a < T; ++a) {
+#pragma unroll
+        for (int c = a; c < T; ++c, ++g)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int i = 16 * a + 4 * v + kr, j = 16 * c + kc;
+            if (i < ns && j < ns) {
+              put(i, j, ag[g][v]);
+              if (c > a) put(j, i, ag[g][v]);
+            }
+          }
+#pragma unroll
+        for (int c = 0; c < T; ++c)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int i = 16 * a + 4 * v + kr, j = 16 * c + kc;
+            if (i < ns && j < ns) put(i, ns + j, ah[a][c][v]);
+          }
+      }
     }
     __syncthreads();
-    if (rb + kGramRows < r1) fetch(rb + kGramRows);
-    if (worker)
-      for (int r = grp; r < nr; r += groups) {
-        const double *row = buf + r * w2;
-        double xi[kGT], xj[kGT];
-#pragma unroll
-        for (int a = 0; a < kGT; ++a) xi[a] = row[min(i0 + a, w2 - 1)];
-#pragma unroll
-        for (int c = 0; c < kGT; ++c) xj[c] = row[min(j0 + c, w2 - 1)];
-#pragma unroll
-        for (int a = 0; a < kGT; ++a)
-#pragma unroll
-          for (int c = 0; c < kGT; ++c) acc[a][c] += xi[a] * xj[c];
-      }
-    __syncthreads();
   }
-  // pairwise tree over the thread groups (a power of two) in LDS, fixed
-  // order: at each level the upper half of the groups hands its tiles to
-  // the lower half
-  for (int half = groups >> 1; half >= 1; half >>= 1) {
-    if (worker && grp >= half && grp < 2 * half)
-#pragma unroll
-      for (int a = 0; a < kGT; ++a)
-#pragma unroll
-        for (int c = 0; c < kGT; ++c) {
-          const int i = i0 + a, j = j0 + c;
-          if (i < ns && j < w2) buf[(grp - half) * nout + i * w2 + j] = acc[a][c];
-        }
-    __syncthreads();
-    if (worker && grp < half)
-#pragma unroll
-      for (int a = 0; a < kGT; ++a)
-#pragma unroll
-        for (int c = 0; c < kGT; ++c) {
-          const int i = i0 + a, j = j0 + c;
-          if (i < ns && j < w2) acc[a][c] += buf[grp * nout + i * w2 + j];
-        }
-    __syncthreads();
-  }
-  if (worker && grp == 0)
-#pragma unroll
-    for (int a = 0; a < kGT; ++a)
-#pragma unroll
-      for (int c = 0; c < kGT; ++c) {
-        const int i = i0 + a, j = j0 + c;
-        if (i < ns && j < w2) partial[(int64_t)blockIdx.x * nout + i * w2 + j] = acc[a][c];
-      }
+  double *out = partial + (int64_t)blockIdx.x * ns * w2;
+  for (int e = threadIdx.x; e < ns * w2; e += blockDim.x) out[e] = red[e];
 }
 
 // out[g][e] = sum of in[q][e] over the parts q of group g (grid.y = groups of
@@ -917,11 +920,11 @@ static inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t -
 // rows per Gram block: about 512 blocks, a multiple of the staging chunk
 constexpr int kSumGroup = 32;  // partial Gram matrices added per thread in the first pass
 
-// rows per Gram workgroup: about one workgroup per CU, each streaming its
-// slab chunk after chunk (loads of the next chunk overlap the FMAs)
+// rows per Gram workgroup: about three workgroups per CU (three waves per
+// SIMD), a multiple of the 16 rows the four waves take per round
 static int64_t gram_rows_for(int64_t D) {
-  int64_t r = std::max<int64_t>((D + 255) / 256, kGramRows);
-  return (r + kGramRows - 1) / kGramRows * kGramRows;
+  int64_t r = std::max<int64_t>((D + 767) / 768, 16);
+  return (r + 15) / 16 * 16;
 }
 
 // rows per update workgroup
@@ -958,8 +961,8 @@ struct LobpcgRun {
     CIB_REQUIRE(o.max_iter >= 1, CIB_E_INVALID, "max_iter must be >= 1");
     tol = o.tol > 0 ? o.tol : (H.dtype == CIB_F64 ? 1e-9 : 1e-5);
     ld = 3 * b;
-    S.reset(ctx, (size_t)D * ld);
-    HS.reset(ctx, (size_t)D * ld);
+    S.reset(ctx, (size_t)D * ld + kGramPad);
+    HS.reset(ctx, (size_t)D * ld + kGramPad);
     diag.reset(ctx, D);
     gram_rows = gram_rows_for(D);
     gram_blocks = (int)((D + gram_rows - 1) / gram_rows);
@@ -1014,7 +1017,13 @@ struct LobpcgRun {
   void rr_update(int ns) {
     {
       KTimer kt(ctx, K_GRAM, s);
-      hipLaunchKernelGGL(k_gram, dim3(gram_blocks), dim3(256), 0, s, D, ns, ld, S.p, HS.p, gram_rows, partial.p);
+      const int T = (ns + 15) / 16;
+      if (T == 1)
+        hipLaunchKernelGGL(k_gram<1>, dim3(gram_blocks), dim3(256), 0, s, D, ns, ld, S.p, HS.p, gram_rows, partial.p);
+      else if (T == 2)
+        hipLaunchKernelGGL(k_gram<2>, dim3(gram_blocks), dim3(256), 0, s, D, ns, ld, S.p, HS.p, gram_rows, partial.p);
+      else
+        hipLaunchKernelGGL(k_gram<3>, dim3(gram_blocks), dim3(256), 0, s, D, ns, ld, S.p, HS.p, gram_rows, partial.p);
       const int nout = ns * 2 * ns;
       const int groups = (gram_blocks + kSumGroup - 1) / kSumGroup;
       hipLaunchKernelGGL(k_sum_parts, dim3((nout + 255) / 256, groups), dim3(256), 0, s, nout, gram_blocks,
