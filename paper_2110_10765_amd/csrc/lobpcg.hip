@@ -818,67 +818,124 @@ struct UpdArgs {
   const int32_t *locked;  // per column: converged at the previous check (W = 0)
 };
 
-// Threads (row, column c).  All reads of a row precede the barrier, all writes
-// follow it, so the update is in place.  (Staging the rows through LDS first
-// measured 60% slower.)  Per-column sums of the squared residuals and |x|^2
-// are reduced over the threads in a fixed order.
-__global__ __launch_bounds__(256) void k_update(UpdArgs g) {
-  __shared__ double Cs[kNS * 2 * kMaxBlock];
+// [X P] = S [Cx Cp] and [HX HP] = HS [Cx Cp] on the float64 matrix cores, then
+// the residual R = HX - X diag(lambda), the preconditioned W and the new
+// blocks written in place.  One wave per 16 rows: the contraction index k
+// (a column of S) is split as k = KS (l / 16) + s, so lane l reads the KS
+// consecutive columns of row 16 q + (l % 16) it needs (left operand
+// A[i][k] = S[row i][k]) and keeps the matching rows of [Cx Cp] (right
+// operand) in registers for every step s.  Output element v of lane l is row
+// 4 v + (l / 16), column 16 t + (l % 16) of output tile t; the lane holding x
+// also holds hx, so the residual needs no exchange.  All reads of a row come
+// before its writes (the MFMAs consume every loaded value), so the update is
+// in place.  Per-column sums of the squared residuals and |x|^2 are reduced
+// over lanes and waves in a fixed order.
+template <int TN>   // 16-column output tiles over the 2b columns of [Cx Cp]
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_update(UpdArgs g) {
+  constexpr int KMAX = kNS / 4;   // steps of the contraction (ns <= 48)
   __shared__ double lam[kMaxBlock];
-  __shared__ double red[2][256];
-  const int b = g.b, ns = g.ns, ld = g.ld, tid = threadIdx.x;
-  for (int k = tid; k < ns * 2 * b; k += blockDim.x) Cs[k] = g.C[k];
-  if (tid < b) lam[tid] = g.lam[tid];
+  __shared__ double red[2][4][64];
+  __shared__ double Cs[kNS][16 * TN];   // [Cx Cp], zero past ns rows / 2b columns
+  __shared__ double rows[4][2][16][kNS + 1];   // per wave: its 16 rows of S and HS (padded)
+  const int b = g.b, ns = g.ns, ld = g.ld, nb2 = 2 * b;
+  const int wv = uni((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
+  const int kr = lane >> 4, kc = lane & 15;
+  const int KS = (ns + 3) / 4;
+  if (threadIdx.x < b) lam[threadIdx.x] = g.lam[threadIdx.x];
+  for (int e = threadIdx.x; e < kNS * 16 * TN; e += blockDim.x) {
+    const int k = e / (16 * TN), j = e % (16 * TN);
+    Cs[k][j] = (k < ns && j < nb2) ? g.C[k * nb2 + j] : 0.0;
+  }
   __syncthreads();
-  const int rows_per_pass = blockDim.x / b;
-  const int c = tid % b, rr = tid / b;
-  const bool active = rr < rows_per_pass;
   const int64_t r0 = (int64_t)blockIdx.x * g.rows_per_blk;
   const int64_t r1 = min(g.D, r0 + g.rows_per_blk);
-  double rs = 0.0, xs = 0.0;
-  for (int64_t base = r0; base < r1; base += rows_per_pass) {
-    const int64_t i = base + rr;
-    const bool ok = active && i < r1;
-    double x = 0.0, p = 0.0, hx = 0.0, hp = 0.0;
-    if (ok) {
-      const double *s = g.S + i * ld;
-      const double *h = g.HS + i * ld;
-      for (int k = 0; k < ns; ++k) {
-        const double sk = s[k], hk = h[k];
-        const double cx = Cs[k * 2 * b + c], cp = Cs[k * 2 * b + b + c];
-        x += sk * cx;
-        p += sk * cp;
-        hx += hk * cx;
-        hp += hk * cp;
+  double rs = 0.0, xs = 0.0;   // this lane's column kc (when kc < b)
+  for (int64_t rb = r0 + 16 * (int64_t)wv; rb < r1; rb += 64) {
+    // the 16 rows go to LDS with row-contiguous loads (lane = column), the
+    // operands come back out in the MFMA layout (row stride kNS + 1 keeps
+    // the 16 rows of one read in distinct banks)
+#pragma unroll 4
+    for (int r = 0; r < 16; ++r) {
+      const int64_t i = rb + r;
+      const bool ok = i < r1 && lane < ns;
+      const int64_t off = (i < r1 ? i : r0) * ld + (lane < ns ? lane : 0);
+      const double vs = g.S[off], vh = g.HS[off];
+      if (lane < kNS) {
+        rows[wv][0][r][lane] = ok ? vs : 0.0;
+        rows[wv][1][r][lane] = ok ? vh : 0.0;
       }
     }
-    __syncthreads();
-    if (ok) {
-      const double res = hx - lam[c] * x;
-      double den = g.diag[i] - lam[c];
-      if (fabs(den) < 1e-2) den = den < 0 ? -1e-2 : 1e-2;
-      const double w = g.locked[c] ? 0.0 : res / den;   // soft locking
+    wave_lds_sync();
+    double as[KMAX], ah[KMAX];
+#pragma unroll
+    for (int st = 0; st < KMAX; ++st) {
+      const int k = min(KS * kr + st, kNS - 1);
+      const bool ok = st < KS && KS * kr + st < ns;
+      as[st] = ok ? rows[wv][0][kc][k] : 0.0;
+      ah[st] = ok ? rows[wv][1][kc][k] : 0.0;
+    }
+    wave_lds_sync();
+    dbl4 xo[TN], ho[TN];
+#pragma unroll
+    for (int t = 0; t < TN; ++t) {
+      xo[t] = dbl4{0.0, 0.0, 0.0, 0.0};
+      ho[t] = dbl4{0.0, 0.0, 0.0, 0.0};
+    }
+#pragma unroll
+    for (int st = 0; st < KMAX; ++st)
+      if (st < KS)
+#pragma unroll
+        for (int t = 0; t < TN; ++t) {
+          const double cb = Cs[min(KS * kr + st, kNS - 1)][16 * t + kc];
+          xo[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(as[st], cb, xo[t], 0, 0, 0);
+          ho[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ah[st], cb, ho[t], 0, 0, 0);
+        }
+    // tile 0 holds the X columns (j < b) and, for b < 16, P columns; later
+    // tiles hold P columns only (P = S Cp: column j - b of the third block)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t i = rb + 4 * v + kr;
+      if (i >= r1 || kc >= nb2) continue;
       double *s = g.S + i * ld;
       double *h = g.HS + i * ld;
-      s[c] = x;
-      s[b + c] = w;
-      s[2 * b + c] = p;
-      h[c] = hx;
-      h[2 * b + c] = hp;
-      if (g.w32) g.w32[i * b + c] = (float)w;
-      rs += res * res;
-      xs += x * x;
+      const double x = xo[0][v], hx = ho[0][v];
+      if (kc < b) {
+        const double res = hx - lam[kc] * x;
+        double den = g.diag[i] - lam[kc];
+        if (fabs(den) < 1e-2) den = den < 0 ? -1e-2 : 1e-2;
+        const double w = g.locked[kc] ? 0.0 : res / den;   // soft locking
+        s[kc] = x;
+        s[b + kc] = w;
+        h[kc] = hx;
+        if (g.w32) g.w32[i * b + kc] = (float)w;
+        rs += res * res;
+        xs += x * x;
+      } else {
+        s[b + kc] = x;
+        h[b + kc] = hx;
+      }
     }
-    __syncthreads();
+#pragma unroll
+    for (int t = 1; t < TN; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t i = rb + 4 * v + kr;
+        const int j = 16 * t + kc;
+        if (i >= r1 || j >= nb2) continue;
+        g.S[i * ld + b + j] = xo[t][v];
+        g.HS[i * ld + b + j] = ho[t][v];
+      }
   }
-  red[0][tid] = active ? rs : 0.0;
-  red[1][tid] = active ? xs : 0.0;
+  // column kc: lanes kc, kc + 16, kc + 32, kc + 48 of each wave, then waves
+  red[0][wv][lane] = rs;
+  red[1][wv][lane] = xs;
   __syncthreads();
-  if (tid < 2 * b) {
-    const int cc = tid % b, which = tid / b;
+  if (threadIdx.x < 2 * b) {
+    const int cc = threadIdx.x % b, which = threadIdx.x / b;
     double t = 0.0;
-    for (int q = 0; q < rows_per_pass; ++q) t += red[which][q * b + cc];
-    g.npart[(int64_t)blockIdx.x * 2 * b + tid] = t;
+    for (int w = 0; w < 4; ++w)
+      for (int q = 0; q < 4; ++q) t += red[which][w][16 * q + cc];
+    g.npart[(int64_t)blockIdx.x * 2 * b + threadIdx.x] = t;
   }
 }
 
@@ -928,7 +985,7 @@ static int64_t gram_rows_for(int64_t D) {
 }
 
 // rows per update workgroup
-static int64_t upd_rows_for(int64_t D) { return std::max<int64_t>(64, (D + 4095) / 4096); }
+static int64_t upd_rows_for(int64_t D) { return std::max<int64_t>(64, (D + 4095) / 4096 + 63) / 64 * 64; }
 
 struct LobpcgRun {
   cib_ctx *ctx;
@@ -1036,7 +1093,11 @@ struct LobpcgRun {
     { KTimer kt(ctx, K_RR, s); hipLaunchKernelGGL(k_rayleigh_ritz, dim3(1), dim3(256), 0, s, ra); }
     UpdArgs ua{D, b, ns, ld, S.p, HS.p, C.p, lam.p, diag.p, H.dtype == CIB_F32 ? x32.p : nullptr,
                npart.p, (int)upd_rows, locked.p};
-    { KTimer kt(ctx, K_UPDATE, s); hipLaunchKernelGGL(k_update, dim3(upd_blocks), dim3(256), 0, s, ua); }
+    {
+      KTimer kt(ctx, K_UPDATE, s);
+      if (2 * b <= 16) hipLaunchKernelGGL(k_update<1>, dim3(upd_blocks), dim3(256), 0, s, ua);
+      else hipLaunchKernelGGL(k_update<2>, dim3(upd_blocks), dim3(256), 0, s, ua);
+    }
     // per-block residual sums: groups of kSumGroup first, then k_finish
     const int ugroups = (upd_blocks + kSumGroup - 1) / kSumGroup;
     hipLaunchKernelGGL(k_sum_parts, dim3(1, ugroups), dim3(256), 0, s, 2 * b, upd_blocks, kSumGroup, npart.p,
