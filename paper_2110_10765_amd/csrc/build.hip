@@ -66,7 +66,8 @@ __global__ __launch_bounds__(256) void k_expand_basis(int64_t D, int nA, int nB,
                                                       const uint64_t *__restrict__ b_bits,
                                                       uint64_t *__restrict__ words,
                                                       int32_t *__restrict__ row_a,
-                                                      int32_t *__restrict__ row_p) {
+                                                      int32_t *__restrict__ row_p,
+                                                      int32_t *__restrict__ row_b) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= D) return;
   int lo = 0, hi = nA;  // largest alpha with a_off[alpha] <= i
@@ -78,6 +79,7 @@ __global__ __launch_bounds__(256) void k_expand_basis(int64_t D, int nA, int nB,
   const int beta = bseg_start[a_seg[lo]] + p;
   row_a[i] = lo;
   row_p[i] = p;
+  row_b[i] = beta;
   for (int w = 0; w < WA; ++w) words[(int64_t)w * D + i] = a_bits[(int64_t)w * nA + lo];
   for (int w = 0; w < WB; ++w) words[(int64_t)(WA + w) * D + i] = b_bits[(int64_t)w * nB + beta];
 }
@@ -384,7 +386,7 @@ __global__ __launch_bounds__(256) void k_adj_pass(AdjArgs g) {
 struct RowArgs {
   int64_t D;
   int nA, nB, nseg;
-  const int32_t *row_a, *row_p, *a_seg, *a_len, *bseg_start;
+  const int32_t *row_a, *row_p, *row_b, *a_seg, *a_len, *bseg_start;
   const int64_t *a_off;
   const uint64_t *a_bits, *b_bits;
   const double *eA;
@@ -414,11 +416,15 @@ __device__ __forceinline__ void row_diag(const RowArgs &g, int64_t i, int64_t e0
   for (int64_t k0 = e0; k0 < e1; k0 += kWave) {
     const int64_t k = k0 + lane;
     const bool valid = k < e1;
-    const bool ok = valid && g.ls_pos[k] < len_a;
+    // all reads of the entry at once, at a clamped index
+    const int64_t kq = valid ? k : e0;
+    const int pos = g.ls_pos[kq];
+    const int info = FILL ? g.ls_info[kq] : 0;
+    const double lval = FILL ? g.ls_val[kq] : 0.0;
+    const bool ok = valid && pos < len_a;
     const uint64_t m = ballot(ok);
     if (FILL && ok) {
-      const int info = g.ls_info[k];
-      double v = g.ls_val[k];
+      double v = lval;
       const int kb = info & 3;
       if (kb == 0) {  // diagonal: E_A + E_B + sum_{x in alpha, y in beta} V^AB_{xy,xy}
         v = g.diag[i];
@@ -428,7 +434,7 @@ __device__ __forceinline__ void row_diag(const RowArgs &g, int64_t i, int64_t e0
         v += s * sum_over_bits<W>(ab, [&](int x) { return vt_at(g.it, g.it.arb[x * g.it.nA + x], bc); });
       }
       const int64_t o = out + cnt + (k - k0);
-      g.col[o] = (int32_t)(off_a + g.ls_pos[k]);
+      g.col[o] = (int32_t)(off_a + pos);
       val[o] = (T)v;
     }
     cnt += __popcll(m);
@@ -461,12 +467,33 @@ __device__ __forceinline__ void row_tiles(const RowArgs &g, int64_t t0, int64_t 
                                           int64_t out, int64_t &cnt, const L1View<ST> &L, int32_t *mark) {
   const int lane = lane_id();
   T *val = static_cast<T *>(g.val);
+  // the tile data of a batch of 64 is read together, one batch ahead of its
+  // use (unconditional reads at a clamped index: a read under a branch would
+  // make the compiler wait for the look-ahead as well)
+  struct Batch {
+    int info, len, off, rb;
+    double val;
+  };
+  auto fetch = [&](int64_t tb, Batch &d) {
+    const int64_t t = min(tb + lane, t1 - 1);
+    d.info = g.t_info[t];
+    d.len = g.t_len[t];
+    if (FILL) {
+      d.off = (int)g.t_off[t];
+      d.rb = g.t_rb[t];
+      d.val = g.t_val[t];
+    }
+  };
+  Batch nx;
+  if (t0 < t1) fetch(t0, nx);
   for (int64_t tb = t0; tb < t1; tb += kWave) {
     const int64_t t = tb + lane;
+    const Batch cur = nx;
+    fetch(tb + kWave, nx);
     int ne = 0, info = 0, l0 = 0;
     if (t < t1) {
-      info = g.t_info[t];
-      const int len = g.t_len[t];
+      info = cur.info;
+      const int len = cur.len;
       if ((info & 3) == 2) {
         ne = p < len;
       } else {  // first entry of the sorted segment with position >= len
@@ -485,17 +512,12 @@ __device__ __forceinline__ void row_tiles(const RowArgs &g, int64_t t0, int64_t 
     if (FILL) {
       const int orel = incl - ne;   // lane's first output, relative to out + cnt
       const bool two = (info & 3) == 2;
-      int32_t coff = 0, rb = 0;
-      double tv = 0.0;
-      if (ne) {
-        coff = (int32_t)g.t_off[t];
-        tv = g.t_val[t];
-      }
+      const int32_t coff = ne ? cur.off : 0, rb = (!two && ne) ? cur.rb : 0;
+      const double tv = ne ? cur.val : 0.0;
       if (two && ne) {
         g.col[out + cnt + orel] = coff + p;
         val[out + cnt + orel] = (T)tv;
       }
-      if (!two && ne) rb = g.t_rb[t];
       // kA = 1 entries, spread over the lanes
       const int n1 = two ? 0 : ne;
       const int incl1 = wave_incl_scan_dpp(n1);
@@ -530,7 +552,7 @@ __device__ __forceinline__ void row_tiles(const RowArgs &g, int64_t t0, int64_t 
           double sum = 0.0;
           if (g.it.nB > 0)
             sum = sum_over_bits<W>(bb, [&](int y) { return vt_at(g.it, orb, g.it.bcol[y * g.it.nB + y]); });
-          v = g.t_val[tb + own] + sa * sum;
+          v = g.t_val[tb + own] + sa * sum;   // (rare: a read, not a lane permute in a branch)
         } else {              // one A and one B orbital change
           const double sb = (li >> 2) & 1 ? -1.0 : 1.0;
           v = sa * sb * vt_at(g.it, orb, li >> 3);
@@ -564,7 +586,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
   const int64_t i = (int64_t)blockIdx.x * (blockDim.x / kWave) + wv;
   if (i >= g.D) return;
   const int alpha = uni(g.row_a[i]), p = uni(g.row_p[i]);
-  const int beta = uni(g.bseg_start[g.a_seg[alpha]] + p);
+  const int beta = uni(g.row_b[i]);
   const int len_a = uni(g.a_len[alpha]);
   const int64_t off_a = uni(g.a_off[alpha]);
   uint64_t ab[W], bb[W];
@@ -735,7 +757,7 @@ static void expand_w(const cib_basis &b, hipStream_t s) {
   const unsigned nblk = (unsigned)((p.D + 255) / 256);
   hipLaunchKernelGGL(k_expand_basis<W>, dim3(nblk), dim3(256), 0, s, p.D, p.nA(), p.nB(), p.WA,
                      p.WB, b.a_off.p, b.a_seg.p, b.bseg_start.p, b.a_bits.p, b.b_bits.p,
-                     b.words.p, b.row_a.p, b.row_p.p);
+                     b.words.p, b.row_a.p, b.row_p.p, b.row_b.p);
 }
 
 void launch_expand_basis(const cib_basis &b, hipStream_t s) {
@@ -912,7 +934,7 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
   // ---- per-row counting passes (both triangles), offsets
   RowArgs ra{};
   ra.D = p.D; ra.nA = nA; ra.nB = nB; ra.nseg = nseg;
-  ra.row_a = b.row_a.p; ra.row_p = b.row_p.p; ra.a_seg = b.a_seg.p; ra.a_len = b.a_len.p;
+  ra.row_a = b.row_a.p; ra.row_p = b.row_p.p; ra.row_b = b.row_b.p; ra.a_seg = b.a_seg.p; ra.a_len = b.a_len.p;
   ra.bseg_start = b.bseg_start.p; ra.a_off = b.a_off.p; ra.a_bits = b.a_bits.p; ra.b_bits = b.b_bits.p;
   ra.eA = eA.p; ra.t_ptr = t_ptr.p; ra.tstride = nchunk; ra.t_off = t_off.p; ra.t_len = t_len.p; ra.t_info = t_info.p;
   ra.t_val = t_val.p; ra.t_rb = t_rb.p; ra.ls_ptr = ls_ptr.p; ra.l1_seg = l1_seg.p; ra.ls_self = ls_self.p;

@@ -184,7 +184,7 @@ struct cib_basis {
   cib::DBuf<uint64_t> a_bits, b_bits;   // SoA: word w of configuration k at [w * n + k]
   cib::DBuf<int32_t> a_m2, a_q, a_len, a_seg, b_m2, b_q, b_seg, bseg_start;
   cib::DBuf<int64_t> a_off;
-  cib::DBuf<int32_t> row_a, row_p;      // per state: A-block and position in it
+  cib::DBuf<int32_t> row_a, row_p, row_b;   // per state: A-block, position in it, B configuration
   cib::DBuf<uint64_t> words;            // SoA: (WA + WB) words x D
 };
 

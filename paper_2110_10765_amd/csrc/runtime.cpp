@@ -226,6 +226,7 @@ cib_basis *make_basis(cib_ctx *ctx, const cib_basis_spec &spec, hipStream_t s) {
   b->a_off.upload(p.a_off.data(), p.a_off.size(), s);
   b->row_a.reset(ctx, p.D);
   b->row_p.reset(ctx, p.D);
+  b->row_b.reset(ctx, p.D);
   b->words.reset(ctx, (size_t)(p.WA + p.WB) * p.D);
   launch_expand_basis(*b, s);
   CIB_HIP(hipStreamSynchronize(s));  // host staging vectors go out of scope
