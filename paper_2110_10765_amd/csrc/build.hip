@@ -206,9 +206,52 @@ struct TileArgs {
   int32_t *tcnt;          // count pass: per unit
   const int64_t *t_ptr;   // fill pass: per unit
   int64_t *t_off;
-  int32_t *t_len, *t_info, *t_rb;
-  double *t_val;
+  int32_t *t_len, *t_src, *t_dst;   // fill pass: (alpha, alpha') of every tile
 };
+
+// Phase, info and value of one tile, alpha the bra (row) and alpha' the ket
+// (column): kA = 1 (p <- h, spectators in common): info = 1 | p << 2 | h << 10
+// | phase bit << 18 | 2M list of alpha' << 19, value = phase x AA spectator
+// sum, rb = row base of p <- h in the V^AB transition table; kA = 2: info 2,
+// value = phase x pair element.
+template <int W>
+__global__ __launch_bounds__(256) void k_tile_val(int64_t n, const int32_t *__restrict__ src,
+                                                  const int32_t *__restrict__ dst,
+                                                  const uint64_t *__restrict__ a_bits, int nAc,
+                                                  const int32_t *__restrict__ a_seg, DevInter it,
+                                                  int32_t *__restrict__ t_info, double *__restrict__ t_val,
+                                                  int32_t *__restrict__ t_rb) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const int alpha = src[e], j = dst[e];
+  uint64_t ra[W], ca[W], part[W], hole[W], common[W];
+  load_bits<W>(a_bits, nAc, alpha, ra);
+  load_bits<W>(a_bits, nAc, j, ca);
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    part[w] = ra[w] & ~ca[w];
+    hole[w] = ca[w] & ~ra[w];
+    common[w] = ra[w] & ca[w];
+  }
+  const int p1 = pop_lowest<W>(part), h1 = pop_lowest<W>(hole);
+  const int p2 = pop_lowest<W>(part), h2 = pop_lowest<W>(hole);
+  int info;
+  double val;
+  if (p2 < 0) {  // kA = 1
+    const int sg = sign_single<W>(ca, p1, h1);
+    const double sum = sum_over_bits<W>(
+        common, [&](int x) { return vbar_same(it.pidxA, it.prowA, it.nA, it.vA, p1, x, h1); });
+    val = sg * sum;
+    info = 1 | (p1 << 2) | (h1 << 10) | ((sg < 0) << 18) | (a_seg[j] << 19);
+    t_rb[e] = it.arb ? it.arb[p1 * it.nA + h1] : 0;
+  } else {       // kA = 2
+    const int sg = sign_double<W>(ca, p1, p2, h1, h2);
+    val = sg * v_pair(it.pidxA, it.prowA, it.nA, it.vA, p1, p2, h1, h2);
+    info = 2;
+  }
+  t_info[e] = info;
+  t_val[e] = val;
+}
 
 constexpr int kTileChunk = 256;   // candidate configurations per wave
 
@@ -235,46 +278,34 @@ __global__ __launch_bounds__(256) void k_tile_pass(TileArgs g) {
   const int m = uni(g.a_m2[alpha]);
   int64_t out = FILL ? uni(g.t_ptr[unit]) : 0;
   int cnt = 0;
+  // candidate bits one chunk ahead (clamped, unconditional reads)
+  uint64_t na[W];
+  int nm = 0;
+  auto fetch = [&](int j0) {
+    const int jj = min(j0 + lane, je - 1);
+    load_bits<W>(g.a_bits, g.nA, jj, na);
+    nm = g.a_m2[jj];
+  };
+  fetch(jb);
   for (int j0 = jb; j0 < je; j0 += kWave) {
     const int j = j0 + lane;
     bool ok = false;
     uint64_t ca[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) ca[w] = na[w];
+    const int cm = nm;
+    fetch(j0 + kWave);
     if (j < je) {
-      load_bits<W>(g.a_bits, g.nA, j, ca);
       const int d = popc_xor<W>(ra, ca);
-      ok = d <= 2 || (d == 4 && g.a_m2[j] == m);
+      ok = d <= 2 || (d == 4 && cm == m);
     }
     const uint64_t msk = ballot(ok);
     if (FILL && ok) {
       const int64_t o = out + cnt + mask_rank(msk);
       g.t_off[o] = g.a_off[j];
       g.t_len[o] = g.a_len[j];
-      uint64_t part[W], hole[W], common[W];
-#pragma unroll
-      for (int w = 0; w < W; ++w) {
-        part[w] = ra[w] & ~ca[w];
-        hole[w] = ca[w] & ~ra[w];
-        common[w] = ra[w] & ca[w];
-      }
-      const int p1 = pop_lowest<W>(part), h1 = pop_lowest<W>(hole);
-      const int p2 = pop_lowest<W>(part), h2 = pop_lowest<W>(hole);
-      int info;
-      double val;
-      if (p2 < 0) {  // kA = 1: p1 <- h1, spectators in common
-        const int s = sign_single<W>(ca, p1, h1);
-        double sum = 0.0;
-        for (int x = pop_lowest<W>(common); x >= 0; x = pop_lowest<W>(common))
-          sum += vbar_same(g.it.pidxA, g.it.prowA, g.it.nA, g.it.vA, p1, x, h1);
-        val = s * sum;
-        info = 1 | (p1 << 2) | (h1 << 10) | ((s < 0) << 18) | (g.a_seg[j] << 19);
-        g.t_rb[o] = g.it.arb ? g.it.arb[p1 * g.it.nA + h1] : 0;
-      } else {       // kA = 2
-        const int s = sign_double<W>(ca, p1, p2, h1, h2);
-        val = s * v_pair(g.it.pidxA, g.it.prowA, g.it.nA, g.it.vA, p1, p2, h1, h2);
-        info = 2;
-      }
-      g.t_info[o] = info;
-      g.t_val[o] = val;
+      g.t_src[o] = alpha;
+      g.t_dst[o] = j;
     }
     cnt += __popcll(msk);
   }
@@ -297,9 +328,57 @@ struct AdjArgs {
   DevInter it;
   int32_t *ls_cnt, *l1_cnt;           // count pass
   const int64_t *ls_ptr, *l1_seg;     // fill pass
-  int32_t *ls_self, *ls_pos, *ls_info, *l1_pos, *l1_info;
-  double *ls_val;
+  int32_t *ls_self, *ls_pos, *l1_pos;
+  int32_t *ls_src, *ls_dst, *l1_src, *l1_dst;   // (beta, beta') of every entry
 };
+
+// Phase, value and table column of one B adjacency entry (beta bra, beta'
+// ket).  Entry info: orbitals changed (0, 1, 2) | phase bit << 2 | (one
+// change b <- d) the column of b <- d in the V^AB transition table << 3.
+// The value is the B-only part: E_B for beta' = beta, the spectator sum for
+// one change, the pair element for two.
+template <int W>
+__global__ __launch_bounds__(256) void k_adj_val(int64_t n, const int32_t *__restrict__ src,
+                                                 const int32_t *__restrict__ dst,
+                                                 const uint64_t *__restrict__ b_bits, int nBc,
+                                                 const double *__restrict__ eB, DevInter it,
+                                                 int32_t *__restrict__ info_out, double *__restrict__ val_out) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const int beta = src[e], bj = dst[e];
+  uint64_t rb[W], cb[W], part[W], hole[W], common[W];
+  load_bits<W>(b_bits, nBc, beta, rb);
+  load_bits<W>(b_bits, nBc, bj, cb);
+  int d = 0;
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    part[w] = rb[w] & ~cb[w];
+    hole[w] = cb[w] & ~rb[w];
+    common[w] = rb[w] & cb[w];
+    d += __popcll(part[w]);
+  }
+  const int p1 = pop_lowest<W>(part), h1 = pop_lowest<W>(hole);
+  const int p2 = pop_lowest<W>(part), h2 = pop_lowest<W>(hole);
+  int info = 0;
+  double val = 0.0;
+  if (d == 0) {
+    val = eB[beta];
+  } else if (d == 1) {
+    const int sg = sign_single<W>(cb, p1, h1);
+    info = 1 | ((sg < 0) << 2) | ((it.bcol ? it.bcol[p1 * it.nB + h1] : 0) << 3);
+    if (val_out) {
+      const double sum = sum_over_bits<W>(
+          common, [&](int y) { return vbar_same(it.pidxB, it.prowB, it.nB, it.vB, p1, y, h1); });
+      val = sg * sum;
+    }
+  } else {
+    const int sg = sign_double<W>(cb, p1, p2, h1, h2);
+    info = 2;
+    if (val_out) val = sg * v_pair(it.pidxB, it.prowB, it.nB, it.vB, p1, p2, h1, h2);
+  }
+  info_out[e] = info;
+  if (val_out) val_out[e] = val;
+}
 
 template <int W, bool FILL>
 __global__ __launch_bounds__(256) void k_adj_pass(AdjArgs g) {
@@ -321,57 +400,33 @@ __global__ __launch_bounds__(256) void k_adj_pass(AdjArgs g) {
   int c_ls = 0, c_l1 = 0;
   const int64_t ls0 = FILL && own ? uni(g.ls_ptr[beta]) : 0;
   const int64_t l10 = FILL ? uni(g.l1_seg[unit]) : 0;
+  // candidate bits one chunk ahead (clamped, unconditional reads)
+  uint64_t nb_[W];
+  auto fetch = [&](int j0) { load_bits<W>(g.b_bits, g.nB, min(j0 + lane, hi - 1), nb_); };
+  if (lo < hi) fetch(lo);
   for (int j0 = lo; j0 < hi; j0 += kWave) {
     const int j = j0 + lane;
     int d = 99;
     uint64_t cb[W];
-    if (j < hi) {
-      load_bits<W>(g.b_bits, g.nB, j, cb);
-      d = popc_xor<W>(rb, cb);
-    }
+#pragma unroll
+    for (int w = 0; w < W; ++w) cb[w] = nb_[w];
+    fetch(j0 + kWave);
+    if (j < hi) d = popc_xor<W>(rb, cb);
     const bool in_ls = own && d <= 4;
     const bool in_l1 = d <= 2;
     const uint64_t m_ls = ballot(in_ls), m_l1 = ballot(in_l1);
-    if (FILL && (in_ls || in_l1)) {
-      uint64_t part[W], hole[W], common[W];
-#pragma unroll
-      for (int w = 0; w < W; ++w) {
-        part[w] = rb[w] & ~cb[w];
-        hole[w] = cb[w] & ~rb[w];
-        common[w] = rb[w] & cb[w];
-      }
-      const int p1 = pop_lowest<W>(part), h1 = pop_lowest<W>(hole);
-      const int p2 = pop_lowest<W>(part), h2 = pop_lowest<W>(hole);
-      int info = 0, sg = 1;
-      double val = 0.0;
-      if (d == 0) {
-        val = g.eB[beta];
-      } else if (d == 2) {
-        sg = sign_single<W>(cb, p1, h1);
-        info = 1 | ((sg < 0) << 2) | ((g.it.bcol ? g.it.bcol[p1 * g.it.nB + h1] : 0) << 3);
-        if (in_ls) {
-          double sum = 0.0;
-          for (int y = pop_lowest<W>(common); y >= 0; y = pop_lowest<W>(common))
-            sum += vbar_same(g.it.pidxB, g.it.prowB, g.it.nB, g.it.vB, p1, y, h1);
-          val = sg * sum;
-        }
-      } else {
-        sg = sign_double<W>(cb, p1, p2, h1, h2);
-        info = 2;
-        val = sg * v_pair(g.it.pidxB, g.it.prowB, g.it.nB, g.it.vB, p1, p2, h1, h2);
-      }
-      if (in_ls) {
-        const int64_t o = ls0 + c_ls + mask_rank(m_ls);
-        g.ls_pos[o] = j - lo;
-        g.ls_info[o] = info;
-        g.ls_val[o] = val;
-        if (d == 0) g.ls_self[beta] = (int32_t)o;
-      }
-      if (in_l1) {
-        const int64_t o = l10 + c_l1 + mask_rank(m_l1);
-        g.l1_pos[o] = j - lo;
-        g.l1_info[o] = info;
-      }
+    if (FILL && in_ls) {
+      const int64_t o = ls0 + c_ls + mask_rank(m_ls);
+      g.ls_pos[o] = j - lo;
+      g.ls_src[o] = beta;
+      g.ls_dst[o] = j;
+      if (d == 0) g.ls_self[beta] = (int32_t)o;
+    }
+    if (FILL && in_l1) {
+      const int64_t o = l10 + c_l1 + mask_rank(m_l1);
+      g.l1_pos[o] = j - lo;
+      g.l1_src[o] = beta;
+      g.l1_dst[o] = j;
     }
     c_ls += __popcll(m_ls);
     c_l1 += __popcll(m_l1);
@@ -911,23 +966,43 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
   DBuf<int32_t> t_len(ctx, at_least1(n_tiles)), t_info(ctx, at_least1(n_tiles));
   DBuf<int32_t> tl_len(ctx, at_least1(n_lt)), tl_info(ctx, at_least1(n_lt));
   DBuf<int32_t> t_rb(ctx, at_least1(n_tiles)), tl_rb(ctx, at_least1(n_lt));
+  DBuf<int32_t> t_src(ctx, at_least1(n_tiles)), t_dst(ctx, at_least1(n_tiles));
+  DBuf<int32_t> tl_src(ctx, at_least1(n_lt)), tl_dst(ctx, at_least1(n_lt));
   DBuf<double> t_val(ctx, at_least1(n_tiles)), tl_val(ctx, at_least1(n_lt));
-  DBuf<int32_t> ls_self(ctx, nB), ls_pos(ctx, n_ls), ls_info(ctx, n_ls), l1_pos(ctx, n_l1),
-      l1_info(ctx, n_l1);
-  DBuf<double> ls_val(ctx, n_ls);
+  DBuf<int32_t> ls_self(ctx, nB), ls_pos(ctx, at_least1(n_ls)), ls_info(ctx, at_least1(n_ls)),
+      l1_pos(ctx, at_least1(n_l1)), l1_info(ctx, at_least1(n_l1));
+  DBuf<int32_t> ls_src(ctx, at_least1(n_ls)), ls_dst(ctx, at_least1(n_ls));
+  DBuf<int32_t> l1_src(ctx, at_least1(n_l1)), l1_dst(ctx, at_least1(n_l1));
+  DBuf<double> ls_val(ctx, at_least1(n_ls));
   CIB_HIP(hipEventRecord(ev.e[2], s));
-  ta.t_ptr = t_ptr.p; ta.t_off = t_off.p; ta.t_len = t_len.p; ta.t_info = t_info.p; ta.t_val = t_val.p;
-  ta.t_rb = t_rb.p;
-  tl.t_ptr = tl_ptr.p; tl.t_off = tl_off.p; tl.t_len = tl_len.p; tl.t_info = tl_info.p; tl.t_val = tl_val.p;
-  tl.t_rb = tl_rb.p;
+  ta.t_ptr = t_ptr.p; ta.t_off = t_off.p; ta.t_len = t_len.p; ta.t_src = t_src.p; ta.t_dst = t_dst.p;
+  tl.t_ptr = tl_ptr.p; tl.t_off = tl_off.p; tl.t_len = tl_len.p; tl.t_src = tl_src.p; tl.t_dst = tl_dst.p;
+  auto nb256 = [](int64_t n) { return dim3((unsigned)std::max<int64_t>((n + 255) / 256, 1)); };
   {
     KTimer kt(ctx, K_TILE, s);
     hipLaunchKernelGGL((k_tile_pass<W, true, false>), dim3(tblk), dim3(256), 0, s, ta);
     hipLaunchKernelGGL((k_tile_pass<W, true, true>), dim3(tblk), dim3(256), 0, s, tl);
+    // phases and values, one thread per tile
+    if (n_tiles)
+      hipLaunchKernelGGL((k_tile_val<W>), nb256(n_tiles), dim3(256), 0, s, n_tiles, t_src.p, t_dst.p,
+                         b.a_bits.p, nA, b.a_seg.p, it, t_info.p, t_val.p, t_rb.p);
+    if (n_lt)
+      hipLaunchKernelGGL((k_tile_val<W>), nb256(n_lt), dim3(256), 0, s, n_lt, tl_src.p, tl_dst.p,
+                         b.a_bits.p, nA, b.a_seg.p, it, tl_info.p, tl_val.p, tl_rb.p);
   }
   aa.ls_ptr = ls_ptr.p; aa.l1_seg = l1_seg.p; aa.ls_self = ls_self.p; aa.ls_pos = ls_pos.p;
-  aa.ls_info = ls_info.p; aa.l1_pos = l1_pos.p; aa.l1_info = l1_info.p; aa.ls_val = ls_val.p;
-  { KTimer kt(ctx, K_ADJ, s); hipLaunchKernelGGL((k_adj_pass<W, true>), dim3(ablk), dim3(256), 0, s, aa); }
+  aa.l1_pos = l1_pos.p; aa.ls_src = ls_src.p; aa.ls_dst = ls_dst.p; aa.l1_src = l1_src.p; aa.l1_dst = l1_dst.p;
+  {
+    KTimer kt(ctx, K_ADJ, s);
+    hipLaunchKernelGGL((k_adj_pass<W, true>), dim3(ablk), dim3(256), 0, s, aa);
+    // phases, table columns and B-only values, one thread per entry
+    if (n_ls)
+      hipLaunchKernelGGL((k_adj_val<W>), nb256(n_ls), dim3(256), 0, s, n_ls, ls_src.p, ls_dst.p, b.b_bits.p,
+                         nB, eB.p, it, ls_info.p, ls_val.p);
+    if (n_l1)
+      hipLaunchKernelGGL((k_adj_val<W>), nb256(n_l1), dim3(256), 0, s, n_l1, l1_src.p, l1_dst.p, b.b_bits.p,
+                         nB, eB.p, it, l1_info.p, (double *)nullptr);
+  }
   CIB_HIP(hipGetLastError());
   CIB_HIP(hipEventRecord(ev.e[3], s));
 
