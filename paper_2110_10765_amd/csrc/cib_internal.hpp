@@ -264,7 +264,25 @@ void spmm_sym(const cib_matrix &H, const void *X, int64_t ldx, void *Y, int64_t 
 // residuals, b Ritz values) is copied to host memory by lobpcg_copy_status.
 constexpr int kStatusLen = 1 + 2 * kMaxBlock;
 struct LobpcgRun;
+// Arguments of one Rayleigh-Ritz step (device pointers of one solve).
+struct RRArgs {
+  int ns, b, nparts;
+  const double *partial;
+  double *C;        // ns x 2b: [Cx | Cp]
+  double *lam;      // b
+  int32_t *flag;    // [0]: rank of the search space, [1]: fallback taken
+  double drop_tol;
+  const double *hlow;  // lower bound of the spectrum of H (Gershgorin)
+  long long *clk;      // optional: wall-clock stamps of the phases (thread 0)
+};
+
 LobpcgRun *lobpcg_create(cib_ctx *ctx, const cib_matrix &H, const cib_lobpcg_opts &o, hipStream_t s);
+// iterate() == iterate_pre(), the Rayleigh-Ritz step of lobpcg_rr_args(),
+// iterate_post(); launch_rr_group runs n such steps (device array) at once
+void lobpcg_iterate_pre(LobpcgRun *r);
+RRArgs lobpcg_rr_args(const LobpcgRun *r);
+void lobpcg_iterate_post(LobpcgRun *r);
+void launch_rr_group(const RRArgs *dev_args, int n, hipStream_t s);
 void lobpcg_start(LobpcgRun *r);
 void lobpcg_iterate(LobpcgRun *r);
 void lobpcg_copy_status(LobpcgRun *r, double *host);

@@ -287,16 +287,6 @@ __global__ __launch_bounds__(1024) void k_min(int64_t n, const double *in, doubl
 }
 
 // ------------------------------------------------------------ Rayleigh-Ritz
-struct RRArgs {
-  int ns, b, nparts;
-  const double *partial;
-  double *C;        // ns x 2b: [Cx | Cp]
-  double *lam;      // b
-  int32_t *flag;    // [0]: rank of the search space, [1]: fallback taken
-  double drop_tol;
-  const double *hlow;  // lower bound of the spectrum of H (Gershgorin)
-  long long *clk;      // optional: wall-clock stamps of the phases (thread 0)
-};
 
 __device__ __forceinline__ uint32_t sign_word(double v) {
   return (uint32_t)(__builtin_bit_cast(uint64_t, v) >> 32);
@@ -356,7 +346,7 @@ __device__ __forceinline__ int sturm_count(const double *d, const double *e2, in
 // twisted LDL^T / UDU^T factorisations, re-orthogonalised inside clusters;
 // (8) back to M's basis with the Householder reflectors; (9) coefficients
 // C_x = scale * Z^T y and C_p = C_x with the X rows zeroed (P = W C_W + P C_P).
-__global__ __launch_bounds__(256) void k_rayleigh_ritz(RRArgs g) {
+__device__ __forceinline__ void rayleigh_ritz(const RRArgs &g) {
   __shared__ double G[kNS][kLd], Hm[kNS][kLd], Z[kNS][kLd];
   __shared__ double scale[kNS], dd[kNS], ee[kNS], e2[kNS], beta[kNS], dinv[kNS];
   __shared__ double pw[4][kNS];
@@ -806,6 +796,21 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz(RRArgs g) {
   if (g.clk && tid == 0) g.clk[10] = wall_clock64();
 }
 
+__global__ __launch_bounds__(256) void k_rayleigh_ritz(RRArgs g) { rayleigh_ritz(g); }
+
+// The Rayleigh-Ritz steps of several independent solves in one launch, one
+// workgroup each (each on its own compute unit): the serving loop's batch.
+__global__ __launch_bounds__(256) void k_rayleigh_ritz_group(const RRArgs *__restrict__ gs) {
+  const RRArgs g = gs[blockIdx.x];
+  rayleigh_ritz(g);
+}
+
+void launch_rr_group(const RRArgs *dev_args, int n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_rayleigh_ritz_group, dim3(n), dim3(256), 0, s, dev_args);
+  CIB_HIP(hipGetLastError());
+}
+
 // ------------------------------------------------------------ update
 struct UpdArgs {
   int64_t D;
@@ -1072,6 +1077,18 @@ struct LobpcgRun {
   }
 
   void rr_update(int ns) {
+    gram_step(ns);
+    RRArgs ra = rr_args(ns);
+    { KTimer kt(ctx, K_RR, s); hipLaunchKernelGGL(k_rayleigh_ritz, dim3(1), dim3(256), 0, s, ra); }
+    update_step(ns);
+  }
+
+  RRArgs rr_args(int ns) const {
+    return RRArgs{ns, b, 1, gram.p, C.p, lam.p, flag.p, H.dtype == CIB_F64 ? 1e-10 : 1e-7, hlow.p,
+                  clk_on ? clk.p : nullptr};
+  }
+
+  void gram_step(int ns) {
     {
       KTimer kt(ctx, K_GRAM, s);
       const int T = (ns + 15) / 16;
@@ -1088,9 +1105,9 @@ struct LobpcgRun {
       hipLaunchKernelGGL(k_sum_parts, dim3((nout + 255) / 256, 1), dim3(256), 0, s, nout, groups, groups,
                          partial2.p, gram.p);
     }
-    RRArgs ra{ns, b, 1, gram.p, C.p, lam.p, flag.p, H.dtype == CIB_F64 ? 1e-10 : 1e-7, hlow.p,
-              clk_on ? clk.p : nullptr};
-    { KTimer kt(ctx, K_RR, s); hipLaunchKernelGGL(k_rayleigh_ritz, dim3(1), dim3(256), 0, s, ra); }
+  }
+
+  void update_step(int ns) {
     UpdArgs ua{D, b, ns, ld, S.p, HS.p, C.p, lam.p, diag.p, H.dtype == CIB_F32 ? x32.p : nullptr,
                npart.p, (int)upd_rows, locked.p};
     {
@@ -1158,6 +1175,17 @@ struct LobpcgRun {
     rr_update(iters == 1 ? 2 * b : 3 * b);
   }
 
+  // one iteration in three parts, for a caller that batches the middle
+  // (Rayleigh-Ritz) part of several solves into one launch
+  int step_ns = 0;
+  void iterate_pre() {
+    ++iters;
+    step_ns = iters == 1 ? 2 * b : 3 * b;
+    spmm(1, H.dtype == CIB_F32);
+    gram_step(step_ns);
+  }
+  void iterate_post() { update_step(step_ns); }
+
   void copy_status(double *host) {
     CIB_HIP(hipMemcpyAsync(host, status.p, sizeof(double) * kStatusLen, hipMemcpyDeviceToHost, s));
   }
@@ -1193,6 +1221,9 @@ LobpcgRun *lobpcg_create(cib_ctx *ctx, const cib_matrix &H, const cib_lobpcg_opt
   return new LobpcgRun(ctx, H, o, s, false);
 }
 void lobpcg_start(LobpcgRun *r) { r->start(); }
+void lobpcg_iterate_pre(LobpcgRun *r) { r->iterate_pre(); }
+RRArgs lobpcg_rr_args(const LobpcgRun *r) { return r->rr_args(r->step_ns); }
+void lobpcg_iterate_post(LobpcgRun *r) { r->iterate_post(); }
 void lobpcg_iterate(LobpcgRun *r) { r->iterate(); }
 void lobpcg_copy_status(LobpcgRun *r, double *host) { r->copy_status(host); }
 int lobpcg_iters(const LobpcgRun *r) { return r->iters; }

@@ -1,18 +1,22 @@
 // Continuous-batching serving loop (cib_serve).
 //
-// Two host threads share one context:
-//   builder  takes requests in arrival order once they have arrived and a slot
-//            is free, builds the basis and the interaction tables, runs the
-//            counting passes of the H build, then waits until the request's
-//            whole device footprint (H, LOBPCG state, build scratch) fits the
-//            HBM budget, fills H and hands the request to the solver;
+// Host threads share one context:
+//   builders (four, one stream each) take requests in arrival order once they
+//            have arrived and a slot is free, build the basis and the
+//            interaction tables, run the counting passes of the H build, then
+//            wait until the request's whole device footprint (H, LOBPCG state,
+//            build scratch) fits the HBM budget, fill H and hand the request to
+//            the solver;
 //   solver   keeps every admitted request's H and LOBPCG state resident and,
 //            each step, enqueues one stage for every active request
 //            (initialisation for new ones, one LOBPCG iteration for the rest)
-//            on a pool of streams so their kernels overlap on the device,
-//            waits once, reads every status block from pinned memory, and
-//            retires converged requests (releasing their memory and budget).
+//            on a pool of streams so their kernels overlap on the device; the
+//            Rayleigh-Ritz steps of the iterating requests go out as one
+//            launch, one workgroup per request.  It then waits once, reads
+//            every status block from pinned memory, and retires converged
+//            requests (releasing their memory and budget).
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -91,22 +95,39 @@ cib_status serve_run(cib_ctx *ctx, const cib_request *reqs, int n, const cib_ser
   std::stable_sort(order.begin(), order.end(),
                    [&](int a, int b) { return reqs[a].arrival_s < reqs[b].arrival_s; });
 
-  std::vector<hipStream_t> streams(nstreams + 1, nullptr);
+  // several builder threads (one stream each): the builds of small requests
+  // are bound by launches and host waits, so they overlap well
+  const int nbuild = 4;
+  std::vector<hipStream_t> streams(nstreams + 1 + nbuild, nullptr);
   for (auto &st : streams) CIB_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
-  hipStream_t bstream = streams[nstreams];
+  hipStream_t gstream = streams[nstreams];   // batched Rayleigh-Ritz steps
   double *pinned = nullptr;
   CIB_HIP(hipHostMalloc((void **)&pinned, sizeof(double) * kStatusLen * (size_t)sh.max_active,
                         hipHostMallocDefault));
+  // per status slot: the event that ends a solve's pre-Rayleigh-Ritz part;
+  // the batch's arguments go host (pinned) -> device once per step
+  std::vector<hipEvent_t> slot_ev(sh.max_active, nullptr);
+  for (auto &e : slot_ev) CIB_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  hipEvent_t rr_done = nullptr;
+  CIB_HIP(hipEventCreateWithFlags(&rr_done, hipEventDisableTiming));
+  RRArgs *rr_host = nullptr;
+  CIB_HIP(hipHostMalloc((void **)&rr_host, sizeof(RRArgs) * (size_t)sh.max_active, hipHostMallocDefault));
+  DBuf<RRArgs> rr_dev(ctx, (size_t)sh.max_active);
   std::vector<int> free_slots;
   for (int k = sh.max_active - 1; k >= 0; --k) free_slots.push_back(k);
   std::string builder_error;
   cib_status builder_status = CIB_OK;
 
-  // ------------------------------------------------------------ builder thread
-  std::thread builder([&] {
+  // ------------------------------------------------------------ builder threads
+  std::atomic<int> next_k{0};
+  int builders_left = nbuild;
+  auto builder_fn = [&](int bt) {
     int dev = ctx->device;
     (void)hipSetDevice(dev);
-    for (int k = 0; k < n; ++k) {
+    hipStream_t bstream = streams[nstreams + 1 + bt];
+    for (;;) {
+      const int k = next_k.fetch_add(1);
+      if (k >= n) break;
       const int i = order[k];
       const cib_request &q = reqs[i];
       cib_result &res = results[i];
@@ -155,9 +176,14 @@ cib_status serve_run(cib_ctx *ctx, const cib_request *reqs, int n, const cib_ser
         job->inter.reset();  // tables are no longer needed once H is built
       } catch (const Error &e) {
         st = e.code;
-        if (st == CIB_E_DEVICE) { builder_error = e.what(); builder_status = st; }
+        if (st == CIB_E_DEVICE) {
+          std::lock_guard<std::mutex> lk(sh.mu);
+          builder_error = e.what();
+          builder_status = st;
+        }
       } catch (const std::exception &e) {
         st = CIB_E_DEVICE;
+        std::lock_guard<std::mutex> lk(sh.mu);
         builder_error = e.what();
         builder_status = st;
       }
@@ -176,9 +202,13 @@ cib_status serve_run(cib_ctx *ctx, const cib_request *reqs, int n, const cib_ser
       sh.cv.notify_all();
     }
     std::lock_guard<std::mutex> lk(sh.mu);
-    sh.builder_done = true;
+    if (--builders_left == 0) sh.builder_done = true;
     sh.cv.notify_all();
-  });
+  };
+  std::vector<std::thread> builders;
+  for (int bt = 0; bt < nbuild; ++bt) builders.emplace_back(builder_fn, bt);
+
+  auto slot_of = [&](const Job *j) { return (int)((j->status - pinned) / kStatusLen); };
 
   // ------------------------------------------------------------ solver loop
   std::vector<Job *> active;
@@ -203,7 +233,10 @@ cib_status serve_run(cib_ctx *ctx, const cib_request *reqs, int n, const cib_ser
         if (active.empty() && sh.builder_done) break;
       }
       if (now() > deadline) break;
-      // enqueue one stage per active request
+      // enqueue one stage per active request: a new solve starts on its
+      // stream; the others run one iteration whose Rayleigh-Ritz steps go
+      // out as one launch (one workgroup per solve) between the parts
+      std::vector<Job *> iter_jobs;
       for (Job *j : active) {
         hipStream_t s = streams[j->stream];
         if (!j->started) {
@@ -211,12 +244,31 @@ cib_status serve_run(cib_ctx *ctx, const cib_request *reqs, int n, const cib_ser
           j->lp = lobpcg_create(ctx, *j->H, lo, s);
           lobpcg_start(j->lp);
           j->started = true;
+          lobpcg_copy_status(j->lp, j->status);
         } else {
-          lobpcg_iterate(j->lp);
+          lobpcg_iterate_pre(j->lp);
+          CIB_HIP(hipEventRecord(slot_ev[slot_of(j)], s));
+          iter_jobs.push_back(j);
         }
-        lobpcg_copy_status(j->lp, j->status);
+      }
+      if (!iter_jobs.empty()) {
+        const int m = (int)iter_jobs.size();
+        for (int q = 0; q < m; ++q) {
+          CIB_HIP(hipStreamWaitEvent(gstream, slot_ev[slot_of(iter_jobs[q])], 0));
+          rr_host[q] = lobpcg_rr_args(iter_jobs[q]->lp);
+        }
+        CIB_HIP(hipMemcpyAsync(rr_dev.p, rr_host, sizeof(RRArgs) * m, hipMemcpyHostToDevice, gstream));
+        launch_rr_group(rr_dev.p, m, gstream);
+        CIB_HIP(hipEventRecord(rr_done, gstream));
+        for (Job *j : iter_jobs) {
+          hipStream_t s = streams[j->stream];
+          CIB_HIP(hipStreamWaitEvent(s, rr_done, 0));
+          lobpcg_iterate_post(j->lp);
+          lobpcg_copy_status(j->lp, j->status);
+        }
       }
       for (int k = 0; k < nstreams; ++k) CIB_HIP(hipStreamSynchronize(streams[k]));
+      CIB_HIP(hipStreamSynchronize(gstream));
       // retire
       std::vector<Job *> keep;
       for (Job *j : active) {
@@ -255,11 +307,14 @@ cib_status serve_run(cib_ctx *ctx, const cib_request *reqs, int n, const cib_ser
     sh.cancelled = true;
     sh.cv.notify_all();
   }
-  builder.join();
+  for (auto &t : builders) t.join();
   for (auto &st : streams) (void)hipStreamSynchronize(st);
   for (Job *j : active) delete j;
   for (Job *j : sh.ready) delete j;
   for (auto &st : streams) (void)hipStreamDestroy(st);
+  for (auto &e : slot_ev) (void)hipEventDestroy(e);
+  (void)hipEventDestroy(rr_done);
+  (void)hipHostFree(rr_host);
   (void)hipHostFree(pinned);
   if (loop_status != CIB_OK) throw Error(loop_status, loop_error);
   if (builder_status != CIB_OK) throw Error(builder_status, builder_error);
