@@ -134,25 +134,57 @@ def workload_rates(cib, ctx, cigen, name, b, reps=20):
     return out
 
 
-def serve_run(cib, ctx, cigen, dtype, n_req, budget=0):
+def serve_run(cib, ctx, cigen, dtype, n_req, budget=0, rate=math.inf):
+    """The 512-request stream (trace seed 5).  rate = inf: all requests at
+    t = 0 (closed loop, capacity); finite: Poisson arrivals replayed in real
+    time, latency = t_done - t_arrive."""
     reqs = []
-    for r in cigen.request_trace(n_req):
+    for r in cigen.request_trace(n_req, rate=rate):
         r = dict(r)
         r["tables"] = cigen.make_tables(r["spec"], r["seed"])
         r["dtype"] = dtype
         r["tol"] = 0.0   # library default per dtype
         reqs.append(r)
     t0 = time.perf_counter()
-    res = cib.serve(ctx, reqs, hbm_budget_bytes=budget)
+    res = cib.serve(ctx, reqs, hbm_budget_bytes=budget, realtime=not math.isinf(rate))
     wall = time.perf_counter() - t0
     import numpy as np
     ok = [x for x in res if x["status"] == 0]
     lat = np.asarray([x["t_done"] - x["t_arrive"] for x in ok])
-    return {"requests": n_req, "ok": len(ok),
-            "empty_basis": sum(1 for x in res if x["status"] == cib.CIB_E_EMPTY_BASIS),
-            "solves_per_s": len(ok) / wall, "makespan_s": wall,
-            "p50_s": float(np.percentile(lat, 50)) if len(lat) else None,
-            "p99_s": float(np.percentile(lat, 99)) if len(lat) else None}
+    wait = np.asarray([x["t_admit"] - x["t_arrive"] for x in ok])
+    out = {"requests": n_req, "ok": len(ok),
+           "empty_basis": sum(1 for x in res if x["status"] == cib.CIB_E_EMPTY_BASIS),
+           "nomem": sum(1 for x in res if x["status"] == cib.CIB_E_NOMEM),
+           "solves_per_s": len(ok) / wall, "makespan_s": wall,
+           "p50_s": float(np.percentile(lat, 50)) if len(lat) else None,
+           "p99_s": float(np.percentile(lat, 99)) if len(lat) else None,
+           "admit_wait_p99_s": float(np.percentile(wait, 99)) if len(wait) else None}
+    if not math.isinf(rate):
+        out["arrival_rate_per_s"] = rate
+    if budget:
+        out["hbm_budget_bytes"] = budget
+    return out
+
+
+def serve_suite(cib, ctx, cigen, n_req, sweep=True):
+    """Closed-loop capacity C per dtype; with sweep, Poisson replays of the
+    same trace at 0.5, 0.8, 0.95 C (float32) and 0.8 C (float64), and the
+    closed loop under 2 GiB and 8 GiB HBM budgets (admission queueing)."""
+    sub = {}
+    for dt in ("f32", "f64"):
+        sub["serve_" + dt] = serve_run(cib, ctx, cigen, dt, n_req)
+    if not sweep:
+        return sub
+    for dt, fracs in (("f32", (0.5, 0.8, 0.95)), ("f64", (0.8,))):
+        cap = sub["serve_" + dt]["solves_per_s"]
+        for f in fracs:
+            sub["serve_%s_poisson_%02d" % (dt, round(100 * f))] = serve_run(cib, ctx, cigen, dt, n_req,
+                                                                             rate=f * cap)
+    for dt in ("f32", "f64"):
+        for gib in (2, 8):
+            sub["serve_%s_budget_%dgib" % (dt, gib)] = serve_run(cib, ctx, cigen, dt, n_req,
+                                                                 budget=gib << 30)
+    return sub
 
 
 def cpu_baseline(cigen, name, seconds=15.0):
@@ -190,6 +222,8 @@ def main():
     ap.add_argument("--extra", default="ab_n3_3p3_cut4:8,ab_n5_4p4_cut4:8")
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-serve-sweep", action="store_true",
+                    help="serving: closed loop only (no Poisson replays, no budget runs)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy 1 GiB five times (scale factor for the HBM byte counters)")
@@ -301,8 +335,7 @@ def main():
     sub["workloads"] = ws
     if not args.no_serve:
         try:
-            sub["serve_f32"] = serve_run(cib, ctx, cigen, "f32", args.serve_requests)
-            sub["serve_f64"] = serve_run(cib, ctx, cigen, "f64", args.serve_requests)
+            sub.update(serve_suite(cib, ctx, cigen, args.serve_requests, sweep=not args.no_serve_sweep))
         except cib.CibError as e:
             sub["serve"] = {"error": str(e)}
     line = {
