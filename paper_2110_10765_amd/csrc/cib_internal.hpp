@@ -264,6 +264,28 @@ void spmm_sym(const cib_matrix &H, const void *X, int64_t ldx, void *Y, int64_t 
 // residuals, b Ritz values) is copied to host memory by lobpcg_copy_status.
 constexpr int kStatusLen = 1 + 2 * kMaxBlock;
 struct LobpcgRun;
+// Arguments of the SpMM row kernel for nvec 8 / 16 with 16-byte aligned rows.
+struct VecArgs {
+  int64_t D;
+  const int64_t *rp;
+  const int32_t *col;
+  const void *val;
+  const int64_t *lrp;
+  const int32_t *lcol;
+  const void *lval;
+  const void *X;
+  int64_t ldx;
+  void *Y;
+  int64_t ldy;
+  int64_t xr[9];     // XCD x takes rows [xr[x], xr[x + 1]) (single launches only)
+};
+// false when the vector kernel does not apply (nvec, alignment); blocks =
+// workgroups of the matrix in a grouped launch
+bool spmm_vec_args(const cib_matrix &H, const void *X, int64_t ldx, void *Y, int64_t ldy, int nvec, VecArgs &a,
+                   int &blocks);
+void launch_spmm_group(cib_dtype dt, int nvec, const VecArgs *dev_args, const int32_t *dev_off, int njobs,
+                       int total_blocks, hipStream_t s);
+
 // Arguments of one Rayleigh-Ritz step (device pointers of one solve).
 struct RRArgs {
   int ns, b, nparts;
@@ -276,13 +298,86 @@ struct RRArgs {
   long long *clk;      // optional: wall-clock stamps of the phases (thread 0)
 };
 
+// Per-stage arguments of one LOBPCG iteration (device pointers of one solve).
+struct UpdArgs {
+  int64_t D;
+  int b, ns, ld;
+  double *S, *HS;
+  const double *C, *lam, *diag;
+  float *w32;             // optional float32 copy of W (dense D x b)
+  double *npart;          // per block: b residual sums, b |x|^2 sums
+  int rows_per_blk;
+  const int32_t *locked;  // per column: converged at the previous check (W = 0)
+};
+struct WidenArgs {
+  int64_t D;
+  int b;
+  const float *in;
+  double *out;
+  int ldo;
+};
+struct GramArgs {
+  int64_t D;
+  int ns, ld;
+  const double *S, *HS;
+  int64_t rows_per_blk;
+  double *partial;
+};
+struct SumArgs {   // out[g][e] = sum of in[q][e] over parts q of group g (groups of per)
+  int nout, nparts, per;
+  const double *in;
+  double *out;
+};
+struct FinishArgs {
+  int b, nev, nparts;
+  const double *npart, *lam;
+  double tol;
+  double *status;
+  int32_t *locked;
+};
+
+// One LOBPCG iteration of one solve, stage by stage, with each stage's
+// workgroup count (the serving loop's grouped launches).
+struct IterPlan {
+  cib_dtype dt;
+  int nvec;
+  VecArgs spmm;
+  int spmm_blocks;
+  bool widen;
+  WidenArgs wid;
+  int widen_blocks;
+  int T;
+  GramArgs gram;
+  int gram_blocks;
+  SumArgs gs1, gs2;
+  int gs1_blocks, gs2_blocks;
+  RRArgs rr;
+  int TN;
+  UpdArgs upd;
+  int upd_blocks;
+  SumArgs us;
+  int us_blocks;
+  FinishArgs fin;
+  const double *status;   // device status block the iteration ends with
+};
+
+// Runs one planned iteration of several solves: every stage is one launch
+// over all of them (per kernel variant), arguments staged through pinned
+// memory with one copy.
+struct GroupRunner {
+  cib_ctx *ctx = nullptr;
+  char *host = nullptr;
+  cib::DBuf<char> dev;
+  size_t cap = 0;
+  explicit GroupRunner(cib_ctx *c) : ctx(c) {}
+  ~GroupRunner();
+  void run(const std::vector<LobpcgRun *> &runs, const std::vector<IterPlan> &plans, hipStream_t s);
+};
+
 LobpcgRun *lobpcg_create(cib_ctx *ctx, const cib_matrix &H, const cib_lobpcg_opts &o, hipStream_t s);
-// iterate() == iterate_pre(), the Rayleigh-Ritz step of lobpcg_rr_args(),
-// iterate_post(); launch_rr_group runs n such steps (device array) at once
-void lobpcg_iterate_pre(LobpcgRun *r);
-RRArgs lobpcg_rr_args(const LobpcgRun *r);
-void lobpcg_iterate_post(LobpcgRun *r);
-void launch_rr_group(const RRArgs *dev_args, int n, hipStream_t s);
+// advances the solve by one iteration's plan; false: not eligible (nothing advanced)
+bool lobpcg_plan_iteration(LobpcgRun *r, IterPlan &p);
+
 void lobpcg_start(LobpcgRun *r);
 void lobpcg_iterate(LobpcgRun *r);
 void lobpcg_copy_status(LobpcgRun *r, double *host);

@@ -113,6 +113,19 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
+// Job of workgroup b in a grouped launch (several independent problems in
+// one grid): off[0..n) holds each job's first workgroup, ascending, off[0] = 0.
+// The search reads the same entries in every lane.
+__device__ __forceinline__ int group_job(const int32_t *off, int n, int b) {
+  int lo = 0, hi = n;   // the last job whose first workgroup is <= b
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= b) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
 // Map a linear block index so that each XCD (blocks are dispatched to the 8
 // XCDs round-robin) works on one contiguous range of logical blocks, which
 // keeps the data those blocks share inside one XCD's L2.

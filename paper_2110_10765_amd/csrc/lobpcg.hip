@@ -120,6 +120,13 @@ __global__ __launch_bounds__(256) void k_widen(int64_t D, int b, const float *in
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k < D * b) out[(k / b) * ldo + (k % b)] = (double)in[k];
 }
+__global__ __launch_bounds__(256) void k_widen_group(const WidenArgs *__restrict__ as, const int32_t *__restrict__ off,
+                                                     int njobs) {
+  const int j = group_job(off, njobs, (int)blockIdx.x);
+  const WidenArgs a = as[j];
+  const int64_t k = (int64_t)(blockIdx.x - off[j]) * blockDim.x + threadIdx.x;
+  if (k < a.D * a.b) a.out[(k / a.b) * a.ldo + (k % a.b)] = (double)a.in[k];
+}
 
 __global__ __launch_bounds__(256) void k_copy_cols(int64_t D, int n, const double *S, int lds, double *out,
                                                    int64_t ldo) {
@@ -147,15 +154,15 @@ constexpr int kGramPad = 48;    // doubles allocated past the last row of S and 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 template <int T>   // 16-column tiles per side: ns <= 16 T
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_gram(
-    int64_t D, int ns, int ld, const double *__restrict__ S, const double *__restrict__ HS,
-    int64_t rows_per_blk, double *__restrict__ partial) {
+__device__ __forceinline__ void gram_block(int64_t D, int ns, int ld, const double *__restrict__ S,
+                                           const double *__restrict__ HS, int64_t rows_per_blk,
+                                           double *__restrict__ partial, int blk) {
   constexpr int NG = T * (T + 1) / 2;   // upper tiles of S^T S
   __shared__ double red[kNS * 2 * kNS];
   const int wv = uni((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
   const int kr = lane >> 4, kc = lane & 15;
   const int w2 = 2 * ns;
-  const int64_t r0 = (int64_t)blockIdx.x * rows_per_blk;
+  const int64_t r0 = (int64_t)blk * rows_per_blk;
   const int64_t r1 = min(D, r0 + rows_per_blk);
   dbl4 ag[NG], ah[T][T];
 #pragma unroll
@@ -232,19 +239,33 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     }
     __syncthreads();
   }
-  double *out = partial + (int64_t)blockIdx.x * ns * w2;
+  double *out = partial + (int64_t)blk * ns * w2;
   for (int e = threadIdx.x; e < ns * w2; e += blockDim.x) out[e] = red[e];
+}
+
+template <int T>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_gram(
+    int64_t D, int ns, int ld, const double *__restrict__ S, const double *__restrict__ HS,
+    int64_t rows_per_blk, double *__restrict__ partial) {
+  gram_block<T>(D, ns, ld, S, HS, rows_per_blk, partial, blockIdx.x);
+}
+
+template <int T>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_gram_group(
+    const GramArgs *__restrict__ as, const int32_t *__restrict__ off, int njobs) {
+  const int j = group_job(off, njobs, (int)blockIdx.x);
+  const GramArgs a = as[j];
+  gram_block<T>(a.D, a.ns, a.ld, a.S, a.HS, a.rows_per_blk, a.partial, blockIdx.x - off[j]);
 }
 
 // out[g][e] = sum of in[q][e] over the parts q of group g (grid.y = groups of
 // `per` consecutive parts), in a fixed order.  One thread per output element
 // (coalesced); all loads of a group are in flight together.  The Gram
 // reduction runs it twice: groups of 32 partial matrices, then the group sums.
-__global__ __launch_bounds__(256) void k_sum_parts(int nout, int nparts, int per, const double *__restrict__ in,
-                                                   double *__restrict__ out) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void sum_parts_elem(int nout, int nparts, int per, const double *__restrict__ in,
+                                               double *__restrict__ out, int e, int grp) {
   if (e >= nout) return;
-  const int q0 = blockIdx.y * per, q1 = min(nparts, q0 + per);
+  const int q0 = grp * per, q1 = min(nparts, q0 + per);
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   int q = q0;
   for (; q + 8 <= q1; q += 8) {
@@ -255,7 +276,22 @@ __global__ __launch_bounds__(256) void k_sum_parts(int nout, int nparts, int per
     for (int t = 0; t < 8; ++t) acc[t & 3] += v[t];
   }
   for (; q < q1; ++q) acc[q & 3] += in[(int64_t)q * nout + e];
-  out[(int64_t)blockIdx.y * nout + e] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+  out[(int64_t)grp * nout + e] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+}
+
+__global__ __launch_bounds__(256) void k_sum_parts(int nout, int nparts, int per, const double *__restrict__ in,
+                                                   double *__restrict__ out) {
+  sum_parts_elem(nout, nparts, per, in, out, blockIdx.x * blockDim.x + threadIdx.x, blockIdx.y);
+}
+
+// a job's workgroups cover (element block, group) as x + xblocks * group
+__global__ __launch_bounds__(256) void k_sum_parts_group(const SumArgs *__restrict__ as,
+                                                         const int32_t *__restrict__ off, int njobs) {
+  const int j = group_job(off, njobs, (int)blockIdx.x);
+  const SumArgs a = as[j];
+  const int loc = blockIdx.x - off[j];
+  const int xb = (a.nout + 255) / 256;
+  sum_parts_elem(a.nout, a.nparts, a.per, a.in, a.out, (loc % xb) * 256 + threadIdx.x, loc / xb);
 }
 
 // Gershgorin lower bound of H: min_i (H_ii - sum_{j != i} |H_ij|), both halves.
@@ -805,23 +841,8 @@ __global__ __launch_bounds__(256) void k_rayleigh_ritz_group(const RRArgs *__res
   rayleigh_ritz(g);
 }
 
-void launch_rr_group(const RRArgs *dev_args, int n, hipStream_t s) {
-  if (n <= 0) return;
-  hipLaunchKernelGGL(k_rayleigh_ritz_group, dim3(n), dim3(256), 0, s, dev_args);
-  CIB_HIP(hipGetLastError());
-}
 
 // ------------------------------------------------------------ update
-struct UpdArgs {
-  int64_t D;
-  int b, ns, ld;
-  double *S, *HS;
-  const double *C, *lam, *diag;
-  float *w32;             // optional float32 copy of W (dense D x b)
-  double *npart;          // per block: b residual sums, b |x|^2 sums
-  int rows_per_blk;
-  const int32_t *locked;  // per column: converged at the previous check (W = 0)
-};
 
 // [X P] = S [Cx Cp] and [HX HP] = HS [Cx Cp] on the float64 matrix cores, then
 // the residual R = HX - X diag(lambda), the preconditioned W and the new
@@ -836,7 +857,7 @@ struct UpdArgs {
 // in place.  Per-column sums of the squared residuals and |x|^2 are reduced
 // over lanes and waves in a fixed order.
 template <int TN>   // 16-column output tiles over the 2b columns of [Cx Cp]
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_update(UpdArgs g) {
+__device__ __forceinline__ void update_block(const UpdArgs &g, int blk) {
   constexpr int KMAX = kNS / 4;   // steps of the contraction (ns <= 48)
   __shared__ double lam[kMaxBlock];
   __shared__ double red[2][4][64];
@@ -852,7 +873,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     Cs[k][j] = (k < ns && j < nb2) ? g.C[k * nb2 + j] : 0.0;
   }
   __syncthreads();
-  const int64_t r0 = (int64_t)blockIdx.x * g.rows_per_blk;
+  const int64_t r0 = (int64_t)blk * g.rows_per_blk;
   const int64_t r1 = min(g.D, r0 + g.rows_per_blk);
   double rs = 0.0, xs = 0.0;   // this lane's column kc (when kc < b)
   for (int64_t rb = r0 + 16 * (int64_t)wv; rb < r1; rb += 64) {
@@ -940,14 +961,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     double t = 0.0;
     for (int w = 0; w < 4; ++w)
       for (int q = 0; q < 4; ++q) t += red[which][w][16 * q + cc];
-    g.npart[(int64_t)blockIdx.x * 2 * b + threadIdx.x] = t;
+    g.npart[(int64_t)blk * 2 * b + threadIdx.x] = t;
   }
 }
 
+template <int TN>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_update(UpdArgs g) {
+  update_block<TN>(g, blockIdx.x);
+}
+
+template <int TN>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_update_group(
+    const UpdArgs *__restrict__ as, const int32_t *__restrict__ off, int njobs) {
+  const int j = group_job(off, njobs, (int)blockIdx.x);
+  const UpdArgs g = as[j];
+  update_block<TN>(g, blockIdx.x - off[j]);
+}
+
 // Relative residual norms and the count of converged leading pairs.
-__global__ __launch_bounds__(256) void k_finish(int b, int nev, int nparts, const double *npart,
-                                                const double *lam, double tol, double *status,
-                                                int32_t *locked) {
+__device__ __forceinline__ void finish_body(int b, int nev, int nparts, const double *npart, const double *lam,
+                                            double tol, double *status, int32_t *locked) {
   // 16 slices of the partial sums per column, then a fixed-order sum
   __shared__ double ra[16][kMaxBlock], rx[16][kMaxBlock];
   __shared__ double rs[kMaxBlock];
@@ -974,6 +1007,17 @@ __global__ __launch_bounds__(256) void k_finish(int b, int nev, int nparts, cons
     status[0] = conv;
     for (int k = 0; k < b; ++k) { status[1 + k] = rs[k]; status[1 + kMaxBlock + k] = lam[k]; }
   }
+}
+
+__global__ __launch_bounds__(256) void k_finish(int b, int nev, int nparts, const double *npart,
+                                                const double *lam, double tol, double *status,
+                                                int32_t *locked) {
+  finish_body(b, nev, nparts, npart, lam, tol, status, locked);
+}
+
+__global__ __launch_bounds__(256) void k_finish_group(const FinishArgs *__restrict__ as) {
+  const FinishArgs a = as[blockIdx.x];
+  finish_body(a.b, a.nev, a.nparts, a.npart, a.lam, a.tol, a.status, a.locked);
 }
 
 // ------------------------------------------------------------ host driver
@@ -1175,16 +1219,48 @@ struct LobpcgRun {
     rr_update(iters == 1 ? 2 * b : 3 * b);
   }
 
-  // one iteration in three parts, for a caller that batches the middle
-  // (Rayleigh-Ritz) part of several solves into one launch
-  int step_ns = 0;
-  void iterate_pre() {
+  // One iteration as the arguments of each stage, for a caller that runs
+  // the same stage of several solves as one launch (the launch parameters
+  // are those of iterate(), so the results are the same bits).  False (and
+  // nothing advanced) when the SpMM does not take the vector kernel.
+  bool plan_iteration(IterPlan &p) {
+    const bool f32 = H.dtype == CIB_F32;
+    const void *X = f32 ? (const void *)x32.p : (const void *)(S.p + b);
+    void *Y = f32 ? (void *)y32.p : (void *)(HS.p + b);
+    const int64_t ldx = f32 ? b : ld;
+    if (!spmm_vec_args(H, X, ldx, Y, ldx, b, p.spmm, p.spmm_blocks)) return false;
     ++iters;
-    step_ns = iters == 1 ? 2 * b : 3 * b;
-    spmm(1, H.dtype == CIB_F32);
-    gram_step(step_ns);
+    const int ns = iters == 1 ? 2 * b : 3 * b;
+    step_ns = ns;
+    p.dt = H.dtype;
+    p.nvec = b;
+    p.widen = f32;
+    p.wid = WidenArgs{D, b, y32.p, HS.p + b, ld};
+    p.widen_blocks = (int)nblk(D * b);
+    p.T = (ns + 15) / 16;
+    p.gram = GramArgs{D, ns, ld, S.p, HS.p, gram_rows, partial.p};
+    p.gram_blocks = gram_blocks;
+    const int nout = ns * 2 * ns, xb = (nout + 255) / 256;
+    const int groups = (gram_blocks + kSumGroup - 1) / kSumGroup;
+    p.gs1 = SumArgs{nout, gram_blocks, kSumGroup, partial.p, partial2.p};
+    p.gs1_blocks = xb * groups;
+    p.gs2 = SumArgs{nout, groups, groups, partial2.p, gram.p};
+    p.gs2_blocks = xb;
+    p.rr = rr_args(ns);
+    p.TN = 2 * b <= 16 ? 1 : 2;
+    p.upd = UpdArgs{D, b, ns, ld, S.p, HS.p, C.p, lam.p, diag.p, f32 ? x32.p : nullptr, npart.p, (int)upd_rows,
+                    locked.p};
+    p.upd_blocks = upd_blocks;
+    const int ugroups = (upd_blocks + kSumGroup - 1) / kSumGroup;
+    p.us = SumArgs{2 * b, upd_blocks, kSumGroup, npart.p, npart2.p};
+    p.us_blocks = ugroups;   // 2b <= 32 outputs: one element block per group
+    p.fin = FinishArgs{b, nev, ugroups, npart2.p, lam.p, tol, status.p, nullptr};
+    p.fin.locked = locked.p;
+    p.status = status.p;
+    return true;
   }
-  void iterate_post() { update_step(step_ns); }
+
+  int step_ns = 0;
 
   void copy_status(double *host) {
     CIB_HIP(hipMemcpyAsync(host, status.p, sizeof(double) * kStatusLen, hipMemcpyDeviceToHost, s));
@@ -1221,9 +1297,122 @@ LobpcgRun *lobpcg_create(cib_ctx *ctx, const cib_matrix &H, const cib_lobpcg_opt
   return new LobpcgRun(ctx, H, o, s, false);
 }
 void lobpcg_start(LobpcgRun *r) { r->start(); }
-void lobpcg_iterate_pre(LobpcgRun *r) { r->iterate_pre(); }
-RRArgs lobpcg_rr_args(const LobpcgRun *r) { return r->rr_args(r->step_ns); }
-void lobpcg_iterate_post(LobpcgRun *r) { r->iterate_post(); }
+bool lobpcg_plan_iteration(LobpcgRun *r, IterPlan &p) { return r->plan_iteration(p); }
+
+// ------------------------------------------------------------ grouped iterations
+// The stage arrays of one group (same dtype, block size and tile counts) and
+// each stage's workgroup offsets, packed into one staging buffer.
+namespace {
+template <typename A>
+size_t put(char *base, size_t &at, const A *src, size_t n) {
+  at = (at + 255) / 256 * 256;
+  const size_t o = at;
+  if (base) std::memcpy(base + o, src, sizeof(A) * n);
+  at += sizeof(A) * n;
+  return o;
+}
+}  // namespace
+
+GroupRunner::~GroupRunner() {
+  if (host) (void)hipHostFree(host);
+}
+
+void GroupRunner::run(const std::vector<LobpcgRun *> &runs, const std::vector<IterPlan> &plans, hipStream_t s) {
+  const int n = (int)runs.size();
+  if (n == 0) return;
+  // groups by kernel variant, in job order
+  std::vector<std::vector<int>> groups;
+  auto key = [&](const IterPlan &p) { return ((int)p.dt << 16) | (p.nvec << 8) | (p.T << 4) | p.TN; };
+  for (int j = 0; j < n; ++j) {
+    bool placed = false;
+    for (auto &g : groups)
+      if (key(plans[g[0]]) == key(plans[j])) { g.push_back(j); placed = true; break; }
+    if (!placed) groups.push_back({j});
+  }
+  struct Layout {
+    size_t spmm, ospmm, wid, owid, gram, ogram, gs1, ogs1, gs2, ogs2, rr, upd, oupd, us, ous, fin;
+    int tspmm, twid, tgram, tgs1, tgs2, tupd, tus;
+  };
+  std::vector<Layout> lay(groups.size());
+  // two passes: sizes, then the copy into the (grown) staging buffer
+  for (int pass = 0; pass < 2; ++pass) {
+    char *base = pass ? host : nullptr;
+    size_t at = 0;
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+      const auto &g = groups[gi];
+      const int m = (int)g.size();
+      std::vector<VecArgs> a_sp(m);
+      std::vector<WidenArgs> a_w(m);
+      std::vector<GramArgs> a_g(m);
+      std::vector<SumArgs> a_s1(m), a_s2(m), a_us(m);
+      std::vector<RRArgs> a_rr(m);
+      std::vector<UpdArgs> a_u(m);
+      std::vector<FinishArgs> a_f(m);
+      std::vector<int32_t> o_sp(m + 1, 0), o_w(m + 1, 0), o_g(m + 1, 0), o_s1(m + 1, 0), o_s2(m + 1, 0),
+          o_u(m + 1, 0), o_us(m + 1, 0);
+      for (int q = 0; q < m; ++q) {
+        const IterPlan &p = plans[g[q]];
+        a_sp[q] = p.spmm; a_w[q] = p.wid; a_g[q] = p.gram; a_s1[q] = p.gs1; a_s2[q] = p.gs2;
+        a_rr[q] = p.rr; a_u[q] = p.upd; a_us[q] = p.us; a_f[q] = p.fin;
+        o_sp[q + 1] = o_sp[q] + p.spmm_blocks;
+        o_w[q + 1] = o_w[q] + p.widen_blocks;
+        o_g[q + 1] = o_g[q] + p.gram_blocks;
+        o_s1[q + 1] = o_s1[q] + p.gs1_blocks;
+        o_s2[q + 1] = o_s2[q] + p.gs2_blocks;
+        o_u[q + 1] = o_u[q] + p.upd_blocks;
+        o_us[q + 1] = o_us[q] + p.us_blocks;
+      }
+      Layout &L = lay[gi];
+      L.spmm = put(base, at, a_sp.data(), m); L.ospmm = put(base, at, o_sp.data(), m + 1);
+      L.wid = put(base, at, a_w.data(), m); L.owid = put(base, at, o_w.data(), m + 1);
+      L.gram = put(base, at, a_g.data(), m); L.ogram = put(base, at, o_g.data(), m + 1);
+      L.gs1 = put(base, at, a_s1.data(), m); L.ogs1 = put(base, at, o_s1.data(), m + 1);
+      L.gs2 = put(base, at, a_s2.data(), m); L.ogs2 = put(base, at, o_s2.data(), m + 1);
+      L.rr = put(base, at, a_rr.data(), m);
+      L.upd = put(base, at, a_u.data(), m); L.oupd = put(base, at, o_u.data(), m + 1);
+      L.us = put(base, at, a_us.data(), m); L.ous = put(base, at, o_us.data(), m + 1);
+      L.fin = put(base, at, a_f.data(), m);
+      L.tspmm = o_sp[m]; L.twid = o_w[m]; L.tgram = o_g[m]; L.tgs1 = o_s1[m]; L.tgs2 = o_s2[m];
+      L.tupd = o_u[m]; L.tus = o_us[m];
+    }
+    if (pass == 0 && at > cap) {
+      if (host) (void)hipHostFree(host);
+      host = nullptr;
+      CIB_HIP(hipHostMalloc((void **)&host, at, hipHostMallocDefault));
+      dev.reset(ctx, at);
+      cap = at;
+    }
+    if (pass == 1) CIB_HIP(hipMemcpyAsync(dev.p, host, at, hipMemcpyHostToDevice, s));
+  }
+  const char *d = dev.p;
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    const Layout &L = lay[gi];
+    const int m = (int)groups[gi].size();
+    const IterPlan &p0 = plans[groups[gi][0]];
+    auto off = [&](size_t o) { return reinterpret_cast<const int32_t *>(d + o); };
+    launch_spmm_group(p0.dt, p0.nvec, reinterpret_cast<const VecArgs *>(d + L.spmm), off(L.ospmm), m, L.tspmm, s);
+    if (p0.widen)
+      hipLaunchKernelGGL(k_widen_group, dim3(L.twid), dim3(256), 0, s, reinterpret_cast<const WidenArgs *>(d + L.wid),
+                         off(L.owid), m);
+    const GramArgs *ga = reinterpret_cast<const GramArgs *>(d + L.gram);
+    if (p0.T == 1) hipLaunchKernelGGL(k_gram_group<1>, dim3(L.tgram), dim3(256), 0, s, ga, off(L.ogram), m);
+    else if (p0.T == 2) hipLaunchKernelGGL(k_gram_group<2>, dim3(L.tgram), dim3(256), 0, s, ga, off(L.ogram), m);
+    else hipLaunchKernelGGL(k_gram_group<3>, dim3(L.tgram), dim3(256), 0, s, ga, off(L.ogram), m);
+    hipLaunchKernelGGL(k_sum_parts_group, dim3(L.tgs1), dim3(256), 0, s, reinterpret_cast<const SumArgs *>(d + L.gs1),
+                       off(L.ogs1), m);
+    hipLaunchKernelGGL(k_sum_parts_group, dim3(L.tgs2), dim3(256), 0, s, reinterpret_cast<const SumArgs *>(d + L.gs2),
+                       off(L.ogs2), m);
+    hipLaunchKernelGGL(k_rayleigh_ritz_group, dim3(m), dim3(256), 0, s, reinterpret_cast<const RRArgs *>(d + L.rr));
+    const UpdArgs *ua = reinterpret_cast<const UpdArgs *>(d + L.upd);
+    if (p0.TN == 1) hipLaunchKernelGGL(k_update_group<1>, dim3(L.tupd), dim3(256), 0, s, ua, off(L.oupd), m);
+    else hipLaunchKernelGGL(k_update_group<2>, dim3(L.tupd), dim3(256), 0, s, ua, off(L.oupd), m);
+    hipLaunchKernelGGL(k_sum_parts_group, dim3(L.tus), dim3(256), 0, s, reinterpret_cast<const SumArgs *>(d + L.us),
+                       off(L.ous), m);
+    hipLaunchKernelGGL(k_finish_group, dim3(m), dim3(256), 0, s, reinterpret_cast<const FinishArgs *>(d + L.fin));
+    CIB_HIP(hipGetLastError());
+  }
+}
+
 void lobpcg_iterate(LobpcgRun *r) { r->iterate(); }
 void lobpcg_copy_status(LobpcgRun *r, double *host) { r->copy_status(host); }
 int lobpcg_iters(const LobpcgRun *r) { return r->iters; }

@@ -10,9 +10,10 @@
 //   solver   keeps every admitted request's H and LOBPCG state resident and,
 //            each step, enqueues one stage for every active request
 //            (initialisation for new ones, one LOBPCG iteration for the rest)
-//            on a pool of streams so their kernels overlap on the device; the
-//            Rayleigh-Ritz steps of the iterating requests go out as one
-//            launch, one workgroup per request.  It then waits once, reads
+//            (a new solve starts on its own stream); the iterating requests
+//            run each stage of their iteration as one launch over all of them
+//            (their workgroups in one grid; the Rayleigh-Ritz step one
+//            workgroup per request).  It then waits once, reads
 //            every status block from pinned memory, and retires converged
 //            requests (releasing their memory and budget).
 #include <algorithm>
@@ -104,15 +105,7 @@ cib_status serve_run(cib_ctx *ctx, const cib_request *reqs, int n, const cib_ser
   double *pinned = nullptr;
   CIB_HIP(hipHostMalloc((void **)&pinned, sizeof(double) * kStatusLen * (size_t)sh.max_active,
                         hipHostMallocDefault));
-  // per status slot: the event that ends a solve's pre-Rayleigh-Ritz part;
-  // the batch's arguments go host (pinned) -> device once per step
-  std::vector<hipEvent_t> slot_ev(sh.max_active, nullptr);
-  for (auto &e : slot_ev) CIB_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-  hipEvent_t rr_done = nullptr;
-  CIB_HIP(hipEventCreateWithFlags(&rr_done, hipEventDisableTiming));
-  RRArgs *rr_host = nullptr;
-  CIB_HIP(hipHostMalloc((void **)&rr_host, sizeof(RRArgs) * (size_t)sh.max_active, hipHostMallocDefault));
-  DBuf<RRArgs> rr_dev(ctx, (size_t)sh.max_active);
+  GroupRunner runner(ctx);   // grouped iterations (arguments staged in pinned memory)
   std::vector<int> free_slots;
   for (int k = sh.max_active - 1; k >= 0; --k) free_slots.push_back(k);
   std::string builder_error;
@@ -208,8 +201,6 @@ cib_status serve_run(cib_ctx *ctx, const cib_request *reqs, int n, const cib_ser
   std::vector<std::thread> builders;
   for (int bt = 0; bt < nbuild; ++bt) builders.emplace_back(builder_fn, bt);
 
-  auto slot_of = [&](const Job *j) { return (int)((j->status - pinned) / kStatusLen); };
-
   // ------------------------------------------------------------ solver loop
   std::vector<Job *> active;
   int next_stream = 0;
@@ -233,10 +224,13 @@ cib_status serve_run(cib_ctx *ctx, const cib_request *reqs, int n, const cib_ser
         if (active.empty() && sh.builder_done) break;
       }
       if (now() > deadline) break;
-      // enqueue one stage per active request: a new solve starts on its
-      // stream; the others run one iteration whose Rayleigh-Ritz steps go
-      // out as one launch (one workgroup per solve) between the parts
-      std::vector<Job *> iter_jobs;
+      // enqueue one stage per active request: a new solve starts on its own
+      // stream; the others run one iteration together, every stage of it one
+      // launch over all of them (a solve the grouped SpMM cannot take
+      // iterates on its own stream)
+      std::vector<LobpcgRun *> g_runs;
+      std::vector<IterPlan> g_plans;
+      std::vector<Job *> g_jobs;
       for (Job *j : active) {
         hipStream_t s = streams[j->stream];
         if (!j->started) {
@@ -245,27 +239,23 @@ cib_status serve_run(cib_ctx *ctx, const cib_request *reqs, int n, const cib_ser
           lobpcg_start(j->lp);
           j->started = true;
           lobpcg_copy_status(j->lp, j->status);
+          continue;
+        }
+        IterPlan p;
+        if (lobpcg_plan_iteration(j->lp, p)) {
+          g_runs.push_back(j->lp);
+          g_plans.push_back(p);
+          g_jobs.push_back(j);
         } else {
-          lobpcg_iterate_pre(j->lp);
-          CIB_HIP(hipEventRecord(slot_ev[slot_of(j)], s));
-          iter_jobs.push_back(j);
-        }
-      }
-      if (!iter_jobs.empty()) {
-        const int m = (int)iter_jobs.size();
-        for (int q = 0; q < m; ++q) {
-          CIB_HIP(hipStreamWaitEvent(gstream, slot_ev[slot_of(iter_jobs[q])], 0));
-          rr_host[q] = lobpcg_rr_args(iter_jobs[q]->lp);
-        }
-        CIB_HIP(hipMemcpyAsync(rr_dev.p, rr_host, sizeof(RRArgs) * m, hipMemcpyHostToDevice, gstream));
-        launch_rr_group(rr_dev.p, m, gstream);
-        CIB_HIP(hipEventRecord(rr_done, gstream));
-        for (Job *j : iter_jobs) {
-          hipStream_t s = streams[j->stream];
-          CIB_HIP(hipStreamWaitEvent(s, rr_done, 0));
-          lobpcg_iterate_post(j->lp);
+          lobpcg_iterate(j->lp);
           lobpcg_copy_status(j->lp, j->status);
         }
+      }
+      if (!g_runs.empty()) {
+        runner.run(g_runs, g_plans, gstream);
+        for (size_t q = 0; q < g_jobs.size(); ++q)
+          CIB_HIP(hipMemcpyAsync(g_jobs[q]->status, g_plans[q].status, sizeof(double) * kStatusLen,
+                                 hipMemcpyDeviceToHost, gstream));
       }
       for (int k = 0; k < nstreams; ++k) CIB_HIP(hipStreamSynchronize(streams[k]));
       CIB_HIP(hipStreamSynchronize(gstream));
@@ -312,9 +302,7 @@ cib_status serve_run(cib_ctx *ctx, const cib_request *reqs, int n, const cib_ser
   for (Job *j : active) delete j;
   for (Job *j : sh.ready) delete j;
   for (auto &st : streams) (void)hipStreamDestroy(st);
-  for (auto &e : slot_ev) (void)hipEventDestroy(e);
-  (void)hipEventDestroy(rr_done);
-  (void)hipHostFree(rr_host);
+
   (void)hipHostFree(pinned);
   if (loop_status != CIB_OK) throw Error(loop_status, loop_error);
   if (builder_status != CIB_OK) throw Error(builder_status, builder_error);

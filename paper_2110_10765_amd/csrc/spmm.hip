@@ -95,21 +95,6 @@ struct Bfly {
   }
 };
 
-struct VecArgs {
-  int64_t D;
-  const int64_t *rp;
-  const int32_t *col;
-  const void *val;
-  const int64_t *lrp;
-  const int32_t *lcol;
-  const void *lval;
-  const void *X;
-  int64_t ldx;
-  void *Y;
-  int64_t ldy;
-  int64_t xr[9];     // XCD x takes rows [xr[x], xr[x + 1])
-};
-
 // nvec == NV (8 or 16) with 16-byte aligned rows of X.  One wave per row.
 // The wave reads 64 consecutive entries of the row (lower part, then upper
 // part) with one coalesced load of col and of val; the entries are handed to groups of G lanes by
@@ -124,7 +109,7 @@ struct VecArgs {
 // columns into chunks, one per XCD, so that X stays in L2, and streaming
 // col/val with non-temporal loads were both measured slower.
 template <typename T, int NV>
-__global__ __launch_bounds__(256) void k_spmm_vec(const VecArgs a) {
+__device__ __forceinline__ void spmm_vec_row(const VecArgs &a, int64_t i) {
   constexpr int PER16 = 16 / sizeof(T);  // values per 16-byte load
   constexpr int G = NV / PER16;          // lanes per entry
   constexpr int E = kWave / G;           // entries per gather instruction
@@ -134,11 +119,6 @@ __global__ __launch_bounds__(256) void k_spmm_vec(const VecArgs a) {
   const T *__restrict__ val = static_cast<const T *>(a.val);
   const T *__restrict__ lval = static_cast<const T *>(a.lval);
   const T *__restrict__ X = static_cast<const T *>(a.X);
-  // workgroups go to the 8 XCDs round-robin; XCD x (block mod 8) walks its
-  // own range of rows, the ranges holding equal numbers of stored entries
-  const int x = blockIdx.x & 7;
-  const int64_t i = a.xr[x] + (int64_t)(blockIdx.x >> 3) * (blockDim.x / kWave) + (threadIdx.x >> 6);
-  if (i >= a.xr[x + 1]) return;
   const int lane = lane_id();
   const int e = lane / G, g = lane % G;
   const int64_t lb = a.lrp[i], ub = a.rp[i];
@@ -201,6 +181,28 @@ __global__ __launch_bounds__(256) void k_spmm_vec(const VecArgs a) {
   if ((lane & (SEL - 1) & ~(G - 1)) == 0) Y[i * a.ldy + g * PER16 + ((lane / SEL) & (PER16 - 1))] = acc[0];
 }
 
+template <typename T, int NV>
+__global__ __launch_bounds__(256) void k_spmm_vec(const VecArgs a) {
+  // workgroups go to the 8 XCDs round-robin; XCD x (block mod 8) walks its
+  // own range of rows, the ranges holding equal numbers of stored entries
+  const int x = blockIdx.x & 7;
+  const int64_t i = a.xr[x] + (int64_t)(blockIdx.x >> 3) * (blockDim.x / kWave) + (threadIdx.x >> 6);
+  if (i >= a.xr[x + 1]) return;
+  spmm_vec_row<T, NV>(a, i);
+}
+
+// Several matrices in one launch (the serving loop's batch): off[j] is the
+// first workgroup of job j (4 rows per workgroup, plain row order).
+template <typename T, int NV>
+__global__ __launch_bounds__(256) void k_spmm_vec_group(const VecArgs *__restrict__ as,
+                                                        const int32_t *__restrict__ off, int njobs) {
+  const int j = group_job(off, njobs, (int)blockIdx.x);
+  const VecArgs &a = as[j];
+  const int64_t i = (int64_t)(blockIdx.x - off[j]) * (blockDim.x / kWave) + (threadIdx.x >> 6);
+  if (i >= a.D) return;
+  spmm_vec_row<T, NV>(a, i);
+}
+
 // ------------------------------------------------------------ host side
 template <typename T>
 static void spmm_t(const cib_matrix &H, const T *X, int64_t ldx, T *Y, int64_t ldy, int nvec,
@@ -235,6 +237,30 @@ static void spmm_t(const cib_matrix &H, const T *X, int64_t ldx, T *Y, int64_t l
     else
       hipLaunchKernelGGL((k_spmm_sym<T, 16>), dim3(nblk), dim3(256), 0, s, D, H.row_ptr.p,
                          H.col.p, val, H.lo_ptr.p, H.lo_col.p, lval, X, ldx, Y, ldy, nvec, v0);
+  }
+  CIB_HIP(hipGetLastError());
+}
+
+bool spmm_vec_args(const cib_matrix &H, const void *X, int64_t ldx, void *Y, int64_t ldy, int nvec, VecArgs &a,
+                   int &blocks) {
+  const size_t sv = H.dtype == CIB_F64 ? 8 : 4;
+  const bool aligned = ((uintptr_t)X % 16 == 0) && ((ldx * sv) % 16 == 0);
+  if (!aligned || (nvec != 8 && nvec != 16)) return false;
+  a = VecArgs{H.D, H.row_ptr.p, H.col.p, H.val(), H.lo_ptr.p, H.lo_col.p, H.lo_val(), X, ldx, Y, ldy, {}};
+  blocks = (int)((H.D + 3) / 4);
+  return true;
+}
+
+void launch_spmm_group(cib_dtype dt, int nvec, const VecArgs *dev_args, const int32_t *dev_off, int njobs,
+                       int total_blocks, hipStream_t s) {
+  if (njobs <= 0 || total_blocks <= 0) return;
+  const dim3 g((unsigned)total_blocks), t(256);
+  if (dt == CIB_F64) {
+    if (nvec == 8) hipLaunchKernelGGL((k_spmm_vec_group<double, 8>), g, t, 0, s, dev_args, dev_off, njobs);
+    else hipLaunchKernelGGL((k_spmm_vec_group<double, 16>), g, t, 0, s, dev_args, dev_off, njobs);
+  } else {
+    if (nvec == 8) hipLaunchKernelGGL((k_spmm_vec_group<float, 8>), g, t, 0, s, dev_args, dev_off, njobs);
+    else hipLaunchKernelGGL((k_spmm_vec_group<float, 16>), g, t, 0, s, dev_args, dev_off, njobs);
   }
   CIB_HIP(hipGetLastError());
 }
