@@ -397,13 +397,29 @@ __device__ __forceinline__ void rayleigh_ritz(const RRArgs &g) {
   if (g.clk && tid == 0) g.clk[0] = wall_clock64();
   // 1. reduce the partial Gram matrices (fixed order: deterministic); a
   //    retry keeps only the first ns columns ([X W]) of the same matrices
-  for (int e = tid; e < nout; e += nt) {
-    double s = 0.0;
-    for (int q = 0; q < g.nparts; ++q) s += g.partial[(int64_t)q * nout + e];
+  auto place = [&](int e, double s) {
     const int i = e / (2 * ns_full), j = e % (2 * ns_full);
     if (i < ns) {
       if (j < ns) G[i][j] = s;
       else if (j >= ns_full && j - ns_full < ns) Hm[i][j - ns_full] = s;
+    }
+  };
+  if (g.nparts == 1 && nt == 256) {   // one matrix: all of a thread's reads in flight at once
+    constexpr int kPer = (kNS * 2 * kNS + 255) / 256;
+    double v[kPer];
+#pragma unroll
+    for (int t = 0; t < kPer; ++t) {
+      const int e = tid + 256 * t;
+      v[t] = e < nout ? g.partial[e] : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < kPer; ++t)
+      if (tid + 256 * t < nout) place(tid + 256 * t, 0.0 + v[t]);
+  } else {
+    for (int e = tid; e < nout; e += nt) {
+      double s = 0.0;
+      for (int q = 0; q < g.nparts; ++q) s += g.partial[(int64_t)q * nout + e];
+      place(e, s);
     }
   }
   __syncthreads();
