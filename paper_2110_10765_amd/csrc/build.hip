@@ -159,6 +159,54 @@ __device__ __forceinline__ double sum_over_bits(const uint64_t *s, F f) {
   return sum;
 }
 
+// Table offsets of the spectator sums of one row: for each occupied orbital
+// x of a configuration, in ascending x, the diagonal transition x <- x in the
+// table's row map (A) or column map (B).  Written once per row to the wave's
+// LDS slots, so a sum then issues all its table reads at once.  Slots past
+// the occupation hold map[0] (reads stay in bounds and are not added); more
+// than kSpec occupied orbitals fall back to the loop over the bits.
+constexpr int kSpec = 8;
+struct SpecIdx {
+  int n;
+  const int32_t *r;   // LDS, kSpec slots, 16-byte aligned
+};
+
+template <int W>
+__device__ __forceinline__ SpecIdx spec_idx(const uint64_t *bits, const int32_t *map, int nmap, int32_t *slot) {
+  const int lane = lane_id();
+  if (lane < kSpec) slot[lane] = map[0];
+  int below = 0;
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    const uint64_t t = uni(bits[w]);
+    const int x = w * kWave + lane;
+    const int rank = below + (int)__popcll(t & ((1ull << lane) - 1));
+    if (x < nmap && ((t >> lane) & 1) && rank < kSpec) slot[rank] = map[x * (nmap + 1)];
+    below += (int)__popcll(t);
+  }
+  wave_lds_sync();
+  return SpecIdx{below, slot};
+}
+
+// sum over the occupied orbitals of f(offset), ascending, as sum_over_bits
+template <int W, typename F>
+__device__ __forceinline__ double spec_sum(const SpecIdx &s, const uint64_t *bits, const int32_t *map, int nmap,
+                                           F f) {
+  if (s.n > kSpec) return sum_over_bits<W>(bits, [&](int x) { return f(map[x * (nmap + 1)]); });
+  double sum = 0.0;
+#pragma unroll
+  for (int k0 = 0; k0 < kSpec; k0 += 4) {
+    if (k0 >= s.n) break;
+    const int4 r = *reinterpret_cast<const int4 *>(s.r + k0);
+    const double v0 = f(r.x), v1 = f(r.y), v2 = f(r.z), v3 = f(r.w);
+    sum += v0;
+    if (k0 + 1 < s.n) sum += v1;
+    if (k0 + 2 < s.n) sum += v2;
+    if (k0 + 3 < s.n) sum += v3;
+  }
+  return sum;
+}
+
 // Diagonal element of every state, E_A(alpha) + E_B(beta) + sum over the
 // occupied pairs (x in alpha, y in beta) of V^AB_{(x,y),(x,y)}; one thread
 // per state, added in the order the row pass used to add them.
@@ -464,8 +512,8 @@ struct RowArgs {
 // order, kept while position < len(alpha) (a prefix).
 template <int W, bool FILL, typename T>
 __device__ __forceinline__ void row_diag(const RowArgs &g, int64_t i, int64_t e0, int64_t e1, int alpha,
-                                         int len_a, int64_t off_a, const uint64_t *ab,
-                                         const uint64_t *bb, int64_t out, int64_t &cnt) {
+                                         int len_a, int64_t off_a, const uint64_t *ab, const SpecIdx &sa_idx,
+                                         int64_t out, int64_t &cnt) {
   const int lane = lane_id();
   T *val = static_cast<T *>(g.val);
   for (int64_t k0 = e0; k0 < e1; k0 += kWave) {
@@ -486,7 +534,7 @@ __device__ __forceinline__ void row_diag(const RowArgs &g, int64_t i, int64_t e0
       } else if (kb == 1) {  // B single: + s_B sum_{x in alpha} V^AB_{(x,b),(x,d)}
         const int32_t bc = info >> 3;
         const double s = (info >> 2) & 1 ? -1.0 : 1.0;
-        v += s * sum_over_bits<W>(ab, [&](int x) { return vt_at(g.it, g.it.arb[x * g.it.nA + x], bc); });
+        v += s * spec_sum<W>(sa_idx, ab, g.it.arb, g.it.nA, [&](int32_t r) { return vt_at(g.it, r, bc); });
       }
       const int64_t o = out + cnt + (k - k0);
       g.col[o] = (int32_t)(off_a + pos);
@@ -519,7 +567,8 @@ struct L1View {
 // kA = 1 entries are expanded over all lanes of the wave.
 template <int W, bool FILL, typename T, bool ST>
 __device__ __forceinline__ void row_tiles(const RowArgs &g, int64_t t0, int64_t t1, int p, const uint64_t *bb,
-                                          int64_t out, int64_t &cnt, const L1View<ST> &L, int32_t *mark) {
+                                          const SpecIdx &sb_idx, int64_t out, int64_t &cnt, const L1View<ST> &L,
+                                          int32_t *mark) {
   const int lane = lane_id();
   T *val = static_cast<T *>(g.val);
   // the tile data of a batch of 64 is read together, one batch ahead of its
@@ -606,7 +655,7 @@ __device__ __forceinline__ void row_tiles(const RowArgs &g, int64_t t0, int64_t 
         if ((li & 3) == 0) {  // B unchanged: AA part + s_A sum_{y in beta} V^AB_{(a,y),(c,y)}
           double sum = 0.0;
           if (g.it.nB > 0)
-            sum = sum_over_bits<W>(bb, [&](int y) { return vt_at(g.it, orb, g.it.bcol[y * g.it.nB + y]); });
+            sum = spec_sum<W>(sb_idx, bb, g.it.bcol, g.it.nB, [&](int32_t c) { return vt_at(g.it, orb, c); });
           v = g.t_val[tb + own] + sa * sum;   // (rare: a read, not a lane permute in a branch)
         } else {              // one A and one B orbital change
           const double sb = (li >> 2) & 1 ? -1.0 : 1.0;
@@ -634,6 +683,7 @@ template <int W, bool FILL, typename T, bool LOWER>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_row_pass(RowArgs g) {
   __shared__ int32_t s_pos[4][kL1Stage], s_info[4][FILL ? kL1Stage : 1], s_seg[4][kMaxSeg + 2];
   __shared__ int32_t s_mark[4][FILL ? kWave : 1];
+  __shared__ __align__(16) int32_t s_spec[4][FILL ? 2 * kSpec : 1];
   // plain block order: rows of very different lengths sit in runs, and
   // giving each XCD one contiguous range of rows (for L2 locality of the
   // tile lists) measured 30-40% slower from the imbalance between XCDs
@@ -645,11 +695,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
   const int len_a = uni(g.a_len[alpha]);
   const int64_t off_a = uni(g.a_off[alpha]);
   uint64_t ab[W], bb[W];
+  SpecIdx sa_idx{0, nullptr}, sb_idx{0, nullptr};
   if (FILL) {
     // (kept in vector registers: the table reads in the per-entry sums over
     // these bits then go through the vector memory path)
     load_bits<W>(g.a_bits, g.nA, alpha, ab);
     load_bits<W>(g.b_bits, g.nB, beta, bb);
+    // spectator sums exist only with two species (one species has no
+    // transition table: its maps are not allocated)
+    if (g.it.nB > 0) {
+      sa_idx = spec_idx<W>(ab, g.it.arb, g.it.nA, s_spec[wv]);
+      sb_idx = spec_idx<W>(bb, g.it.bcol, g.it.nB, s_spec[wv] + kSpec);
+    }
   }
   const int64_t out = FILL ? uni(g.row_ptr[i]) : 0;
   const int64_t l1b = (int64_t)beta * g.nseg;
@@ -666,20 +723,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
     wave_lds_sync();
     const L1View<true> L{s_seg[wv], nullptr, 0, s_pos[wv], FILL ? s_info[wv] : nullptr};
     if (!LOWER) {
-      row_diag<W, FILL, T>(g, i, uni((int64_t)g.ls_self[beta]), uni(g.ls_ptr[beta + 1]), alpha, len_a, off_a, ab, bb, out, cnt);
-      row_tiles<W, FILL, T, true>(g, t0, t1, p, bb, out, cnt, L, s_mark[wv]);
+      row_diag<W, FILL, T>(g, i, uni((int64_t)g.ls_self[beta]), uni(g.ls_ptr[beta + 1]), alpha, len_a, off_a, ab, sa_idx, out, cnt);
+      row_tiles<W, FILL, T, true>(g, t0, t1, p, bb, sb_idx, out, cnt, L, s_mark[wv]);
     } else {
-      row_tiles<W, FILL, T, true>(g, t0, t1, p, bb, out, cnt, L, s_mark[wv]);
-      row_diag<W, FILL, T>(g, i, uni(g.ls_ptr[beta]), uni((int64_t)g.ls_self[beta]), alpha, len_a, off_a, ab, bb, out, cnt);
+      row_tiles<W, FILL, T, true>(g, t0, t1, p, bb, sb_idx, out, cnt, L, s_mark[wv]);
+      row_diag<W, FILL, T>(g, i, uni(g.ls_ptr[beta]), uni((int64_t)g.ls_self[beta]), alpha, len_a, off_a, ab, sa_idx, out, cnt);
     }
   } else {
     const L1View<false> L{nullptr, g.l1_seg + l1b, base, g.l1_pos + base, FILL ? g.l1_info + base : nullptr};
     if (!LOWER) {
-      row_diag<W, FILL, T>(g, i, uni((int64_t)g.ls_self[beta]), uni(g.ls_ptr[beta + 1]), alpha, len_a, off_a, ab, bb, out, cnt);
-      row_tiles<W, FILL, T, false>(g, t0, t1, p, bb, out, cnt, L, s_mark[wv]);
+      row_diag<W, FILL, T>(g, i, uni((int64_t)g.ls_self[beta]), uni(g.ls_ptr[beta + 1]), alpha, len_a, off_a, ab, sa_idx, out, cnt);
+      row_tiles<W, FILL, T, false>(g, t0, t1, p, bb, sb_idx, out, cnt, L, s_mark[wv]);
     } else {
-      row_tiles<W, FILL, T, false>(g, t0, t1, p, bb, out, cnt, L, s_mark[wv]);
-      row_diag<W, FILL, T>(g, i, uni(g.ls_ptr[beta]), uni((int64_t)g.ls_self[beta]), alpha, len_a, off_a, ab, bb, out, cnt);
+      row_tiles<W, FILL, T, false>(g, t0, t1, p, bb, sb_idx, out, cnt, L, s_mark[wv]);
+      row_diag<W, FILL, T>(g, i, uni(g.ls_ptr[beta]), uni((int64_t)g.ls_self[beta]), alpha, len_a, off_a, ab, sa_idx, out, cnt);
     }
   }
   if (!FILL && lane == 0) g.rcnt[i] = (int32_t)cnt;
