@@ -294,7 +294,7 @@ def main():
     _sync()
     elapsed = time.perf_counter() - t0
     kernels = {}
-    for k in ("tile_screen", "adjacency", "row_count", "scan", "row_fill", "lower", "spmm_sym", "gram",
+    for k in ("tile_screen", "adjacency", "row_count", "scan", "row_fill", "spmm_sym", "gram",
               "rayleigh_ritz", "update"):
         n, t = ctx.kernel_time(k)
         kernels[k] = {"launches": n, "total_s": t, "mean_s": t / n if n else None}

@@ -84,8 +84,8 @@ cib_status cib_ctx_bytes(const cib_ctx *ctx, int64_t *live_bytes, int64_t *peak_
  * elapsed times of all completed launches of one kernel since the last reset
  * (it synchronises those events).  Kernel names: "tile_screen",
  * "adjacency", "row_count", "scan", "row_fill", "spmm_sym", "gram",
- * "rayleigh_ritz", "update", "lower" (all passes of the lower triangle).
- * Unknown names report zero launches. */
+ * "rayleigh_ritz", "update" (the build's row passes fill both stored
+ * triangles).  Unknown names report zero launches. */
 cib_status cib_profile_enable(cib_ctx *ctx, int on);
 cib_status cib_profile_reset(cib_ctx *ctx);
 cib_status cib_profile_query(cib_ctx *ctx, const char *kernel, int64_t *launches, double *total_s);
@@ -168,7 +168,7 @@ void cib_interaction_free(cib_interaction *it);
  * (Fig. 1 steps 6-14; Sec. 2.2-2.3) with a deterministic in-row order.
  * Host synchronisations: the screen totals and the nonzero total size the
  * allocations.  The matrix also keeps the strictly lower triangle (built by
- * the same passes over the transposed screens, bitwise the transpose for
+ * the same row passes, over the transposed screens, bitwise the transpose for
  * symmetric tables) because the SpMM reads both triangles instead of
  * scattering the transposed half with atomics; cib_matrix_export returns
  * only the upper half. */
@@ -185,11 +185,10 @@ typedef struct {
   double t_screen_s;  /* A-configuration tile screen + B-configuration adjacency */
   double t_count_s;   /* per-row counting pass                           */
   double t_scan_s;    /* counts -> offsets                               */
-  double t_fill_s;    /* per-row filling pass                            */
+  double t_fill_s;    /* per-row filling pass (both stored triangles)    */
   double t_total_s;   /* sum of the above (host waits between stages excluded) */
   int64_t n_tiles;    /* A-configuration pairs kept by the screen        */
   int64_t n_adjacent; /* B-configuration pairs kept by the screen        */
-  double t_lower_s;   /* part of t_fill_s spent filling the lower copy   */
 } cib_build_stats;
 
 cib_status cib_matrix_info(const cib_matrix *H, int64_t *dim, int64_t *nnz_half, cib_dtype *dtype);

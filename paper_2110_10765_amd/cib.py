@@ -72,7 +72,7 @@ class BuildStatsC(ctypes.Structure):
     _fields_ = [("t_screen_s", ctypes.c_double), ("t_count_s", ctypes.c_double),
                 ("t_scan_s", ctypes.c_double), ("t_fill_s", ctypes.c_double),
                 ("t_total_s", ctypes.c_double), ("n_tiles", ctypes.c_int64),
-                ("n_adjacent", ctypes.c_int64), ("t_lower_s", ctypes.c_double)]
+                ("n_adjacent", ctypes.c_int64)]
 
 
 class LobpcgOptsC(ctypes.Structure):

@@ -669,18 +669,21 @@ __device__ __forceinline__ void row_tiles(const RowArgs &g, int64_t t0, int64_t 
   }
 }
 
-// One wave per row i = (alpha, p).  Upper rows (j >= i): the diagonal A-block
-// from beta itself on (positions < len(alpha)), then tiles alpha' > alpha.
-// Lower rows (j < i): tiles alpha' < alpha, then the diagonal A-block entries
-// before beta.  Both lists come out in ascending column order.  beta's L1
-// list (at most a few hundred entries for these bases) is first copied to
-// LDS, so the per-tile binary searches and the expansion read it there.
+// One wave per row i = (alpha, p), both stored triangles: g holds the upper
+// tiles and outputs, gl the lower ones.  Upper row (j >= i): the diagonal
+// A-block from beta itself on (positions < len(alpha)), then tiles
+// alpha' > alpha.  Lower row (j < i): tiles alpha' < alpha, then the
+// diagonal A-block entries before beta.  Both lists come out in ascending
+// column order.  The row's preamble, its spectator slots and beta's L1 list
+// (at most a few hundred entries for these bases, copied to LDS so the
+// per-tile binary searches and the expansion read it there) serve both
+// triangles; one pass over both measured 6-8% faster than one per triangle.
 // Eight waves per SIMD (the most the hardware holds) are asked for
 // explicitly: the pass waits on chains of dependent reads, and the scalar
 // registers the compiler would otherwise keep cap it at seven (measured 12%
 // slower).
-template <int W, bool FILL, typename T, bool LOWER>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_row_pass(RowArgs g) {
+template <int W, bool FILL, typename T>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_row_pass(RowArgs g, RowArgs gl) {
   __shared__ int32_t s_pos[4][kL1Stage], s_info[4][FILL ? kL1Stage : 1], s_seg[4][kMaxSeg + 2];
   __shared__ int32_t s_mark[4][FILL ? kWave : 1];
   __shared__ __align__(16) int32_t s_spec[4][FILL ? 2 * kSpec : 1];
@@ -708,12 +711,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
       sb_idx = spec_idx<W>(bb, g.it.bcol, g.it.nB, s_spec[wv] + kSpec);
     }
   }
-  const int64_t out = FILL ? uni(g.row_ptr[i]) : 0;
+  const int64_t out_u = FILL ? uni(g.row_ptr[i]) : 0, out_l = FILL ? uni(gl.row_ptr[i]) : 0;
   const int64_t l1b = (int64_t)beta * g.nseg;
   const int64_t base = uni(g.l1_seg[l1b]);
   const int64_t n1 = uni(g.l1_seg[l1b + g.nseg]) - base;
-  int64_t cnt = 0;
-  const int64_t t0 = uni(g.t_ptr[(int64_t)alpha * g.tstride]), t1 = uni(g.t_ptr[(int64_t)(alpha + 1) * g.tstride]);
+  const int64_t t0u = uni(g.t_ptr[(int64_t)alpha * g.tstride]), t1u = uni(g.t_ptr[(int64_t)(alpha + 1) * g.tstride]);
+  const int64_t t0l = uni(gl.t_ptr[(int64_t)alpha * gl.tstride]);
+  const int64_t t1l = uni(gl.t_ptr[(int64_t)(alpha + 1) * gl.tstride]);
+  // beta's Lsame list: [ls_lo, ls_me) before beta itself, [ls_me, ls_hi) from it on
+  const int64_t ls_lo = uni(g.ls_ptr[beta]), ls_hi = uni(g.ls_ptr[beta + 1]), ls_me = uni((int64_t)g.ls_self[beta]);
+  int64_t cu = 0, cl = 0;
   if (n1 <= kL1Stage && g.nseg <= kMaxSeg + 1) {
     for (int64_t k = lane; k < n1; k += kWave) {
       s_pos[wv][k] = g.l1_pos[base + k];
@@ -722,24 +729,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
     for (int h = lane; h <= g.nseg; h += kWave) s_seg[wv][h] = (int32_t)(g.l1_seg[l1b + h] - base);
     wave_lds_sync();
     const L1View<true> L{s_seg[wv], nullptr, 0, s_pos[wv], FILL ? s_info[wv] : nullptr};
-    if (!LOWER) {
-      row_diag<W, FILL, T>(g, i, uni((int64_t)g.ls_self[beta]), uni(g.ls_ptr[beta + 1]), alpha, len_a, off_a, ab, sa_idx, out, cnt);
-      row_tiles<W, FILL, T, true>(g, t0, t1, p, bb, sb_idx, out, cnt, L, s_mark[wv]);
-    } else {
-      row_tiles<W, FILL, T, true>(g, t0, t1, p, bb, sb_idx, out, cnt, L, s_mark[wv]);
-      row_diag<W, FILL, T>(g, i, uni(g.ls_ptr[beta]), uni((int64_t)g.ls_self[beta]), alpha, len_a, off_a, ab, sa_idx, out, cnt);
-    }
+    row_diag<W, FILL, T>(g, i, ls_me, ls_hi, alpha, len_a, off_a, ab, sa_idx, out_u, cu);
+    row_tiles<W, FILL, T, true>(g, t0u, t1u, p, bb, sb_idx, out_u, cu, L, s_mark[wv]);
+    row_tiles<W, FILL, T, true>(gl, t0l, t1l, p, bb, sb_idx, out_l, cl, L, s_mark[wv]);
+    row_diag<W, FILL, T>(gl, i, ls_lo, ls_me, alpha, len_a, off_a, ab, sa_idx, out_l, cl);
   } else {
     const L1View<false> L{nullptr, g.l1_seg + l1b, base, g.l1_pos + base, FILL ? g.l1_info + base : nullptr};
-    if (!LOWER) {
-      row_diag<W, FILL, T>(g, i, uni((int64_t)g.ls_self[beta]), uni(g.ls_ptr[beta + 1]), alpha, len_a, off_a, ab, sa_idx, out, cnt);
-      row_tiles<W, FILL, T, false>(g, t0, t1, p, bb, sb_idx, out, cnt, L, s_mark[wv]);
-    } else {
-      row_tiles<W, FILL, T, false>(g, t0, t1, p, bb, sb_idx, out, cnt, L, s_mark[wv]);
-      row_diag<W, FILL, T>(g, i, uni(g.ls_ptr[beta]), uni((int64_t)g.ls_self[beta]), alpha, len_a, off_a, ab, sa_idx, out, cnt);
-    }
+    row_diag<W, FILL, T>(g, i, ls_me, ls_hi, alpha, len_a, off_a, ab, sa_idx, out_u, cu);
+    row_tiles<W, FILL, T, false>(g, t0u, t1u, p, bb, sb_idx, out_u, cu, L, s_mark[wv]);
+    row_tiles<W, FILL, T, false>(gl, t0l, t1l, p, bb, sb_idx, out_l, cl, L, s_mark[wv]);
+    row_diag<W, FILL, T>(gl, i, ls_lo, ls_me, alpha, len_a, off_a, ab, sa_idx, out_l, cl);
   }
-  if (!FILL && lane == 0) g.rcnt[i] = (int32_t)cnt;
+  if (!FILL && lane == 0) {
+    g.rcnt[i] = (int32_t)cu;
+    gl.rcnt[i] = (int32_t)cl;
+  }
 }
 
 // ------------------------------------------------------------ exclusive scan
@@ -956,7 +960,7 @@ __global__ void k_xcd_rows(int64_t D, const int64_t *rp, const int64_t *lrp, int
 }
 
 struct Events {
-  hipEvent_t e[9];
+  hipEvent_t e[8];
   Events() { for (auto &x : e) CIB_HIP(hipEventCreate(&x)); }
   ~Events() { for (auto &x : e) (void)hipEventDestroy(x); }
   double ms(int a, int b) {
@@ -1082,8 +1086,7 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
   DBuf<double> diag(ctx, p.D);
   {
     KTimer kt(ctx, K_ROW_COUNT, s);
-    hipLaunchKernelGGL((k_row_pass<W, false, double, false>), dim3(rblk), dim3(256), 0, s, ra);
-    hipLaunchKernelGGL((k_row_pass<W, false, double, true>), dim3(rblk), dim3(256), 0, s, rl);
+    hipLaunchKernelGGL((k_row_pass<W, false, double>), dim3(rblk), dim3(256), 0, s, ra, rl);
     hipLaunchKernelGGL((k_state_diag<W>), dim3((unsigned)((p.D + 255) / 256)), dim3(256), 0, s, p.D,
                        b.row_a.p, b.row_p.p, b.a_seg.p, b.bseg_start.p, b.a_bits.p, nA, b.b_bits.p, nB,
                        eA.p, eB.p, it, diag.p);
@@ -1124,20 +1127,12 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
   {
     KTimer kt(ctx, K_ROW_FILL, s);
     if (dt == CIB_F64)
-      hipLaunchKernelGGL((k_row_pass<W, true, double, false>), dim3(rblk), dim3(256), 0, s, ra);
+      hipLaunchKernelGGL((k_row_pass<W, true, double>), dim3(rblk), dim3(256), 0, s, ra, rl);
     else
-      hipLaunchKernelGGL((k_row_pass<W, true, float, false>), dim3(rblk), dim3(256), 0, s, ra);
-  }
-  CIB_HIP(hipEventRecord(ev.e[7], s));
-  {
-    KTimer kt(ctx, K_LOWER, s);
-    if (dt == CIB_F64)
-      hipLaunchKernelGGL((k_row_pass<W, true, double, true>), dim3(rblk), dim3(256), 0, s, rl);
-    else
-      hipLaunchKernelGGL((k_row_pass<W, true, float, true>), dim3(rblk), dim3(256), 0, s, rl);
+      hipLaunchKernelGGL((k_row_pass<W, true, float>), dim3(rblk), dim3(256), 0, s, ra, rl);
   }
   CIB_HIP(hipGetLastError());
-  CIB_HIP(hipEventRecord(ev.e[8], s));
+  CIB_HIP(hipEventRecord(ev.e[7], s));
   DBuf<int64_t> xr(ctx, 9);
   hipLaunchKernelGGL(k_xcd_rows, dim3(1), dim3(64), 0, s, p.D, H.row_ptr.p, H.lo_ptr.p, xr.p);
   CIB_HIP(hipGetLastError());
@@ -1151,9 +1146,8 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
   H.stats.t_screen_s = ev.ms(0, 1) + ev.ms(2, 3);
   H.stats.t_count_s = ev.ms(3, 4);
   H.stats.t_scan_s = ev.ms(4, 5);
-  H.stats.t_fill_s = ev.ms(6, 8);
+  H.stats.t_fill_s = ev.ms(6, 7);
   H.stats.t_total_s = H.stats.t_screen_s + H.stats.t_count_s + H.stats.t_scan_s + H.stats.t_fill_s;
-  H.stats.t_lower_s = ev.ms(7, 8);
   H.stats.n_tiles = n_tiles;
   H.stats.n_adjacent = n_ls + n_l1;
 }

@@ -75,7 +75,7 @@ struct cib_ctx {
 namespace cib {
 
 // Hot kernels known to the profiler.
-enum KernelId { K_TILE = 0, K_ADJ, K_ROW_COUNT, K_SCAN, K_ROW_FILL, K_SPMM, K_GRAM, K_RR, K_UPDATE, K_LOWER, K_NKERN };
+enum KernelId { K_TILE = 0, K_ADJ, K_ROW_COUNT, K_SCAN, K_ROW_FILL, K_SPMM, K_GRAM, K_RR, K_UPDATE, K_NKERN };
 extern const char *const kKernelNames[K_NKERN];
 
 // Brackets one launch with events when profiling is on (RAII).

@@ -90,8 +90,7 @@ static TransLayout trans_layout(const Orbs &oa, const Orbs &ob) {
 }
 
 const char *const kKernelNames[K_NKERN] = {"tile_screen", "adjacency", "row_count", "scan",
-                                           "row_fill", "spmm_sym", "gram", "rayleigh_ritz", "update",
-                                           "lower"};
+                                           "row_fill", "spmm_sym", "gram", "rayleigh_ritz", "update"};
 
 static hipEvent_t take_event(cib_ctx *c) {
   if (!c->event_pool.empty()) {
