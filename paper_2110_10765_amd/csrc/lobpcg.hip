@@ -442,45 +442,48 @@ __device__ __forceinline__ void rayleigh_ritz(const RRArgs &g) {
   }
   __syncthreads();
   if (g.clk && tid == 0) g.clk[2] = wall_clock64();
-  // 3. right-looking Cholesky with dropping.  Lane i of every wave owns row
-  //    i; the trailing update of step k is split over the waves by column
-  //    (wave w takes columns k + 1 + w, k + 1 + w + nw, ...), and column k of
-  //    L reaches the other lanes through lane reads.  Every wave reads the
-  //    unscaled column k in step k, so wave 0 writes the scaled column back
-  //    one step later.
-  {
-    const int i = tid & (kWave - 1), wv = tid >> 6, nw = nt >> 6;
-    double lprev = 0.0, dprev = 0.0;
-    for (int k = 0; k < ns; ++k) {
-      const double piv = G[k][k];
-      const bool kk = scale[k] > 0.0 && piv > drop_tol;   // every lane decides the same
-      // 1/sqrt(piv) from the hardware estimate and one Newton step
-      double y = __builtin_amdgcn_rsq(kk ? piv : 1.0);
-      y = y * fma(-0.5 * (kk ? piv : 1.0) * y, y, 1.5);
-      const double ilkk = kk ? y : 0.0;
-      const double lkk = kk ? piv * y : 0.0;
-      const double lik = (i > k && i < ns) ? G[i][k] * ilkk : 0.0;
-      if (wv == 0 && k > 0) {   // column k - 1 of L, read by nobody in this step
-        if (i > k - 1 && i < ns) G[i][k - 1] = lprev;
-        if (i == k - 1) G[i][i] = dprev;
-      }
-      if (tid == 0) keep[k] = kk;
-      if (kk) {
-        for (int j = k + 1 + wv; j < ns; j += nw) {
-          const double ljk = readlane_f64(lik, j);
-          if (i >= j && i < ns) G[i][j] -= lik * ljk;
+  // 3. right-looking Cholesky with dropping, in one wave with the matrix in
+  //    registers: lane i holds row i, the steps and columns are unrolled so
+  //    that every element of the row is a fixed register, and column k of L
+  //    reaches the other lanes through lane reads.  The whole trailing block
+  //    is updated (rows at or above the pivot have a zero multiplier): only
+  //    the lower triangle and the diagonal are read afterwards, and a
+  //    per-element row test costs more than the update.  (Over four waves
+  //    with the matrix in LDS a step took ~1.2 us of LDS round trips and
+  //    barriers.)
+  if (tid < kWave) {
+    const int i = tid;
+    const int ic = i < kNS ? i : kNS - 1;   // rows past the matrix read a valid row, then zero it
+    double gr[kNS];
+#pragma unroll
+    for (int q = 0; q < kNS; ++q) {
+      const double v = G[ic][q];
+      gr[q] = (i < ns && q < ns) ? v : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < kNS; ++k) {
+      if (k < ns) {
+        const double piv = readlane_f64(gr[k], k);
+        const bool kk = scale[k] > 0.0 && piv > drop_tol;   // every lane decides the same
+        // 1/sqrt(piv) from the hardware estimate and one Newton step
+        double y = __builtin_amdgcn_rsq(kk ? piv : 1.0);
+        y = y * fma(-0.5 * (kk ? piv : 1.0) * y, y, 1.5);
+        const double ilkk = kk ? y : 0.0;
+        const double lkk = kk ? piv * y : 0.0;
+        const double lik = (i > k && i < ns) ? gr[k] * ilkk : 0.0;
+        if (i == 0) keep[k] = kk;
+        if (kk) {
+#pragma unroll
+          for (int j = k + 1; j < kNS; ++j) gr[j] -= lik * readlane_f64(lik, j);   // 0 past the matrix
         }
+        gr[k] = i > k ? lik : (i == k ? lkk : gr[k]);
       }
-      lprev = lik;
-      dprev = lkk;
-      __syncthreads();
     }
-    if (wv == 0 && ns > 0) {
-      if (i > ns - 1 && i < ns) G[i][ns - 1] = lprev;
-      if (i == ns - 1) G[i][i] = dprev;
-    }
-    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kNS; ++q)
+      if (i < ns && q < ns) G[i][q] = gr[q];
   }
+  __syncthreads();
   if (tid < kWave) {
     const int i = tid;
     if (g.clk && i == 0) g.clk[3] = wall_clock64();
