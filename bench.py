@@ -21,7 +21,10 @@ float64 Gram / Rayleigh-Ritz / update).  Printed as one JSON line:
   roofline         the kernel that dominates the step, its algorithmic bytes
                    per launch over its mean HIP-event duration vs 8 TB/s
   cpu_baseline     the CPU oracle (operator application + hashing) on a
-                   bounded sample of the same workload, nnz per second
+                   bounded sample of the same workload, nnz per second; under
+                   "serve", the serving stream through CPU worker processes
+                   running the oracle, over a 20 s window
+  host_nproc       host CPUs of the machine that ran it
 """
 import argparse
 import json
@@ -98,7 +101,26 @@ def measure_spmm(cib, ctx, H, b, reps):
     return t / max(n, 1)
 
 
-def workload_rates(cib, ctx, cigen, name, b, reps=20):
+def measure_copy_gbs(reps=5):
+    """Device-to-device copy of 1 GiB (torch), bytes read + written per
+    second: the measured bandwidth the HBM fractions are also quoted against."""
+    import torch
+    n = 1 << 27
+    src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    gbs = 2.0 * n * 8 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    return gbs
+
+
+def workload_rates(cib, ctx, cigen, name, b, reps=20, copy_gbs=None):
     """Build and SpMM rates of one workload in both dtypes."""
     w = cigen.WORKLOADS[name]
     tables = cigen.make_tables(w.spec, w.seed)
@@ -127,7 +149,13 @@ def workload_rates(cib, ctx, cigen, name, b, reps=20):
             "spmm_nnz_vec_per_s": nnz_full * b / t_spmm,
             "spmm_kernel_s": t_spmm,
             "spmm_hbm_frac": _spmm_bytes(H.nnz, H.dim, b, sv) / t_spmm / 1e9 / HBM_PEAK_GBS,
+            # the paper's counting metric: candidate state pairs (j >= i, what a
+            # brute-force screen compares) per second of screen + count
+            "screen_pairs_per_s": H.dim * (H.dim + 1) / 2 / (st["t_screen_s"] + st["t_count_s"]),
         }
+        if copy_gbs:
+            out[dt]["fill_copy_frac"] = _fill_bytes(H.nnz, H.dim, sv) / st["t_fill_s"] / 1e9 / copy_gbs
+            out[dt]["spmm_copy_frac"] = _spmm_bytes(H.nnz, H.dim, b, sv) / t_spmm / 1e9 / copy_gbs
         H.free()
     inter.free()
     basis.free()
@@ -211,6 +239,64 @@ def cpu_baseline(cigen, name, seconds=15.0):
             "unit": "nnz/s", "cores": threads, "kind": "oracle",
             "sample": "%d random kets of %s (D=%d): H applied by operator strings + hash lookup, "
                       "%.1f s; stored half-entries per second" % (cols_done, name, b.D, total_t)}
+
+
+def _cpu_solve(req):
+    """One request of the serving stream solved by the CPU oracle: basis, the
+    half-stored H from the operator image, and its lowest eigenvalues (dense
+    LAPACK up to D = 600, else ARPACK).  Runs in a worker process."""
+    sys.path.insert(0, ROOT)
+    import cigen
+    import oracle as O
+    t0 = time.perf_counter()
+    b = O.Basis(req["spec"])
+    if b.D > 0:
+        inter = O.Interaction(b, cigen.make_tables(req["spec"], req["seed"]))
+        rp, col, val = O.half_csr(b, inter)
+        k = min(req["nev"], b.D)
+        if b.D <= 600:
+            O.eigs_dense(O.full_from_half(rp, col, val, b.D).toarray(), k)
+        else:
+            O.eigs_sparse(rp, col, val, k, tol=1e-10)
+    return req["id"], b.D, time.perf_counter() - t0
+
+
+def cpu_serve_baseline(n_req, seconds=20.0):
+    """The serving stream through a pool of CPU worker processes running the
+    oracle, closed loop in trace order, over a window of `seconds`: requests
+    finished inside the window per second (the window cuts off the requests
+    still running, so large ones are under-represented)."""
+    import multiprocessing as mp
+    import cigen
+    workers = max(1, min(16, os.cpu_count() or 1))
+    reqs = cigen.request_trace(n_req)
+    done = []
+    # spawned workers: fresh interpreters that never touch the GPU
+    pool = mp.get_context("spawn").Pool(workers)
+    try:
+        t0 = time.perf_counter()
+        it = pool.imap_unordered(_cpu_solve, reqs, chunksize=1)
+        while True:
+            left = seconds - (time.perf_counter() - t0)
+            if left <= 0:
+                break
+            try:
+                done.append(it.next(timeout=left))
+            except mp.TimeoutError:
+                break
+            except StopIteration:
+                break
+        window = min(seconds, time.perf_counter() - t0)
+    finally:
+        pool.terminate()
+        pool.join()
+    dims = sorted(d for _, d, _ in done)
+    return {"value": len(done) / window, "unit": "solves/s", "cores": workers, "kind": "oracle",
+            "sample": "%d of the %d requests of the serving stream finished within a %.0f s window "
+                      "(closed loop, trace order, %d worker processes; D of the finished ones %s-%s): "
+                      "basis, half CSR from the operator image, lowest 4 eigenvalues (LAPACK for D <= "
+                      "600, else ARPACK)" % (len(done), n_req, window, workers,
+                                            dims[0] if dims else "-", dims[-1] if dims else "-")}
 
 
 def main():
@@ -328,10 +414,14 @@ def main():
         "solves_per_s": args.steps / elapsed,
         "kernels": kernels,
     }
+    copy_gbs = measure_copy_gbs()
+    sub["hbm_copy_gbs"] = copy_gbs
+    if roof.get("achieved"):
+        roof["copy_frac"] = roof["achieved"] / copy_gbs
     ws = {}
     for item in filter(None, [args.workload + ":%d" % w.block] + args.extra.split(",")):
         name, bb = item.split(":")
-        ws[name] = workload_rates(cib, ctx, cigen, name, int(bb))
+        ws[name] = workload_rates(cib, ctx, cigen, name, int(bb), copy_gbs=copy_gbs)
     sub["workloads"] = ws
     if not args.no_serve:
         try:
@@ -346,10 +436,12 @@ def main():
         "data": "synthetic (seeded eps ~ n + U(-0.1,0.1), V ~ N(0,1) m-conserving)",
         "config": {"workload": w.name, "D": D, "nnz_half": nnz, "nev": w.nev, "block": w.block,
                    "parallelism": "1 GPU"},
-        "roofline": roof, "submetrics": sub,
+        "roofline": roof, "submetrics": sub, "host_nproc": os.cpu_count(),
     }
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(cigen, w.name)
+        if not args.no_serve:
+            line["cpu_baseline"]["serve"] = cpu_serve_baseline(args.serve_requests)
     print(json.dumps(line))
 
 
