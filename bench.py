@@ -23,7 +23,9 @@ float64 Gram / Rayleigh-Ritz / update).  Printed as one JSON line:
   cpu_baseline     the CPU oracle (operator application + hashing) on a
                    bounded sample of the same workload, nnz per second; under
                    "serve", the serving stream through CPU worker processes
-                   running the oracle, over a 20 s window
+                   running the oracle, over a 20 s window; under "phases",
+                   the oracle's basis, half CSR, SpMM and eigensolve on the
+                   D = 20,004 workload
   host_nproc       host CPUs of the machine that ran it
 """
 import argparse
@@ -241,6 +243,37 @@ def cpu_baseline(cigen, name, seconds=15.0):
                       "%.1f s; stored half-entries per second" % (cols_done, name, b.D, total_t)}
 
 
+def cpu_phase_baseline(cigen, name="ab_n3_3p3_cut4", b=8, seconds=2.0):
+    """The oracle's other phases on the D = 20,004 workload (the largest whose
+    whole half CSR the oracle builds in seconds): basis, half CSR, half-CSR
+    SpMM at block b in both dtypes (the oracle expands the half and also forms
+    |H| |X| on every call), and the lowest 5 eigenvalues by ARPACK."""
+    import numpy as np
+    import oracle as O
+    w = cigen.WORKLOADS[name]
+    t0 = time.perf_counter()
+    basis = O.Basis(w.spec)
+    t1 = time.perf_counter()
+    rp, col, val = O.half_csr(basis, O.Interaction(basis, cigen.make_tables(w.spec, w.seed)))
+    t2 = time.perf_counter()
+    nnz_full = 2 * len(col) - basis.D
+    X = np.random.default_rng(0).standard_normal((basis.D, b))
+    out = {"workload": name, "D": basis.D, "nnz_half": len(col), "basis_s": t1 - t0,
+           "half_csr_s": t2 - t1, "half_csr_nnz_per_s": len(col) / (t2 - t1)}
+    for dt, npt in (("f64", np.float64), ("f32", np.float32)):
+        v, Xd = val.astype(npt), X.astype(npt)
+        n, ts = 0, time.perf_counter()
+        while time.perf_counter() - ts < seconds:
+            O.spmm_half(rp, col, v, Xd)
+            n += 1
+        out["spmm_%s_nnz_vec_per_s" % dt] = nnz_full * b / ((time.perf_counter() - ts) / n)
+    ts = time.perf_counter()
+    O.eigs_sparse(rp, col, val, 5, tol=1e-10)
+    out["eigensolve_s"] = time.perf_counter() - ts
+    out["spmm_block"] = b
+    return out
+
+
 def _cpu_solve(req):
     """One request of the serving stream solved by the CPU oracle: basis, the
     half-stored H from the operator image, and its lowest eigenvalues (dense
@@ -440,6 +473,7 @@ def main():
     }
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(cigen, w.name)
+        line["cpu_baseline"]["phases"] = cpu_phase_baseline(cigen)
         if not args.no_serve:
             line["cpu_baseline"]["serve"] = cpu_serve_baseline(args.serve_requests)
     print(json.dumps(line))
