@@ -23,7 +23,7 @@ __all__ = [
     "count_difference", "popcount", "dim_generating_function",
     "nnz_class_count", "trace_generating_function", "spmm_half",
     "eigs_dense", "eigs_sparse", "full_from_half", "residual_audit",
-    "load_clib", "build_clib", "apply_columns",
+    "load_clib", "build_clib", "apply_columns", "observables",
 ]
 
 
@@ -707,6 +707,22 @@ def spmm_half(row_ptr, col, val, X):
     H = full_from_half(row_ptr, col, val, D)
     X = np.asarray(X, dtype=np.float64)
     return H @ X, abs(H) @ np.abs(X)
+
+
+def observables(basis, tables_list, X):
+    """Expectation values of several operators in several vectors, the
+    step after the eigensolve (Fig. 1 steps 16-20): a[k, v] = sum_ij
+    X[i, v] (O_k)_ij X[j, v], where O_k is the many-body operator defined by
+    tables_list[k] (one-body energies and two-body tables in the layout of
+    the Hamiltonian's).  Each O_k is formed as its half-stored matrix from
+    the operator image (half_csr), expanded, and applied in float64."""
+    X = np.asarray(X, dtype=np.float64)
+    out = np.zeros((len(tables_list), X.shape[1]))
+    for k, t in enumerate(tables_list):
+        rp, col, val = half_csr(basis, Interaction(basis, t))
+        Y = full_from_half(rp, col, val, basis.D) @ X
+        out[k] = np.sum(X * Y, axis=0)
+    return out
 
 
 def eigs_dense(H, k):
