@@ -20,6 +20,7 @@ float64 Gram / Rayleigh-Ritz / update).  Printed as one JSON line:
                    (solves/s, p50/p99 latency) over the 512-request stream
   roofline         the kernel that dominates the step, its algorithmic bytes
                    per launch over its mean HIP-event duration vs 8 TB/s
+                   (also: expectation values of 16 operators in 16 vectors)
   cpu_baseline     the CPU oracle (operator application + hashing) on a
                    bounded sample of the same workload, nnz per second; under
                    "serve", the serving stream through CPU worker processes
@@ -162,6 +163,28 @@ def workload_rates(cib, ctx, cigen, name, b, reps=20, copy_gbs=None):
     inter.free()
     basis.free()
     return out
+
+
+def observables_rate(cib, ctx, cigen, name, nnz_half, m=16, nvec=16):
+    """Expectation values of m random two-body operators (tables seeds
+    2000 + k) in nvec vectors on the workload's basis: wall time of one
+    cib_observables call (each operator built, applied once, freed)."""
+    import torch
+    w = cigen.WORKLOADS[name]
+    basis = cib.build_basis(ctx, w.spec)
+    tabs = [cigen.make_tables(w.spec, 2000 + k) for k in range(m)]
+    tdt = torch.float64 if w.dtype == "f64" else torch.float32
+    g = torch.Generator(device="cpu").manual_seed(3)
+    X = torch.randn(basis.dim, nvec, generator=g, dtype=torch.float64).to(tdt).to("cuda:0")
+    cib.observables(ctx, basis, tabs[:1], X)   # warm
+    _sync()
+    t0 = time.perf_counter()
+    cib.observables(ctx, basis, tabs, X)
+    t = time.perf_counter() - t0
+    nnz_full = 2 * nnz_half - basis.dim
+    basis.free()
+    return {"operators": m, "vectors": nvec, "dtype": w.dtype, "wall_s": t, "per_operator_s": t / m,
+            "pair_vec_per_s": m * nnz_full * nvec / t}
 
 
 def serve_run(cib, ctx, cigen, dtype, n_req, budget=0, rate=math.inf):
@@ -456,6 +479,7 @@ def main():
         name, bb = item.split(":")
         ws[name] = workload_rates(cib, ctx, cigen, name, int(bb), copy_gbs=copy_gbs)
     sub["workloads"] = ws
+    sub["observables"] = observables_rate(cib, ctx, cigen, w.name, nnz)
     if not args.no_serve:
         try:
             sub.update(serve_suite(cib, ctx, cigen, args.serve_requests, sweep=not args.no_serve_sweep))

@@ -204,11 +204,28 @@ void cib_matrix_free(cib_matrix *H);
 /* -------------------------------------------------------------- apply H --
  * Y = H X for nvec vectors (1..64).  X and Y are device arrays of the matrix
  * dtype, D rows, row-major: element (i, v) at X[i * ldx + v], ldx >= nvec
- * (same for Y).  Asynchronous on the context stream; Y is overwritten.  The
- * transposed half of the matrix is applied with device atomics, so results
- * may differ in the last bits between calls. */
+ * (same for Y).  Asynchronous on the context stream; Y is overwritten.  Each
+ * output row is gathered from both stored triangles (no atomics), so every
+ * call gives the same bits. */
 cib_status cib_apply_H(cib_ctx *ctx, const cib_matrix *H, const void *X, int64_t ldx, void *Y,
                        int64_t ldy, int32_t nvec);
+
+/* ---------------------------------------------------------- observables --
+ * Expectation values after the eigensolve (Fig. 1 steps 16-20):
+ * out[k * nvec + v] = x_v^T O_k x_v for the m operators O_k given by ops[k]
+ * (host tables in the cib_tables layout, for `basis`'s orbital sets; a
+ * one-body operator has zero two-body tables) and the nvec vectors x_v
+ * (1..64): X is a device array of `dtype`, D rows, row-major, element
+ * (i, v) at X[i * ldx + v], ldx >= nvec.  Each operator is built as a
+ * half-stored matrix of `dtype` by the same passes as cib_build_H, applied
+ * once, and freed before the next (device memory: one operator's matrix plus
+ * D x nvec values).  The products are summed in float64 in a fixed order, so
+ * results are deterministic.  out: host, m * nvec doubles.  Synchronous.
+ * Errors: CIB_E_INVALID for NULL pointers, m < 1, nvec outside 1..64,
+ * ldx < nvec, a bad dtype or a basis of another context; CIB_E_NOMEM when
+ * an operator's matrix does not fit. */
+cib_status cib_observables(cib_ctx *ctx, const cib_basis *basis, const cib_tables *ops, int32_t m,
+                           cib_dtype dtype, const void *X, int64_t ldx, int32_t nvec, double *out);
 
 /* --------------------------------------------------------------- LOBPCG --
  * Lowest nev eigenpairs of H (Fig. 1 step 15) by block LOBPCG with block size

@@ -40,7 +40,7 @@ EXPORTS = [
     "cib_upload_interaction", "cib_interaction_free",
     "cib_build_H", "cib_build_H_resident", "cib_matrix_info", "cib_matrix_stats",
     "cib_matrix_export", "cib_matrix_device", "cib_matrix_free",
-    "cib_apply_H", "cib_lobpcg", "cib_serve",
+    "cib_apply_H", "cib_observables", "cib_lobpcg", "cib_serve",
 ]
 
 
@@ -145,6 +145,7 @@ def load(path: str = LIB_PATH):
         "cib_matrix_device": ([vp, P(vp), P(vp), P(vp)], i32),
         "cib_matrix_free": ([vp], None),
         "cib_apply_H": ([vp, vp, vp, i64, vp, i64, i32], i32),
+        "cib_observables": ([vp, vp, vp, i32, i32, vp, i64, i32, vp], i32),
         "cib_lobpcg": ([vp, vp, P(LobpcgOptsC), vp, vp, i64, P(LobpcgInfoC)], i32),
         "cib_serve": ([vp, P(RequestC), i32, P(ServeOptsC), P(ResultC)], i32),
     }
@@ -393,6 +394,27 @@ def apply_H(ctx: Context, H: Matrix, X, Y=None):
     X.record_stream(ctx.stream)
     Y.record_stream(ctx.stream)
     return Y
+
+
+def observables(ctx: Context, basis: Basis, tables_list, X):
+    """a[k, v] = x_v^T O_k x_v (numpy float64, shape (m, nvec)) for the
+    operators given by tables_list and the columns of the torch device tensor
+    X (D x nvec, row-major, float64 or float32: the dtype the operators are
+    built and applied in)."""
+    import numpy as np
+    import torch
+    if X.dtype not in (torch.float64, torch.float32) or X.dim() != 2 or X.shape[0] != basis.dim \
+            or X.stride(1) != 1:
+        raise ValueError("X must be a (D, nvec) float64 or float32 tensor with unit column stride")
+    holders = [_TablesHolder(t) for t in tables_list]
+    arr = (TablesC * len(holders))(*[h.c for h in holders])
+    out = np.zeros((len(holders), X.shape[1]), dtype=np.float64)
+    cur = torch.cuda.current_stream(X.device)
+    ctx.stream.wait_stream(cur)          # X is ready on the caller's stream
+    _check(load().cib_observables(ctx.h, basis.h, ctypes.cast(arr, ctypes.c_void_p), len(holders),
+                                  _dtype_code(X.dtype), X.data_ptr(), X.stride(0), X.shape[1],
+                                  out.ctypes.data))
+    return out
 
 
 def lobpcg(ctx: Context, H: Matrix, nev: int, block: int = 8, max_iter: int = 500, tol: float = 0.0,

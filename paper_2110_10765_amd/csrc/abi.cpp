@@ -303,6 +303,22 @@ cib_status cib_apply_H(cib_ctx *ctx, const cib_matrix *H, const void *X, int64_t
   });
 }
 
+// ----------------------------------------------------------- observables
+cib_status cib_observables(cib_ctx *ctx, const cib_basis *b, const cib_tables *ops, int32_t m, cib_dtype dt,
+                           const void *X, int64_t ldx, int32_t nvec, double *out) {
+  return guarded([&] {
+    CIB_REQUIRE(ctx && b && ops && X && out, CIB_E_INVALID, "NULL argument");
+    CIB_REQUIRE(m >= 1, CIB_E_INVALID, "m must be at least 1");
+    CIB_REQUIRE(dt == CIB_F64 || dt == CIB_F32, CIB_E_INVALID, "dtype must be CIB_F64 or CIB_F32");
+    CIB_REQUIRE(nvec >= 1 && nvec <= 64, CIB_E_INVALID, "nvec must be in 1..64");
+    CIB_REQUIRE(ldx >= nvec, CIB_E_INVALID, "leading dimension smaller than nvec");
+    CIB_REQUIRE(b->ctx == ctx, CIB_E_INVALID, "basis belongs to another context");
+    BusyGuard busy(ctx);
+    DeviceGuard g(ctx->device);
+    observables(ctx, *b, ops, m, dt, X, ldx, nvec, out, ctx->stream);
+  });
+}
+
 }  // extern "C"
 
 // ---------------------------------------------------------------- LOBPCG

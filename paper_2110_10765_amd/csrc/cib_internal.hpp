@@ -258,6 +258,9 @@ cib_interaction *upload_interaction(cib_ctx *ctx, const cib_basis &b, const cib_
 
 void spmm_sym(const cib_matrix &H, const void *X, int64_t ldx, void *Y, int64_t ldy, int nvec,
               hipStream_t s);
+// out[k * nvec + v] = x_v^T O_k x_v for the m operators ops (host result).
+void observables(cib_ctx *ctx, const cib_basis &b, const cib_tables *ops, int m, cib_dtype dt, const void *X,
+                 int64_t ldx, int nvec, double *out, hipStream_t s);
 
 // Step-wise LOBPCG (used by the serving loop): all calls enqueue on the run's
 // stream; the status block (kStatusLen doubles: converged count, b relative
