@@ -191,6 +191,21 @@ def request_trace(n: int = 512, trace_seed: int = 5, rate: float = math.inf,
     return out
 
 
+def counting_states(n: int, n_particles: int = 8, n_sp: int = 128, tau: float = 36.0,
+                    seed: int = 0) -> np.ndarray:
+    """Random many-body states for the state-counting test: n states, each
+    n_particles distinct single-particle states out of n_sp, drawn without
+    replacement with weights exp(-k / tau) (biased towards the lowest states;
+    the Gumbel top-k draw).  tau = 36 at 8 particles out of 128 gives two
+    random states a probability of about 6e-6 to differ in at most two
+    particles, the median density of nonzeros the paper quotes for its test.
+    Returns an (n, n_particles) uint16 array, each row ascending."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    keys = -np.arange(n_sp) / tau + rng.gumbel(size=(n, n_sp))
+    idx = np.argpartition(-keys, n_particles - 1, axis=1)[:, :n_particles]
+    return np.sort(idx, axis=1).astype(np.uint16)
+
+
 def random_spec_small(rng: np.random.Generator) -> BasisSpec:
     """A tiny random spec (for property tests): D stays in the hundreds."""
     if rng.random() < 0.3:

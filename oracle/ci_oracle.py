@@ -23,7 +23,7 @@ __all__ = [
     "count_difference", "popcount", "dim_generating_function",
     "nnz_class_count", "trace_generating_function", "spmm_half",
     "eigs_dense", "eigs_sparse", "full_from_half", "residual_audit",
-    "load_clib", "build_clib", "apply_columns", "observables",
+    "load_clib", "build_clib", "apply_columns", "observables", "count_connected",
 ]
 
 
@@ -367,6 +367,31 @@ def count_difference(s1, s2):
             i1 += 1
             i2 += 1
     return 2 * max(only1, only2)
+
+
+def count_connected(mbs, n_sp):
+    """The state-counting test (Sec. 2.1, Listing 2 as a description): for
+    each state i of the list, the number of states j (j = i included) that a
+    two-body operator connects, i.e. that differ from it in at most two
+    particles: popcount(BIN_i xor BIN_j) <= 4 with BIN the full bit string
+    of the state over all n_sp single-particle states.  mbs: (n, N) index
+    tuples.  Returns int64 counts per state (numpy, blocks of rows)."""
+    mbs = np.asarray(mbs, dtype=np.int64)
+    n = mbs.shape[0]
+    nw = max(1, -(-n_sp // 64))
+    words = np.zeros((n, nw), dtype=np.uint64)
+    for k in range(mbs.shape[1]):
+        w, b = mbs[:, k] // 64, (mbs[:, k] % 64).astype(np.uint64)
+        for q in range(nw):
+            sel = w == q
+            words[sel, q] |= np.left_shift(np.uint64(1), b[sel])
+    counts = np.zeros(n, dtype=np.int64)
+    for i0 in range(0, n, 256):
+        d = np.zeros((min(256, n - i0), n), dtype=np.int64)
+        for q in range(nw):
+            d += np.bitwise_count(words[i0:i0 + 256, q][:, None] ^ words[None, :, q])
+        counts[i0:i0 + 256] = (d <= 4).sum(axis=1)
+    return counts
 
 
 # ---------------------------------------------------------------------------
