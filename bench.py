@@ -20,7 +20,8 @@ float64 Gram / Rayleigh-Ritz / update).  Printed as one JSON line:
                    (solves/s, p50/p99 latency) over the 512-request stream
   roofline         the kernel that dominates the step, its algorithmic bytes
                    per launch over its mean HIP-event duration vs 8 TB/s
-                   (also: expectation values of 16 operators in 16 vectors)
+                   (also: expectation values of 16 operators in 16 vectors,
+                   and the state-counting test's comparisons per second)
   cpu_baseline     the CPU oracle (operator application + hashing) on a
                    bounded sample of the same workload, nnz per second; under
                    "serve", the serving stream through CPU worker processes
@@ -185,6 +186,27 @@ def observables_rate(cib, ctx, cigen, name, nnz_half, m=16, nvec=16):
     basis.free()
     return {"operators": m, "vectors": nvec, "dtype": w.dtype, "wall_s": t, "per_operator_s": t / m,
             "pair_vec_per_s": m * nnz_full * nvec / t}
+
+
+def counting_rates(cib, ctx, cigen, n=1 << 17, N=8, reps=3):
+    """The state-counting test at the paper's density: n biased random states
+    of N particles in 128 single-particle states; state comparisons per second
+    (n^2 over the kernel's HIP-event time) for the three methods."""
+    import numpy as np
+    mbs = cigen.counting_states(n, n_particles=N, n_sp=128, tau=36.0, seed=8)
+    total, counts = cib.count_states(ctx, mbs, 128, 0)
+    out = {"n": n, "particles": N, "n_sp": 128, "tau": 36.0, "connected_pairs": total,
+           "median_density": float(np.median(counts)) / n}
+    for m, name in ((0, "hybrid"), (1, "tuples_only"), (2, "bits128")):
+        cib.count_states(ctx, mbs, 128, m, want_counts=False)     # warm
+        ctx.profile(True)
+        for _ in range(reps):
+            tot, _ = cib.count_states(ctx, mbs, 128, m, want_counts=False)
+            assert tot == total
+        k, t = ctx.kernel_time("state_count")
+        ctx.profile(False)
+        out[name] = {"comparisons_per_s": n * n / (t / k), "kernel_s": t / k}
+    return out
 
 
 def serve_run(cib, ctx, cigen, dtype, n_req, budget=0, rate=math.inf):
@@ -480,6 +502,7 @@ def main():
         ws[name] = workload_rates(cib, ctx, cigen, name, int(bb), copy_gbs=copy_gbs)
     sub["workloads"] = ws
     sub["observables"] = observables_rate(cib, ctx, cigen, w.name, nnz)
+    sub["state_count"] = counting_rates(cib, ctx, cigen)
     if not args.no_serve:
         try:
             sub.update(serve_suite(cib, ctx, cigen, args.serve_requests, sweep=not args.no_serve_sweep))

@@ -85,7 +85,7 @@ cib_status cib_ctx_bytes(const cib_ctx *ctx, int64_t *live_bytes, int64_t *peak_
  * (it synchronises those events).  Kernel names: "tile_screen",
  * "adjacency", "row_count", "scan", "row_fill", "spmm_sym", "gram",
  * "rayleigh_ritz", "update" (the build's row passes fill both stored
- * triangles).  Unknown names report zero launches. */
+ * triangles), "state_count".  Unknown names report zero launches. */
 cib_status cib_profile_enable(cib_ctx *ctx, int on);
 cib_status cib_profile_reset(cib_ctx *ctx);
 cib_status cib_profile_query(cib_ctx *ctx, const char *kernel, int64_t *launches, double *total_s);
@@ -226,6 +226,24 @@ cib_status cib_apply_H(cib_ctx *ctx, const cib_matrix *H, const void *X, int64_t
  * an operator's matrix does not fit. */
 cib_status cib_observables(cib_ctx *ctx, const cib_basis *basis, const cib_tables *ops, int32_t m,
                            cib_dtype dtype, const void *X, int64_t ldx, int32_t nvec, double *out);
+
+/* ------------------------------------------------------- state counting --
+ * The state-counting test (Sec. 2.1; Listing 2 as a description): for each
+ * of n many-body states, the number of states of the same list (itself
+ * included) that differ from it in at most two particles, i.e. the nonzeros
+ * of its row for a two-body operator.  mbs: device, n x n_particles uint16
+ * single-particle indices, state-major, each row strictly ascending and
+ * below n_sp (the index-tuple representation).  method: 0 = hybrid (bit
+ * string of the lowest 64 single-particle states as a prefilter, then
+ * count_difference on the tuples), 1 = count_difference on the tuples only,
+ * 2 = popcount of the full 128-bit bit strings (n_sp <= 128); all three give
+ * the same counts.  counts: device int32[n] or NULL; total: host, the sum.
+ * Synchronous.  Errors: CIB_E_INVALID for NULL mbs/total, n outside
+ * 1..2^22, n_particles outside 1..20, n_sp outside n_particles..65534, a bad
+ * method, or method 2 with n_sp > 128.  Rows that are not ascending or hold
+ * repeated indices give meaningless counts (no other effect). */
+cib_status cib_count_states(cib_ctx *ctx, const uint16_t *mbs, int64_t n, int32_t n_particles, int32_t n_sp,
+                            int32_t method, int32_t *counts, int64_t *total);
 
 /* --------------------------------------------------------------- LOBPCG --
  * Lowest nev eigenpairs of H (Fig. 1 step 15) by block LOBPCG with block size

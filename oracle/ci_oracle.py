@@ -369,13 +369,14 @@ def count_difference(s1, s2):
     return 2 * max(only1, only2)
 
 
-def count_connected(mbs, n_sp):
+def count_connected(mbs, n_sp, rows=None):
     """The state-counting test (Sec. 2.1, Listing 2 as a description): for
     each state i of the list, the number of states j (j = i included) that a
     two-body operator connects, i.e. that differ from it in at most two
     particles: popcount(BIN_i xor BIN_j) <= 4 with BIN the full bit string
     of the state over all n_sp single-particle states.  mbs: (n, N) index
-    tuples.  Returns int64 counts per state (numpy, blocks of rows)."""
+    tuples; rows: the states to count for (default all), each against the
+    whole list.  Returns int64 counts (numpy, blocks of rows)."""
     mbs = np.asarray(mbs, dtype=np.int64)
     n = mbs.shape[0]
     nw = max(1, -(-n_sp // 64))
@@ -385,11 +386,13 @@ def count_connected(mbs, n_sp):
         for q in range(nw):
             sel = w == q
             words[sel, q] |= np.left_shift(np.uint64(1), b[sel])
-    counts = np.zeros(n, dtype=np.int64)
-    for i0 in range(0, n, 256):
-        d = np.zeros((min(256, n - i0), n), dtype=np.int64)
+    rows = np.arange(n) if rows is None else np.asarray(rows, dtype=np.int64)
+    counts = np.zeros(len(rows), dtype=np.int64)
+    for i0 in range(0, len(rows), 256):
+        r = rows[i0:i0 + 256]
+        d = np.zeros((len(r), n), dtype=np.int64)
         for q in range(nw):
-            d += np.bitwise_count(words[i0:i0 + 256, q][:, None] ^ words[None, :, q])
+            d += np.bitwise_count(words[r, q][:, None] ^ words[None, :, q])
         counts[i0:i0 + 256] = (d <= 4).sum(axis=1)
     return counts
 

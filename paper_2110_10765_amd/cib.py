@@ -40,7 +40,7 @@ EXPORTS = [
     "cib_upload_interaction", "cib_interaction_free",
     "cib_build_H", "cib_build_H_resident", "cib_matrix_info", "cib_matrix_stats",
     "cib_matrix_export", "cib_matrix_device", "cib_matrix_free",
-    "cib_apply_H", "cib_observables", "cib_lobpcg", "cib_serve",
+    "cib_apply_H", "cib_observables", "cib_count_states", "cib_lobpcg", "cib_serve",
 ]
 
 
@@ -146,6 +146,7 @@ def load(path: str = LIB_PATH):
         "cib_matrix_free": ([vp], None),
         "cib_apply_H": ([vp, vp, vp, i64, vp, i64, i32], i32),
         "cib_observables": ([vp, vp, vp, i32, i32, vp, i64, i32, vp], i32),
+        "cib_count_states": ([vp, vp, i64, i32, i32, i32, vp, P(i64)], i32),
         "cib_lobpcg": ([vp, vp, P(LobpcgOptsC), vp, vp, i64, P(LobpcgInfoC)], i32),
         "cib_serve": ([vp, P(RequestC), i32, P(ServeOptsC), P(ResultC)], i32),
     }
@@ -415,6 +416,25 @@ def observables(ctx: Context, basis: Basis, tables_list, X):
                                   _dtype_code(X.dtype), X.data_ptr(), X.stride(0), X.shape[1],
                                   out.ctypes.data))
     return out
+
+
+def count_states(ctx: Context, mbs, n_sp: int, method: int = 0, want_counts: bool = True):
+    """State-counting test on an (n, N) array of ascending uint16 index
+    tuples (numpy, copied to the device): (total, per-state counts as numpy
+    int32 or None).  method 0 = hybrid, 1 = tuples only, 2 = 128-bit bit
+    strings."""
+    import numpy as np
+    import torch
+    mbs = np.ascontiguousarray(mbs, dtype=np.uint16)
+    n, N = mbs.shape
+    dev = torch.device("cuda", ctx.device)
+    m = torch.from_numpy(mbs.view(np.int16)).to(dev)
+    c = torch.empty(n, dtype=torch.int32, device=dev) if want_counts else None
+    torch.cuda.current_stream(dev).synchronize()
+    total = ctypes.c_int64()
+    _check(load().cib_count_states(ctx.h, m.data_ptr(), n, N, n_sp, method,
+                                   c.data_ptr() if c is not None else None, ctypes.byref(total)))
+    return total.value, (c.cpu().numpy() if c is not None else None)
 
 
 def lobpcg(ctx: Context, H: Matrix, nev: int, block: int = 8, max_iter: int = 500, tol: float = 0.0,

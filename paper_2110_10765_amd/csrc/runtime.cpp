@@ -90,7 +90,8 @@ static TransLayout trans_layout(const Orbs &oa, const Orbs &ob) {
 }
 
 const char *const kKernelNames[K_NKERN] = {"tile_screen", "adjacency", "row_count", "scan",
-                                           "row_fill", "spmm_sym", "gram", "rayleigh_ritz", "update"};
+                                           "row_fill", "spmm_sym", "gram", "rayleigh_ritz", "update",
+                                           "state_count"};
 
 static hipEvent_t take_event(cib_ctx *c) {
   if (!c->event_pool.empty()) {
