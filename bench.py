@@ -105,6 +105,26 @@ def measure_spmm(cib, ctx, H, b, reps):
     return t / max(n, 1)
 
 
+def measure_apply_free(cib, ctx, basis, inter, dtype, b, reps=5):
+    """Matrix-free Y = H X (screens + values + apply pass, nothing stored):
+    wall time per call, and the HIP-event time of the apply pass alone."""
+    import torch
+    dt = torch.float64 if dtype == "f64" else torch.float32
+    X = torch.randn(basis.dim, b, dtype=dt, device="cuda:0")
+    Y = torch.empty_like(X)
+    cib.apply_H_free(ctx, basis, inter, X, Y)
+    _sync()
+    ctx.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        cib.apply_H_free(ctx, basis, inter, X, Y)
+    _sync()
+    wall = (time.perf_counter() - t0) / reps
+    n, t = ctx.kernel_time("apply_free")
+    ctx.profile(False)
+    return wall, t / max(n, 1)
+
+
 def measure_copy_gbs(reps=5):
     """Device-to-device copy of 1 GiB (torch), bytes read + written per
     second: the measured bandwidth the HBM fractions are also quoted against."""
@@ -157,6 +177,11 @@ def workload_rates(cib, ctx, cigen, name, b, reps=20, copy_gbs=None):
             # brute-force screen compares) per second of screen + count
             "screen_pairs_per_s": H.dim * (H.dim + 1) / 2 / (st["t_screen_s"] + st["t_count_s"]),
         }
+        if b in (8, 16):
+            wall, tpass = measure_apply_free(cib, ctx, basis, inter, dt, b)
+            out[dt]["apply_free_wall_s"] = wall
+            out[dt]["apply_free_pass_s"] = tpass
+            out[dt]["apply_free_nnz_vec_per_s"] = nnz_full * b / wall
         if copy_gbs:
             out[dt]["fill_copy_frac"] = _fill_bytes(H.nnz, H.dim, sv) / st["t_fill_s"] / 1e9 / copy_gbs
             out[dt]["spmm_copy_frac"] = _spmm_bytes(H.nnz, H.dim, b, sv) / t_spmm / 1e9 / copy_gbs

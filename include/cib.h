@@ -85,7 +85,8 @@ cib_status cib_ctx_bytes(const cib_ctx *ctx, int64_t *live_bytes, int64_t *peak_
  * (it synchronises those events).  Kernel names: "tile_screen",
  * "adjacency", "row_count", "scan", "row_fill", "spmm_sym", "gram",
  * "rayleigh_ritz", "update" (the build's row passes fill both stored
- * triangles), "state_count".  Unknown names report zero launches. */
+ * triangles), "state_count", "apply_free" (the matrix-free product's row
+ * pass).  Unknown names report zero launches. */
 cib_status cib_profile_enable(cib_ctx *ctx, int on);
 cib_status cib_profile_reset(cib_ctx *ctx);
 cib_status cib_profile_query(cib_ctx *ctx, const char *kernel, int64_t *launches, double *total_s);
@@ -209,6 +210,23 @@ void cib_matrix_free(cib_matrix *H);
  * call gives the same bits. */
 cib_status cib_apply_H(cib_ctx *ctx, const cib_matrix *H, const void *X, int64_t ldx, void *Y,
                        int64_t ldy, int32_t nvec);
+
+/* ----------------------------------------------------- matrix-free H X --
+ * Y = H X without storing H (the multiply variant of the generic loop of
+ * Fig. 2: compare, compute, multiply with the vector elements), for bases
+ * whose matrix does not fit: H is given by the basis and the interaction
+ * uploaded for it, the screens and per-entry values are computed as by
+ * cib_build_H_resident, and one row pass multiplies every entry into X.
+ * Matrix values are rounded to `dtype` as the stored matrix's are; the sum
+ * order differs from cib_apply_H, so the two agree to rounding.  X, Y:
+ * device arrays of `dtype`, D rows, row-major, nvec = 8 or 16 columns,
+ * rows 16-byte aligned (X, Y and ldx * size, ldy * size multiples of 16).
+ * Device memory: the screens (a small fraction of the matrix).  Returns when
+ * Y is written.  Errors: CIB_E_INVALID for NULL pointers, a bad dtype,
+ * nvec, leading dimension or alignment, an interaction of another orbital
+ * set or a basis of another context. */
+cib_status cib_apply_H_free(cib_ctx *ctx, const cib_basis *basis, const cib_interaction *it, cib_dtype dtype,
+                            const void *X, int64_t ldx, void *Y, int64_t ldy, int32_t nvec);
 
 /* ---------------------------------------------------------- observables --
  * Expectation values after the eigensolve (Fig. 1 steps 16-20):

@@ -40,7 +40,7 @@ EXPORTS = [
     "cib_upload_interaction", "cib_interaction_free",
     "cib_build_H", "cib_build_H_resident", "cib_matrix_info", "cib_matrix_stats",
     "cib_matrix_export", "cib_matrix_device", "cib_matrix_free",
-    "cib_apply_H", "cib_observables", "cib_count_states", "cib_lobpcg", "cib_serve",
+    "cib_apply_H", "cib_apply_H_free", "cib_observables", "cib_count_states", "cib_lobpcg", "cib_serve",
 ]
 
 
@@ -146,6 +146,7 @@ def load(path: str = LIB_PATH):
         "cib_matrix_free": ([vp], None),
         "cib_apply_H": ([vp, vp, vp, i64, vp, i64, i32], i32),
         "cib_observables": ([vp, vp, vp, i32, i32, vp, i64, i32, vp], i32),
+        "cib_apply_H_free": ([vp, vp, vp, i32, vp, i64, vp, i64, i32], i32),
         "cib_count_states": ([vp, vp, i64, i32, i32, i32, vp, P(i64)], i32),
         "cib_lobpcg": ([vp, vp, P(LobpcgOptsC), vp, vp, i64, P(LobpcgInfoC)], i32),
         "cib_serve": ([vp, P(RequestC), i32, P(ServeOptsC), P(ResultC)], i32),
@@ -394,6 +395,26 @@ def apply_H(ctx: Context, H: Matrix, X, Y=None):
     cur.wait_stream(ctx.stream)          # later torch work sees Y
     X.record_stream(ctx.stream)
     Y.record_stream(ctx.stream)
+    return Y
+
+
+def apply_H_free(ctx: Context, basis: Basis, inter: Interaction, X, Y=None):
+    """Matrix-free Y = H X for H given by (basis, uploaded interaction);
+    X, Y torch device tensors (D x nvec, row-major, nvec 8 or 16, float64 or
+    float32: the dtype H is evaluated in)."""
+    import torch
+    if X.dtype not in (torch.float64, torch.float32) or X.dim() != 2 or X.shape[0] != basis.dim \
+            or X.stride(1) != 1:
+        raise ValueError("X must be a (D, nvec) float64 or float32 tensor with unit column stride")
+    if Y is None:
+        Y = torch.empty_like(X)
+    if Y.dtype != X.dtype or Y.shape != X.shape or Y.stride(1) != 1:
+        raise ValueError("Y must match X")
+    cur = torch.cuda.current_stream(X.device)
+    ctx.stream.wait_stream(cur)
+    _check(load().cib_apply_H_free(ctx.h, basis.h, inter.h, _dtype_code(X.dtype), X.data_ptr(), X.stride(0),
+                                   Y.data_ptr(), Y.stride(0), X.shape[1]))
+    cur.wait_stream(ctx.stream)
     return Y
 
 

@@ -319,6 +319,26 @@ cib_status cib_observables(cib_ctx *ctx, const cib_basis *b, const cib_tables *o
   });
 }
 
+// -------------------------------------------------------- matrix-free H X
+cib_status cib_apply_H_free(cib_ctx *ctx, const cib_basis *b, const cib_interaction *it, cib_dtype dt,
+                            const void *X, int64_t ldx, void *Y, int64_t ldy, int32_t nvec) {
+  return guarded([&] {
+    CIB_REQUIRE(ctx && b && it && X && Y, CIB_E_INVALID, "NULL argument");
+    CIB_REQUIRE(dt == CIB_F64 || dt == CIB_F32, CIB_E_INVALID, "dtype must be CIB_F64 or CIB_F32");
+    CIB_REQUIRE(nvec == 8 || nvec == 16, CIB_E_INVALID, "nvec must be 8 or 16");
+    CIB_REQUIRE(ldx >= nvec && ldy >= nvec, CIB_E_INVALID, "leading dimension smaller than nvec");
+    const size_t sv = dt == CIB_F64 ? 8 : 4;
+    CIB_REQUIRE((uintptr_t)X % 16 == 0 && (uintptr_t)Y % 16 == 0 && (ldx * sv) % 16 == 0 && (ldy * sv) % 16 == 0,
+                CIB_E_INVALID, "X and Y rows must be 16-byte aligned");
+    CIB_REQUIRE(it->nA == b->plan.oA.n_orb && it->nB == (b->plan.ns == 2 ? b->plan.oB.n_orb : 0),
+                CIB_E_INVALID, "interaction was uploaded for another orbital set");
+    CIB_REQUIRE(b->ctx == ctx, CIB_E_INVALID, "basis belongs to another context");
+    BusyGuard busy(ctx);
+    DeviceGuard g(ctx->device);
+    apply_matrix_free(ctx, *b, *it, dt, ApplyReq{X, ldx, Y, ldy, nvec}, ctx->stream);
+  });
+}
+
 // -------------------------------------------------------- state counting
 cib_status cib_count_states(cib_ctx *ctx, const uint16_t *mbs, int64_t n, int32_t n_particles, int32_t n_sp,
                             int32_t method, int32_t *counts, int64_t *total) {

@@ -17,6 +17,7 @@
 #include <algorithm>
 #include <functional>
 #include <initializer_list>
+#include <type_traits>
 
 #include "cib_internal.hpp"
 #include "device_common.hpp"
@@ -508,12 +509,50 @@ struct RowArgs {
   void *val;
 };
 
+// Where a fill pass sends each entry (column j, value v): NoAcc stores it in
+// the CSR arrays; ApplyAcc multiplies it into row j of X (the matrix-free
+// product, rounding v to T as the stored matrix would) and keeps the sums of
+// the lane's entries in registers.
+struct NoAcc {
+  static constexpr bool kApply = false;
+  __device__ __forceinline__ void add(int32_t, double) {}
+};
+
+template <typename T, int NV>
+struct ApplyAcc {
+  static constexpr bool kApply = true;
+  using V = typename std::conditional<sizeof(T) == 8, double2, float4>::type;
+  static constexpr int PER = 16 / sizeof(T), NL = NV / PER;   // values per load, loads per row
+  const T *X;
+  int64_t ldx;
+  T a[NV];
+  __device__ __forceinline__ void add(int32_t j, double v) {
+    const T h = (T)v;
+    const V *x = reinterpret_cast<const V *>(X + (int64_t)j * ldx);
+    V xv[NL];
+#pragma unroll
+    for (int l = 0; l < NL; ++l) xv[l] = x[l];
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+      if constexpr (sizeof(T) == 8) {
+        a[2 * l] += h * xv[l].x;
+        a[2 * l + 1] += h * xv[l].y;
+      } else {
+        a[4 * l] += h * xv[l].x;
+        a[4 * l + 1] += h * xv[l].y;
+        a[4 * l + 2] += h * xv[l].z;
+        a[4 * l + 3] += h * xv[l].w;
+      }
+    }
+  }
+};
+
 // Diagonal A-block part of a row: Lsame(beta) entries [e0, e1) in position
 // order, kept while position < len(alpha) (a prefix).
-template <int W, bool FILL, typename T>
+template <int W, bool FILL, typename T, class Acc>
 __device__ __forceinline__ void row_diag(const RowArgs &g, int64_t i, int64_t e0, int64_t e1, int alpha,
                                          int len_a, int64_t off_a, const uint64_t *ab, const SpecIdx &sa_idx,
-                                         int64_t out, int64_t &cnt) {
+                                         int64_t out, int64_t &cnt, Acc &acc) {
   const int lane = lane_id();
   T *val = static_cast<T *>(g.val);
   for (int64_t k0 = e0; k0 < e1; k0 += kWave) {
@@ -537,8 +576,12 @@ __device__ __forceinline__ void row_diag(const RowArgs &g, int64_t i, int64_t e0
         v += s * spec_sum<W>(sa_idx, ab, g.it.arb, g.it.nA, [&](int32_t r) { return vt_at(g.it, r, bc); });
       }
       const int64_t o = out + cnt + (k - k0);
-      g.col[o] = (int32_t)(off_a + pos);
-      val[o] = (T)v;
+      if constexpr (Acc::kApply) {
+        acc.add((int32_t)(off_a + pos), v);
+      } else {
+        g.col[o] = (int32_t)(off_a + pos);
+        val[o] = (T)v;
+      }
     }
     cnt += __popcll(m);
     if (m != ballot(valid)) break;
@@ -565,10 +608,10 @@ struct L1View {
 // a kA = 2 tile holds at most one entry (same B position), a kA = 1 tile the
 // prefix of beta's L1 list for the tile's 2M_B list with position < len.
 // kA = 1 entries are expanded over all lanes of the wave.
-template <int W, bool FILL, typename T, bool ST>
+template <int W, bool FILL, typename T, bool ST, class Acc>
 __device__ __forceinline__ void row_tiles(const RowArgs &g, int64_t t0, int64_t t1, int p, const uint64_t *bb,
                                           const SpecIdx &sb_idx, int64_t out, int64_t &cnt, const L1View<ST> &L,
-                                          int32_t *mark) {
+                                          int32_t *mark, Acc &acc) {
   const int lane = lane_id();
   T *val = static_cast<T *>(g.val);
   // the tile data of a batch of 64 is read together, one batch ahead of its
@@ -619,8 +662,12 @@ __device__ __forceinline__ void row_tiles(const RowArgs &g, int64_t t0, int64_t 
       const int32_t coff = ne ? cur.off : 0, rb = (!two && ne) ? cur.rb : 0;
       const double tv = ne ? cur.val : 0.0;
       if (two && ne) {
-        g.col[out + cnt + orel] = coff + p;
-        val[out + cnt + orel] = (T)tv;
+        if constexpr (Acc::kApply) {
+          acc.add(coff + p, tv);
+        } else {
+          g.col[out + cnt + orel] = coff + p;
+          val[out + cnt + orel] = (T)tv;
+        }
       }
       // kA = 1 entries, spread over the lanes
       const int n1 = two ? 0 : ne;
@@ -661,38 +708,26 @@ __device__ __forceinline__ void row_tiles(const RowArgs &g, int64_t t0, int64_t 
           const double sb = (li >> 2) & 1 ? -1.0 : 1.0;
           v = sa * sb * vt_at(g.it, orb, li >> 3);
         }
-        g.col[out + cnt + oo + q] = ocoff + lp;
-        val[out + cnt + oo + q] = (T)v;
+        if constexpr (Acc::kApply) {
+          acc.add(ocoff + lp, v);
+        } else {
+          g.col[out + cnt + oo + q] = ocoff + lp;
+          val[out + cnt + oo + q] = (T)v;
+        }
       }
     }
     cnt += total;
   }
 }
 
-// One wave per row i = (alpha, p), both stored triangles: g holds the upper
-// tiles and outputs, gl the lower ones.  Upper row (j >= i): the diagonal
-// A-block from beta itself on (positions < len(alpha)), then tiles
-// alpha' > alpha.  Lower row (j < i): tiles alpha' < alpha, then the
-// diagonal A-block entries before beta.  Both lists come out in ascending
-// column order.  The row's preamble, its spectator slots and beta's L1 list
-// (at most a few hundred entries for these bases, copied to LDS so the
-// per-tile binary searches and the expansion read it there) serve both
-// triangles; one pass over both measured 6-8% faster than one per triangle.
-// Eight waves per SIMD (the most the hardware holds) are asked for
-// explicitly: the pass waits on chains of dependent reads, and the scalar
-// registers the compiler would otherwise keep cap it at seven (measured 12%
-// slower).
-template <int W, bool FILL, typename T>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_row_pass(RowArgs g, RowArgs gl) {
+// Body of the row passes (count, fill, matrix-free apply) for row i, wave wv
+// of the workgroup; the kernels below describe the enumeration.
+template <int W, bool FILL, typename T, class Acc>
+__device__ __forceinline__ void row_pass(const RowArgs &g, const RowArgs &gl, int64_t i, int wv, Acc &acc) {
   __shared__ int32_t s_pos[4][kL1Stage], s_info[4][FILL ? kL1Stage : 1], s_seg[4][kMaxSeg + 2];
   __shared__ int32_t s_mark[4][FILL ? kWave : 1];
   __shared__ __align__(16) int32_t s_spec[4][FILL ? 2 * kSpec : 1];
-  // plain block order: rows of very different lengths sit in runs, and
-  // giving each XCD one contiguous range of rows (for L2 locality of the
-  // tile lists) measured 30-40% slower from the imbalance between XCDs
-  const int wv = uni((int)(threadIdx.x >> 6)), lane = lane_id();
-  const int64_t i = (int64_t)blockIdx.x * (blockDim.x / kWave) + wv;
-  if (i >= g.D) return;
+  const int lane = lane_id();
   const int alpha = uni(g.row_a[i]), p = uni(g.row_p[i]);
   const int beta = uni(g.row_b[i]);
   const int len_a = uni(g.a_len[alpha]);
@@ -711,7 +746,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
       sb_idx = spec_idx<W>(bb, g.it.bcol, g.it.nB, s_spec[wv] + kSpec);
     }
   }
-  const int64_t out_u = FILL ? uni(g.row_ptr[i]) : 0, out_l = FILL ? uni(gl.row_ptr[i]) : 0;
+  // the CSR offsets of the row (a matrix-free product stores nothing)
+  constexpr bool kStore = FILL && !Acc::kApply;
+  const int64_t out_u = kStore ? uni(g.row_ptr[i]) : 0, out_l = kStore ? uni(gl.row_ptr[i]) : 0;
   const int64_t l1b = (int64_t)beta * g.nseg;
   const int64_t base = uni(g.l1_seg[l1b]);
   const int64_t n1 = uni(g.l1_seg[l1b + g.nseg]) - base;
@@ -729,20 +766,77 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
     for (int h = lane; h <= g.nseg; h += kWave) s_seg[wv][h] = (int32_t)(g.l1_seg[l1b + h] - base);
     wave_lds_sync();
     const L1View<true> L{s_seg[wv], nullptr, 0, s_pos[wv], FILL ? s_info[wv] : nullptr};
-    row_diag<W, FILL, T>(g, i, ls_me, ls_hi, alpha, len_a, off_a, ab, sa_idx, out_u, cu);
-    row_tiles<W, FILL, T, true>(g, t0u, t1u, p, bb, sb_idx, out_u, cu, L, s_mark[wv]);
-    row_tiles<W, FILL, T, true>(gl, t0l, t1l, p, bb, sb_idx, out_l, cl, L, s_mark[wv]);
-    row_diag<W, FILL, T>(gl, i, ls_lo, ls_me, alpha, len_a, off_a, ab, sa_idx, out_l, cl);
+    row_diag<W, FILL, T>(g, i, ls_me, ls_hi, alpha, len_a, off_a, ab, sa_idx, out_u, cu, acc);
+    row_tiles<W, FILL, T, true>(g, t0u, t1u, p, bb, sb_idx, out_u, cu, L, s_mark[wv], acc);
+    row_tiles<W, FILL, T, true>(gl, t0l, t1l, p, bb, sb_idx, out_l, cl, L, s_mark[wv], acc);
+    row_diag<W, FILL, T>(gl, i, ls_lo, ls_me, alpha, len_a, off_a, ab, sa_idx, out_l, cl, acc);
   } else {
     const L1View<false> L{nullptr, g.l1_seg + l1b, base, g.l1_pos + base, FILL ? g.l1_info + base : nullptr};
-    row_diag<W, FILL, T>(g, i, ls_me, ls_hi, alpha, len_a, off_a, ab, sa_idx, out_u, cu);
-    row_tiles<W, FILL, T, false>(g, t0u, t1u, p, bb, sb_idx, out_u, cu, L, s_mark[wv]);
-    row_tiles<W, FILL, T, false>(gl, t0l, t1l, p, bb, sb_idx, out_l, cl, L, s_mark[wv]);
-    row_diag<W, FILL, T>(gl, i, ls_lo, ls_me, alpha, len_a, off_a, ab, sa_idx, out_l, cl);
+    row_diag<W, FILL, T>(g, i, ls_me, ls_hi, alpha, len_a, off_a, ab, sa_idx, out_u, cu, acc);
+    row_tiles<W, FILL, T, false>(g, t0u, t1u, p, bb, sb_idx, out_u, cu, L, s_mark[wv], acc);
+    row_tiles<W, FILL, T, false>(gl, t0l, t1l, p, bb, sb_idx, out_l, cl, L, s_mark[wv], acc);
+    row_diag<W, FILL, T>(gl, i, ls_lo, ls_me, alpha, len_a, off_a, ab, sa_idx, out_l, cl, acc);
   }
   if (!FILL && lane == 0) {
     g.rcnt[i] = (int32_t)cu;
     gl.rcnt[i] = (int32_t)cl;
+  }
+}
+
+// One wave per row i = (alpha, p), both stored triangles: g holds the upper
+// tiles and outputs, gl the lower ones.  Upper row (j >= i): the diagonal
+// A-block from beta itself on (positions < len(alpha)), then tiles
+// alpha' > alpha.  Lower row (j < i): tiles alpha' < alpha, then the
+// diagonal A-block entries before beta.  Both lists come out in ascending
+// column order.  The row's preamble, its spectator slots and beta's L1 list
+// (at most a few hundred entries for these bases, copied to LDS so the
+// per-tile binary searches and the expansion read it there) serve both
+// triangles; one pass over both measured 6-8% faster than one per triangle.
+// Eight waves per SIMD (the most the hardware holds) are asked for
+// explicitly: the pass waits on chains of dependent reads, and the scalar
+// registers the compiler would otherwise keep cap it at seven (measured 12%
+// slower).
+template <int W, bool FILL, typename T>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_row_pass(RowArgs g, RowArgs gl) {
+  // plain block order: rows of very different lengths sit in runs, and
+  // giving each XCD one contiguous range of rows (for L2 locality of the
+  // tile lists) measured 30-40% slower from the imbalance between XCDs
+  const int wv = uni((int)(threadIdx.x >> 6));
+  const int64_t i = (int64_t)blockIdx.x * (blockDim.x / kWave) + wv;
+  if (i >= g.D) return;
+  NoAcc acc;
+  row_pass<W, FILL, T>(g, gl, i, wv, acc);
+}
+
+// Matrix-free product Y = H X (the FMA variant of Fig. 2: compare, compute
+// and multiply without storing H): the fill pass's enumeration of row i,
+// every entry multiplied into its row of X; the lanes' sums are combined by
+// a fixed butterfly and lane 0 writes row i of Y.  X and Y rows of NV values
+// (8 or 16), 16-byte aligned.
+template <int W, typename T, int NV>
+__global__ __launch_bounds__(256) void k_row_apply(RowArgs g, RowArgs gl, const T *X, int64_t ldx, T *Y,
+                                                   int64_t ldy) {
+  const int wv = uni((int)(threadIdx.x >> 6));
+  const int64_t i = (int64_t)blockIdx.x * (blockDim.x / kWave) + wv;
+  if (i >= g.D) return;
+  ApplyAcc<T, NV> acc;
+  acc.X = X;
+  acc.ldx = ldx;
+#pragma unroll
+  for (int u = 0; u < NV; ++u) acc.a[u] = T(0);
+  row_pass<W, true, T>(g, gl, i, wv, acc);
+#pragma unroll
+  for (int u = 0; u < NV; ++u)
+#pragma unroll
+    for (int d = kWave / 2; d > 0; d >>= 1) acc.a[u] += __shfl_xor(acc.a[u], d, kWave);
+  if (lane_id() == 0) {
+    using V = typename ApplyAcc<T, NV>::V;
+    V *y = reinterpret_cast<V *>(Y + i * ldy);
+#pragma unroll
+    for (int l = 0; l < ApplyAcc<T, NV>::NL; ++l) {
+      if constexpr (sizeof(T) == 8) y[l] = V{acc.a[2 * l], acc.a[2 * l + 1]};
+      else y[l] = V{acc.a[4 * l], acc.a[4 * l + 1], acc.a[4 * l + 2], acc.a[4 * l + 3]};
+    }
   }
 }
 
@@ -973,9 +1067,19 @@ struct Events {
 // The upper half (the product) and the strictly lower copy (read by the
 // SpMM) are built by the same passes side by side, so the host waits twice:
 // once for the sizes of the screens' lists, once for the two nonzero counts.
+template <int W, typename T, int NV>
+static void launch_apply(unsigned rblk, const RowArgs &ra, const RowArgs &rl, const ApplyReq &a, hipStream_t s) {
+  hipLaunchKernelGGL((k_row_apply<W, T, NV>), dim3(rblk), dim3(256), 0, s, ra, rl, static_cast<const T *>(a.X),
+                     a.ldx, static_cast<T *>(a.Y), a.ldy);
+}
+
+// The build (ap == nullptr): screens, counts, offsets, fill into H.  With
+// ap: the screens, then the matrix-free product Y = H X instead of a matrix
+// (H is not touched).
 template <int W>
 static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr, cib_dtype dt,
-                    cib_matrix &H, hipStream_t s, const std::function<void(int64_t)> &before_fill) {
+                    cib_matrix &H, hipStream_t s, const std::function<void(int64_t)> &before_fill,
+                    const ApplyReq *ap = nullptr) {
   const Plan &p = b.plan;
   const DevInter it = itr.view();
   const int nA = p.nA(), nB = p.nB(), nseg = p.nseg();
@@ -1084,6 +1188,25 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
   rl.rcnt = rlcnt.p;
   const unsigned rblk = (unsigned)((p.D + 3) / 4);
   DBuf<double> diag(ctx, p.D);
+  if (ap) {
+    hipLaunchKernelGGL((k_state_diag<W>), dim3((unsigned)((p.D + 255) / 256)), dim3(256), 0, s, p.D,
+                       b.row_a.p, b.row_p.p, b.a_seg.p, b.bseg_start.p, b.a_bits.p, nA, b.b_bits.p, nB,
+                       eA.p, eB.p, it, diag.p);
+    ra.diag = rl.diag = diag.p;
+    {
+      KTimer kt(ctx, K_APPLY_FREE, s);
+      if (dt == CIB_F64) {
+        if (ap->nvec == 8) launch_apply<W, double, 8>(rblk, ra, rl, *ap, s);
+        else launch_apply<W, double, 16>(rblk, ra, rl, *ap, s);
+      } else {
+        if (ap->nvec == 8) launch_apply<W, float, 8>(rblk, ra, rl, *ap, s);
+        else launch_apply<W, float, 16>(rblk, ra, rl, *ap, s);
+      }
+    }
+    CIB_HIP(hipGetLastError());
+    CIB_HIP(hipStreamSynchronize(s));   // the screens are freed on return
+    return;
+  }
   {
     KTimer kt(ctx, K_ROW_COUNT, s);
     hipLaunchKernelGGL((k_row_pass<W, false, double>), dim3(rblk), dim3(256), 0, s, ra, rl);
@@ -1150,6 +1273,17 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
   H.stats.t_total_s = H.stats.t_screen_s + H.stats.t_count_s + H.stats.t_scan_s + H.stats.t_fill_s;
   H.stats.n_tiles = n_tiles;
   H.stats.n_adjacent = n_ls + n_l1;
+}
+
+void apply_matrix_free(cib_ctx *ctx, const cib_basis &b, const cib_interaction &it, cib_dtype dt,
+                       const ApplyReq &a, hipStream_t s) {
+  cib_matrix unused;
+  unused.ctx = ctx;
+  switch (b.plan.W) {
+    case 1: build_w<1>(ctx, b, it, dt, unused, s, nullptr, &a); break;
+    case 2: build_w<2>(ctx, b, it, dt, unused, s, nullptr, &a); break;
+    default: build_w<3>(ctx, b, it, dt, unused, s, nullptr, &a); break;
+  }
 }
 
 void build_matrix(cib_ctx *ctx, const cib_basis &b, const cib_interaction &it, cib_dtype dt,

@@ -75,7 +75,7 @@ struct cib_ctx {
 namespace cib {
 
 // Hot kernels known to the profiler.
-enum KernelId { K_TILE = 0, K_ADJ, K_ROW_COUNT, K_SCAN, K_ROW_FILL, K_SPMM, K_GRAM, K_RR, K_UPDATE, K_COUNT, K_NKERN };
+enum KernelId { K_TILE = 0, K_ADJ, K_ROW_COUNT, K_SCAN, K_ROW_FILL, K_SPMM, K_GRAM, K_RR, K_UPDATE, K_COUNT, K_APPLY_FREE, K_NKERN };
 extern const char *const kKernelNames[K_NKERN];
 
 // Brackets one launch with events when profiling is on (RAII).
@@ -258,6 +258,18 @@ cib_interaction *upload_interaction(cib_ctx *ctx, const cib_basis &b, const cib_
 
 void spmm_sym(const cib_matrix &H, const void *X, int64_t ldx, void *Y, int64_t ldy, int nvec,
               hipStream_t s);
+// Matrix-free Y = H X (nvec 8 or 16, 16-byte aligned rows of the dtype):
+// the build's screens and values, then one row pass that multiplies every
+// entry into X instead of storing it.  Returns when Y is written.
+struct ApplyReq {
+  const void *X;
+  int64_t ldx;
+  void *Y;
+  int64_t ldy;
+  int nvec;
+};
+void apply_matrix_free(cib_ctx *ctx, const cib_basis &b, const cib_interaction &it, cib_dtype dt,
+                       const ApplyReq &a, hipStream_t s);
 // State-counting test: per-state counts of states within two particle
 // differences (device counts, optional) and their total (host).
 void count_pairs(cib_ctx *ctx, const uint16_t *mbs, int64_t n, int N, int method, int32_t *counts, int64_t *total,

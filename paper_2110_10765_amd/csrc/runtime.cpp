@@ -91,7 +91,7 @@ static TransLayout trans_layout(const Orbs &oa, const Orbs &ob) {
 
 const char *const kKernelNames[K_NKERN] = {"tile_screen", "adjacency", "row_count", "scan",
                                            "row_fill", "spmm_sym", "gram", "rayleigh_ritz", "update",
-                                           "state_count"};
+                                           "state_count", "apply_free"};
 
 static hipEvent_t take_event(cib_ctx *c) {
   if (!c->event_pool.empty()) {
