@@ -21,7 +21,8 @@ float64 Gram / Rayleigh-Ritz / update).  Printed as one JSON line:
   roofline         the kernel that dominates the step, its algorithmic bytes
                    per launch over its mean HIP-event duration vs 8 TB/s
                    (also: expectation values of 16 operators in 16 vectors,
-                   and the state-counting test's comparisons per second)
+                   the state-counting test's comparisons per second, and the
+                   same eigenpairs by Lanczos)
   cpu_baseline     the CPU oracle (operator application + hashing) on a
                    bounded sample of the same workload, nnz per second; under
                    "serve", the serving stream through CPU worker processes
@@ -211,6 +212,23 @@ def observables_rate(cib, ctx, cigen, name, nnz_half, m=16, nvec=16):
     basis.free()
     return {"operators": m, "vectors": nvec, "dtype": w.dtype, "wall_s": t, "per_operator_s": t / m,
             "pair_vec_per_s": m * nnz_full * nvec / t}
+
+
+def lanczos_rate(cib, ctx, cigen, w, inter, max_iter=1000):
+    """The workload's lowest nev eigenpairs by Lanczos with full
+    reorthogonalisation (the same H build, tolerance and nev as the LOBPCG
+    step): steps, wall time of the solve, device time of its products."""
+    basis = cib.build_basis(ctx, w.spec)
+    H = cib.build_H(ctx, basis, inter, w.dtype)
+    cib.lanczos(ctx, H, w.nev, max_iter=max_iter)           # warm
+    _sync()
+    t0 = time.perf_counter()
+    ev, info, _ = cib.lanczos(ctx, H, w.nev, max_iter=max_iter)
+    wall = time.perf_counter() - t0
+    H.free()
+    basis.free()
+    return {"nev": w.nev, "steps": info["iters"], "status": info["status"], "solve_s": wall,
+            "spmv_s": info["t_spmv_s"], "lowest_eigenvalues": ev.tolist()}
 
 
 def counting_rates(cib, ctx, cigen, n=1 << 17, N=8, reps=3):
@@ -527,6 +545,7 @@ def main():
         ws[name] = workload_rates(cib, ctx, cigen, name, int(bb), copy_gbs=copy_gbs)
     sub["workloads"] = ws
     sub["observables"] = observables_rate(cib, ctx, cigen, w.name, nnz)
+    sub["lanczos"] = lanczos_rate(cib, ctx, cigen, w, inter)
     sub["state_count"] = counting_rates(cib, ctx, cigen)
     if not args.no_serve:
         try:

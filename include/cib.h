@@ -298,6 +298,38 @@ typedef struct {
 cib_status cib_lobpcg(cib_ctx *ctx, const cib_matrix *H, const cib_lobpcg_opts *opts, double *evals,
                       double *evecs, int64_t ld_evecs, cib_lobpcg_info *info);
 
+/* -------------------------------------------------------------- Lanczos --
+ * Lowest nev eigenpairs of H (Fig. 1 step 15; the eigensolver the paper
+ * names beside LOBPCG) by Lanczos with full reorthogonalisation: each step
+ * applies H to one vector (cib_apply_H's SpMM; a float32 H gets a float32
+ * copy of the vector), orthogonalises against every kept vector by
+ * classical Gram-Schmidt applied twice, and extends the tridiagonal matrix
+ * T; T's lowest eigenvalues (bisection of Sturm counts) and vectors
+ * (inverse iteration) are computed on the host every fourth step.  Stops
+ * when every Ritz pair's residual beta_k |s_k| <= tol max(|theta|, 1).
+ * Vectors are float64 on the device: (max_iter + 1) x D doubles. */
+typedef struct {
+  int32_t nev;       /* 1..64, <= D                                          */
+  int32_t max_iter;  /* steps (kept vectors), nev..4096                      */
+  double tol;        /* relative residual; 0: 1e-10 (float64 H), 1e-6 (float32 H) */
+  uint64_t seed;     /* start vector: SplitMix64 of (seed, row)              */
+} cib_lanczos_opts;
+
+typedef struct {
+  int32_t iters, n_converged;
+  double resid[64];     /* relative residual per eigenpair                 */
+  double t_total_s;     /* wall time of the call                           */
+  double t_spmv_s;      /* device time in the products with H (events)     */
+} cib_lanczos_info;
+
+/* evals: host, nev float64.  evecs: device, D x nev float64 row-major with
+ * leading dimension ld_evecs (>= nev), or NULL.  Returns
+ * CIB_E_NOT_CONVERGED (with the current estimates in evals) when max_iter
+ * steps do not reach the tolerance; CIB_E_INVALID for NULL arguments, nev,
+ * max_iter or ld_evecs out of range, or a matrix of another context. */
+cib_status cib_lanczos(cib_ctx *ctx, const cib_matrix *H, const cib_lanczos_opts *opts, double *evals,
+                       double *evecs, int64_t ld_evecs, cib_lanczos_info *info);
+
 /* ---------------------------------------------------------------- serve --
  * Continuous batching of eigensolve requests.  Requests arrive at arrival_s
  * (relative to the call start; replayed in real time when opts->realtime,

@@ -40,7 +40,8 @@ EXPORTS = [
     "cib_upload_interaction", "cib_interaction_free",
     "cib_build_H", "cib_build_H_resident", "cib_matrix_info", "cib_matrix_stats",
     "cib_matrix_export", "cib_matrix_device", "cib_matrix_free",
-    "cib_apply_H", "cib_apply_H_free", "cib_observables", "cib_count_states", "cib_lobpcg", "cib_serve",
+    "cib_apply_H", "cib_apply_H_free", "cib_observables", "cib_count_states", "cib_lobpcg", "cib_lanczos",
+    "cib_serve",
 ]
 
 
@@ -84,6 +85,17 @@ class LobpcgInfoC(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("n_converged", ctypes.c_int32),
                 ("resid", ctypes.c_double * 64), ("t_total_s", ctypes.c_double),
                 ("t_spmm_s", ctypes.c_double), ("n_spmm", ctypes.c_int64)]
+
+
+class LanczosOptsC(ctypes.Structure):
+    _fields_ = [("nev", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("seed", ctypes.c_uint64)]
+
+
+class LanczosInfoC(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("n_converged", ctypes.c_int32),
+                ("resid", ctypes.c_double * 64), ("t_total_s", ctypes.c_double),
+                ("t_spmv_s", ctypes.c_double)]
 
 
 class RequestC(ctypes.Structure):
@@ -149,6 +161,7 @@ def load(path: str = LIB_PATH):
         "cib_apply_H_free": ([vp, vp, vp, i32, vp, i64, vp, i64, i32], i32),
         "cib_count_states": ([vp, vp, i64, i32, i32, i32, vp, P(i64)], i32),
         "cib_lobpcg": ([vp, vp, P(LobpcgOptsC), vp, vp, i64, P(LobpcgInfoC)], i32),
+        "cib_lanczos": ([vp, vp, P(LanczosOptsC), vp, vp, i64, P(LanczosInfoC)], i32),
         "cib_serve": ([vp, P(RequestC), i32, P(ServeOptsC), P(ResultC)], i32),
     }
     for name, (args, res) in sig.items():
@@ -476,6 +489,27 @@ def lobpcg(ctx: Context, H: Matrix, nev: int, block: int = 8, max_iter: int = 50
     d = dict(status=rc, iters=info.iters, n_converged=info.n_converged,
              resid=np.asarray(info.resid[:nev]), t_total_s=info.t_total_s,
              t_spmm_s=info.t_spmm_s, n_spmm=info.n_spmm)
+    return ev, d, vec
+
+
+def lanczos(ctx: Context, H: Matrix, nev: int, max_iter: int = 300, tol: float = 0.0, seed: int = 0,
+            want_vectors: bool = False):
+    """Lowest nev eigenvalues by Lanczos with full reorthogonalisation
+    (numpy float64), info dict, and optionally the eigenvectors as a (D, nev)
+    float64 device tensor."""
+    import torch
+    o = LanczosOptsC(nev, max_iter, tol, seed)
+    ctx.stream.wait_stream(torch.cuda.current_stream())
+    ev = np.zeros(nev, dtype=np.float64)
+    vec = None
+    if want_vectors:
+        vec = torch.empty((H.dim, nev), dtype=torch.float64, device="cuda:%d" % ctx.device)
+    info = LanczosInfoC()
+    rc = load().cib_lanczos(ctx.h, H.h, ctypes.byref(o), ev.ctypes.data,
+                            vec.data_ptr() if vec is not None else None, nev, ctypes.byref(info))
+    _check(rc, allow=(CIB_E_NOT_CONVERGED,))
+    d = dict(status=rc, iters=info.iters, n_converged=info.n_converged,
+             resid=np.asarray(info.resid[:nev]), t_total_s=info.t_total_s, t_spmv_s=info.t_spmv_s)
     return ev, d, vec
 
 

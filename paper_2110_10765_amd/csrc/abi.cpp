@@ -374,6 +374,25 @@ extern "C" cib_status cib_lobpcg(cib_ctx *ctx, const cib_matrix *H, const cib_lo
   return st;
 }
 
+// ---------------------------------------------------------------- Lanczos
+extern "C" cib_status cib_lanczos(cib_ctx *ctx, const cib_matrix *H, const cib_lanczos_opts *o, double *evals,
+                                  double *evecs, int64_t ld_evecs, cib_lanczos_info *info) {
+  cib_status st = CIB_OK;
+  cib_status rc = guarded([&] {
+    CIB_REQUIRE(ctx && H && o && evals, CIB_E_INVALID, "NULL argument");
+    CIB_REQUIRE(H->ctx == ctx, CIB_E_INVALID, "matrix belongs to another context");
+    CIB_REQUIRE(o->nev >= 1 && o->nev <= 64 && o->nev <= H->D, CIB_E_INVALID, "nev must be in 1..min(64, D)");
+    CIB_REQUIRE(o->max_iter >= o->nev && o->max_iter <= 4096, CIB_E_INVALID, "max_iter must be in nev..4096");
+    CIB_REQUIRE(!evecs || ld_evecs >= o->nev, CIB_E_INVALID, "ld_evecs smaller than nev");
+    BusyGuard busy(ctx);
+    DeviceGuard g(ctx->device);
+    st = lanczos_solve(ctx, *H, o->nev, o->max_iter, o->tol, o->seed, evals, evecs, ld_evecs, info, ctx->stream);
+  });
+  if (rc != CIB_OK) return rc;
+  if (st == CIB_E_NOT_CONVERGED) set_last_error("Lanczos reached max_iter before the tolerance");
+  return st;
+}
+
 // ---------------------------------------------------------------- serve
 extern "C" cib_status cib_serve(cib_ctx *ctx, const cib_request *reqs, int32_t n,
                                 const cib_serve_opts *opts, cib_result *results) {

@@ -48,6 +48,14 @@ __device__ __forceinline__ double readlane_f64(double v, int lane) {
   return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo);
 }
 
+// SplitMix64 (Steele, Lea, Flood 2014) as a counter-based generator.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+  x += 0x9e3779b97f4a7c15ULL;
+  x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ULL;
+  x = (x ^ (x >> 27)) * 0x94d049bb133111ebULL;
+  return x ^ (x >> 31);
+}
+
 // Sum over the 64 lanes, returned to every lane (all lanes must be active):
 // DPP exchanges inside each row of 16 (xor 1, xor 2, mirrored halves,
 // mirrored row), then the four row sums read as scalars, in a fixed order.

@@ -83,14 +83,6 @@ __global__ __launch_bounds__(256) void k_select_pass(int64_t n, const double *__
   }
 }
 
-// SplitMix64 (Steele, Lea, Flood 2014) as a counter-based generator.
-__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
-  x += 0x9e3779b97f4a7c15ULL;
-  x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ULL;
-  x = (x ^ (x >> 27)) * 0x94d049bb133111ebULL;
-  return x ^ (x >> 31);
-}
-
 // X0 = e_{idx[c]} + 1e-3 * N(0,1) (Box-Muller from two SplitMix64 uniforms).
 __global__ __launch_bounds__(256) void k_init_x(int64_t D, int b, int ld, const int64_t *idx,
                                                 uint64_t seed, double *S) {
