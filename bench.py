@@ -432,6 +432,8 @@ def main():
     ap.add_argument("--no-serve-sweep", action="store_true",
                     help="serving: closed loop only (no Poisson replays, no budget runs)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-next", action="store_true",
+                    help="skip the observables, Lanczos and state-counting measurements")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy 1 GiB five times (scale factor for the HBM byte counters)")
     ap.add_argument("--spmm-only", default="",
@@ -544,9 +546,10 @@ def main():
         name, bb = item.split(":")
         ws[name] = workload_rates(cib, ctx, cigen, name, int(bb), copy_gbs=copy_gbs)
     sub["workloads"] = ws
-    sub["observables"] = observables_rate(cib, ctx, cigen, w.name, nnz)
-    sub["lanczos"] = lanczos_rate(cib, ctx, cigen, w, inter)
-    sub["state_count"] = counting_rates(cib, ctx, cigen)
+    if not args.no_next:
+        sub["observables"] = observables_rate(cib, ctx, cigen, w.name, nnz)
+        sub["lanczos"] = lanczos_rate(cib, ctx, cigen, w, inter)
+        sub["state_count"] = counting_rates(cib, ctx, cigen)
     if not args.no_serve:
         try:
             sub.update(serve_suite(cib, ctx, cigen, args.serve_requests, sweep=not args.no_serve_sweep))
