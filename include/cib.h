@@ -330,6 +330,16 @@ typedef struct {
 cib_status cib_lanczos(cib_ctx *ctx, const cib_matrix *H, const cib_lanczos_opts *opts, double *evals,
                        double *evecs, int64_t ld_evecs, cib_lanczos_info *info);
 
+/* The host step of cib_lanczos, on its own (no device): the lowest k
+ * eigenpairs of the symmetric tridiagonal matrix with diagonal a[n] and
+ * off-diagonal b[n-1] (b unused when n = 1), by bisection of Sturm counts
+ * and inverse iteration (pivots kept at 2.2e-16 |T| or more), orthonormalised
+ * in order.  theta: k values ascending; S: n x k row-major, column c the
+ * vector of theta[c].  Host arrays.  Errors: CIB_E_INVALID for NULL
+ * arguments or k outside 1..n. */
+cib_status cib_tridiag_lowest(const double *a, const double *b, int32_t n, int32_t k, double *theta,
+                              double *S);
+
 /* ---------------------------------------------------------------- serve --
  * Continuous batching of eigensolve requests.  Requests arrive at arrival_s
  * (relative to the call start; replayed in real time when opts->realtime,

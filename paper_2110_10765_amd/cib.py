@@ -41,7 +41,7 @@ EXPORTS = [
     "cib_build_H", "cib_build_H_resident", "cib_matrix_info", "cib_matrix_stats",
     "cib_matrix_export", "cib_matrix_device", "cib_matrix_free",
     "cib_apply_H", "cib_apply_H_free", "cib_observables", "cib_count_states", "cib_lobpcg", "cib_lanczos",
-    "cib_serve",
+    "cib_tridiag_lowest", "cib_serve",
 ]
 
 
@@ -162,6 +162,7 @@ def load(path: str = LIB_PATH):
         "cib_count_states": ([vp, vp, i64, i32, i32, i32, vp, P(i64)], i32),
         "cib_lobpcg": ([vp, vp, P(LobpcgOptsC), vp, vp, i64, P(LobpcgInfoC)], i32),
         "cib_lanczos": ([vp, vp, P(LanczosOptsC), vp, vp, i64, P(LanczosInfoC)], i32),
+        "cib_tridiag_lowest": ([vp, vp, i32, i32, vp, vp], i32),
         "cib_serve": ([vp, P(RequestC), i32, P(ServeOptsC), P(ResultC)], i32),
     }
     for name, (args, res) in sig.items():
@@ -511,6 +512,20 @@ def lanczos(ctx: Context, H: Matrix, nev: int, max_iter: int = 300, tol: float =
     d = dict(status=rc, iters=info.iters, n_converged=info.n_converged,
              resid=np.asarray(info.resid[:nev]), t_total_s=info.t_total_s, t_spmv_s=info.t_spmv_s)
     return ev, d, vec
+
+
+def tridiag_lowest(a, b, k):
+    """Host step of the Lanczos solver: lowest k eigenpairs (values, n x k
+    vectors) of the symmetric tridiagonal matrix with diagonal a and
+    off-diagonal b (numpy float64)."""
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    n = len(a)
+    th = np.zeros(k)
+    S = np.zeros((n, k))
+    _check(load().cib_tridiag_lowest(a.ctypes.data, b.ctypes.data if len(b) else None, n, k,
+                                     th.ctypes.data, S.ctypes.data))
+    return th, S
 
 
 def serve(ctx: Context, requests: Sequence[dict], hbm_budget_bytes: int = 0, max_active: int = 0,

@@ -393,6 +393,18 @@ extern "C" cib_status cib_lanczos(cib_ctx *ctx, const cib_matrix *H, const cib_l
   return st;
 }
 
+extern "C" cib_status cib_tridiag_lowest(const double *a, const double *b, int32_t n, int32_t k, double *theta,
+                                        double *S) {
+  return guarded([&] {
+    CIB_REQUIRE(a && theta && S && (n < 2 || b), CIB_E_INVALID, "NULL argument");
+    CIB_REQUIRE(n >= 1 && k >= 1 && k <= n, CIB_E_INVALID, "need 1 <= k <= n");
+    std::vector<double> av(a, a + n), bv(b, b + (n - 1)), th, Sv;
+    tri_lowest(av, bv, n, k, th, Sv);
+    std::copy(th.begin(), th.end(), theta);
+    std::copy(Sv.begin(), Sv.end(), S);
+  });
+}
+
 // ---------------------------------------------------------------- serve
 extern "C" cib_status cib_serve(cib_ctx *ctx, const cib_request *reqs, int32_t n,
                                 const cib_serve_opts *opts, cib_result *results) {

@@ -407,6 +407,11 @@ size_t lobpcg_bytes(int64_t D, int b, cib_dtype dt);
 cib_status serve_run(cib_ctx *ctx, const cib_request *reqs, int n, const cib_serve_opts &o,
                      cib_result *results);
 
+// Lowest k eigenpairs of the symmetric tridiagonal matrix (diagonal a[n],
+// off-diagonal b[n-1]) on the host: values th[k] ascending, vectors S (n x k,
+// S[j * k + c]) orthonormal.
+void tri_lowest(const std::vector<double> &a, const std::vector<double> &b, int n, int k, std::vector<double> &th,
+                std::vector<double> &S);
 cib_status lanczos_solve(cib_ctx *ctx, const cib_matrix &H, int nev, int max_iter, double tol, uint64_t seed,
                          double *evals, double *evecs, int64_t ld_evecs, cib_lanczos_info *info, hipStream_t s);
 cib_status lobpcg_solve(cib_ctx *ctx, const cib_matrix &H, const cib_lobpcg_opts &o, double *evals,

@@ -149,6 +149,8 @@ void tri_solve(const std::vector<double> &a, const std::vector<double> &b, int n
   }
 }
 
+}  // namespace
+
 // lowest k eigenpairs of T: values in th, vectors (n x k, column c at S[j * k + c])
 void tri_lowest(const std::vector<double> &a, const std::vector<double> &b, int n, int k, std::vector<double> &th,
                 std::vector<double> &S) {
@@ -174,18 +176,31 @@ void tri_lowest(const std::vector<double> &a, const std::vector<double> &b, int 
   }
   S.assign((size_t)n * k, 0.0);
   std::vector<double> y(n);
+  // pivots of the inverse-iteration solves kept at eps |T| or more: a shift
+  // equal to an eigenvalue to the last bit makes a pivot vanish, and a
+  // near-zero replacement would overflow the solution (growth stays below
+  // 1 / eps per solve, and every solve is followed by a normalisation)
+  const double pivsolve = std::max(pivmin, 2.2e-16 * tnorm);
   for (int c = 0; c < k; ++c) {
     for (int i = 0; i < n; ++i) y[i] = 1.0 + 0.01 * ((i * 7919 + c * 104729) % 101) / 101.0;
     for (int it = 0; it < 3; ++it) {
-      tri_solve(a, b, n, th[c], pivmin, y);
+      tri_solve(a, b, n, th[c], pivsolve, y);
       // orthogonalise against the vectors already found (clusters), normalise
       for (int q = 0; q < c; ++q) {
         double dot = 0.0;
         for (int i = 0; i < n; ++i) dot += S[(size_t)i * k + q] * y[i];
         for (int i = 0; i < n; ++i) y[i] -= dot * S[(size_t)i * k + q];
       }
+      // normalise, dividing by the largest entry first (a solve can return
+      // entries near the overflow threshold; their squares would overflow)
+      double big = 0.0;
+      for (int i = 0; i < n; ++i) big = std::max(big, std::fabs(y[i]));
+      if (!(big > 0.0) || !std::isfinite(big)) big = 1.0;
       double nrm = 0.0;
-      for (int i = 0; i < n; ++i) nrm += y[i] * y[i];
+      for (int i = 0; i < n; ++i) {
+        y[i] /= big;
+        nrm += y[i] * y[i];
+      }
       nrm = std::sqrt(nrm);
       if (!(nrm > 0.0)) nrm = 1.0;
       for (int i = 0; i < n; ++i) y[i] /= nrm;
@@ -193,8 +208,6 @@ void tri_lowest(const std::vector<double> &a, const std::vector<double> &b, int 
     for (int i = 0; i < n; ++i) S[(size_t)i * k + c] = y[i];
   }
 }
-
-}  // namespace
 
 cib_status lanczos_solve(cib_ctx *ctx, const cib_matrix &H, int nev, int max_iter, double tol, uint64_t seed,
                          double *evals, double *evecs, int64_t ld_evecs, cib_lanczos_info *info, hipStream_t s) {

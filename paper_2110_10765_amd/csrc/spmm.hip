@@ -229,14 +229,22 @@ static void spmm_t(const cib_matrix &H, const T *X, int64_t ldx, T *Y, int64_t l
     CIB_HIP(hipGetLastError());
     return;
   }
+  // B vector columns per wave step, the narrowest that covers the columns
+  // left: one vector (the Lanczos product) gives 64 entry slots per step
+  // instead of 8
+  auto launch = [&](auto bc, int v0) {
+    constexpr int B = decltype(bc)::value;
+    hipLaunchKernelGGL((k_spmm_sym<T, B>), dim3(nblk), dim3(256), 0, s, D, H.row_ptr.p, H.col.p, val,
+                       H.lo_ptr.p, H.lo_col.p, lval, X, ldx, Y, ldy, nvec, v0);
+  };
   for (int v0 = 0; v0 < nvec; v0 += 16) {
     KTimer kt(H.ctx, K_SPMM, s);
-    if (nvec - v0 <= 8)
-      hipLaunchKernelGGL((k_spmm_sym<T, 8>), dim3(nblk), dim3(256), 0, s, D, H.row_ptr.p, H.col.p,
-                         val, H.lo_ptr.p, H.lo_col.p, lval, X, ldx, Y, ldy, nvec, v0);
-    else
-      hipLaunchKernelGGL((k_spmm_sym<T, 16>), dim3(nblk), dim3(256), 0, s, D, H.row_ptr.p,
-                         H.col.p, val, H.lo_ptr.p, H.lo_col.p, lval, X, ldx, Y, ldy, nvec, v0);
+    const int left = nvec - v0;
+    if (left == 1) launch(std::integral_constant<int, 1>{}, v0);
+    else if (left == 2) launch(std::integral_constant<int, 2>{}, v0);
+    else if (left <= 4) launch(std::integral_constant<int, 4>{}, v0);
+    else if (left <= 8) launch(std::integral_constant<int, 8>{}, v0);
+    else launch(std::integral_constant<int, 16>{}, v0);
   }
   CIB_HIP(hipGetLastError());
 }
