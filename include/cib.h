@@ -344,11 +344,17 @@ cib_status cib_tridiag_lowest(const double *a, const double *b, int32_t n, int32
  * Continuous batching of eigensolve requests.  Requests arrive at arrival_s
  * (relative to the call start; replayed in real time when opts->realtime,
  * else all are available at once).  A request is admitted when a slot is free
- * (max_active) and its device footprint fits the HBM budget; each step of the
- * loop advances every active request by one stage (basis, H build, LOBPCG
- * initialisation, one LOBPCG iteration) on a pool of streams so that the
- * requests' work overlaps, reads all convergence flags back in one
- * transfer, and retires finished requests, releasing their memory. */
+ * (max_active) and its device footprint fits the HBM budget.  Four builder
+ * threads, each on a stream of its own, take admitted requests through the
+ * basis and the H build while the solver loop runs.  Each solver step starts
+ * the solves of newly built requests (one of n_streams streams each) and
+ * advances every iterating request by one LOBPCG iteration, one launch per
+ * stage covering all of them (SpMM, Gram, partial sums, Rayleigh-Ritz,
+ * update, residual sums, finish; the launch parameters of each request are
+ * those of its own solve, so its iterates are the same bits as when it runs
+ * alone; a request the grouped SpMM cannot take iterates on its own stream),
+ * reads the convergence flags back, and retires finished requests,
+ * releasing their memory. */
 typedef struct {
   uint64_t id;
   double arrival_s;
