@@ -52,3 +52,14 @@ def test_status_codes_match_header():
     txt = open(HEADER).read()
     for name, val in re.findall(r"#define (CIB_E?_?[A-Z_]+) \(?(-?\d+)\)?", txt):
         assert getattr(cib, name) == int(val), name
+
+
+def test_missing_library_fails_loudly():
+    """No CPU fallback: without the built library every entry point raises."""
+    code = ("import paper_2110_10765_amd.cib as c\n"
+            "try:\n"
+            "    c.load('/nonexistent/libcib.so')\n"
+            "except RuntimeError as e:\n"
+            "    print('raised', 'not found' in str(e))\n")
+    out = subprocess.run(["python", "-c", code], capture_output=True, text=True, cwd=ROOT, timeout=300)
+    assert "raised True" in out.stdout, out.stdout + out.stderr
