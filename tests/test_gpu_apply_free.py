@@ -94,3 +94,28 @@ def test_apply_free_rejects_bad_arguments():
     other = cib.build_basis(ctx, cigen.WORKLOADS["ab_n3_3p3_cut4"].spec)
     with pytest.raises(cib.CibError):
         cib.apply_H_free(ctx, other, inter, torch.zeros((other.dim, 8), dtype=torch.float64, device="cuda:0"))
+
+
+@pytest.mark.parametrize("spec,seed", [(cigen.BasisSpec.one(6, 2, 0, -1), 25),
+                                       (cigen.BasisSpec.two(6, 1, 2, 2, 1, 3), 26)])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_apply_free_three_words(spec, seed, dtype):
+    """168 orbitals (three 64-bit words per configuration), against the oracle."""
+    import torch
+    from paper_2110_10765_amd import cib
+    ctx = gpu_ctx()
+    print("case", spec, dtype, flush=True)
+    b = cib.build_basis(ctx, spec)
+    inter = cib.upload_interaction(ctx, b, oracle_tables(spec, seed))
+    rp, col, val = oracle_csr(spec, seed)
+    X = np.random.default_rng(seed).standard_normal((b.dim, 8))
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    if dtype == "f32":
+        X = X.astype(np.float32).astype(np.float64)
+        val = val.astype(np.float32).astype(np.float64)
+    Y = cib.apply_H_free(ctx, b, inter, torch.tensor(X, dtype=tdt, device="cuda:0"))
+    torch.cuda.synchronize()
+    Yref, absHX = O.spmm_half(rp, col, val, X)
+    k = 2 * int(np.diff(rp).max()) + 2
+    u = EPS64 if dtype == "f64" else EPS32
+    assert np.all(np.abs(Y.cpu().numpy().astype(np.float64) - Yref) <= _gamma(k, u) * absHX + 1e-300)

@@ -27,6 +27,11 @@ SMALL = {
     "ragged_2sp": cigen.Workload("ragged_2sp", cigen.BasisSpec.two(2, 2, 3, 3, 1, 3), 22, 4, 8, "f64"),
     "tiny_2sp": cigen.Workload("tiny_2sp", cigen.BasisSpec.two(1, 1, 1, 1, 0, -1), 23, 2, 2, "f64"),
     "one_state": cigen.Workload("one_state", cigen.BasisSpec.one(1, 8, 0, -1), 24, 1, 1, "f64"),
+    # the largest orbital sets: n <= 6 is 168 orbitals, three 64-bit words;
+    # N = 2 connects every pair (a dense H), and a mixed basis has three
+    # words for A and one for B
+    "w3_1sp_dense": cigen.Workload("w3_1sp_dense", cigen.BasisSpec.one(6, 2, 0, -1), 25, 4, 8, "f64"),
+    "w3_2sp_mixed": cigen.Workload("w3_2sp_mixed", cigen.BasisSpec.two(6, 1, 2, 2, 1, 3), 26, 4, 8, "f64"),
 }
 TOL_ABS = 64 * EPS64 * 2.0 ** 8
 
