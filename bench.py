@@ -440,8 +440,8 @@ def main():
                     help="NAME:block:dtype -- only build H and run 10 SpMMs (for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU; --gpus %d is not supported (multi-GPU "
-              "sharding is a design note only)" % args.gpus, file=sys.stderr)
+        print("bench.py: runs on one GPU; --gpus %d is not supported (multi-GPU sharding "
+              "is a design note only)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     import torch
