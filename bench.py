@@ -195,7 +195,8 @@ def workload_rates(cib, ctx, cigen, name, b, reps=20, copy_gbs=None):
 def observables_rate(cib, ctx, cigen, name, nnz_half, m=16, nvec=16):
     """Expectation values of m random two-body operators (tables seeds
     2000 + k) in nvec vectors on the workload's basis: wall time of one
-    cib_observables call (each operator built, applied once, freed)."""
+    cib_observables call (each operator applied once by the matrix-free
+    product at 8 or 16 vectors)."""
     import torch
     w = cigen.WORKLOADS[name]
     basis = cib.build_basis(ctx, w.spec)

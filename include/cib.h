@@ -234,10 +234,12 @@ cib_status cib_apply_H_free(cib_ctx *ctx, const cib_basis *basis, const cib_inte
  * (host tables in the cib_tables layout, for `basis`'s orbital sets; a
  * one-body operator has zero two-body tables) and the nvec vectors x_v
  * (1..64): X is a device array of `dtype`, D rows, row-major, element
- * (i, v) at X[i * ldx + v], ldx >= nvec.  Each operator is built as a
- * half-stored matrix of `dtype` by the same passes as cib_build_H, applied
- * once, and freed before the next (device memory: one operator's matrix plus
- * D x nvec values).  The products are summed in float64 in a fixed order, so
+ * (i, v) at X[i * ldx + v], ldx >= nvec.  Each operator is applied once:
+ * with nvec = 8 or 16 and 16-byte aligned rows by the matrix-free product
+ * of cib_apply_H_free (device memory: the screens), otherwise built as a
+ * half-stored matrix of `dtype` by the same passes as cib_build_H, applied,
+ * and freed before the next (device memory: one operator's matrix), plus
+ * D x nvec values.  The products are summed in float64 in a fixed order, so
  * results are deterministic.  out: host, m * nvec doubles.  Synchronous.
  * Errors: CIB_E_INVALID for NULL pointers, m < 1, nvec outside 1..64,
  * ldx < nvec, a bad dtype or a basis of another context; CIB_E_NOMEM when

@@ -2,15 +2,15 @@
 // (one-body energies and two-body tables in the Hamiltonian's layout) and n
 // vectors x_v, a[k][v] = x_v^T O_k x_v.
 //
-// Each operator is built as a half-stored matrix by the same passes as H
-// (screen, phases, matrix elements, count, scan, fill) and applied once by
-// the symmetric SpMM; the operator's matrix is freed before the next one is
-// built, so the memory held is one operator's.  The products x_v . (O_k x_v)
-// are summed in float64 in a fixed order: per workgroup, each thread owns
-// one column and a stride of rows, the workgroup's partial sums are added in
-// thread order, and one pass adds the workgroups' sums in workgroup order
-// (the register accumulators and fixed-order tree of the paper's scalar
-// reductions, with no atomics).
+// Each operator is applied once: with 8 or 16 vectors by the matrix-free
+// product (the build's screens and values multiplied into X, no CSR held),
+// otherwise built as a half-stored matrix by the same passes as H and
+// applied by the symmetric SpMM, then freed before the next operator.  The
+// products x_v . (O_k x_v) are summed in float64 in a fixed order: per
+// workgroup, each thread owns one column and a stride of rows, the
+// workgroup's partial sums are added in thread order, and one pass adds the
+// workgroups' sums in workgroup order (the register accumulators and
+// fixed-order tree of the paper's scalar reductions, with no atomics).
 #include <memory>
 
 #include "cib_internal.hpp"
@@ -68,13 +68,20 @@ void observables(cib_ctx *ctx, const cib_basis &b, const cib_tables *ops, int m,
     hipStream_t s;
     ~SyncFirst() { (void)hipStreamSynchronize(s); }
   };
+  // 8 or 16 vectors in 16-byte rows: the matrix-free product (the build's
+  // screens and values, no CSR); otherwise the operator is built and applied
+  const bool free_ok = (nvec == 8 || nvec == 16) && (uintptr_t)X % 16 == 0 && (ldx * sv) % 16 == 0;
   for (int k = 0; k < m; ++k) {
     std::unique_ptr<cib_interaction> it(upload_interaction(ctx, b, ops[k], s));
     cib_matrix H;
     H.ctx = ctx;
     SyncFirst sync{s};
-    build_matrix(ctx, b, *it, dt, H, s, nullptr);
-    spmm_sym(H, X, ldx, Y.p, nvec, nvec, s);
+    if (free_ok) {
+      apply_matrix_free(ctx, b, *it, dt, ApplyReq{X, ldx, Y.p, (int64_t)nvec, nvec}, s);
+    } else {
+      build_matrix(ctx, b, *it, dt, H, s, nullptr);
+      spmm_sym(H, X, ldx, Y.p, nvec, nvec, s);
+    }
     if (dt == CIB_F64)
       hipLaunchKernelGGL(k_col_dots<double>, dim3(nblk), dim3(kDotThreads), 0, s, D, nvec,
                          static_cast<const double *>(X), ldx, Y.p, (int64_t)nvec, partial.p);
