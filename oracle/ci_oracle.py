@@ -24,6 +24,7 @@ __all__ = [
     "nnz_class_count", "trace_generating_function", "spmm_half",
     "eigs_dense", "eigs_sparse", "full_from_half", "residual_audit",
     "load_clib", "build_clib", "apply_columns", "observables", "count_connected",
+    "level_occupations", "mb_orbital_groups", "clamped_shift", "block_precond_apply",
 ]
 
 
@@ -775,3 +776,71 @@ def residual_audit(row_ptr, col, val, lam, X):
     X = np.asarray(X, dtype=np.float64)
     r = np.linalg.norm(Y - X * np.asarray(lam)[None, :], axis=0)
     return r / (np.maximum(np.abs(lam), 1.0) * np.linalg.norm(X, axis=0))
+
+
+# ---------------------------------------------------------------------------
+# Block-diagonal preconditioner over many-body basis orbitals (Sec. 2: states
+# with the same (n, l, j) values of their particles and any m values form a
+# group; the grouping gives LOBPCG a block-diagonal preconditioner).
+# ---------------------------------------------------------------------------
+def level_occupations(orbs, bits):
+    """Particles in each (n, 2j) level of one species' bit string, levels in
+    the orbital order."""
+    occ = {}
+    for k, (n, twoj, _) in enumerate(orbs):
+        occ.setdefault((n, twoj), 0)
+        if (bits >> k) & 1:
+            occ[(n, twoj)] += 1
+    return tuple(occ[key] for key in sorted(occ))
+
+
+def mb_orbital_groups(basis, max_block):
+    """Blocks of the preconditioner as lists of state indices.
+
+    The many-body basis orbital of a state is its pair of level-occupation
+    tuples (species A, species B).  Groups are ordered by their lowest state;
+    a group's states are ascending; a group of more than max_block states is
+    cut into consecutive runs of max_block (the last shorter)."""
+    groups = {}
+    order = []
+    for i in range(basis.D):
+        key = (level_occupations(basis.orbs[0], basis.A[i]),
+               level_occupations(basis.orbs[1], basis.B[i]) if basis.spec.n_species == 2 else ())
+        if key not in groups:
+            groups[key] = []
+            order.append(key)
+        groups[key].append(i)
+    blocks = []
+    for key in order:
+        g = groups[key]
+        for s in range(0, len(g), max_block):
+            blocks.append(g[s:s + max_block])
+    return blocks
+
+
+def clamped_shift(x, floor=1e-2):
+    """x moved away from zero to magnitude floor, sign kept (zero goes up):
+    the guard of the diagonal preconditioner (diag - lambda)^-1."""
+    if abs(x) >= floor:
+        return x
+    return -floor if x < 0 else floor
+
+
+def block_precond_apply(row_ptr, col, val, blocks, R, theta, floor=1e-2):
+    """W[:, c] = M_c^-1 R[:, c] with M_c the block diagonal of H - theta_c I
+    over the given blocks, each block inverted through its eigenpairs
+    (numpy's eigh) with eigenvalue gaps clamped like the diagonal
+    preconditioner's: M_c^-1 = Q diag(1 / clamp(lambda_j - theta_c)) Q^T.
+    float64 throughout."""
+    D = len(row_ptr) - 1
+    Hf = full_from_half(row_ptr, col, val, D)
+    R = np.asarray(R, dtype=np.float64)
+    W = np.zeros_like(R)
+    for idx in blocks:
+        idx = np.asarray(idx, dtype=np.int64)
+        lam, Q = np.linalg.eigh(Hf[idx][:, idx].toarray())
+        T = Q.T @ R[idx]
+        for c, th in enumerate(theta):
+            T[:, c] /= np.array([clamped_shift(l - th, floor) for l in lam])
+        W[idx] = Q @ T
+    return W
