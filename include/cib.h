@@ -61,6 +61,7 @@ typedef struct cib_ctx cib_ctx;
 typedef struct cib_basis cib_basis;
 typedef struct cib_interaction cib_interaction;
 typedef struct cib_matrix cib_matrix;
+typedef struct cib_precond cib_precond;
 
 /* Device-memory hooks.  alloc returns device memory of at least `bytes`
  * (256-byte aligned) or NULL; free releases it.  NULL hooks: hipMalloc and
@@ -265,12 +266,46 @@ cib_status cib_observables(cib_ctx *ctx, const cib_basis *basis, const cib_table
 cib_status cib_count_states(cib_ctx *ctx, const uint16_t *mbs, int64_t n, int32_t n_particles, int32_t n_sp,
                             int32_t method, int32_t *counts, int64_t *total);
 
+/* ------------------------------------------------------- preconditioner --
+ * Block-diagonal LOBPCG preconditioner over many-body basis orbitals (Sec. 2:
+ * the states whose particles have the same (n, l, j) values, any m, form a
+ * group, and the groups give a block-diagonal preconditioner).  A state's
+ * group is the pair of its species' level occupations (particles per (n, 2j)
+ * level); groups are ordered by their lowest state, states ascending inside;
+ * a group of more than max_block (1..64) states is cut into consecutive runs
+ * of max_block, and each run is one block.  Set-up: the blocks of H (its
+ * stored entries whose row and column share a block) and their eigenpairs
+ * by cyclic Jacobi rotations in float64 on the device.  Apply, for column c:
+ * W_c = Q diag(1 / g(lambda_j - theta_c)) Q^T R_c per block, g moving gaps
+ * below 1e-2 in magnitude to +-1e-2; max_block = 1 is exactly the diagonal
+ * preconditioner.  H must have been built on basis b (same D); the object
+ * keeps no reference to either.  Device memory: D x (max_block + 2) doubles
+ * at most.  Synchronous. */
+cib_status cib_precond_create(cib_ctx *ctx, const cib_basis *b, const cib_matrix *H, int32_t max_block,
+                              cib_precond **out);
+/* blocks, groups, largest block, and the most Jacobi sweeps a block took */
+cib_status cib_precond_info(const cib_precond *P, int64_t *n_blocks, int64_t *n_groups, int32_t *largest,
+                            int32_t *max_sweeps);
+/* Host copies of the blocks: perm (D int32: states in block order) and
+ * block_off (n_blocks + 1 int64: start of each block in perm); either may be
+ * NULL. */
+cib_status cib_precond_export(const cib_precond *P, int32_t *perm, int64_t *block_off);
+/* W = M(theta)^-1 R for ncol (1..16) columns: R, W device float64, D x ncol
+ * row-major with leading dimensions ldr, ldw >= ncol (W may be R, with ldw ==
+ * ldr; no other overlap); theta host,
+ * ncol shifts.  Deterministic (fixed summation order).  Synchronous. */
+cib_status cib_precond_apply(cib_ctx *ctx, const cib_precond *P, const double *theta, const double *R, int64_t ldr,
+                             double *W, int64_t ldw, int32_t ncol);
+void cib_precond_free(cib_precond *P);
+
 /* --------------------------------------------------------------- LOBPCG --
  * Lowest nev eigenpairs of H (Fig. 1 step 15) by block LOBPCG with block size
  * `block` (nev <= block <= 16, 3*block <= D).  Search space [X, W, P]; all
  * dense work (Gram matrices, Rayleigh-Ritz, residual norms) in float64 on the
  * device; the SpMM runs in the matrix dtype.  Preconditioner: diagonal,
- * W = R / (diag(H) - lambda) with |diag - lambda| clamped below at 1e-2.
+ * W = R / (diag(H) - lambda) with |diag - lambda| clamped below at 1e-2, or,
+ * when `precond` is set, the block-diagonal one of cib_precond_create (same
+ * guard on each block's eigenvalue gaps).
  * Converged when ||H x_k - lambda_k x_k|| <= tol * max(|lambda_k|, 1) for all
  * k < nev (tol <= 0: 1e-9 for float64 H; 1e-5 for float32 H, whose SpMM
  * rounding floors the residual near 1e-6 while the eigenvalue error, quadratic
@@ -285,6 +320,7 @@ typedef struct {
   double tol;
   uint64_t seed;
   const double *x0;
+  const cib_precond *precond;   /* NULL: diagonal; else made for this H */
 } cib_lobpcg_opts;
 
 typedef struct {

@@ -42,6 +42,7 @@ EXPORTS = [
     "cib_matrix_export", "cib_matrix_device", "cib_matrix_free",
     "cib_apply_H", "cib_apply_H_free", "cib_observables", "cib_count_states", "cib_lobpcg", "cib_lanczos",
     "cib_tridiag_lowest", "cib_serve",
+    "cib_precond_create", "cib_precond_info", "cib_precond_export", "cib_precond_apply", "cib_precond_free",
 ]
 
 
@@ -78,7 +79,8 @@ class BuildStatsC(ctypes.Structure):
 
 class LobpcgOptsC(ctypes.Structure):
     _fields_ = [("nev", ctypes.c_int32), ("block", ctypes.c_int32), ("max_iter", ctypes.c_int32),
-                ("tol", ctypes.c_double), ("seed", ctypes.c_uint64), ("x0", ctypes.c_void_p)]
+                ("tol", ctypes.c_double), ("seed", ctypes.c_uint64), ("x0", ctypes.c_void_p),
+                ("precond", ctypes.c_void_p)]
 
 
 class LobpcgInfoC(ctypes.Structure):
@@ -164,6 +166,11 @@ def load(path: str = LIB_PATH):
         "cib_lanczos": ([vp, vp, P(LanczosOptsC), vp, vp, i64, P(LanczosInfoC)], i32),
         "cib_tridiag_lowest": ([vp, vp, i32, i32, vp, vp], i32),
         "cib_serve": ([vp, P(RequestC), i32, P(ServeOptsC), P(ResultC)], i32),
+        "cib_precond_create": ([vp, vp, vp, i32, P(vp)], i32),
+        "cib_precond_info": ([vp, P(i64), P(i64), P(i32), P(i32)], i32),
+        "cib_precond_export": ([vp, vp, vp], i32),
+        "cib_precond_apply": ([vp, vp, vp, vp, i64, vp, i64, i32], i32),
+        "cib_precond_free": ([vp], None),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -472,12 +479,59 @@ def count_states(ctx: Context, mbs, n_sp: int, method: int = 0, want_counts: boo
     return total.value, (c.cpu().numpy() if c is not None else None)
 
 
+class Precond:
+    """Block-diagonal preconditioner over many-body basis orbitals
+    (cib_precond_create); blocks, groups, largest block and Jacobi sweeps as
+    attributes."""
+
+    def __init__(self, ctx: Context, basis: Basis, H: Matrix, max_block: int = 64):
+        self.ctx, self.dim = ctx, H.dim
+        h = ctypes.c_void_p()
+        _check(load().cib_precond_create(ctx.h, basis.h, H.h, int(max_block), ctypes.byref(h)))
+        self.h = h
+        nb, ng, lg, sw = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
+        _check(load().cib_precond_info(self.h, ctypes.byref(nb), ctypes.byref(ng), ctypes.byref(lg),
+                                       ctypes.byref(sw)))
+        self.n_blocks, self.n_groups, self.largest, self.max_sweeps = nb.value, ng.value, lg.value, sw.value
+
+    def blocks(self):
+        """(perm int32 [D], block_off int64 [n_blocks + 1]) host arrays."""
+        perm = np.zeros(self.dim, dtype=np.int32)
+        off = np.zeros(self.n_blocks + 1, dtype=np.int64)
+        _check(load().cib_precond_export(self.h, perm.ctypes.data, off.ctypes.data))
+        return perm, off
+
+    def apply(self, R, theta, W=None):
+        """W = M(theta)^-1 R; R, W float64 device tensors (D x ncol)."""
+        import torch
+        if W is None:
+            W = torch.empty_like(R)
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        self.ctx.stream.wait_stream(torch.cuda.current_stream())
+        _check(load().cib_precond_apply(self.ctx.h, self.h, th.ctypes.data, R.data_ptr(), R.stride(0),
+                                        W.data_ptr(), W.stride(0), int(R.shape[1])))
+        return W
+
+    def free(self):
+        if self.h:
+            load().cib_precond_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
 def lobpcg(ctx: Context, H: Matrix, nev: int, block: int = 8, max_iter: int = 500, tol: float = 0.0,
-           seed: int = 0, x0=None, want_vectors: bool = False):
+           seed: int = 0, x0=None, want_vectors: bool = False, precond: Precond = None):
     """Lowest nev eigenvalues (numpy float64), info dict, and optionally the
-    eigenvectors as a (D, nev) float64 device tensor."""
+    eigenvectors as a (D, nev) float64 device tensor.  precond: a Precond
+    made for H (block-diagonal), else the diagonal preconditioner."""
     import torch
-    o = LobpcgOptsC(nev, block, max_iter, tol, seed, x0.data_ptr() if x0 is not None else None)
+    o = LobpcgOptsC(nev, block, max_iter, tol, seed, x0.data_ptr() if x0 is not None else None,
+                    precond.h if precond is not None else None)
     ctx.stream.wait_stream(torch.cuda.current_stream())
     ev = np.zeros(nev, dtype=np.float64)
     vec = None

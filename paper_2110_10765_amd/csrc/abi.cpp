@@ -1,4 +1,5 @@
 // extern "C" entry points: argument checks, error translation, handle life.
+#include <algorithm>
 #include <chrono>
 #include <memory>
 
@@ -372,6 +373,69 @@ extern "C" cib_status cib_lobpcg(cib_ctx *ctx, const cib_matrix *H, const cib_lo
   if (rc != CIB_OK) return rc;
   if (st == CIB_E_NOT_CONVERGED) set_last_error("LOBPCG reached max_iter before the tolerance");
   return st;
+}
+
+// ---------------------------------------------------------------- preconditioner
+cib_status cib_precond_create(cib_ctx *ctx, const cib_basis *b, const cib_matrix *H, int32_t max_block,
+                              cib_precond **out) {
+  return guarded([&] {
+    CIB_REQUIRE(ctx && b && H && out, CIB_E_INVALID, "NULL argument");
+    *out = nullptr;
+    CIB_REQUIRE(max_block >= 1 && max_block <= 64, CIB_E_INVALID, "max_block must be in 1..64");
+    CIB_REQUIRE(b->ctx == ctx && H->ctx == ctx, CIB_E_INVALID, "basis or matrix belongs to another context");
+    CIB_REQUIRE(H->D == b->plan.D, CIB_E_INVALID, "matrix was not built on this basis");
+    BusyGuard busy(ctx);
+    DeviceGuard g(ctx->device);
+    std::unique_ptr<cib_precond> P(new cib_precond);
+    precond_create(ctx, *b, *H, max_block, *P, ctx->stream);
+    *out = P.release();
+  });
+}
+
+cib_status cib_precond_info(const cib_precond *P, int64_t *n_blocks, int64_t *n_groups, int32_t *largest,
+                            int32_t *max_sweeps) {
+  return guarded([&] {
+    CIB_REQUIRE(P, CIB_E_INVALID, "NULL argument");
+    if (n_blocks) *n_blocks = P->n_blocks;
+    if (n_groups) *n_groups = P->n_groups;
+    if (largest) *largest = P->largest;
+    if (max_sweeps) *max_sweeps = P->max_sweeps;
+  });
+}
+
+cib_status cib_precond_export(const cib_precond *P, int32_t *perm, int64_t *block_off) {
+  return guarded([&] {
+    CIB_REQUIRE(P, CIB_E_INVALID, "NULL argument");
+    if (perm) std::copy(P->perm_h.begin(), P->perm_h.end(), perm);
+    if (block_off) std::copy(P->boff_h.begin(), P->boff_h.end(), block_off);
+  });
+}
+
+cib_status cib_precond_apply(cib_ctx *ctx, const cib_precond *P, const double *theta, const double *R, int64_t ldr,
+                             double *W, int64_t ldw, int32_t ncol) {
+  return guarded([&] {
+    CIB_REQUIRE(ctx && P && theta && R && W, CIB_E_INVALID, "NULL argument");
+    CIB_REQUIRE(ncol >= 1 && ncol <= 16, CIB_E_INVALID, "ncol must be in 1..16");
+    CIB_REQUIRE(ldr >= ncol && ldw >= ncol, CIB_E_INVALID, "leading dimension smaller than ncol");
+    CIB_REQUIRE(P->ctx == ctx, CIB_E_INVALID, "preconditioner belongs to another context");
+    CIB_REQUIRE(R != W || ldr == ldw, CIB_E_INVALID, "in-place apply needs ldr == ldw");
+    BusyGuard busy(ctx);
+    DeviceGuard g(ctx->device);
+    cib_precond *Pm = const_cast<cib_precond *>(P);
+    Pm->theta.upload(theta, (size_t)ncol, ctx->stream);
+    precond_apply(*P, Pm->theta.p, ncol, R, ldr, W, ldw, nullptr, 0, ctx->stream);
+    CIB_HIP(hipStreamSynchronize(ctx->stream));
+  });
+}
+
+void cib_precond_free(cib_precond *P) {
+  if (!P) return;
+  try {
+    DeviceGuard g(P->ctx->device);
+    (void)hipStreamSynchronize(P->ctx->stream);
+  } catch (...) {
+  }
+  delete P;
 }
 
 // ---------------------------------------------------------------- Lanczos

@@ -188,6 +188,20 @@ struct cib_basis {
   cib::DBuf<uint64_t> words;            // SoA: (WA + WB) words x D
 };
 
+// Block-diagonal preconditioner: blocks of states (runs of at most
+// max_block states of one many-body basis orbital), their eigenvectors and
+// eigenvalues.
+struct cib_precond {
+  cib_ctx *ctx = nullptr;
+  int64_t D = 0, n_blocks = 0, n_groups = 0;
+  int largest = 0, max_block = 0, max_sweeps = 0;
+  cib::DBuf<int32_t> perm;          // D: states in block order
+  cib::DBuf<int64_t> boff, qoff;    // n_blocks + 1: block starts in perm, in Q
+  cib::DBuf<double> Q, lam, theta;  // eigenvectors (s x s each), eigenvalues (D), shifts
+  std::vector<int32_t> perm_h;
+  std::vector<int64_t> boff_h;
+};
+
 struct cib_interaction {
   cib_ctx *ctx = nullptr;
   int nA = 0, nB = 0;
@@ -274,6 +288,12 @@ void apply_matrix_free(cib_ctx *ctx, const cib_basis &b, const cib_interaction &
 // differences (device counts, optional) and their total (host).
 void count_pairs(cib_ctx *ctx, const uint16_t *mbs, int64_t n, int N, int method, int32_t *counts, int64_t *total,
                  hipStream_t s);
+// Block-diagonal preconditioner: set-up (groups, blocks, eigenpairs) and
+// W = M(theta)^-1 R for ncol <= 16 columns (theta on the device).
+void precond_create(cib_ctx *ctx, const cib_basis &b, const cib_matrix &H, int max_block, cib_precond &P,
+                    hipStream_t s);
+void precond_apply(const cib_precond &P, const double *theta_dev, int ncol, const double *R, int64_t ldr, double *W,
+                   int64_t ldw, float *w32, int64_t ld32, hipStream_t s);
 // out[k * nvec + v] = x_v^T O_k x_v for the m operators ops (host result).
 void observables(cib_ctx *ctx, const cib_basis &b, const cib_tables *ops, int m, cib_dtype dt, const void *X,
                  int64_t ldx, int nvec, double *out, hipStream_t s);

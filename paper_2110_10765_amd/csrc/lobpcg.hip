@@ -938,9 +938,13 @@ __device__ __forceinline__ void update_block(const UpdArgs &g, int blk) {
       const double x = xo[0][v], hx = ho[0][v];
       if (kc < b) {
         const double res = hx - lam[kc] * x;
-        double den = g.diag[i] - lam[kc];
-        if (fabs(den) < 1e-2) den = den < 0 ? -1e-2 : 1e-2;
-        const double w = g.locked[kc] ? 0.0 : res / den;   // soft locking
+        double w = res;   // no diagonal: the block preconditioner follows
+        if (g.diag) {
+          double den = g.diag[i] - lam[kc];
+          if (fabs(den) < 1e-2) den = den < 0 ? -1e-2 : 1e-2;
+          w = res / den;
+        }
+        if (g.locked[kc]) w = 0.0;   // soft locking
         s[kc] = x;
         s[b + kc] = w;
         h[kc] = hx;
@@ -1163,13 +1167,17 @@ struct LobpcgRun {
   }
 
   void update_step(int ns) {
-    UpdArgs ua{D, b, ns, ld, S.p, HS.p, C.p, lam.p, diag.p, H.dtype == CIB_F32 ? x32.p : nullptr,
+    const cib_precond *P = opts.precond;
+    float *w32 = H.dtype == CIB_F32 ? x32.p : nullptr;
+    UpdArgs ua{D, b, ns, ld, S.p, HS.p, C.p, lam.p, P ? nullptr : diag.p, P ? nullptr : w32,
                npart.p, (int)upd_rows, locked.p};
     {
       KTimer kt(ctx, K_UPDATE, s);
       if (2 * b <= 16) hipLaunchKernelGGL(k_update<1>, dim3(upd_blocks), dim3(256), 0, s, ua);
       else hipLaunchKernelGGL(k_update<2>, dim3(upd_blocks), dim3(256), 0, s, ua);
     }
+    // block preconditioner: W (the residuals, zero where locked) in place
+    if (P) precond_apply(*P, lam.p, b, S.p + b, ld, S.p + b, ld, w32, b, s);
     // per-block residual sums: groups of kSumGroup first, then k_finish
     const int ugroups = (upd_blocks + kSumGroup - 1) / kSumGroup;
     hipLaunchKernelGGL(k_sum_parts, dim3(1, ugroups), dim3(256), 0, s, 2 * b, upd_blocks, kSumGroup, npart.p,
@@ -1433,6 +1441,8 @@ cib_status lobpcg_solve(cib_ctx *ctx, const cib_matrix &H, const cib_lobpcg_opts
                         double *evecs, int64_t ld_evecs, cib_lobpcg_info *info) {
   const auto t0 = std::chrono::steady_clock::now();
   CIB_REQUIRE(!evecs || ld_evecs >= o.nev, CIB_E_INVALID, "ld_evecs < nev");
+  CIB_REQUIRE(!o.precond || (o.precond->ctx == ctx && o.precond->D == H.D), CIB_E_INVALID,
+              "preconditioner was not made for this matrix's basis and context");
   LobpcgRun L(ctx, H, o, ctx->stream, true);
   double *st = static_cast<double *>(ctx->pinned_buf(sizeof(double) * kStatusLen));
   L.start();

@@ -149,6 +149,7 @@ cib_status serve_run(cib_ctx *ctx, const cib_request *reqs, int n, const cib_ser
       try {
         CIB_REQUIRE(q.tables, CIB_E_INVALID, "request without tables");
         CIB_REQUIRE(q.solve.x0 == nullptr, CIB_E_INVALID, "serving requests cannot pass x0");
+        CIB_REQUIRE(q.solve.precond == nullptr, CIB_E_INVALID, "serving requests cannot pass a preconditioner");
         CIB_REQUIRE(q.solve.nev >= 1 && q.solve.nev <= 16, CIB_E_INVALID, "nev must be in 1..16");
         job->basis.reset(make_basis(ctx, q.basis, bstream));
         res.dim = job->basis->plan.D;
