@@ -232,6 +232,37 @@ def lanczos_rate(cib, ctx, cigen, w, inter, max_iter=1000):
             "spmv_s": info["t_spmv_s"], "lowest_eigenvalues": ev.tolist()}
 
 
+def precond_rates(cib, ctx, cigen, w, inter, caps=(16, 32, 64), max_iter=1000):
+    """LOBPCG on the step's workload with the block-diagonal preconditioner
+    over many-body basis orbitals (blocks of at most cap states) against the
+    diagonal one: set-up wall time (groups, blocks, Jacobi eigenpairs),
+    iterations and solve wall time."""
+    basis = cib.build_basis(ctx, w.spec)
+    H = cib.build_H(ctx, basis, inter, w.dtype)
+    cib.lobpcg(ctx, H, w.nev, block=w.block, max_iter=max_iter)        # warm
+    _sync()
+    t0 = time.perf_counter()
+    _, info, _ = cib.lobpcg(ctx, H, w.nev, block=w.block, max_iter=max_iter)
+    out = {"diagonal": {"iters": info["iters"], "status": info["status"],
+                        "solve_s": time.perf_counter() - t0}}
+    for cap in caps:
+        cib.Precond(ctx, basis, H, cap).free()                       # warm
+        _sync()
+        t0 = time.perf_counter()
+        P = cib.Precond(ctx, basis, H, cap)
+        setup = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        _, info, _ = cib.lobpcg(ctx, H, w.nev, block=w.block, max_iter=max_iter, precond=P)
+        out["block_%d" % cap] = {"iters": info["iters"], "status": info["status"],
+                                 "solve_s": time.perf_counter() - t0, "setup_s": setup,
+                                 "blocks": P.n_blocks, "groups": P.n_groups, "largest": P.largest,
+                                 "max_jacobi_sweeps": P.max_sweeps}
+        P.free()
+    H.free()
+    basis.free()
+    return out
+
+
 def counting_rates(cib, ctx, cigen, n=1 << 17, N=8, reps=3):
     """The state-counting test at the paper's density: n biased random states
     of N particles in 128 single-particle states; state comparisons per second
@@ -550,6 +581,7 @@ def main():
     if not args.no_next:
         sub["observables"] = observables_rate(cib, ctx, cigen, w.name, nnz)
         sub["lanczos"] = lanczos_rate(cib, ctx, cigen, w, inter)
+        sub["block_precond"] = precond_rates(cib, ctx, cigen, w, inter)
         sub["state_count"] = counting_rates(cib, ctx, cigen)
     if not args.no_serve:
         try:

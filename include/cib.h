@@ -279,7 +279,7 @@ cib_status cib_count_states(cib_ctx *ctx, const uint16_t *mbs, int64_t n, int32_
  * W_c = Q diag(1 / g(lambda_j - theta_c)) Q^T R_c per block, g moving gaps
  * below 1e-2 in magnitude to +-1e-2; max_block = 1 is exactly the diagonal
  * preconditioner.  H must have been built on basis b (same D); the object
- * keeps no reference to either.  Device memory: D x (max_block + 2) doubles
+ * keeps no reference to either.  Device memory: D x (max_block + 4) doubles
  * at most.  Synchronous. */
 cib_status cib_precond_create(cib_ctx *ctx, const cib_basis *b, const cib_matrix *H, int32_t max_block,
                               cib_precond **out);
