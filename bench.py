@@ -468,6 +468,8 @@ def main():
                     help="skip the observables, Lanczos and state-counting measurements")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy 1 GiB five times (scale factor for the HBM byte counters)")
+    ap.add_argument("--precond-only", action="store_true",
+                    help="only the block-diagonal preconditioner measurement (JSON line)")
     ap.add_argument("--spmm-only", default="",
                     help="NAME:block:dtype -- only build H and run 10 SpMMs (for counter runs)")
     args = ap.parse_args()
@@ -500,6 +502,16 @@ def main():
         print(json.dumps({"workload": name, "dtype": dt, "block": int(bb), "D": H.dim,
                           "nnz_half": H.nnz, "spmm_kernel_s": t,
                           "algorithmic_bytes": _spmm_bytes(H.nnz, H.dim, int(bb), sv)}))
+        return
+
+    if args.precond_only:
+        # the block-diagonal preconditioner's set-up and LOBPCG runs with it
+        # on the step's workload, alone (for kernel traces)
+        w = cigen.WORKLOADS[args.workload]
+        ctx = cib.Context(0)
+        b0 = cib.build_basis(ctx, w.spec)
+        inter = cib.upload_interaction(ctx, b0, cigen.make_tables(w.spec, w.seed))
+        print(json.dumps({"workload": w.name, "block_precond": precond_rates(cib, ctx, cigen, w, inter)}))
         return
 
     w = cigen.WORKLOADS[args.workload]

@@ -31,7 +31,7 @@
 
 namespace cib {
 
-constexpr int kPcMax = 64;        // largest block (rows of the LDS tiles)
+constexpr int kPcMax = 64;        // largest block
 constexpr int kPcCols = 16;       // columns per application
 constexpr int kPcSweeps = 40;     // Jacobi sweep limit
 
@@ -64,13 +64,14 @@ __global__ __launch_bounds__(256) void k_pc_extract(int64_t D, const int64_t *__
 
 // In: M holds each block (s x s, row-major).  Out: M holds its eigenvectors
 // (column j = eigenvector j) and lam[boff[k] + j] eigenvalue j; sweeps[k]
-// the sweeps taken.
+// the sweeps taken.  SM >= every block's size (LDS tiles of SM rows).
+template <int SM>
 __global__ __launch_bounds__(256) void k_pc_jacobi(const int64_t *__restrict__ boff, const int64_t *__restrict__ qoff,
                                                    double *__restrict__ M, double *__restrict__ lam,
                                                    int32_t *__restrict__ sweeps) {
-  __shared__ double A[kPcMax][kPcMax + 1], V[kPcMax][kPcMax + 1];
-  __shared__ double cs[kPcMax / 2], sn[kPcMax / 2];
-  __shared__ int pp[kPcMax / 2], qq[kPcMax / 2];
+  __shared__ double A[SM][SM + 1], V[SM][SM + 1];
+  __shared__ double cs[SM / 2], sn[SM / 2];
+  __shared__ int pp[SM / 2], qq[SM / 2];
   __shared__ double red[2][256];
   const int t = threadIdx.x, k = blockIdx.x;
   const int64_t o = boff[k];
@@ -156,13 +157,14 @@ __global__ __launch_bounds__(256) void k_pc_jacobi(const int64_t *__restrict__ b
 
 // W[perm rows of block k][c] = Q (Q^T R / g(lam - theta_c)); W may be R (each
 // block reads all its rows before it writes them, and blocks share no rows).
+template <int SM>
 __global__ __launch_bounds__(256) void k_pc_apply(const int32_t *__restrict__ perm, const int64_t *__restrict__ boff,
                                                   const int64_t *__restrict__ qoff, const double *__restrict__ Q,
                                                   const double *__restrict__ lam, const double *__restrict__ theta,
                                                   int ncol, const double *R, int64_t ldr, double *W, int64_t ldw,
                                                   float *__restrict__ w32, int64_t ld32) {
-  __shared__ double Qs[kPcMax][kPcMax + 1];
-  __shared__ double Rs[kPcMax][kPcCols + 1], Ts[kPcMax][kPcCols + 1];
+  __shared__ double Qs[SM][SM + 1];
+  __shared__ double Rs[SM][kPcCols + 1], Ts[SM][kPcCols + 1];
   __shared__ double th[kPcCols];
   const int t = threadIdx.x, k = blockIdx.x;
   const int64_t o = boff[k];
@@ -227,15 +229,22 @@ void precond_create(cib_ctx *ctx, const cib_basis &b, const cib_matrix &H, int m
   if (pl.ns == 2) cb = occupation_classes(pl.B, pl.oB);
   const int64_t ncb = pl.ns == 2 ? (int64_t)*std::max_element(cb.begin(), cb.end()) + 1 : 1;
   // group of each state, numbered by first appearance in state order
-  std::vector<int32_t> grp(D);
+  // (a direct table over the key range when it is small, else a map)
+  const int64_t nca = *std::max_element(ca.begin(), ca.end()) + 1;
+  const bool direct = nca * ncb <= (int64_t(1) << 22);
+  std::vector<int32_t> table(direct ? nca * ncb : 0, -1);
   std::map<int64_t, int32_t> gid;
+  int32_t ngi = 0;
+  std::vector<int32_t> grp(D);
   for (int alpha = 0; alpha < pl.nA(); ++alpha)
     for (int64_t i = pl.a_off[alpha]; i < pl.a_off[alpha + 1]; ++i) {
       int64_t key = ca[alpha] * ncb;
       if (pl.ns == 2) key += cb[pl.bseg_start[pl.a_seg[alpha]] + (i - pl.a_off[alpha])];
-      grp[i] = gid.emplace(key, (int32_t)gid.size()).first->second;
+      int32_t &slot = direct ? table[key] : gid.emplace(key, -1).first->second;
+      if (slot < 0) slot = ngi++;
+      grp[i] = slot;
     }
-  const int64_t ng = (int64_t)gid.size();
+  const int64_t ng = ngi;
   std::vector<int64_t> gstart(ng + 1, 0);
   for (int64_t i = 0; i < D; ++i) ++gstart[grp[i] + 1];
   for (int64_t g = 0; g < ng; ++g) gstart[g + 1] += gstart[g];
@@ -288,7 +297,10 @@ void precond_create(cib_ctx *ctx, const cib_basis &b, const cib_matrix &H, int m
   else
     hipLaunchKernelGGL(k_pc_extract<float>, ge, dim3(256), 0, st, D, H.row_ptr.p, H.col.p, H.val32.p, dblk.p,
                        dpos.p, P.boff.p, P.qoff.p, P.Q.p);
-  hipLaunchKernelGGL(k_pc_jacobi, dim3((unsigned)nb), dim3(256), 0, st, P.boff.p, P.qoff.p, P.Q.p, P.lam.p, sw.p);
+  const dim3 gj((unsigned)nb);
+  if (largest <= 16) hipLaunchKernelGGL(k_pc_jacobi<16>, gj, dim3(256), 0, st, P.boff.p, P.qoff.p, P.Q.p, P.lam.p, sw.p);
+  else if (largest <= 32) hipLaunchKernelGGL(k_pc_jacobi<32>, gj, dim3(256), 0, st, P.boff.p, P.qoff.p, P.Q.p, P.lam.p, sw.p);
+  else hipLaunchKernelGGL(k_pc_jacobi<kPcMax>, gj, dim3(256), 0, st, P.boff.p, P.qoff.p, P.Q.p, P.lam.p, sw.p);
   CIB_HIP(hipGetLastError());
   std::vector<int32_t> swh(nb);
   CIB_HIP(hipMemcpyAsync(swh.data(), sw.p, sizeof(int32_t) * nb, hipMemcpyDeviceToHost, st));
@@ -298,8 +310,16 @@ void precond_create(cib_ctx *ctx, const cib_basis &b, const cib_matrix &H, int m
 
 void precond_apply(const cib_precond &P, const double *theta_dev, int ncol, const double *R, int64_t ldr, double *W,
                    int64_t ldw, float *w32, int64_t ld32, hipStream_t st) {
-  hipLaunchKernelGGL(k_pc_apply, dim3((unsigned)P.n_blocks), dim3(256), 0, st, P.perm.p, P.boff.p, P.qoff.p, P.Q.p,
-                     P.lam.p, theta_dev, ncol, R, ldr, W, ldw, w32, ld32);
+  const dim3 g((unsigned)P.n_blocks);
+  if (P.largest <= 16)
+    hipLaunchKernelGGL(k_pc_apply<16>, g, dim3(256), 0, st, P.perm.p, P.boff.p, P.qoff.p, P.Q.p, P.lam.p, theta_dev,
+                       ncol, R, ldr, W, ldw, w32, ld32);
+  else if (P.largest <= 32)
+    hipLaunchKernelGGL(k_pc_apply<32>, g, dim3(256), 0, st, P.perm.p, P.boff.p, P.qoff.p, P.Q.p, P.lam.p, theta_dev,
+                       ncol, R, ldr, W, ldw, w32, ld32);
+  else
+    hipLaunchKernelGGL(k_pc_apply<kPcMax>, g, dim3(256), 0, st, P.perm.p, P.boff.p, P.qoff.p, P.Q.p, P.lam.p,
+                       theta_dev, ncol, R, ldr, W, ldw, w32, ld32);
   CIB_HIP(hipGetLastError());
 }
 
