@@ -484,7 +484,7 @@ class Precond:
     (cib_precond_create); blocks, groups, largest block and Jacobi sweeps as
     attributes."""
 
-    def __init__(self, ctx: Context, basis: Basis, H: Matrix, max_block: int = 64):
+    def __init__(self, ctx: Context, basis: Basis, H: Matrix, max_block: int = 16):
         self.ctx, self.dim = ctx, H.dim
         h = ctypes.c_void_p()
         _check(load().cib_precond_create(ctx.h, basis.h, H.h, int(max_block), ctypes.byref(h)))
