@@ -284,6 +284,12 @@ void precond_create(cib_ctx *ctx, const cib_basis &b, const cib_matrix &H, int m
   P.lam.reset(ctx, D);
   P.theta.reset(ctx, kPcCols);
   DBuf<int32_t> dblk(ctx, D), dpos(ctx, D), sw(ctx, nb);
+  // waits for the stream before the buffers above (and the caller's P, if a
+  // step throws) are released
+  struct SyncOnExit {
+    hipStream_t s;
+    ~SyncOnExit() { (void)hipStreamSynchronize(s); }
+  } sync_on_exit{st};
   P.perm.upload(P.perm_h.data(), D, st);
   P.boff.upload(P.boff_h.data(), nb + 1, st);
   P.qoff.upload(qoff.data(), nb + 1, st);
