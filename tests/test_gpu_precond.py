@@ -30,6 +30,10 @@ SMALL = {
     "one_species": (cigen.WORKLOADS["sp1_n2_N4"].spec, 1),
     "mixed": (cigen.BasisSpec.two(2, 2, 2, 3, 1, 2), 5),
     "cut4": (cigen.WORKLOADS["ab_n3_3p3_cut4"].spec, 1),
+    # configurations over two and three 64-bit words (112 and 168 orbitals)
+    "w3_1sp": (cigen.BasisSpec.one(6, 2, 0, -1), 25),
+    "w3_2sp": (cigen.BasisSpec.two(6, 1, 2, 2, 1, 3), 26),
+    "w2_b": (cigen.BasisSpec.two(4, 2, 5, 2, 0, 2), 27),
 }
 
 
@@ -76,7 +80,7 @@ def _block_tol(Hf, idx, theta, r):
     return tol
 
 
-@pytest.mark.parametrize("name", ["mixed", "cut4"])
+@pytest.mark.parametrize("name", ["mixed", "cut4", "w3_1sp", "w2_b"])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("ncol", [1, 5, 16])
 def test_apply_matches_oracle(name, dtype, ncol):
