@@ -421,9 +421,8 @@ cib_status cib_precond_apply(cib_ctx *ctx, const cib_precond *P, const double *t
     CIB_REQUIRE(R != W || ldr == ldw, CIB_E_INVALID, "in-place apply needs ldr == ldw");
     BusyGuard busy(ctx);
     DeviceGuard g(ctx->device);
-    cib_precond *Pm = const_cast<cib_precond *>(P);
-    Pm->theta.upload(theta, (size_t)ncol, ctx->stream);
-    precond_apply(*P, Pm->theta.p, ncol, R, ldr, W, ldw, nullptr, 0, ctx->stream);
+    P->theta.upload(theta, (size_t)ncol, ctx->stream);
+    precond_apply(*P, P->theta.p, ncol, R, ldr, W, ldw, nullptr, 0, ctx->stream);
     CIB_HIP(hipStreamSynchronize(ctx->stream));
   });
 }

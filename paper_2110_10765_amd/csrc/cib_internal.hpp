@@ -197,7 +197,8 @@ struct cib_precond {
   int largest = 0, max_block = 0, max_sweeps = 0;
   cib::DBuf<int32_t> perm;          // D: states in block order
   cib::DBuf<int64_t> boff, qoff;    // n_blocks + 1: block starts in perm, in Q
-  cib::DBuf<double> Q, lam, theta;  // eigenvectors (s x s each), eigenvalues (D), shifts
+  cib::DBuf<double> Q, lam;         // eigenvectors (s x s each), eigenvalues (D)
+  mutable cib::DBuf<double> theta;  // shifts staged by each apply call (one call per ctx at a time)
   std::vector<int32_t> perm_h;
   std::vector<int64_t> boff_h;
 };
