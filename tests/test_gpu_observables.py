@@ -24,6 +24,8 @@ pytestmark = pytest.mark.gpu
 SPECS = {
     "one_species": cigen.WORKLOADS["sp1_n2_N4"].spec,
     "two_species": cigen.BasisSpec.two(1, 3, 2, 2, 1, 4),
+    # configurations over three 64-bit words (168 orbitals)
+    "three_words": cigen.BasisSpec.one(6, 2, 0, -1),
 }
 
 
