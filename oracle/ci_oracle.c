@@ -68,6 +68,7 @@ static int op_create(st_t *s, int k) {
 /* ---------------- basis hash map: state -> index ---------------- */
 typedef struct { int64_t cap; int64_t *idx; const st_t *st; } smap_t;
 
+/* the 64-bit finaliser fmix64 of MurmurHash3 (Appleby), published constants */
 static uint64_t mix64(uint64_t x) {
   x ^= x >> 33; x *= 0xff51afd7ed558ccdULL; x ^= x >> 33;
   x *= 0xc4ceb9fe1a85ec53ULL; x ^= x >> 33; return x;
