@@ -1080,6 +1080,7 @@ template <int W>
 static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr, cib_dtype dt,
                     cib_matrix &H, hipStream_t s, const std::function<void(int64_t)> &before_fill,
                     const ApplyReq *ap = nullptr) {
+  UnwindFence fence(s);
   const Plan &p = b.plan;
   const DevInter it = itr.view();
   const int nA = p.nA(), nB = p.nB(), nseg = p.nseg();

@@ -88,6 +88,27 @@ struct KTimer {
   ~KTimer();
 };
 
+// Kernels queued on a stream may still use buffers that a throw releases on
+// its way out: while an UnwindFence is alive on this thread, the first device
+// buffer released during exception unwinding waits for its stream, so no
+// block goes back to the allocator (or its cache, shared with the other
+// threads of the context) while a kernel can still touch it.  Declare the
+// fence before the buffers it protects (it is destroyed after them).
+class UnwindFence {
+ public:
+  explicit UnwindFence(hipStream_t s);
+  ~UnwindFence();
+  UnwindFence(const UnwindFence &) = delete;
+  UnwindFence &operator=(const UnwindFence &) = delete;
+  static void wait_if_unwinding();
+
+ private:
+  hipStream_t s_;
+  UnwindFence *prev_;
+  int depth_;
+  bool waited_ = false;
+};
+
 // Typed device buffer owned through the context allocator.
 template <typename T>
 struct DBuf {
@@ -111,7 +132,10 @@ struct DBuf {
     p = count ? static_cast<T *>(c->alloc(count * sizeof(T))) : nullptr;
   }
   void release() {
-    if (p && ctx) ctx->free(p);
+    if (p && ctx) {
+      UnwindFence::wait_if_unwinding();
+      ctx->free(p);
+    }
     p = nullptr;
     n = 0;
   }
@@ -335,7 +359,6 @@ struct RRArgs {
   int32_t *flag;    // [0]: rank of the search space, [1]: fallback taken
   double drop_tol;
   const double *hlow;  // lower bound of the spectrum of H (Gershgorin)
-  long long *clk;      // optional: wall-clock stamps of the phases (thread 0)
 };
 
 // Per-stage arguments of one LOBPCG iteration (device pointers of one solve).

@@ -130,6 +130,7 @@ static void launch_count(int NP, dim3 g, hipStream_t s, int64_t n, int N, const 
 
 void count_pairs(cib_ctx *ctx, const uint16_t *mbs, int64_t n, int N, int method, int32_t *counts, int64_t *total,
                  hipStream_t s) {
+  UnwindFence fence(s);
   DBuf<CountState> st(ctx, (size_t)n);
   DBuf<int32_t> own;
   if (!counts) {

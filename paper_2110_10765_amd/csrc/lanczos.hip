@@ -212,6 +212,7 @@ void tri_lowest(const std::vector<double> &a, const std::vector<double> &b, int 
 cib_status lanczos_solve(cib_ctx *ctx, const cib_matrix &H, int nev, int max_iter, double tol, uint64_t seed,
                          double *evals, double *evecs, int64_t ld_evecs, cib_lanczos_info *info, hipStream_t s) {
   const auto t0 = std::chrono::steady_clock::now();
+  UnwindFence fence(s);
   const int64_t D = H.D;
   const int m = (int)std::min<int64_t>(max_iter, D);
   const bool f32 = H.dtype == CIB_F32;

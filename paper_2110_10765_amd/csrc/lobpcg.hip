@@ -386,7 +386,6 @@ __device__ __forceinline__ void rayleigh_ritz(const RRArgs &g) {
   int ns = ns_full, r = 0, nb = 0;
   double drop_tol = g.drop_tol, tnorm = 0.0, pivmin = 0.0;
   for (int attempt = 0; attempt < 2; ++attempt) {
-  if (g.clk && tid == 0) g.clk[0] = wall_clock64();
   // 1. reduce the partial Gram matrices (fixed order: deterministic); a
   //    retry keeps only the first ns columns ([X W]) of the same matrices
   auto place = [&](int e, double s) {
@@ -415,7 +414,6 @@ __device__ __forceinline__ void rayleigh_ritz(const RRArgs &g) {
     }
   }
   __syncthreads();
-  if (g.clk && tid == 0) g.clk[1] = wall_clock64();
   // 2. symmetrise, scale to unit diagonal
   for (int i = tid; i < ns; i += nt) {
     const double d = G[i][i];
@@ -433,7 +431,6 @@ __device__ __forceinline__ void rayleigh_ritz(const RRArgs &g) {
     }
   }
   __syncthreads();
-  if (g.clk && tid == 0) g.clk[2] = wall_clock64();
   // 3. right-looking Cholesky with dropping, in one wave with the matrix in
   //    registers: lane i holds row i, the steps and columns are unrolled so
   //    that every element of the row is a fixed register, and column k of L
@@ -478,7 +475,6 @@ __device__ __forceinline__ void rayleigh_ritz(const RRArgs &g) {
   __syncthreads();
   if (tid < kWave) {
     const int i = tid;
-    if (g.clk && i == 0) g.clk[3] = wall_clock64();
     const bool kp = i < ns && keep[i];
     const uint64_t km = __ballot(kp);
     if (kp) kidx[mask_rank(km)] = i;
@@ -536,7 +532,6 @@ __device__ __forceinline__ void rayleigh_ritz(const RRArgs &g) {
   }
   __syncthreads();
   r = rank_s;
-  if (g.clk && tid == 0) g.clk[4] = wall_clock64();
   // 4c. T1 = Hm Z^T into G (L is no longer needed), then M = Z T1 into Hm
   //     (dots of up to 48 terms, 8 table reads in flight)
   for (int e = tid; e < r * r; e += nt) {
@@ -588,7 +583,6 @@ __device__ __forceinline__ void rayleigh_ritz(const RRArgs &g) {
     }
   }
   __syncthreads();
-  if (g.clk && tid == 0) g.clk[5] = wall_clock64();
   // 5. Householder tridiagonalisation of M (r x r in Hm).  Lane i of every
   //    wave owns row i and computes the reflector redundantly (DPP sums, so
   //    every wave gets the same bits); the product with the trailing block
@@ -641,7 +635,6 @@ __device__ __forceinline__ void rayleigh_ritz(const RRArgs &g) {
   __syncthreads();
   for (int i = tid; i + 1 < r; i += nt) e2[i] = ee[i] * ee[i];
   __syncthreads();
-  if (g.clk && tid == 0) g.clk[6] = wall_clock64();
   // 6. lowest nb eigenvalues by multisection of the Gershgorin interval:
   //    gsz threads per eigenvalue (32 when nb <= 8, else 16), each round
   //    cutting the interval into gsz + 1 parts, until (gsz + 1)^rounds > 2^53
@@ -657,7 +650,6 @@ __device__ __forceinline__ void rayleigh_ritz(const RRArgs &g) {
   pivmin = fmax(1e-300, 2.2e-308 * fmax(emax, 1.0));
   gl -= 2.2e-16 * tnorm * 4 + pivmin;
   gu += 2.2e-16 * tnorm * 4 + pivmin;
-  if (g.clk && tid == 0) g.clk[11] = wall_clock64();
   {
     const int gsz = nb <= 8 ? 32 : 16;
     const int rounds = gsz == 32 ? 11 : 14;
@@ -677,7 +669,6 @@ __device__ __forceinline__ void rayleigh_ritz(const RRArgs &g) {
     }
     if (t == 0 && grp < nb) theta[grp] = 0.5 * (lo + hi);
   }
-  if (g.clk && tid == 0) g.clk[12] = wall_clock64();
   __syncthreads();
   // a Ritz value below the spectrum of H means a numerically dependent
   // direction spoiled the reduced matrix: redo without P and a looser drop
@@ -693,7 +684,6 @@ __device__ __forceinline__ void rayleigh_ritz(const RRArgs &g) {
   if (tid == 0) g.flag[1] = 1;
   __syncthreads();
   }
-  if (g.clk && tid == 0) g.clk[7] = wall_clock64();
   // 7. eigenvectors of the tridiagonal by twisted factorisation (one thread
   //    each); workspace and vectors in G (free after step 4b):
   //    rows [0, kNS) cols [0, 16): Y; rows [0,kNS) cols [16, 32): D+; [32, 48): D-
@@ -791,7 +781,6 @@ __device__ __forceinline__ void rayleigh_ritz(const RRArgs &g) {
     }
   }
   __syncthreads();
-  if (g.clk && tid == 0) g.clk[8] = wall_clock64();
   // 8. y <- Q y with the reflectors (last one first); 16 lanes per column,
   //    each lane owning rows i = t mod 16 (no cross-lane memory hazards)
   {
@@ -809,7 +798,6 @@ __device__ __forceinline__ void rayleigh_ritz(const RRArgs &g) {
     }
   }
   __syncthreads();
-  if (g.clk && tid == 0) g.clk[9] = wall_clock64();
   // 9. coefficients in S's columns
   if (tid == 0) g.flag[0] = r;
   for (int e = tid; e < ns_full * b; e += nt) {
@@ -840,7 +828,6 @@ __device__ __forceinline__ void rayleigh_ritz(const RRArgs &g) {
     g.C[k * 2 * b + b + c] = k < b ? 0.0 : v;
   }
   for (int c = tid; c < b; c += nt) g.lam[c] = c < nb ? theta[c] : 0.0;
-  if (g.clk && tid == 0) g.clk[10] = wall_clock64();
 }
 
 __global__ __launch_bounds__(256) void k_rayleigh_ritz(RRArgs g) { rayleigh_ritz(g); }
@@ -1066,8 +1053,6 @@ struct LobpcgRun {
   DBuf<double> selv;
   int64_t sel_half = 0;
   DBuf<int32_t> flag, locked;
-  DBuf<long long> clk;
-  bool clk_on = false;
   int iters = 0;
   double t_spmm = 0.0;
   int64_t n_spmm = 0;
@@ -1104,8 +1089,6 @@ struct LobpcgRun {
     selv.reset(ctx, 2 * sel_half + kMaxBlock);
     flag.reset(ctx, 4);
     locked.reset(ctx, kMaxBlock);
-    clk_on = std::getenv("CIB_DEBUG_RR_CLOCK") != nullptr;
-    if (clk_on) clk.reset(ctx, 16);
     if (H.dtype == CIB_F32) {
       x32.reset(ctx, (size_t)D * b);
       y32.reset(ctx, (size_t)D * b);
@@ -1143,8 +1126,7 @@ struct LobpcgRun {
   }
 
   RRArgs rr_args(int ns) const {
-    return RRArgs{ns, b, 1, gram.p, C.p, lam.p, flag.p, H.dtype == CIB_F64 ? 1e-10 : 1e-7, hlow.p,
-                  clk_on ? clk.p : nullptr};
+    return RRArgs{ns, b, 1, gram.p, C.p, lam.p, flag.p, H.dtype == CIB_F64 ? 1e-10 : 1e-7, hlow.p};
   }
 
   void gram_step(int ns) {
@@ -1443,30 +1425,19 @@ cib_status lobpcg_solve(cib_ctx *ctx, const cib_matrix &H, const cib_lobpcg_opts
   CIB_REQUIRE(!evecs || ld_evecs >= o.nev, CIB_E_INVALID, "ld_evecs < nev");
   CIB_REQUIRE(!o.precond || (o.precond->ctx == ctx && o.precond->D == H.D), CIB_E_INVALID,
               "preconditioner was not made for this matrix's basis and context");
+  UnwindFence fence(ctx->stream);
   LobpcgRun L(ctx, H, o, ctx->stream, true);
   double *st = static_cast<double *>(ctx->pinned_buf(sizeof(double) * kStatusLen));
   L.start();
   L.copy_status(st);
   CIB_HIP(hipStreamSynchronize(L.s));
   L.spmm_time_accumulate();
-  // CIB_DEBUG_DUMP=<file>: on a non-finite status, write the last reduced Gram
-  // matrices, coefficients and Ritz values (float64, raw) for offline analysis
-  auto dump = [&](int ns) {
-    const char *path = std::getenv("CIB_DEBUG_DUMP");
-    if (!path) return;
-    std::vector<double> h(kNS * 2 * kNS + kNS * 2 * kMaxBlock + kMaxBlock + 4, 0.0);
-    h[0] = ns; h[1] = L.b; h[2] = L.iters;
-    CIB_HIP(hipMemcpy(h.data() + 4, L.gram.p, sizeof(double) * ns * 2 * ns, hipMemcpyDeviceToHost));
-    CIB_HIP(hipMemcpy(h.data() + 4 + kNS * 2 * kNS, L.C.p, sizeof(double) * kNS * 2 * kMaxBlock, hipMemcpyDeviceToHost));
-    if (FILE *f = std::fopen(path, "wb")) { std::fwrite(h.data(), sizeof(double), h.size(), f); std::fclose(f); }
-  };
   auto finite = [&] {
     for (int k = 0; k < L.b; ++k)
       if (!std::isfinite(st[1 + k]) || !std::isfinite(st[1 + kMaxBlock + k])) return false;
     return true;
   };
   int conv = (int)st[0];
-  if (!finite()) dump(L.b);
   CIB_REQUIRE(finite(), CIB_E_DEVICE, "LOBPCG produced non-finite Ritz values");
   while (conv < L.nev && L.iters < L.max_iter) {
     L.iterate();
@@ -1474,20 +1445,11 @@ cib_status lobpcg_solve(cib_ctx *ctx, const cib_matrix &H, const cib_lobpcg_opts
     CIB_HIP(hipStreamSynchronize(L.s));
     L.spmm_time_accumulate();
     conv = (int)st[0];
-    if (!finite()) dump(L.iters == 1 ? 2 * L.b : 3 * L.b);
     CIB_REQUIRE(finite(), CIB_E_DEVICE, "LOBPCG produced non-finite Ritz values");
   }
   for (int k = 0; k < L.nev; ++k) evals[k] = st[1 + kMaxBlock + k];
   if (evecs) L.copy_vectors(evecs, ld_evecs);
   CIB_HIP(hipStreamSynchronize(L.s));
-  if (L.clk_on) {  // debug: phase durations of the last Rayleigh-Ritz step (100 MHz counter)
-    long long c[16];
-    CIB_HIP(hipMemcpy(c, L.clk.p, sizeof(c), hipMemcpyDeviceToHost));
-    std::fprintf(stderr, "rayleigh_ritz phases (us):");
-    for (int k = 0; k < 10; ++k) std::fprintf(stderr, " %d:%.2f", k + 1, (c[k + 1] - c[k]) * 0.01);
-    std::fprintf(stderr, " | 7a:%.2f 7b:%.2f 7c:%.2f\n", (c[11] - c[6]) * 0.01, (c[12] - c[11]) * 0.01,
-                 (c[7] - c[12]) * 0.01);
-  }
   if (info) {
     info->iters = L.iters;
     info->n_converged = conv;

@@ -55,6 +55,7 @@ __global__ void k_sum_cols(int nblk, int nvec, const double *__restrict__ partia
 
 void observables(cib_ctx *ctx, const cib_basis &b, const cib_tables *ops, int m, cib_dtype dt, const void *X,
                  int64_t ldx, int nvec, double *out, hipStream_t s) {
+  UnwindFence fence(s);
   const int64_t D = b.plan.D;
   const size_t sv = dt == CIB_F64 ? 8 : 4;
   const int nblk = (int)((D + kDotRows - 1) / kDotRows);

@@ -1,5 +1,6 @@
 // Host runtime: context, allocator cache, error reporting, interaction upload.
 #include <algorithm>
+#include <exception>
 #include <map>
 
 #include "cib_internal.hpp"
@@ -7,6 +8,22 @@
 namespace cib {
 
 static thread_local std::string g_last_error;
+
+static thread_local UnwindFence *t_fence = nullptr;
+
+UnwindFence::UnwindFence(hipStream_t s) : s_(s), prev_(t_fence), depth_(std::uncaught_exceptions()) {
+  t_fence = this;
+}
+
+UnwindFence::~UnwindFence() { t_fence = prev_; }
+
+void UnwindFence::wait_if_unwinding() {
+  UnwindFence *f = t_fence;
+  if (!f || f->waited_ || std::uncaught_exceptions() <= f->depth_) return;
+  (void)hipStreamSynchronize(f->s_);  // the error being thrown is the one reported
+  f->waited_ = true;
+}
+
 void set_last_error(const std::string &msg) { g_last_error = msg; }
 const char *last_error_cstr() { return g_last_error.c_str(); }
 
@@ -141,6 +158,7 @@ cib_interaction *upload_interaction(cib_ctx *ctx, const cib_basis &b, const cib_
   if (p.ns == 2)
     CIB_REQUIRE(t.eps[1] && t.v_same[1] && t.v_ab, CIB_E_INVALID,
                 "tables: two species need eps[1], v_same[1] and v_ab");
+  UnwindFence fence(s);
   std::unique_ptr<cib_interaction> it(new cib_interaction);
   it->ctx = ctx;
   it->nA = p.oA.n_orb;
@@ -193,6 +211,7 @@ cib_interaction *upload_interaction(cib_ctx *ctx, const cib_basis &b, const cib_
 
 
 cib_basis *make_basis(cib_ctx *ctx, const cib_basis_spec &spec, hipStream_t s) {
+  UnwindFence fence(s);
   std::unique_ptr<cib_basis> b(new cib_basis);
   b->ctx = ctx;
   make_plan(spec, b->plan);
