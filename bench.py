@@ -309,10 +309,81 @@ def serve_run(cib, ctx, cigen, dtype, n_req, budget=0, rate=math.inf):
            "p50_s": float(np.percentile(lat, 50)) if len(lat) else None,
            "p99_s": float(np.percentile(lat, 99)) if len(lat) else None,
            "admit_wait_p99_s": float(np.percentile(wait, 99)) if len(wait) else None}
+    err = serve_sample_errors(res)
+    if err:
+        out["eval_rel_err_vs_oracle_f64"] = err
     if not math.isinf(rate):
         out["arrival_rate_per_s"] = rate
     if budget:
         out["hbm_budget_bytes"] = budget
+    return out
+
+
+def _golden(name):
+    path = os.path.join(ROOT, "tests", "golden", name + ".json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        return json.load(f)
+
+
+def _rel_err(ev, ref):
+    import numpy as np
+    ev, ref = np.asarray(ev, dtype=float), np.asarray(ref, dtype=float)
+    return (np.abs(ev - ref) / np.maximum(np.abs(ref), 1.0)).tolist()
+
+
+def serve_sample_errors(res):
+    """Eigenvalue error of each result in the stored sample of the trace
+    (oracle float64 eigenvalues, tests/golden/serve_sample.json), relative
+    to max(|lambda|, 1): per request id and the largest."""
+    g = _golden("serve_sample")
+    if not g:
+        return None
+    ref = {r["id"]: r["evals_f64"] for r in g["requests"]}
+    per = {}
+    for x in res:
+        if x["status"] == 0 and x["id"] in ref:
+            k = len(ref[x["id"]])
+            per[str(x["id"])] = max(_rel_err(list(x["evals"])[:k], ref[x["id"]]))
+    if not per:
+        return None
+    return {"max": max(per.values()), "per_request": per}
+
+
+def small_case_us(cib, ctx, cigen, name="sp1_n2_N4", reps=20):
+    """The D = 849 one-species workload (launch-latency bound): device time of
+    the build (HIP events around its kernels), of one SpMM at its block, and
+    the wall time of cib_lobpcg, in microseconds; eigenvalue error against
+    the stored oracle (LAPACK) values."""
+    w = cigen.WORKLOADS[name]
+    basis = cib.build_basis(ctx, w.spec)
+    inter = cib.upload_interaction(ctx, basis, cigen.make_tables(w.spec, w.seed))
+    H = cib.build_H(ctx, basis, inter, w.dtype)
+    H.free()
+    builds = []
+    for _ in range(reps):
+        H = cib.build_H(ctx, basis, inter, w.dtype)
+        builds.append(H.stats()["t_total_s"])
+        H.free()
+    H = cib.build_H(ctx, basis, inter, w.dtype)
+    t_spmm = measure_spmm(cib, ctx, H, w.block, reps)
+    cib.lobpcg(ctx, H, w.nev, block=w.block, max_iter=1000)
+    _sync()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        ev, info, _ = cib.lobpcg(ctx, H, w.nev, block=w.block, max_iter=1000)
+    solve = (time.perf_counter() - t0) / 5
+    out = {"D": H.dim, "nnz_half": H.nnz, "dtype": w.dtype, "block": w.block,
+           "build_device_us": 1e6 * sum(builds) / len(builds), "spmm_kernel_us": 1e6 * t_spmm,
+           "lobpcg_wall_us": 1e6 * solve, "lobpcg_iters": info["iters"]}
+    g = _golden(name)
+    if g:
+        ref = g.get("evals_f64_lapack", g["evals_f64"])[:w.nev]
+        out["eval_rel_err_vs_oracle_f64"] = max(_rel_err(ev, ref))
+    H.free()
+    inter.free()
+    basis.free()
     return out
 
 
@@ -472,6 +543,8 @@ def main():
                     help="only the block-diagonal preconditioner measurement (JSON line)")
     ap.add_argument("--spmm-only", default="",
                     help="NAME:block:dtype -- only build H and run 10 SpMMs (for counter runs)")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="only the closed-loop serving runs, float32 and float64 H (for kernel traces)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: runs on one GPU; --gpus %d is not supported (multi-GPU sharding "
@@ -502,6 +575,11 @@ def main():
         print(json.dumps({"workload": name, "dtype": dt, "block": int(bb), "D": H.dim,
                           "nnz_half": H.nnz, "spmm_kernel_s": t,
                           "algorithmic_bytes": _spmm_bytes(H.nnz, H.dim, int(bb), sv)}))
+        return
+
+    if args.serve_only:
+        ctx = cib.Context(0)
+        print(json.dumps({"serve": serve_suite(cib, ctx, cigen, args.serve_requests, sweep=False)}))
         return
 
     if args.precond_only:
@@ -572,7 +650,12 @@ def main():
 
     build_t = sum(r["build"] for r in rec) / len(rec)
     build_dev = sum(r["build_device"] for r in rec) / len(rec)
+    g = _golden(w.name)
+    step_err = None
+    if g:
+        step_err = _rel_err(rec[-1]["ev"], g["evals_f64"][:w.nev])
     sub = {
+        "step_eval_rel_err_vs_oracle_f64": {"max": max(step_err), "per_eigenvalue": step_err} if step_err else None,
         "step_breakdown_s": {k: sum(r[k] for r in rec) / len(rec) for k in ("basis", "build", "solve")},
         "build_device_s": build_dev,
         "build_wall_nnz_per_s": nnz / build_t,
@@ -590,6 +673,7 @@ def main():
         name, bb = item.split(":")
         ws[name] = workload_rates(cib, ctx, cigen, name, int(bb), copy_gbs=copy_gbs)
     sub["workloads"] = ws
+    sub["small_case"] = small_case_us(cib, ctx, cigen)
     if not args.no_next:
         sub["observables"] = observables_rate(cib, ctx, cigen, w.name, nnz)
         sub["lanczos"] = lanczos_rate(cib, ctx, cigen, w, inter)

@@ -234,29 +234,36 @@ class Context:
     default-priority one unless `stream` is given), so that torch tensors and
     library work can be ordered with stream waits."""
 
-    def __init__(self, device: int = 0, stream=None, torch_allocator: bool = False):
+    def __init__(self, device: int = 0, stream=None, torch_allocator: bool = False, allocator=None):
+        """allocator: optional (alloc(nbytes) -> int address or None,
+        free(address)) Python callables for the library's device memory;
+        torch_allocator=True uses torch's caching allocator."""
         lib = load()
         import torch
         if stream is None:
             stream = torch.cuda.Stream(device=device)
         self._alloc = None
         ap = None
-        if torch_allocator:
-            import torch
+        if torch_allocator and allocator is None:
             dev = device
+            allocator = (lambda n: torch.cuda.caching_allocator_alloc(int(n), dev),
+                         torch.cuda.caching_allocator_delete)
+        if allocator is not None:
+            alloc_fn, free_fn = allocator
 
             @ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
             def _a(n, user):
                 try:
-                    return torch.cuda.caching_allocator_alloc(int(n), dev)
+                    return alloc_fn(int(n))
                 except Exception:
                     return None
 
             @ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
             def _f(p, user):
-                torch.cuda.caching_allocator_delete(p)
+                free_fn(p)
 
             self._alloc = AllocatorC(_a, _f, None)
+            self._hooks = (_a, _f)
             ap = ctypes.byref(self._alloc)
         self.stream = stream
         h = ctypes.c_void_p()

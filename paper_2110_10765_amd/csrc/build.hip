@@ -1078,24 +1078,27 @@ static void launch_apply(unsigned rblk, const RowArgs &ra, const RowArgs &rl, co
 // (H is not touched).
 template <int W>
 static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr, cib_dtype dt,
-                    cib_matrix &H, hipStream_t s, const std::function<void(int64_t)> &before_fill,
-                    const ApplyReq *ap = nullptr) {
+                    cib_matrix &H, hipStream_t s, const BuildReserve &reserve, const ApplyReq *ap = nullptr) {
   UnwindFence fence(s);
   const Plan &p = b.plan;
   const DevInter it = itr.view();
   const int nA = p.nA(), nB = p.nB(), nseg = p.nseg();
   Events ev;
-
-  CIB_HIP(hipEventRecord(ev.e[0], s));
-  DBuf<double> eA(ctx, nA), eB(ctx, nB);
-  launch_substate_energy(b, it, eA.p, eB.p, s);
+  auto bytes = [](size_t count, size_t elem) { return dev_bytes(count * elem); };
 
   // ---- counting passes of the two screens (tiles of both triangles)
   const int nchunk = (nA + kTileChunk - 1) / kTileChunk;
   const int64_t nunit = (int64_t)nA * nchunk;
+  const int64_t nscr = std::max(scan_scratch({nunit, nunit, nB, (int64_t)nB * nseg}), scan_scratch({p.D, p.D}));
+  if (reserve)
+    reserve(0, bytes(nA, 8) + bytes(nB, 8) + 2 * bytes(nunit, 4) + bytes(nB, 4) + bytes((size_t)nB * nseg, 4) +
+                   2 * bytes(nunit + 1, 8) + bytes(nB + 1, 8) + bytes((size_t)nB * nseg + 1, 8) + bytes(nscr, 8) +
+                   bytes(4, 8));
+  CIB_HIP(hipEventRecord(ev.e[0], s));
+  DBuf<double> eA(ctx, nA), eB(ctx, nB);
+  launch_substate_energy(b, it, eA.p, eB.p, s);
   DBuf<int32_t> tcnt(ctx, nunit), tlcnt(ctx, nunit), ls_cnt(ctx, nB), l1_cnt(ctx, (size_t)nB * nseg);
   DBuf<int64_t> t_ptr(ctx, nunit + 1), tl_ptr(ctx, nunit + 1), ls_ptr(ctx, nB + 1), l1_seg(ctx, (size_t)nB * nseg + 1);
-  const int64_t nscr = std::max(scan_scratch({nunit, nunit, nB, (int64_t)nB * nseg}), scan_scratch({p.D, p.D}));
   DBuf<int64_t> scratch(ctx, nscr), totals(ctx, 4);
   TileArgs ta{};
   ta.nA = nA; ta.nchunk = nchunk; ta.a_bits = b.a_bits.p; ta.a_m2 = b.a_m2.p; ta.a_len = b.a_len.p;
@@ -1128,6 +1131,13 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
 
   // ---- filling passes of the two screens
   auto at_least1 = [](int64_t n) { return (size_t)std::max<int64_t>(n, 1); };
+  if (reserve) {
+    const size_t nt = at_least1(n_tiles), nl = at_least1(n_lt), ns = at_least1(n_ls), n1 = at_least1(n_l1);
+    // screens, row counts, diagonal and the two offset arrays
+    reserve(1, (bytes(nt, 8) + 5 * bytes(nt, 4) + bytes(nt, 8)) + (bytes(nl, 8) + 5 * bytes(nl, 4) + bytes(nl, 8)) +
+                   bytes(nB, 4) + 4 * bytes(ns, 4) + 4 * bytes(n1, 4) + bytes(ns, 8) + 2 * bytes(p.D, 4) +
+                   bytes(p.D, 8) + 2 * bytes(p.D + 1, 8));
+  }
   DBuf<int64_t> t_off(ctx, at_least1(n_tiles)), tl_off(ctx, at_least1(n_lt));
   DBuf<int32_t> t_len(ctx, at_least1(n_tiles)), t_info(ctx, at_least1(n_tiles));
   DBuf<int32_t> tl_len(ctx, at_least1(n_lt)), tl_info(ctx, at_least1(n_lt));
@@ -1229,7 +1239,10 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
   int64_t n2[2];
   read_totals({H.row_ptr.p + p.D, H.lo_ptr.p + p.D}, totals.p, n2, s);
   const int64_t nnz = n2[0], nlo = n2[1];
-  if (before_fill) before_fill(nnz);
+  const size_t sv = dt == CIB_F64 ? 8 : 4;
+  if (reserve)
+    reserve(2, bytes(at_least1(nnz), 4) + bytes(at_least1(nlo), 4) + bytes(at_least1(nnz), sv) +
+                   bytes(at_least1(nlo), sv) + bytes(9, 8));
 
   // ---- filling passes
   H.col.reset(ctx, at_least1(nnz));
@@ -1288,11 +1301,11 @@ void apply_matrix_free(cib_ctx *ctx, const cib_basis &b, const cib_interaction &
 }
 
 void build_matrix(cib_ctx *ctx, const cib_basis &b, const cib_interaction &it, cib_dtype dt,
-                  cib_matrix &H, hipStream_t s, const std::function<void(int64_t)> &before_fill) {
+                  cib_matrix &H, hipStream_t s, const BuildReserve &reserve) {
   switch (b.plan.W) {
-    case 1: build_w<1>(ctx, b, it, dt, H, s, before_fill); break;
-    case 2: build_w<2>(ctx, b, it, dt, H, s, before_fill); break;
-    default: build_w<3>(ctx, b, it, dt, H, s, before_fill); break;
+    case 1: build_w<1>(ctx, b, it, dt, H, s, reserve); break;
+    case 2: build_w<2>(ctx, b, it, dt, H, s, reserve); break;
+    default: build_w<3>(ctx, b, it, dt, H, s, reserve); break;
   }
 }
 

@@ -1280,6 +1280,8 @@ struct LobpcgRun {
   }
 };
 
+// The device bytes of a LobpcgRun (its constructor's allocations, each as
+// the context allocator rounds it).
 size_t lobpcg_bytes(int64_t D, int b, cib_dtype dt) {
   const int64_t gram_rows = gram_rows_for(D);
   const int64_t gram_blocks = (D + gram_rows - 1) / gram_rows;
@@ -1287,10 +1289,14 @@ size_t lobpcg_bytes(int64_t D, int b, cib_dtype dt) {
   const int64_t upd_blocks = (D + upd_rows - 1) / upd_rows;
   const int64_t groups = (gram_blocks + kSumGroup - 1) / kSumGroup;
   const int64_t ugroups = (upd_blocks + kSumGroup - 1) / kSumGroup;
-  const int64_t sel = std::max<int64_t>(1, (D + kSelChunk - 1) / kSelChunk) * b;
-  size_t n = (size_t)D * 3 * b * 8 * 2 + (size_t)D * 8 + (size_t)(gram_blocks + groups) * kNS * 2 * kNS * 8 +
-             (size_t)(upd_blocks + ugroups) * 2 * kMaxBlock * 8 + (size_t)sel * 2 * 16 + 64 * 1024;
-  if (dt == CIB_F32) n += (size_t)D * b * 4 * 2;
+  const int64_t sel_half = std::max<int64_t>(1, (D + kSelChunk - 1) / kSelChunk) * b;
+  auto d8 = [](int64_t n) { return dev_bytes((size_t)n * 8); };
+  auto d4 = [](int64_t n) { return dev_bytes((size_t)n * 4); };
+  size_t n = 2 * d8(D * 3 * b + kGramPad) + d8(D) + d8(gram_blocks * kNS * 2 * kNS) +
+             d8(groups * kNS * 2 * kNS) + d8(kNS * 2 * kNS) + d8(1) + d8(kNS * 2 * kMaxBlock) + d8(kMaxBlock) +
+             d8(upd_blocks * 2 * kMaxBlock) + d8(ugroups * 2 * kMaxBlock) + d8(kStatusLen) + d8(kMaxBlock) +
+             d8(2 * sel_half) + d8(2 * sel_half + kMaxBlock) + d4(4) + d4(kMaxBlock);
+  if (dt == CIB_F32) n += 2 * d4(D * b);
   return n;
 }
 

@@ -210,11 +210,49 @@ cib_interaction *upload_interaction(cib_ctx *ctx, const cib_basis &b, const cib_
 }
 
 
+// Device bytes the context allocator takes for a request of n bytes.
+size_t dev_bytes(size_t n) { return n ? (std::max<size_t>(n, 256) + 255) & ~(size_t)255 : 0; }
+
+// Peak device bytes of upload_interaction (every table, the transition
+// staging and the blocked cross tables it frees at the end).
+size_t interaction_device_bytes(const Plan &p) {
+  auto lay = [](const PairLayout &L) {
+    return dev_bytes(L.pidx.size() * 4) + dev_bytes(L.prow.size() * 8) +
+           dev_bytes((size_t)std::max<int64_t>(L.total, 1) * 8);
+  };
+  size_t n = dev_bytes((size_t)p.oA.n_orb * 8) + lay(pair_layout(p.oA, p.oA, true));
+  if (p.ns == 2) {
+    const TransLayout T = trans_layout(p.oA, p.oB);
+    n += dev_bytes((size_t)p.oB.n_orb * 8) + lay(pair_layout(p.oB, p.oB, true)) +
+         lay(pair_layout(p.oA, p.oB, false)) + dev_bytes((size_t)p.oA.n_orb * p.oB.n_orb * 8) +
+         dev_bytes(std::max<size_t>(T.atr.size(), 1) * 4) + dev_bytes(std::max<size_t>(T.btr.size(), 1) * 4) +
+         dev_bytes(std::max<size_t>(T.blocks.size(), 1) * sizeof(VtBlock)) + dev_bytes(T.arb.size() * 4) +
+         dev_bytes(T.bcol.size() * 4) + dev_bytes((size_t)std::max<int64_t>(T.total, 1) * 8);
+  }
+  return n;
+}
+
+// Device bytes of a basis made from plan p (make_basis).
+size_t basis_device_bytes(const Plan &p) {
+  const size_t W = p.W, nA = p.nA(), nB = p.nB(), D = p.D;
+  auto i32 = [](size_t n) { return dev_bytes(std::max<size_t>(n, 1) * 4); };
+  return dev_bytes(W * nA * 8) + dev_bytes(W * nB * 8) + i32(p.A.m2.size()) + i32(p.A.q.size()) +
+         i32(p.a_len.size()) + i32(p.a_seg.size()) + i32(p.B.m2.size()) + i32(p.B.q.size()) +
+         i32(p.b_seg.size()) + i32(p.bseg_start.size()) + dev_bytes(p.a_off.size() * 8) + 3 * dev_bytes(D * 4) +
+         dev_bytes((size_t)(p.WA + p.WB) * D * 8);
+}
+
 cib_basis *make_basis(cib_ctx *ctx, const cib_basis_spec &spec, hipStream_t s) {
+  Plan p;
+  make_plan(spec, p);
+  return make_basis(ctx, std::move(p), s);
+}
+
+cib_basis *make_basis(cib_ctx *ctx, Plan &&plan, hipStream_t s) {
   UnwindFence fence(s);
   std::unique_ptr<cib_basis> b(new cib_basis);
   b->ctx = ctx;
-  make_plan(spec, b->plan);
+  b->plan = std::move(plan);
   const Plan &p = b->plan;
   CIB_REQUIRE(p.D > 0, CIB_E_EMPTY_BASIS, "the spec admits no state");
   CIB_REQUIRE(p.D < (int64_t(1) << 31), CIB_E_OVERFLOW, "basis dimension exceeds 2^31-1");

@@ -60,13 +60,10 @@ struct Shared {
 
 }  // namespace
 
-static size_t footprint(const cib_basis &b, int64_t nnz, cib_dtype dt, int block) {
-  const int64_t D = b.plan.D;
-  const size_t sv = dt == CIB_F64 ? 8 : 4;
-  // upper half + strictly lower copy
-  size_t h = (size_t)(2 * nnz - D) * (4 + sv) + 16 * (size_t)(D + 1);
-  return h + lobpcg_bytes(D, block, dt);
-}
+// A request gives way (frees what it holds and starts again later) when its
+// build needs more of the budget than is free: waiting while holding memory
+// could deadlock the builders.
+struct GiveWay {};
 
 cib_status serve_run(cib_ctx *ctx, const cib_request *reqs, int n, const cib_serve_opts &o,
                      cib_result *results) {
@@ -146,28 +143,76 @@ cib_status serve_run(cib_ctx *ctx, const cib_request *reqs, int n, const cib_ser
       job->req = &q;
       job->res = &res;
       cib_status st = CIB_OK;
+      // the budget covers everything a request allocates: basis and tables,
+      // the build's scratch, H, the solver state and the SpMM's row-window
+      // plan.  Each allocation group is reserved (exact bytes) before it is
+      // made; only the first reservation waits, with nothing held.
+      auto unreserve = [&](size_t bytes) {
+        std::lock_guard<std::mutex> lk(sh.mu);
+        sh.in_use -= bytes;
+        job->reserved -= bytes;
+        sh.cv.notify_all();
+      };
       try {
         CIB_REQUIRE(q.tables, CIB_E_INVALID, "request without tables");
         CIB_REQUIRE(q.solve.x0 == nullptr, CIB_E_INVALID, "serving requests cannot pass x0");
         CIB_REQUIRE(q.solve.precond == nullptr, CIB_E_INVALID, "serving requests cannot pass a preconditioner");
         CIB_REQUIRE(q.solve.nev >= 1 && q.solve.nev <= 16, CIB_E_INVALID, "nev must be in 1..16");
-        job->basis.reset(make_basis(ctx, q.basis, bstream));
-        res.dim = job->basis->plan.D;
+        Plan plan;
+        make_plan(q.basis, plan);
+        CIB_REQUIRE(plan.D > 0, CIB_E_EMPTY_BASIS, "the spec admits no state");
+        res.dim = plan.D;
         CIB_REQUIRE(3 * (int64_t)q.solve.block <= res.dim, CIB_E_INVALID, "need 3 * block <= D");
-        job->inter.reset(upload_interaction(ctx, *job->basis, *q.tables, bstream));
-        job->H.reset(new cib_matrix);
-        job->H->ctx = ctx;
-        build_matrix(ctx, *job->basis, *job->inter, q.dtype, *job->H, bstream, [&](int64_t nnz) {
-          const size_t need = footprint(*job->basis, nnz, q.dtype, q.solve.block);
-          CIB_REQUIRE(need <= sh.budget, CIB_E_NOMEM, "request footprint exceeds the HBM budget");
-          std::unique_lock<std::mutex> lk(sh.mu);
-          sh.cv.wait(lk, [&] { return sh.in_use + need <= sh.budget || sh.cancelled; });
-          CIB_REQUIRE(!sh.cancelled, CIB_E_CANCELLED, "cancelled");
-          sh.in_use += need;
-          job->reserved = need;
-        });
-        res.nnz_half = job->H->nnz;
-        job->inter.reset();  // tables are no longer needed once H is built
+        const size_t basis_b = basis_device_bytes(plan), inter_b = interaction_device_bytes(plan);
+        size_t known = basis_b + inter_b;   // grows as a build learns its sizes
+        for (;;) {
+          CIB_REQUIRE(known <= sh.budget, CIB_E_NOMEM, "request footprint exceeds the HBM budget");
+          {
+            std::unique_lock<std::mutex> lk(sh.mu);
+            sh.cv.wait(lk, [&] { return sh.in_use + known <= sh.budget || sh.cancelled; });
+            CIB_REQUIRE(!sh.cancelled, CIB_E_CANCELLED, "cancelled");
+            sh.in_use += known;
+            job->reserved = known;
+          }
+          size_t stages = 0, scratch = 0;
+          try {
+            job->basis.reset(make_basis(ctx, Plan(plan), bstream));
+            job->inter.reset(upload_interaction(ctx, *job->basis, *q.tables, bstream));
+            job->H.reset(new cib_matrix);
+            job->H->ctx = ctx;
+            // stages 0, 1, 3: scratch freed when the build returns; 2: the
+            // stored entries (with them, the solver state they will need);
+            // 4: the SpMM's row-window plan
+            const BuildReserve reserve = [&](int stage, size_t bytes) {
+              if (stage == 0 || stage == 1 || stage == 3) scratch += bytes;
+              if (stage == 2) bytes += lobpcg_bytes(plan.D, q.solve.block, q.dtype);
+              stages += bytes;
+              const size_t want = basis_b + inter_b + stages;
+              known = std::max(known, want);
+              if (job->reserved >= want) return;
+              CIB_REQUIRE(want <= sh.budget, CIB_E_NOMEM, "request footprint exceeds the HBM budget");
+              std::lock_guard<std::mutex> lk(sh.mu);
+              const size_t more = want - job->reserved;
+              if (sh.in_use + more > sh.budget) throw GiveWay{};
+              sh.in_use += more;
+              job->reserved += more;
+            };
+            build_matrix(ctx, *job->basis, *job->inter, q.dtype, *job->H, bstream, reserve);
+            spmm_prepare(*job->H, bstream, reserve);
+          } catch (const GiveWay &) {
+            // everything built so far is released (its stream drained first)
+            // and the request starts again once its whole known footprint fits
+            job->H.reset();
+            job->inter.reset();
+            job->basis.reset();
+            unreserve(job->reserved);
+            continue;
+          }
+          res.nnz_half = job->H->nnz;
+          job->inter.reset();            // tables are no longer needed once H is built
+          unreserve(inter_b + scratch);  // the build's scratch is gone too
+          break;
+        }
       } catch (const Error &e) {
         st = e.code;
         if (st == CIB_E_DEVICE) {
@@ -232,11 +277,18 @@ cib_status serve_run(cib_ctx *ctx, const cib_request *reqs, int n, const cib_ser
       std::vector<LobpcgRun *> g_runs;
       std::vector<IterPlan> g_plans;
       std::vector<Job *> g_jobs;
+      std::vector<Job *> failed;
       for (Job *j : active) {
         hipStream_t s = streams[j->stream];
         if (!j->started) {
           cib_lobpcg_opts lo = j->req->solve;
-          j->lp = lobpcg_create(ctx, *j->H, lo, s);
+          try {
+            j->lp = lobpcg_create(ctx, *j->H, lo, s);
+          } catch (const Error &e) {
+            if (e.code != CIB_E_NOMEM) throw;
+            failed.push_back(j);   // this request alone fails; the others go on
+            continue;
+          }
           lobpcg_start(j->lp);
           j->started = true;
           lobpcg_copy_status(j->lp, j->status);
@@ -260,7 +312,22 @@ cib_status serve_run(cib_ctx *ctx, const cib_request *reqs, int n, const cib_ser
       }
       for (int k = 0; k < nstreams; ++k) CIB_HIP(hipStreamSynchronize(streams[k]));
       CIB_HIP(hipStreamSynchronize(gstream));
-      // retire
+      // retire (and release the requests whose solver state did not fit)
+      auto release = [&](Job *j) {
+        free_slots.push_back((int)((j->status - pinned) / kStatusLen));
+        const size_t rel = j->reserved;
+        delete j;
+        std::lock_guard<std::mutex> lk(sh.mu);
+        sh.in_use -= rel;
+        --sh.active;
+        sh.cv.notify_all();
+      };
+      for (Job *j : failed) {
+        j->res->status = CIB_E_NOMEM;
+        j->res->t_done = now();
+        active.erase(std::find(active.begin(), active.end(), j));
+        release(j);
+      }
       std::vector<Job *> keep;
       for (Job *j : active) {
         const int nev = j->req->solve.nev;
@@ -276,13 +343,7 @@ cib_status serve_run(cib_ctx *ctx, const cib_request *reqs, int n, const cib_ser
           r.evals[k] = j->status[1 + kMaxBlock + k];
         }
         r.t_done = now();
-        free_slots.push_back((int)((j->status - pinned) / kStatusLen));
-        const size_t rel = j->reserved;
-        delete j;
-        std::lock_guard<std::mutex> lk(sh.mu);
-        sh.in_use -= rel;
-        --sh.active;
-        sh.cv.notify_all();
+        release(j);
       }
       active.swap(keep);
     }

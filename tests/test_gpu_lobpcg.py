@@ -58,7 +58,7 @@ def test_lobpcg_f32(name):
 
 
 @pytest.mark.parametrize("name,dtype", [("ab_n3_3p3_cut6", "f32"), ("ab_n5_4p4_cut4", "f32"),
-                                        ("ab_n3_3p3_cut6", "f64")])
+                                        ("ab_n3_3p3_cut6", "f64"), ("ab_n5_4p4_cut4", "f64")])
 def test_lobpcg_full_size(name, dtype):
     if not os.path.exists(os.path.join(GOLD, name + ".json")):
         pytest.skip("stored oracle eigenvalues not generated")
@@ -68,6 +68,17 @@ def test_lobpcg_full_size(name, dtype):
     assert info["status"] == 0, info
     tol = 1e-6 if dtype == "f32" else 1e-10
     assert _rel(ev, np.asarray(g["evals_f64"])[:w.nev]).max() <= tol, (ev, g["evals_f64"][:w.nev])
+
+
+@pytest.mark.parametrize("name", ["ab_n5_4p4_cut4", "ab_n3_3p3_cut6"])
+def test_lobpcg_f32_against_f64_same_gpu(name):
+    """The float32-H solve against the float64-H solve of the same basis on
+    the same device: every requested eigenvalue within 1e-6 relative."""
+    w = cigen.WORKLOADS[name]
+    ev64, info64, _ = _solve(w, "f64", max_iter=1000)
+    ev32, info32, _ = _solve(w, "f32", max_iter=1000)
+    assert info64["status"] == 0 and info32["status"] == 0
+    assert _rel(ev32, ev64).max() <= 1e-6, (ev32, ev64)
 
 
 def test_lobpcg_block_sizes_and_small_basis():

@@ -75,11 +75,48 @@ def test_serve_mix_equals_alone_and_oracle(dtype):
     # the same requests one at a time through cib_lobpcg: the serving loop
     # runs the same kernels (the Rayleigh-Ritz steps batched into one launch),
     # so every iteration must agree and the solves take as many iterations
-    for q, r in list(zip(reqs, res))[:8]:
+    for q, r in zip(reqs, res):
         if r["status"] == 0:
             ev, iters = _alone(q)
             assert r["iters"] == iters, (q["spec"], r["iters"], iters)
             assert _rel(r["evals"], ev).max() <= tol
+
+
+def _sample_golden():
+    from tests.common import golden
+    g = golden("serve_sample")
+    return {r["id"]: r for r in g["requests"]}
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_serve_full_shell_mix_equals_alone_and_oracle(dtype):
+    """The serving trace's requests as drawn (shells up to 4: 70 orbitals per
+    species, two 64-bit words), small ones beside two of D = 21,048 and
+    59,462: every result equals its alone cib_lobpcg solve (same iteration
+    count, eigenvalues within the dtype tolerance) and the oracle's float64
+    eigenvalues (dense LAPACK up to D = 4000, else stored ARPACK values)."""
+    from paper_2110_10765_amd import cib
+    ctx = gpu_ctx()
+    gold = _sample_golden()
+    ids = sorted(gold)
+    trace = {r["id"]: r for r in cigen.request_trace(512, trace_seed=5)}
+    reqs = []
+    for i in ids:
+        r = trace[i]
+        reqs.append(dict(r, dtype=dtype, tol=0.0, max_iter=800, tables=oracle_tables(r["spec"], r["seed"])))
+    assert any(q["spec"].nmax[0] == 4 and gold[q["id"]]["D"] > 20000 for q in reqs)
+    print("serve full-shell mix", dtype, [gold[i]["D"] for i in ids], flush=True)
+    res = cib.serve(ctx, reqs, max_active=16, n_streams=4)
+    tol = 1e-10 if dtype == "f64" else 1e-6
+    for q, r in zip(reqs, res):
+        g = gold[q["id"]]
+        assert r["id"] == q["id"] and r["status"] == 0, r
+        assert r["dim"] == g["D"] and r["nnz_half"] == g["nnz_half"]
+        ref = np.asarray(g["evals_f64"])[:q["nev"]]
+        assert _rel(r["evals"][:q["nev"]], ref).max() <= tol, (q["id"], r["evals"], ref)
+        ev, iters = _alone(q)
+        assert r["iters"] == iters, (q["id"], r["iters"], iters)
+        assert _rel(r["evals"][:q["nev"]], ev).max() <= tol
 
 
 def test_serve_small_budget_queues_and_rejects():
