@@ -265,6 +265,19 @@ cib_status cib_observables(cib_ctx *ctx, const cib_basis *basis, const cib_table
  * repeated indices give meaningless counts (no other effect). */
 cib_status cib_count_states(cib_ctx *ctx, const uint16_t *mbs, int64_t n, int32_t n_particles, int32_t n_sp,
                             int32_t method, int32_t *counts, int64_t *total);
+/* cib_count_states for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and the same results, with their scratch (the
+ * encoded states, the counts when counts is NULL, the total) in one static
+ * device array of about 7.9 MB that every device the library runs on holds
+ * until the process ends.  No hipMalloc, hipFree or other allocation.  n is
+ * limited to 1..131072 (2^17): larger n gives CIB_E_INVALID with the limit
+ * in the message; the other arguments and errors are those of
+ * cib_count_states.  Every call on one device uses that device's array
+ * (clearing the counts first), so calls that overlap on one device race and
+ * must be serialised by the caller.  Synchronous. */
+cib_status cib_count_states_noalloc(cib_ctx *ctx, const uint16_t *mbs, int64_t n, int32_t n_particles,
+                                    int32_t n_sp, int32_t method, int32_t *counts, int64_t *total);
 
 /* ------------------------------------------------------- preconditioner --
  * Block-diagonal LOBPCG preconditioner over many-body basis orbitals (Sec. 2:

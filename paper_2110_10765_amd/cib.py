@@ -40,7 +40,8 @@ EXPORTS = [
     "cib_upload_interaction", "cib_interaction_free",
     "cib_build_H", "cib_build_H_resident", "cib_matrix_info", "cib_matrix_stats",
     "cib_matrix_export", "cib_matrix_device", "cib_matrix_free",
-    "cib_apply_H", "cib_apply_H_free", "cib_observables", "cib_count_states", "cib_lobpcg", "cib_lanczos",
+    "cib_apply_H", "cib_apply_H_free", "cib_observables", "cib_count_states",
+    "cib_count_states_noalloc", "cib_lobpcg", "cib_lanczos",
     "cib_tridiag_lowest", "cib_serve",
     "cib_precond_create", "cib_precond_info", "cib_precond_export", "cib_precond_apply", "cib_precond_free",
 ]
@@ -162,6 +163,7 @@ def load(path: str = LIB_PATH):
         "cib_observables": ([vp, vp, vp, i32, i32, vp, i64, i32, vp], i32),
         "cib_apply_H_free": ([vp, vp, vp, i32, vp, i64, vp, i64, i32], i32),
         "cib_count_states": ([vp, vp, i64, i32, i32, i32, vp, P(i64)], i32),
+        "cib_count_states_noalloc": ([vp, vp, i64, i32, i32, i32, vp, P(i64)], i32),
         "cib_lobpcg": ([vp, vp, P(LobpcgOptsC), vp, vp, i64, P(LobpcgInfoC)], i32),
         "cib_lanczos": ([vp, vp, P(LanczosOptsC), vp, vp, i64, P(LanczosInfoC)], i32),
         "cib_tridiag_lowest": ([vp, vp, i32, i32, vp, vp], i32),
@@ -467,11 +469,13 @@ def observables(ctx: Context, basis: Basis, tables_list, X):
     return out
 
 
-def count_states(ctx: Context, mbs, n_sp: int, method: int = 0, want_counts: bool = True):
+def count_states(ctx: Context, mbs, n_sp: int, method: int = 0, want_counts: bool = True,
+                 noalloc: bool = False):
     """State-counting test on an (n, N) array of ascending uint16 index
     tuples (numpy, copied to the device): (total, per-state counts as numpy
     int32 or None).  method 0 = hybrid, 1 = tuples only, 2 = 128-bit bit
-    strings."""
+    strings.  noalloc: call cib_count_states_noalloc (library scratch in a
+    static device array, n <= 2^17) instead of cib_count_states."""
     import numpy as np
     import torch
     mbs = np.ascontiguousarray(mbs, dtype=np.uint16)
@@ -481,8 +485,9 @@ def count_states(ctx: Context, mbs, n_sp: int, method: int = 0, want_counts: boo
     c = torch.empty(n, dtype=torch.int32, device=dev) if want_counts else None
     torch.cuda.current_stream(dev).synchronize()
     total = ctypes.c_int64()
-    _check(load().cib_count_states(ctx.h, m.data_ptr(), n, N, n_sp, method,
-                                   c.data_ptr() if c is not None else None, ctypes.byref(total)))
+    fn = load().cib_count_states_noalloc if noalloc else load().cib_count_states
+    _check(fn(ctx.h, m.data_ptr(), n, N, n_sp, method, c.data_ptr() if c is not None else None,
+              ctypes.byref(total)))
     return total.value, (c.cpu().numpy() if c is not None else None)
 
 

@@ -72,6 +72,7 @@ cib_status cib_create(int device, const cib_allocator *a, void *hip_stream, cib_
     std::unique_ptr<cib_ctx> c(new cib_ctx);
     c->device = device;
     DeviceGuard g(device);
+    static_scratch_init(device);
     if (a) { c->user = *a; c->has_user = true; }
     if (hip_stream) {
       c->stream = static_cast<hipStream_t>(hip_stream);
@@ -353,6 +354,22 @@ cib_status cib_count_states(cib_ctx *ctx, const uint16_t *mbs, int64_t n, int32_
     BusyGuard busy(ctx);
     DeviceGuard g(ctx->device);
     count_pairs(ctx, mbs, n, n_particles, method, counts, total, ctx->stream);
+  });
+}
+
+cib_status cib_count_states_noalloc(cib_ctx *ctx, const uint16_t *mbs, int64_t n, int32_t n_particles,
+                                    int32_t n_sp, int32_t method, int32_t *counts, int64_t *total) {
+  return guarded([&] {
+    CIB_REQUIRE(ctx && mbs && total, CIB_E_INVALID, "NULL argument");
+    CIB_REQUIRE(n >= 1 && n <= static_count_max_states(), CIB_E_INVALID,
+                "n must be in 1.." + std::to_string(static_count_max_states()) + " (the static scratch)");
+    CIB_REQUIRE(n_particles >= 1 && n_particles <= 20, CIB_E_INVALID, "n_particles must be in 1..20");
+    CIB_REQUIRE(n_sp >= n_particles && n_sp <= 65534, CIB_E_INVALID, "n_sp must be in n_particles..65534");
+    CIB_REQUIRE(method >= 0 && method <= 2, CIB_E_INVALID, "method must be 0, 1 or 2");
+    CIB_REQUIRE(method != 2 || n_sp <= 128, CIB_E_INVALID, "method 2 needs n_sp <= 128");
+    BusyGuard busy(ctx);
+    DeviceGuard g(ctx->device);
+    count_pairs_static(ctx->device, mbs, n, n_particles, method, counts, total, ctx->stream);
   });
 }
 

@@ -339,6 +339,14 @@ void apply_matrix_free(cib_ctx *ctx, const cib_basis &b, const cib_interaction &
 // differences (device counts, optional) and their total (host).
 void count_pairs(cib_ctx *ctx, const uint16_t *mbs, int64_t n, int N, int method, int32_t *counts, int64_t *total,
                  hipStream_t s);
+// The same test with no device allocation: scratch in a static device array
+// (up to static_count_max_states() states), whose address on a device is set
+// up once by static_scratch_init with that device current (the context's
+// creation does it).
+void static_scratch_init(int device);
+int64_t static_count_max_states();
+void count_pairs_static(int device, const uint16_t *mbs, int64_t n, int N, int method, int32_t *counts,
+                        int64_t *total, hipStream_t s);
 // Block-diagonal preconditioner: set-up (groups, blocks, eigenpairs) and
 // W = M(theta)^-1 R for ncol <= 16 columns (theta on the device).
 void precond_create(cib_ctx *ctx, const cib_basis &b, const cib_matrix &H, int max_block, cib_precond &P,

@@ -128,6 +128,72 @@ static void launch_count(int NP, dim3 g, hipStream_t s, int64_t n, int N, const 
   }
 }
 
+// ---------------------------------------------------------- no allocation
+// For callers that cannot allocate device memory (code under HIP graph
+// capture, tight serving loops, harnesses that forbid hipMalloc): the same
+// kernels with their scratch (encoded states, per-state counts, the total)
+// in one static device array.  Host code never names the array in a launch
+// or a copy: its address on each device is looked up once, with that device
+// current, and kept per device.
+constexpr int64_t kStaticCountStates = int64_t(1) << 17;
+constexpr size_t kStaticCountBytes =
+    (size_t)kStaticCountStates * sizeof(CountState) + (size_t)kStaticCountStates * sizeof(int32_t) + 256;
+static __device__ __align__(256) unsigned char scratch[kStaticCountBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices] = {};
+
+void static_scratch_init(int device) {
+  CIB_REQUIRE(device >= 0 && device < kMaxDevices, CIB_E_INVALID, "device index beyond the static scratch table");
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (g_scratch_ptr[device]) return;
+  int cur = -1;
+  CIB_HIP(hipGetDevice(&cur));
+  CIB_REQUIRE(cur == device, CIB_E_DEVICE, "static scratch set-up needs its device current");
+  void *ptr = nullptr;
+  CIB_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+  CIB_REQUIRE(ptr != nullptr, CIB_E_DEVICE, "hipGetSymbolAddress returned no address for the static scratch");
+  g_scratch_ptr[device] = ptr;
+}
+
+__global__ void k_fill_i32(int64_t n, int32_t *__restrict__ p, int32_t v) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+int64_t static_count_max_states() { return kStaticCountStates; }
+
+void count_pairs_static(int device, const uint16_t *mbs, int64_t n, int N, int method, int32_t *counts,
+                        int64_t *total, hipStream_t s) {
+  CIB_REQUIRE(n <= kStaticCountStates, CIB_E_INVALID,
+              "n exceeds the static scratch (" + std::to_string(kStaticCountStates) + " states)");
+  void *base = nullptr;
+  {
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    base = device >= 0 && device < kMaxDevices ? g_scratch_ptr[device] : nullptr;
+  }
+  CIB_REQUIRE(base, CIB_E_DEVICE, "static scratch was not set up on this device");
+  char *b = static_cast<char *>(base);
+  CountState *st = reinterpret_cast<CountState *>(b);
+  int32_t *own = reinterpret_cast<int32_t *>(b + (size_t)kStaticCountStates * sizeof(CountState));
+  int64_t *tot = reinterpret_cast<int64_t *>(b + (size_t)kStaticCountStates * (sizeof(CountState) + sizeof(int32_t)));
+  if (!counts) counts = own;
+  const dim3 g256((unsigned)((n + 255) / 256));
+  hipLaunchKernelGGL(k_count_encode, g256, dim3(256), 0, s, n, N, mbs, st);
+  // every call starts from zero counts: the array keeps the last call's values
+  hipLaunchKernelGGL(k_fill_i32, g256, dim3(256), 0, s, n, counts, 0);
+  const int NP = (N + 3) / 4 * 4;
+  const dim3 g((unsigned)((n + kCountThreads - 1) / kCountThreads), (unsigned)((n + kCountSlab - 1) / kCountSlab));
+  if (method == 0) launch_count<0>(NP, g, s, n, N, st, counts);
+  else if (method == 1) launch_count<1>(NP, g, s, n, N, st, counts);
+  else launch_count<2>(NP, g, s, n, N, st, counts);
+  hipLaunchKernelGGL(k_count_total, dim3(1), dim3(256), 0, s, n, counts, tot);
+  CIB_HIP(hipGetLastError());
+  CIB_HIP(hipMemcpyAsync(total, tot, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  CIB_HIP(hipStreamSynchronize(s));
+}
+
 void count_pairs(cib_ctx *ctx, const uint16_t *mbs, int64_t n, int N, int method, int32_t *counts, int64_t *total,
                  hipStream_t s) {
   UnwindFence fence(s);
