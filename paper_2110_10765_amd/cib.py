@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import weakref
 from typing import Optional, Sequence
 
 import numpy as np
@@ -274,9 +275,20 @@ class Context:
         self.device = device
 
     def close(self):
+        """Free every handle still made on this context, then the context
+        (handles must not outlive it; the cyclic garbage collector may run
+        their finalizers in any order)."""
         if getattr(self, "h", None):
+            for child in list(getattr(self, "_children", ())):
+                child.free()
             load().cib_destroy(self.h)
             self.h = None
+
+    def _adopt(self, child):
+        if not hasattr(self, "_children"):
+            self._children = weakref.WeakSet()
+        self._children.add(child)
+        return child
 
     def __del__(self):
         try:
@@ -303,6 +315,7 @@ class Context:
 class Basis:
     def __init__(self, ctx: Context, h, dim):
         self.ctx, self.h, self.dim = ctx, h, dim
+        ctx._adopt(self)
 
     def info(self):
         d, nab = ctypes.c_int64(), ctypes.c_int64()
@@ -332,6 +345,7 @@ class Basis:
 class Interaction:
     def __init__(self, ctx, h):
         self.ctx, self.h = ctx, h
+        ctx._adopt(self)
 
     def free(self):
         if self.h:
@@ -348,6 +362,7 @@ class Interaction:
 class Matrix:
     def __init__(self, ctx: Context, h):
         self.ctx, self.h = ctx, h
+        ctx._adopt(self)
         d, n, t = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
         _check(load().cib_matrix_info(h, ctypes.byref(d), ctypes.byref(n), ctypes.byref(t)))
         self.dim, self.nnz, self.dtype = d.value, n.value, ("f64" if t.value == CIB_F64 else "f32")
@@ -501,6 +516,7 @@ class Precond:
         h = ctypes.c_void_p()
         _check(load().cib_precond_create(ctx.h, basis.h, H.h, int(max_block), ctypes.byref(h)))
         self.h = h
+        ctx._adopt(self)
         nb, ng, lg, sw = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
         _check(load().cib_precond_info(self.h, ctypes.byref(nb), ctypes.byref(ng), ctypes.byref(lg),
                                        ctypes.byref(sw)))

@@ -38,8 +38,6 @@ void set_last_error(const std::string &msg);
   } while (0)
 
 constexpr int kMaxWords = 3;     // 64-bit words per species (nmax <= 6)
-constexpr int kWinRows = 64;     // rows of one SpMM window
-constexpr int kWinChunk = 8;     // columns (X rows) per staged chunk
 constexpr int kMaxBlock = 16;    // LOBPCG block size limit
 constexpr int kMaxSeg = 127;     // 2M_B segments (7 bits in tile info)
 
@@ -255,15 +253,6 @@ struct cib_matrix {
   cib_build_stats stats{};
   // row ranges of equal stored entries (both triangles), one per XCD
   int64_t xcd_rows[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-  // SpMM row windows (made by the first product that uses them): for window
-  // w (rows [w * kWinRows, (w + 1) * kWinRows)), win_chunks[win_off[w] ..
-  // win_off[w + 1]) lists, ascending, the chunks of kWinChunk consecutive
-  // columns that hold a stored entry of one of its rows (both triangles)
-  mutable bool win_planned = false;
-  mutable int64_t n_win = 0;
-  mutable int64_t win_xcd[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-  mutable cib::DBuf<int64_t> win_off;
-  mutable cib::DBuf<int32_t> win_chunks;
   const void *lo_val() const { return dtype == CIB_F64 ? (const void *)lo_val64.p : (const void *)lo_val32.p; }
   const void *val() const { return dtype == CIB_F64 ? (const void *)val64.p : (const void *)val32.p; }
 };
@@ -319,10 +308,6 @@ cib_interaction *upload_interaction(cib_ctx *ctx, const cib_basis &b, const cib_
 
 void spmm_sym(const cib_matrix &H, const void *X, int64_t ldx, void *Y, int64_t ldy, int nvec,
               hipStream_t s);
-// Makes the SpMM's row-window plan of H now (otherwise the first product
-// that uses it makes it), reserving its device bytes through reserve (stage
-// 3: scratch freed on return; stage 4: the plan, kept with H).
-void spmm_prepare(const cib_matrix &H, hipStream_t s, const BuildReserve &reserve);
 // Matrix-free Y = H X (nvec 8 or 16, 16-byte aligned rows of the dtype):
 // the build's screens and values, then one row pass that multiplies every
 // entry into X instead of storing it.  Returns when Y is written.

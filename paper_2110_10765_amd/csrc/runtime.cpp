@@ -307,12 +307,28 @@ cib::DevInter cib_interaction::view() const {
 // ------------------------------------------------------------------ context
 static size_t round_up(size_t n) { return (n + 255) & ~(size_t)255; }
 
+// A user allocator hook may run HIP calls of its own (torch's caching
+// allocator does, also on the library's worker threads): the device it
+// leaves current is put back, and an error it leaves on this thread is its
+// own and is discarded, so that the library's next launch check does not
+// report it.
+template <typename F>
+static void *call_hook(F &&f) {
+  int dev = -1;
+  const bool have = hipGetDevice(&dev) == hipSuccess;
+  void *r = f();
+  int now = -1;
+  if (have && hipGetDevice(&now) == hipSuccess && now != dev) (void)hipSetDevice(dev);
+  (void)hipGetLastError();
+  return r;
+}
+
 void *cib_ctx::alloc(size_t bytes) {
   bytes = round_up(std::max<size_t>(bytes, 256));
   void *p = nullptr;
   std::lock_guard<std::mutex> g(mu);
   if (has_user) {
-    p = user.alloc(bytes, user.user);
+    p = call_hook([&] { return user.alloc(bytes, user.user); });
     CIB_REQUIRE(p, CIB_E_NOMEM, "allocator returned NULL");
   } else {
     auto it = cache.find(bytes);
@@ -349,7 +365,10 @@ void cib_ctx::free(void *p) {
   if (it != sizes.end()) sizes.erase(it);
   live -= (int64_t)bytes;
   if (has_user) {
-    user.free(p, user.user);
+    call_hook([&] {
+      user.free(p, user.user);
+      return (void *)nullptr;
+    });
   } else {
     cache.emplace(bytes, p);
     cached += (int64_t)bytes;

@@ -144,8 +144,7 @@ cib_status serve_run(cib_ctx *ctx, const cib_request *reqs, int n, const cib_ser
       job->res = &res;
       cib_status st = CIB_OK;
       // the budget covers everything a request allocates: basis and tables,
-      // the build's scratch, H, the solver state and the SpMM's row-window
-      // plan.  Each allocation group is reserved (exact bytes) before it is
+      // the build's scratch, H and the solver state.  Each allocation group is reserved (exact bytes) before it is
       // made; only the first reservation waits, with nothing held.
       auto unreserve = [&](size_t bytes) {
         std::lock_guard<std::mutex> lk(sh.mu);
@@ -180,11 +179,10 @@ cib_status serve_run(cib_ctx *ctx, const cib_request *reqs, int n, const cib_ser
             job->inter.reset(upload_interaction(ctx, *job->basis, *q.tables, bstream));
             job->H.reset(new cib_matrix);
             job->H->ctx = ctx;
-            // stages 0, 1, 3: scratch freed when the build returns; 2: the
-            // stored entries (with them, the solver state they will need);
-            // 4: the SpMM's row-window plan
+            // stages 0, 1: scratch freed when the build returns; 2: the
+            // stored entries (with them, the solver state they will need)
             const BuildReserve reserve = [&](int stage, size_t bytes) {
-              if (stage == 0 || stage == 1 || stage == 3) scratch += bytes;
+              if (stage < 2) scratch += bytes;
               if (stage == 2) bytes += lobpcg_bytes(plan.D, q.solve.block, q.dtype);
               stages += bytes;
               const size_t want = basis_b + inter_b + stages;
@@ -198,7 +196,6 @@ cib_status serve_run(cib_ctx *ctx, const cib_request *reqs, int n, const cib_ser
               job->reserved += more;
             };
             build_matrix(ctx, *job->basis, *job->inter, q.dtype, *job->H, bstream, reserve);
-            spmm_prepare(*job->H, bstream, reserve);
           } catch (const GiveWay &) {
             // everything built so far is released (its stream drained first)
             // and the request starts again once its whole known footprint fits

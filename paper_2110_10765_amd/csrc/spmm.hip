@@ -16,13 +16,6 @@
 namespace cib {
 using namespace dev;
 
-constexpr int64_t kWinMinRows = 8192;   // smaller bases keep X in L2: the gather kernel
-
-__global__ void k_i64_to_i32(int64_t n, const int64_t *__restrict__ in, int32_t *__restrict__ out) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < n) out[i] = (int32_t)in[i];
-}
-
 // ------------------------------------------------------------ general path
 // Any nvec, any alignment: a wave per row, 64 / B entry slots times B vector
 // columns, so a gather of x_j is one contiguous segment.
@@ -210,274 +203,6 @@ __global__ __launch_bounds__(256) void k_spmm_vec_group(const VecArgs *__restric
   spmm_vec_row<T, NV>(a, i);
 }
 
-// ------------------------------------------------------------ row windows
-// Every stored entry of a row gathers one row of X, and few of those rows
-// are in L1: the gathers are one L2 request per entry, and that request
-// rate, not HBM, set the time of the kernel above.  A window of kWinRows
-// consecutive rows references each X row several times (about 2-3 times per
-// row of 8-row chunks at 64 rows), so here one workgroup takes a window and
-// stages the X rows it references into LDS once, with coalesced loads of
-// whole chunks of kWinChunk rows, and the entries read x_j from LDS.
-//
-// The plan lists, per window, the chunks its entries reference (both stored
-// triangles), ascending.  The product walks that list in batches: as many
-// chunks as the LDS buffer holds, spanning fewer than kWinSpan chunk ids, so
-// that a table indexed by (chunk - first chunk of the batch) gives each
-// entry its LDS slot with one read.  A row's entries are ascending in
-// column, so each batch takes the next run of entries of every row (a
-// cursor per row); the per-lane sums of a row stay in registers across the
-// batches and are reduced once at the end (fixed order: deterministic).
-constexpr int kWinMaxWords = 8192;   // plan bitmap: up to 262,144 chunks (32 KB of LDS)
-constexpr int kWinThreads = 512;     // 8 waves, kWinRows / 8 rows each
-constexpr int kWinXsBytes = 65536;   // staged X per batch (two workgroups per CU)
-constexpr int kWinSpan = 4096;       // chunk ids one batch may span (slot table entries)
-
-// Exclusive prefix sum of one int per thread over a 256-thread workgroup
-// (fixed order), and the total.
-__device__ __forceinline__ int block_excl_scan256(int v, int &total) {
-  __shared__ int wsum[4];
-  const int incl = wave_incl_scan_dpp(v);
-  const int wv = threadIdx.x >> 6;
-  if (lane_id() == kWave - 1) wsum[wv] = incl;
-  __syncthreads();
-  int before = 0;
-  for (int q = 0; q < wv; ++q) before += wsum[q];
-  total = (wsum[0] + wsum[1]) + (wsum[2] + wsum[3]);
-  __syncthreads();
-  return before + incl - v;
-}
-
-// Plan passes, one workgroup per window: the referenced chunks are marked in
-// an LDS bitmap; LIST = false counts them (cnt[w]), LIST = true writes them
-// ascending from off[w].
-template <bool LIST>
-__global__ __launch_bounds__(256) void k_win_mark(int64_t D, const int64_t *__restrict__ rp,
-                                                  const int32_t *__restrict__ col,
-                                                  const int64_t *__restrict__ lrp,
-                                                  const int32_t *__restrict__ lcol, int nwords,
-                                                  int64_t *__restrict__ cnt, const int64_t *__restrict__ off,
-                                                  int32_t *__restrict__ list) {
-  __shared__ uint32_t bm[kWinMaxWords];
-  const int64_t w = blockIdx.x;
-  const int64_t r0 = w * kWinRows, r1 = r0 + kWinRows < D ? r0 + kWinRows : D;
-  for (int q = threadIdx.x; q < nwords; q += 256) bm[q] = 0u;
-  __syncthreads();
-  const int wv = threadIdx.x >> 6, lane = lane_id();
-  for (int64_t i = r0 + wv; i < r1; i += 4) {
-    for (int half = 0; half < 2; ++half) {
-      const int64_t k0 = half ? rp[i] : lrp[i], k1 = half ? rp[i + 1] : lrp[i + 1];
-      const int32_t *c = half ? col : lcol;
-      for (int64_t k = k0 + lane; k < k1; k += kWave) {
-        const uint32_t ch = (uint32_t)c[k] / kWinChunk;
-        atomicOr(&bm[ch >> 5], 1u << (ch & 31));
-      }
-    }
-  }
-  __syncthreads();
-  const int per = (nwords + 255) / 256;
-  const int q0 = threadIdx.x * per, q1 = q0 + per < nwords ? q0 + per : nwords;
-  int c = 0;
-  for (int q = q0; q < q1; ++q) c += __popc(bm[q]);
-  int total = 0;
-  const int before = block_excl_scan256(c, total);
-  if (!LIST) {
-    if (threadIdx.x == 0) cnt[w] = total;
-    return;
-  }
-  int64_t at = off[w] + before;
-  for (int q = q0; q < q1; ++q) {
-    uint32_t m = bm[q];
-    while (m) {
-      const int b = __builtin_ctz(m);
-      m &= m - 1;
-      list[at++] = q * 32 + b;
-    }
-  }
-}
-
-struct WinArgs {
-  VecArgs v;
-  const int64_t *woff;
-  const int32_t *chunks;
-  int64_t wx[9];   // XCD x takes windows [wx[x], wx[x + 1])
-};
-
-template <typename T, int NV>
-__global__ __launch_bounds__(kWinThreads) void k_spmm_win(const WinArgs wa) {
-  constexpr int PER16 = 16 / sizeof(T);            // values per 16-byte part
-  constexpr int G = NV / PER16;                    // parts (lanes) per X row
-  constexpr int E = kWave / G;                     // entries per gather instruction
-  constexpr int RPW = kWinRows / (kWinThreads / kWave);
-  constexpr int XS = kWinXsBytes / (NV * (int)sizeof(T));   // X rows per batch
-  constexpr int KCH = XS / kWinChunk;              // chunks per batch
-  using V = typename std::conditional<sizeof(T) == 8, double2, float4>::type;
-  __shared__ V xs[XS * G];
-  __shared__ uint16_t tbl[kWinSpan];
-  __shared__ int rcur[kWinRows];
-  const VecArgs &a = wa.v;
-  const int x = blockIdx.x & 7;
-  const int64_t w = wa.wx[x] + (blockIdx.x >> 3);
-  if (w >= wa.wx[x + 1]) return;                    // the whole workgroup
-  const int64_t D = a.D;
-  const int wv = uni((int)(threadIdx.x >> 6));
-  const int lane = lane_id(), e = lane / G, g = lane % G;
-  const int64_t rb = w * kWinRows + wv * RPW;
-  const T *__restrict__ X = static_cast<const T *>(a.X);
-  const int32_t *__restrict__ col = a.col;
-  const int32_t *__restrict__ lcol = a.lcol;
-  const T *__restrict__ val = static_cast<const T *>(a.val);
-  const T *__restrict__ lval = static_cast<const T *>(a.lval);
-  if (lane < RPW) rcur[wv * RPW + lane] = 0;
-  T acc[RPW][PER16];
-#pragma unroll
-  for (int q = 0; q < RPW; ++q)
-#pragma unroll
-    for (int t = 0; t < PER16; ++t) acc[q][t] = T(0);
-  const int64_t c0 = wa.woff[w], c1 = wa.woff[w + 1];
-  for (int64_t s = c0; s < c1;) {
-    // the batch: at most KCH chunks, ids within kWinSpan of the first
-    const int32_t id0 = wa.chunks[s];
-    int64_t s1 = s + KCH < c1 ? s + KCH : c1;
-    for (int64_t t0 = s; t0 < s1; t0 += kWave) {
-      const int64_t t = t0 + lane;
-      const int32_t id = t < s1 ? wa.chunks[t] : id0;
-      const uint64_t m = __ballot(id - id0 >= kWinSpan);
-      if (m) {
-        s1 = t0 + __builtin_ctzll(m);
-        break;
-      }
-    }
-    const int nch = (int)(s1 - s);
-    for (int q = threadIdx.x; q < nch * kWinChunk * G; q += kWinThreads) {
-      const int k = q / (kWinChunk * G), rem = q % (kWinChunk * G);
-      const int rr = rem / G, part = rem % G;
-      const int64_t row = (int64_t)wa.chunks[s + k] * kWinChunk + rr;
-      V v;
-      if constexpr (sizeof(T) == 8) v = make_double2(0.0, 0.0);
-      else v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (row < D) v = reinterpret_cast<const V *>(X + row * a.ldx)[part];
-      xs[(k * kWinChunk + rr) * G + part] = v;
-    }
-    for (int k = threadIdx.x; k < nch; k += kWinThreads) tbl[wa.chunks[s + k] - id0] = (uint16_t)k;
-    const int64_t cend = ((int64_t)wa.chunks[s1 - 1] + 1) * kWinChunk;   // the batch's columns end here
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < RPW; ++q) {
-      const int64_t i = rb + q;
-      if (i >= D) continue;
-      const int64_t lb = a.lrp[i], ub = a.rp[i];
-      const int nl = (int)(a.lrp[i + 1] - lb);
-      const int n = nl + (int)(a.rp[i + 1] - ub);
-      int cur = uni(rcur[wv * RPW + q]);
-      while (cur < n) {
-        // loads issued for every lane (lanes past the row read the row's
-        // first upper entry and discard it)
-        const int p = cur + lane;
-        const bool in = p < n, lo = p < nl;
-        const int64_t k = !in ? ub : lo ? lb + p : ub + (p - nl);
-        const int32_t *cp = in && lo ? lcol : col;
-        const T *vp = in && lo ? lval : val;
-        const int32_t jl = cp[k];
-        const T hl = vp[k];
-        const bool ok = in && jl < cend;
-        const int cnt = (int)__popcll(__ballot(ok));   // a prefix of the lanes: columns ascend
-        if (cnt == 0) break;
-        const int32_t j = ok ? jl : 0;
-        const T h = ok ? hl : T(0);
-#pragma unroll
-        for (int u = 0; u < G; ++u) {
-          if (u * E >= cnt) break;
-          const int src = u * E + e;
-          const int32_t jj = __shfl(j, src, kWave);
-          const T hh = __shfl(h, src, kWave);
-          const bool use = src < cnt;
-          // (the plan puts every entry's chunk in a batch; the clamps only
-          // keep a wrong plan inside the arrays)
-          const int ch = use ? min(max(jj / kWinChunk - id0, 0), kWinSpan - 1) : 0;
-          const int slot = min((int)tbl[ch], KCH - 1) * kWinChunk + (jj & (kWinChunk - 1));
-          const V xv = xs[slot * G + g];
-          if (use) {
-            if constexpr (sizeof(T) == 8) {
-              acc[q][0] += hh * xv.x;
-              acc[q][1] += hh * xv.y;
-            } else {
-              acc[q][0] += hh * xv.x;
-              acc[q][1] += hh * xv.y;
-              acc[q][2] += hh * xv.z;
-              acc[q][3] += hh * xv.w;
-            }
-          }
-        }
-        cur += cnt;
-        if (cnt < kWave) break;
-      }
-      if (lane == 0) rcur[wv * RPW + q] = cur;
-    }
-    __syncthreads();   // the next batch overwrites xs and tbl
-    s = s1;
-  }
-  constexpr int SEL = kWave / PER16;
-  T *Y = static_cast<T *>(a.Y);
-#pragma unroll
-  for (int q = 0; q < RPW; ++q) {
-    Bfly<T, PER16, kWave / 2, G>::run(acc[q], lane);
-    const int64_t i = rb + q;
-    if (i < D && (lane & (SEL - 1) & ~(G - 1)) == 0)
-      Y[i * a.ldy + g * PER16 + ((lane / SEL) & (PER16 - 1))] = acc[q][0];
-  }
-}
-
-// Window plan of H (once per matrix): chunk counts, offsets, chunk lists,
-// and window ranges for the 8 XCDs.  False when the basis is too large for
-// the plan's bitmap (the gather kernel is used then).
-static bool win_eligible(const cib_matrix &H) {
-  const int64_t nchunk = (H.D + kWinChunk - 1) / kWinChunk;
-  return H.D >= kWinMinRows && (nchunk + 31) / 32 <= kWinMaxWords;
-}
-
-static bool win_plan(const cib_matrix &H, hipStream_t s, const BuildReserve &reserve = nullptr) {
-  if (H.win_planned) return H.n_win > 0;
-  if (!win_eligible(H)) {
-    H.win_planned = true;
-    return false;
-  }
-  UnwindFence fence(s);
-  const int64_t D = H.D;
-  const int nwords = (int)(((D + kWinChunk - 1) / kWinChunk + 31) / 32);
-  cib_ctx *ctx = H.ctx;
-  const int64_t nw = (D + kWinRows - 1) / kWinRows;
-  const size_t nscr = scan_scratch({nw});
-  if (reserve) {
-    reserve(3, dev_bytes((size_t)nw * 4) + dev_bytes((size_t)nw * 8) + dev_bytes(nscr * 8));
-    reserve(4, dev_bytes(((size_t)nw + 1) * 8));
-  }
-  DBuf<int32_t> cnt32(ctx, (size_t)nw);
-  DBuf<int64_t> cnt(ctx, (size_t)nw), scratch(ctx, nscr);
-  hipLaunchKernelGGL((k_win_mark<false>), dim3((unsigned)nw), dim3(256), 0, s, D, H.row_ptr.p, H.col.p,
-                     H.lo_ptr.p, H.lo_col.p, nwords, cnt.p, (const int64_t *)nullptr, (int32_t *)nullptr);
-  hipLaunchKernelGGL(k_i64_to_i32, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, s, nw, cnt.p, cnt32.p);
-  H.win_off.reset(ctx, (size_t)nw + 1);
-  launch_scans({{cnt32.p, nw, H.win_off.p}}, scratch.p, s);
-  int64_t total = 0;
-  CIB_HIP(hipMemcpyAsync(&total, H.win_off.p + nw, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  CIB_HIP(hipStreamSynchronize(s));
-  if (reserve) reserve(4, dev_bytes((size_t)std::max<int64_t>(total, 1) * 4));
-  H.win_chunks.reset(ctx, (size_t)std::max<int64_t>(total, 1));
-  hipLaunchKernelGGL((k_win_mark<true>), dim3((unsigned)nw), dim3(256), 0, s, D, H.row_ptr.p, H.col.p,
-                     H.lo_ptr.p, H.lo_col.p, nwords, (int64_t *)nullptr, H.win_off.p, H.win_chunks.p);
-  CIB_HIP(hipGetLastError());
-  // XCD x takes the windows that start in its row range (ranges of equal
-  // stored entries)
-  for (int q = 0; q < 9; ++q) H.win_xcd[q] = std::min<int64_t>(nw, (H.xcd_rows[q] + kWinRows - 1) / kWinRows);
-  H.win_xcd[8] = nw;
-  CIB_HIP(hipStreamSynchronize(s));
-  H.n_win = nw;
-  H.win_planned = true;
-  return true;
-}
-
-void spmm_prepare(const cib_matrix &H, hipStream_t s, const BuildReserve &reserve) { win_plan(H, s, reserve); }
-
 // ------------------------------------------------------------ host side
 template <typename T>
 static void spmm_t(const cib_matrix &H, const T *X, int64_t ldx, T *Y, int64_t ldy, int nvec,
@@ -487,19 +212,6 @@ static void spmm_t(const cib_matrix &H, const T *X, int64_t ldx, T *Y, int64_t l
   const T *lval = static_cast<const T *>(H.lo_val());
   const unsigned nblk = (unsigned)((D + 3) / 4);
   const bool aligned = ((uintptr_t)X % 16 == 0) && ((ldx * sizeof(T)) % 16 == 0);
-  if (aligned && (nvec == 8 || nvec == 16) && win_plan(H, s)) {
-    WinArgs wa{VecArgs{D, H.row_ptr.p, H.col.p, val, H.lo_ptr.p, H.lo_col.p, lval, X, ldx, Y, ldy, {}},
-               H.win_off.p, H.win_chunks.p, {}};
-    int64_t most = 0;
-    for (int x = 0; x < 9; ++x) wa.wx[x] = H.win_xcd[x];
-    for (int x = 0; x < 8; ++x) most = std::max<int64_t>(most, wa.wx[x + 1] - wa.wx[x]);
-    const unsigned grid = (unsigned)std::max<int64_t>(8, 8 * most);
-    KTimer kt(H.ctx, K_SPMM, s);
-    if (nvec == 8) hipLaunchKernelGGL((k_spmm_win<T, 8>), dim3(grid), dim3(kWinThreads), 0, s, wa);
-    else hipLaunchKernelGGL((k_spmm_win<T, 16>), dim3(grid), dim3(kWinThreads), 0, s, wa);
-    CIB_HIP(hipGetLastError());
-    return;
-  }
   if (aligned && (nvec == 8 || nvec == 16)) {
     // Each XCD takes one contiguous range of rows holding an eighth of the
     // stored entries (both triangles): X rows gathered by nearby rows stay in
@@ -541,9 +253,7 @@ bool spmm_vec_args(const cib_matrix &H, const void *X, int64_t ldx, void *Y, int
                    int &blocks) {
   const size_t sv = H.dtype == CIB_F64 ? 8 : 4;
   const bool aligned = ((uintptr_t)X % 16 == 0) && ((ldx * sv) % 16 == 0);
-  // (the window kernel runs alone: a solve on a matrix that takes it
-  // iterates by itself, with the same kernels as cib_lobpcg)
-  if (!aligned || (nvec != 8 && nvec != 16) || win_eligible(H)) return false;
+  if (!aligned || (nvec != 8 && nvec != 16)) return false;
   a = VecArgs{H.D, H.row_ptr.p, H.col.p, H.val(), H.lo_ptr.p, H.lo_col.p, H.lo_val(), X, ldx, Y, ldy, {}};
   blocks = (int)((H.D + 3) / 4);
   return true;
