@@ -75,6 +75,11 @@ typedef struct {
 /* Create a context on HIP device `device`.  hip_stream: a hipStream_t to issue
  * work on (NULL: the context creates its own default-priority stream). */
 cib_status cib_create(int device, const cib_allocator *alloc, void *hip_stream, cib_ctx **out);
+/* Release a context.  Handles made on it (basis, interaction, matrix,
+ * preconditioner) may be freed before or after: while some are live the
+ * context is only marked, and the free of the last one releases it, so the
+ * stream and allocator given to cib_create must stay valid until then.  No
+ * other call may use a destroyed context. */
 void cib_destroy(cib_ctx *ctx);
 const char *cib_last_error(void);
 /* Device bytes currently held by the context's allocations (live, not cached). */

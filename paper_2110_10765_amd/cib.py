@@ -275,9 +275,11 @@ class Context:
         self.device = device
 
     def close(self):
-        """Free every handle still made on this context, then the context
-        (handles must not outlive it; the cyclic garbage collector may run
-        their finalizers in any order)."""
+        """Free every handle still made on this context that is reachable,
+        then the context.  Handles the cyclic garbage collector finalizes
+        later (it clears the weak set first and runs finalizers in any order)
+        are still safe: the library keeps a destroyed context until its last
+        handle is freed."""
         if getattr(self, "h", None):
             for child in list(getattr(self, "_children", ())):
                 child.free()

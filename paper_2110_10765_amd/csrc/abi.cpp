@@ -117,8 +117,11 @@ cib_status cib_profile_query(cib_ctx *ctx, const char *kernel, int64_t *launches
   });
 }
 
-void cib_destroy(cib_ctx *ctx) {
-  if (!ctx) return;
+}  // extern "C"
+
+namespace {
+
+void ctx_teardown(cib_ctx *ctx) {
   try {
     DeviceGuard g(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
@@ -130,6 +133,37 @@ void cib_destroy(cib_ctx *ctx) {
   } catch (...) {
   }
   delete ctx;
+}
+
+void handle_made(cib_ctx *ctx) {
+  std::lock_guard<std::mutex> l(ctx->life_mu);
+  ++ctx->handles;
+}
+
+// After a handle's own release: the context goes too if it was destroyed
+// while this was its last handle.
+void handle_freed(cib_ctx *ctx) {
+  bool last;
+  {
+    std::lock_guard<std::mutex> l(ctx->life_mu);
+    last = --ctx->handles == 0 && ctx->destroyed;
+  }
+  if (last) ctx_teardown(ctx);
+}
+
+}  // namespace
+
+extern "C" {
+
+void cib_destroy(cib_ctx *ctx) {
+  if (!ctx) return;
+  bool now;
+  {
+    std::lock_guard<std::mutex> l(ctx->life_mu);
+    ctx->destroyed = true;
+    now = ctx->handles == 0;
+  }
+  if (now) ctx_teardown(ctx);
 }
 
 cib_status cib_ctx_bytes(const cib_ctx *ctx, int64_t *live, int64_t *peak) {
@@ -149,6 +183,7 @@ cib_status cib_build_basis(cib_ctx *ctx, const cib_basis_spec *spec, cib_basis *
     std::unique_ptr<cib_basis> b(make_basis(ctx, *spec, ctx->stream));
     const Plan &p = b->plan;
     if (dim) *dim = p.D;
+    handle_made(ctx);
     *out = b.release();
   });
 }
@@ -181,12 +216,14 @@ cib_status cib_basis_export(const cib_basis *b, uint64_t *host_words) {
 
 void cib_basis_free(cib_basis *b) {
   if (!b) return;
+  cib_ctx *ctx = b->ctx;
   try {
-    DeviceGuard g(b->ctx->device);
-    (void)hipStreamSynchronize(b->ctx->stream);
+    DeviceGuard g(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
   } catch (...) {
   }
   delete b;
+  handle_freed(ctx);
 }
 
 // ------------------------------------------------------------ interaction
@@ -197,17 +234,20 @@ cib_status cib_upload_interaction(cib_ctx *ctx, const cib_basis *b, const cib_ta
     BusyGuard busy(ctx);
     DeviceGuard g(ctx->device);
     *out = upload_interaction(ctx, *b, *t, ctx->stream);
+    handle_made(ctx);
   });
 }
 
 void cib_interaction_free(cib_interaction *it) {
   if (!it) return;
+  cib_ctx *ctx = it->ctx;
   try {
-    DeviceGuard g(it->ctx->device);
-    (void)hipStreamSynchronize(it->ctx->stream);
+    DeviceGuard g(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
   } catch (...) {
   }
   delete it;
+  handle_freed(ctx);
 }
 
 // ---------------------------------------------------------------- build H
@@ -224,6 +264,7 @@ cib_status cib_build_H_resident(cib_ctx *ctx, const cib_basis *b, const cib_inte
     H->ctx = ctx;
     build_matrix(ctx, *b, *it, dt, *H, ctx->stream, nullptr);
     if (nnz) *nnz = H->nnz;
+    handle_made(ctx);
     *out = H.release();
   });
 }
@@ -283,12 +324,14 @@ cib_status cib_matrix_device(const cib_matrix *H, const int64_t **row_ptr, const
 
 void cib_matrix_free(cib_matrix *H) {
   if (!H) return;
+  cib_ctx *ctx = H->ctx;
   try {
-    DeviceGuard g(H->ctx->device);
-    (void)hipStreamSynchronize(H->ctx->stream);
+    DeviceGuard g(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
   } catch (...) {
   }
   delete H;
+  handle_freed(ctx);
 }
 
 // ---------------------------------------------------------------- apply H
@@ -405,6 +448,7 @@ cib_status cib_precond_create(cib_ctx *ctx, const cib_basis *b, const cib_matrix
     DeviceGuard g(ctx->device);
     std::unique_ptr<cib_precond> P(new cib_precond);
     precond_create(ctx, *b, *H, max_block, *P, ctx->stream);
+    handle_made(ctx);
     *out = P.release();
   });
 }
@@ -446,12 +490,14 @@ cib_status cib_precond_apply(cib_ctx *ctx, const cib_precond *P, const double *t
 
 void cib_precond_free(cib_precond *P) {
   if (!P) return;
+  cib_ctx *ctx = P->ctx;
   try {
-    DeviceGuard g(P->ctx->device);
-    (void)hipStreamSynchronize(P->ctx->stream);
+    DeviceGuard g(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
   } catch (...) {
   }
   delete P;
+  handle_freed(ctx);
 }
 
 // ---------------------------------------------------------------- Lanczos

@@ -57,6 +57,11 @@ struct cib_ctx {
   int64_t live = 0, peak = 0, cached = 0;
   bool busy = false;
   void *pinned = nullptr;  // small pinned host staging buffer
+  // Handles made on this context and not yet freed.  cib_destroy while some
+  // are live only marks the context; the free of the last one releases it.
+  std::mutex life_mu;
+  int64_t handles = 0;
+  bool destroyed = false;
   size_t pinned_bytes = 0;
 
   // per-kernel event timing (cib_profile_*)

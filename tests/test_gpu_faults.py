@@ -11,6 +11,8 @@
   two solves, give identical bits (fixed summation orders throughout).
 * The serving budget bounds the context's device memory: its peak stays
   within the budget plus the serving loop's own small buffers.
+* A context destroyed while handles made on it are live stays usable by
+  their frees (the cyclic garbage collector finalizes in any order).
 """
 import ctypes
 import threading
@@ -88,6 +90,33 @@ def test_build_nomem_at_every_allocation():
     rp_r, col_r, val_r = oracle_csr(w.spec, w.seed)
     assert np.array_equal(rp, rp_r) and np.array_equal(col, col_r)
     assert np.abs(val - val_r).max() <= 1e-12
+
+
+def test_destroy_before_handles():
+    import gc
+    import torch
+    from paper_2110_10765_amd import cib
+    lib = cib.load()
+    ctx = cib.Context(0, torch_allocator=True)
+    w = cigen.WORKLOADS["ab_n3_3p3_cut4"]
+    b = cib.build_basis(ctx, w.spec)
+    H = cib.build_H(ctx, b, oracle_tables(w.spec, w.seed), "f64")
+    rp_r, col_r, val_r = oracle_csr(w.spec, w.seed)
+    lib.cib_destroy(ctx.h)  # the context is kept while b and H live
+    ctx.h = None
+    rp, col, val = _csr(H)
+    assert np.array_equal(rp, rp_r) and np.array_equal(col, col_r)
+    H.free()
+    b.free()  # the last handle: the context goes with it
+    # a cycle holding a context and its handles, collected in one pass
+    ctx2 = cib.Context(0, torch_allocator=True)
+    b2 = cib.build_basis(ctx2, w.spec)
+    H2 = cib.build_H(ctx2, b2, oracle_tables(w.spec, w.seed), "f32")
+    cycle = [ctx2, b2, H2]
+    cycle.append(cycle)
+    del ctx2, b2, H2, cycle
+    gc.collect()
+    torch.cuda.synchronize()
 
 
 def test_torch_allocator_build_product_solve():
