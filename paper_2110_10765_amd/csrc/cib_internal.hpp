@@ -376,8 +376,8 @@ void launch_spmm_group(cib_dtype dt, int nvec, const VecArgs *dev_args, const in
 
 // Arguments of one Rayleigh-Ritz step (device pointers of one solve).
 struct RRArgs {
-  int ns, b, nparts;
-  const double *partial;
+  int ns, b;
+  const double *gram;   // [S^T S | S^T H S], ns x 2 ns row-major
   double *C;        // ns x 2b: [Cx | Cp]
   double *lam;      // b
   int32_t *flag;    // [0]: rank of the search space, [1]: fallback taken

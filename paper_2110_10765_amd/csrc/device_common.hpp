@@ -33,11 +33,13 @@ __device__ __forceinline__ int64_t uni(int64_t v) {
 __device__ __forceinline__ uint64_t uni(uint64_t v) { return (uint64_t)uni((int64_t)v); }
 
 // Lane permutation within rows of 16 lanes through DPP (no LDS round trip).
+// For the permutations used here every lane has a valid source, so no old
+// value is needed (bound_ctrl).
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v) {
   const uint64_t u = __builtin_bit_cast(uint64_t, v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, false);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)u, CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, true);
   return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo);
 }
 

@@ -316,519 +316,7 @@ __global__ __launch_bounds__(1024) void k_min(int64_t n, const double *in, doubl
 
 // ------------------------------------------------------------ Rayleigh-Ritz
 
-__device__ __forceinline__ uint32_t sign_word(double v) {
-  return (uint32_t)(__builtin_bit_cast(uint64_t, v) >> 32);
-}
-
-// Number of eigenvalues of the symmetric tridiagonal (d, e2 = e^2) below x:
-// the sign changes of p_0 = 1, p_i = (d_i - x) p_{i-1} - e2_{i-1} p_{i-2}
-// (the characteristic polynomials of the leading blocks), which are the
-// negative pivots q_i = p_i / p_{i-1} of T - x I = L D L^T.  A zero p_i is
-// replaced by a tiny value of the sign opposite to p_{i-1} (a pivot of -0).
-// No division: one dependent FMA per step, and the sign changes are counted
-// from the sign bits.  p is rescaled by a power of two (exact) when it leaves
-// [2^-500, 2^500].  Steps past n are padded with d - x = 1, e2 = 0, which
-// repeat p and add no sign change.
-__device__ __forceinline__ int sturm_count(const double *d, const double *e2, int n, double x) {
-  double pm = 1.0;
-  double p = d[0] - x;
-  p = p == 0.0 ? -0x1p-600 : p;
-  uint32_t c = sign_word(p) >> 31;
-  for (int i0 = 1; i0 < n; i0 += 8) {
-    double dv[8], ev[8];
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      const int i = min(i0 + t, n - 1);
-      const bool in = i0 + t < n;
-      const double di = d[i], ei = e2[i - 1];
-      dv[t] = in ? di - x : 1.0;
-      ev[t] = in ? ei : 0.0;
-    }
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      // (the replacement depends on p only, so it is off the dependent chain)
-      const double rep = copysign(fmax(0x1p-600 * fabs(p), 0x1p-1000), -p);
-      double pn = fma(dv[t], p, -ev[t] * pm);
-      pn = pn == 0.0 ? rep : pn;
-      c += (sign_word(pn) ^ sign_word(p)) >> 31;
-      pm = p;
-      p = pn;
-    }
-    const double m = fmax(fabs(p), fabs(pm));
-    if (m > 0x1p500 || m < 0x1p-500) {
-      const double sc = ldexp(1.0, min(max(-ilogb(m), -1000), 1000));
-      p *= sc;
-      pm *= sc;
-    }
-  }
-  return (int)c;
-}
-
-// One workgroup.  (1) reduce the partial Gram matrices; (2) scale S^T S and
-// S^T H S to unit diagonal; (3) Cholesky S^T S = L L^T dropping columns whose
-// residual pivot falls below drop_tol (directions already spanned); (4) the
-// kept rows and columns compacted, Z = L^-1 and the reduced matrix
-// M = Z (S^T H S) Z^T;
-// (5) Householder reduction of M to tridiagonal form; (6) the lowest b
-// eigenvalues by multisection of Sturm counts; (7) their eigenvectors from
-// twisted LDL^T / UDU^T factorisations, re-orthogonalised inside clusters;
-// (8) back to M's basis with the Householder reflectors; (9) coefficients
-// C_x = scale * Z^T y and C_p = C_x with the X rows zeroed (P = W C_W + P C_P).
-__device__ __forceinline__ void rayleigh_ritz(const RRArgs &g) {
-  __shared__ double G[kNS][kLd], Hm[kNS][kLd], Z[kNS][kLd];
-  __shared__ double scale[kNS], dd[kNS], ee[kNS], e2[kNS], beta[kNS], dinv[kNS];
-  __shared__ double pw[4][kNS];
-  __shared__ double theta[kMaxBlock];
-  __shared__ int keep[kNS], kidx[kNS];
-  __shared__ int rank_s, retry_s;
-  const int ns_full = g.ns, b = g.b, tid = threadIdx.x, nt = blockDim.x;
-  const int nout = ns_full * 2 * ns_full;
-  int ns = ns_full, r = 0, nb = 0;
-  double drop_tol = g.drop_tol, tnorm = 0.0, pivmin = 0.0;
-  for (int attempt = 0; attempt < 2; ++attempt) {
-  // 1. reduce the partial Gram matrices (fixed order: deterministic); a
-  //    retry keeps only the first ns columns ([X W]) of the same matrices
-  auto place = [&](int e, double s) {
-    const int i = e / (2 * ns_full), j = e % (2 * ns_full);
-    if (i < ns) {
-      if (j < ns) G[i][j] = s;
-      else if (j >= ns_full && j - ns_full < ns) Hm[i][j - ns_full] = s;
-    }
-  };
-  if (g.nparts == 1 && nt == 256) {   // one matrix: all of a thread's reads in flight at once
-    constexpr int kPer = (kNS * 2 * kNS + 255) / 256;
-    double v[kPer];
-#pragma unroll
-    for (int t = 0; t < kPer; ++t) {
-      const int e = tid + 256 * t;
-      v[t] = e < nout ? g.partial[e] : 0.0;
-    }
-#pragma unroll
-    for (int t = 0; t < kPer; ++t)
-      if (tid + 256 * t < nout) place(tid + 256 * t, 0.0 + v[t]);
-  } else {
-    for (int e = tid; e < nout; e += nt) {
-      double s = 0.0;
-      for (int q = 0; q < g.nparts; ++q) s += g.partial[(int64_t)q * nout + e];
-      place(e, s);
-    }
-  }
-  __syncthreads();
-  // 2. symmetrise, scale to unit diagonal
-  for (int i = tid; i < ns; i += nt) {
-    const double d = G[i][i];
-    scale[i] = d > 1e-300 ? 1.0 / sqrt(d) : 0.0;
-  }
-  __syncthreads();
-  for (int e = tid; e < ns * ns; e += nt) {
-    const int i = e / ns, j = e % ns;
-    if (i <= j) {
-      const double si = scale[i] * scale[j];
-      const double gv = 0.5 * (G[i][j] + G[j][i]) * si;
-      const double hv = 0.5 * (Hm[i][j] + Hm[j][i]) * si;
-      G[i][j] = gv; G[j][i] = gv;
-      Hm[i][j] = hv; Hm[j][i] = hv;
-    }
-  }
-  __syncthreads();
-  // 3. right-looking Cholesky with dropping, in one wave with the matrix in
-  //    registers: lane i holds row i, the steps and columns are unrolled so
-  //    that every element of the row is a fixed register, and column k of L
-  //    reaches the other lanes through lane reads.  The whole trailing block
-  //    is updated (rows at or above the pivot have a zero multiplier): only
-  //    the lower triangle and the diagonal are read afterwards, and a
-  //    per-element row test costs more than the update.  (Over four waves
-  //    with the matrix in LDS a step took ~1.2 us of LDS round trips and
-  //    barriers.)
-  if (tid < kWave) {
-    const int i = tid;
-    const int ic = i < kNS ? i : kNS - 1;   // rows past the matrix read a valid row, then zero it
-    double gr[kNS];
-#pragma unroll
-    for (int q = 0; q < kNS; ++q) {
-      const double v = G[ic][q];
-      gr[q] = (i < ns && q < ns) ? v : 0.0;
-    }
-#pragma unroll
-    for (int k = 0; k < kNS; ++k) {
-      if (k < ns) {
-        const double piv = readlane_f64(gr[k], k);
-        const bool kk = scale[k] > 0.0 && piv > drop_tol;   // every lane decides the same
-        // 1/sqrt(piv) from the hardware estimate and one Newton step
-        double y = __builtin_amdgcn_rsq(kk ? piv : 1.0);
-        y = y * fma(-0.5 * (kk ? piv : 1.0) * y, y, 1.5);
-        const double ilkk = kk ? y : 0.0;
-        const double lkk = kk ? piv * y : 0.0;
-        const double lik = (i > k && i < ns) ? gr[k] * ilkk : 0.0;
-        if (i == 0) keep[k] = kk;
-        if (kk) {
-#pragma unroll
-          for (int j = k + 1; j < kNS; ++j) gr[j] -= lik * readlane_f64(lik, j);   // 0 past the matrix
-        }
-        gr[k] = i > k ? lik : (i == k ? lkk : gr[k]);
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < kNS; ++q)
-      if (i < ns && q < ns) G[i][q] = gr[q];
-  }
-  __syncthreads();
-  if (tid < kWave) {
-    const int i = tid;
-    const bool kp = i < ns && keep[i];
-    const uint64_t km = __ballot(kp);
-    if (kp) kidx[mask_rank(km)] = i;
-    if (i == 0) rank_s = (int)__popcll(km);
-    wave_lds_sync();
-    // 4a. compact L (G) and S^T H S (Hm) to the kept rows and columns, in
-    //     place: kidx increases, so every source lies at or after its
-    //     target in both indices, and a batch's loads precede its stores
-    const int rr = rank_s;
-    if (rr < ns && i < rr) {
-      const int ka = kidx[i];
-      for (int q0 = 0; q0 < rr; q0 += 8) {
-        double lv[8], hv[8];
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-          const int kq = kidx[min(q0 + t, rr - 1)];
-          lv[t] = G[ka][kq];
-          hv[t] = Hm[ka][kq];
-        }
-#pragma unroll
-        for (int t = 0; t < 8; ++t)
-          if (q0 + t < rr) {
-            G[i][q0 + t] = lv[t];
-            Hm[i][q0 + t] = hv[t];
-          }
-      }
-    }
-    wave_lds_sync();
-    // 4b. Z = L^-1 (r x r, lower triangular): lane j solves for column j by
-    //     forward substitution
-    if (i < rr) dinv[i] = 1.0 / G[i][i];
-    wave_lds_sync();
-    if (i < rr) {
-      for (int a = 0; a < i; ++a) Z[a][i] = 0.0;
-      Z[i][i] = dinv[i];
-      for (int a = i + 1; a < rr; ++a) {
-        double s0 = 0.0, s1 = 0.0;
-        for (int q0 = i; q0 < a; q0 += 8) {
-          double lv[8], zv[8];
-#pragma unroll
-          for (int t = 0; t < 8; ++t) {
-            const int q = min(q0 + t, a - 1);
-            lv[t] = G[a][q];
-            zv[t] = Z[q][i];
-          }
-#pragma unroll
-          for (int t = 0; t < 8; t += 2) {
-            if (q0 + t < a) s0 += lv[t] * zv[t];
-            if (q0 + t + 1 < a) s1 += lv[t + 1] * zv[t + 1];
-          }
-        }
-        Z[a][i] = -(s0 + s1) * dinv[a];
-      }
-    }
-  }
-  __syncthreads();
-  r = rank_s;
-  // 4c. T1 = Hm Z^T into G (L is no longer needed), then M = Z T1 into Hm
-  //     (dots of up to 48 terms, 8 table reads in flight)
-  for (int e = tid; e < r * r; e += nt) {
-    const int a = e / r, q = e % r;
-    double s0 = 0.0, s1 = 0.0;
-    for (int t0 = 0; t0 <= q; t0 += 8) {
-      double hv[8], zv[8];
-#pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        const int tt = min(t0 + t, q);
-        hv[t] = Hm[a][tt];
-        zv[t] = Z[q][tt];
-      }
-#pragma unroll
-      for (int t = 0; t < 8; t += 2) {
-        if (t0 + t <= q) s0 += hv[t] * zv[t];
-        if (t0 + t + 1 <= q) s1 += hv[t + 1] * zv[t + 1];
-      }
-    }
-    G[a][q] = s0 + s1;
-  }
-  __syncthreads();
-  for (int e = tid; e < r * r; e += nt) {
-    const int p = e / r, q = e % r;
-    double s0 = 0.0, s1 = 0.0;
-    for (int a0 = 0; a0 <= p; a0 += 8) {
-      double zv[8], tv[8];
-#pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        const int a = min(a0 + t, p);
-        zv[t] = Z[p][a];
-        tv[t] = G[a][q];
-      }
-#pragma unroll
-      for (int t = 0; t < 8; t += 2) {
-        if (a0 + t <= p) s0 += zv[t] * tv[t];
-        if (a0 + t + 1 <= p) s1 += zv[t + 1] * tv[t + 1];
-      }
-    }
-    Hm[p][q] = s0 + s1;
-  }
-  __syncthreads();
-  for (int e = tid; e < r * r; e += nt) {
-    const int i = e / r, j = e % r;
-    if (i < j) {
-      const double v = 0.5 * (Hm[i][j] + Hm[j][i]);
-      Hm[i][j] = v;
-      Hm[j][i] = v;
-    }
-  }
-  __syncthreads();
-  // 5. Householder tridiagonalisation of M (r x r in Hm).  Lane i of every
-  //    wave owns row i and computes the reflector redundantly (DPP sums, so
-  //    every wave gets the same bits); the product with the trailing block
-  //    and the rank-2 update are split over the waves by column ranges, and
-  //    the partial products are combined in LDS in wave order.  The
-  //    reflector of step k is kept in column k below the subdiagonal, its
-  //    scale in beta[k].
-  {
-    const int i = tid & (kWave - 1), wv = tid >> 6;
-    const bool row = i < r;
-    for (int k = 0; k + 2 < r; ++k) {
-      const bool act = row && i > k;
-      const double xi = act ? Hm[i][k] : 0.0;
-      const double sigma = wave_sum_dpp(xi * xi);
-      const double x0 = Hm[k + 1][k];
-      const double tail = sigma - x0 * x0;
-      const bool refl = tail > 1e-300;
-      const double alpha = refl ? -copysign(sqrt(sigma), x0) : x0;
-      const double bk = refl ? 2.0 / (tail + (x0 - alpha) * (x0 - alpha)) : 0.0;
-      const double vi = i == k + 1 ? x0 - alpha : xi;
-      const int m = r - k - 1;
-      const int q = (m + 3) / 4;
-      const int j0 = k + 1 + wv * q, j1 = min(r, j0 + q);
-      double acc = 0.0;
-      for (int j = j0; j < j1; ++j) {
-        const double vj = readlane_f64(vi, j);
-        if (act) acc += Hm[i][j] * vj;
-      }
-      if (i < kNS) pw[wv][i] = acc;
-      __syncthreads();
-      const double pi = i < kNS ? bk * ((pw[0][i] + pw[1][i]) + (pw[2][i] + pw[3][i])) : 0.0;
-      const double K = 0.5 * bk * wave_sum_dpp(vi * pi);
-      const double wi = pi - K * vi;
-      for (int j = j0; j < j1; ++j) {
-        const double vj = readlane_f64(vi, j), wj = readlane_f64(wi, j);
-        if (act) Hm[i][j] -= vi * wj + wi * vj;
-      }
-      if (wv == 0 && act) Hm[i][k] = vi;
-      if (tid == 0) {
-        beta[k] = bk;
-        ee[k] = alpha;
-      }
-      __syncthreads();
-    }
-  }
-  for (int i = tid; i < r; i += nt) {
-    dd[i] = Hm[i][i];
-    if (i == r - 2) ee[i] = Hm[r - 1][r - 2];
-  }
-  __syncthreads();
-  for (int i = tid; i + 1 < r; i += nt) e2[i] = ee[i] * ee[i];
-  __syncthreads();
-  // 6. lowest nb eigenvalues by multisection of the Gershgorin interval:
-  //    gsz threads per eigenvalue (32 when nb <= 8, else 16), each round
-  //    cutting the interval into gsz + 1 parts, until (gsz + 1)^rounds > 2^53
-  nb = b < r ? b : r;
-  double gl = 1e300, gu = -1e300, emax = 0.0;
-  for (int i = 0; i < r; ++i) {
-    const double rad = (i > 0 ? fabs(ee[i - 1]) : 0.0) + (i + 1 < r ? fabs(ee[i]) : 0.0);
-    gl = fmin(gl, dd[i] - rad);
-    gu = fmax(gu, dd[i] + rad);
-    if (i + 1 < r) emax = fmax(emax, e2[i]);
-  }
-  tnorm = fmax(fabs(gl), fabs(gu));
-  pivmin = fmax(1e-300, 2.2e-308 * fmax(emax, 1.0));
-  gl -= 2.2e-16 * tnorm * 4 + pivmin;
-  gu += 2.2e-16 * tnorm * 4 + pivmin;
-  {
-    const int gsz = nb <= 8 ? 32 : 16;
-    const int rounds = gsz == 32 ? 11 : 14;
-    const double inv = 1.0 / (gsz + 1);
-    const int grp = tid / gsz, t = tid % gsz;
-    double lo = gl, hi = gu;
-    for (int round = 0; round < rounds; ++round) {
-      const double x = lo + (t + 1) * (hi - lo) * inv;
-      const bool above = grp < nb ? sturm_count(dd, e2, r, x) > grp : true;
-      const uint64_t m = __ballot(above);
-      const uint64_t gm = (m >> ((tid & 63) & ~(gsz - 1))) & ((1ull << gsz) - 1ull);
-      const int first = __builtin_ctzll(gm | (1ull << gsz));  // first sub-point with count > grp
-      const double nlo = first == 0 ? lo : lo + first * (hi - lo) * inv;
-      const double nhi = first == gsz ? hi : lo + (first + 1) * (hi - lo) * inv;
-      lo = nlo;
-      hi = nhi;
-    }
-    if (t == 0 && grp < nb) theta[grp] = 0.5 * (lo + hi);
-  }
-  __syncthreads();
-  // a Ritz value below the spectrum of H means a numerically dependent
-  // direction spoiled the reduced matrix: redo without P and a looser drop
-  if (tid == 0) {
-    const double lowb = g.hlow ? g.hlow[0] : -INFINITY;
-    retry_s = attempt == 0 && nb > 0 &&
-              (!(theta[0] == theta[0]) || theta[0] < lowb - 1e-6 * fmax(1.0, fabs(lowb)));
-  }
-  __syncthreads();
-  if (!retry_s) break;
-  ns = min(ns_full, 2 * b);
-  drop_tol = fmax(drop_tol * 1e4, 1e-6);
-  if (tid == 0) g.flag[1] = 1;
-  __syncthreads();
-  }
-  // 7. eigenvectors of the tridiagonal by twisted factorisation (one thread
-  //    each); workspace and vectors in G (free after step 4b):
-  //    rows [0, kNS) cols [0, 16): Y; rows [0,kNS) cols [16, 32): D+; [32, 48): D-
-  if (tid < nb) {
-    const int c = tid;
-    const double th = theta[c];
-    double *Y = &G[0][0];
-    auto Yr = [&](int i) -> double & { return G[i][c]; };
-    auto Dp = [&](int i) -> double & { return G[i][16 + c]; };
-    auto Dm = [&](int i) -> double & { return G[i][32 + c]; };
-    (void)Y;
-    // the pivots are carried in registers and only stored for later
-    double qc = dd[0] - th;
-    Dp(0) = qc;
-    for (int i = 0; i + 1 < r; ++i) {
-      double q = qc;
-      if (fabs(q) < pivmin) q = -pivmin;
-      qc = dd[i + 1] - th - e2[i] / q;
-      Dp(i + 1) = qc;
-    }
-    qc = dd[r - 1] - th;
-    Dm(r - 1) = qc;
-    for (int i = r - 2; i >= 0; --i) {
-      double q = qc;
-      if (fabs(q) < pivmin) q = -pivmin;
-      qc = dd[i] - th - e2[i] / q;
-      Dm(i) = qc;
-    }
-    int tw = 0;
-    double best = 1e300;
-    for (int i = 0; i < r; ++i) {
-      const double gam = fabs(Dp(i) + Dm(i) - (dd[i] - th));
-      if (gam < best) { best = gam; tw = i; }
-    }
-    // outward recurrences from the twist; a pivot is kept away from zero
-    // (|q| >= 1e-280 (1 + |e|)) and the partial vector is rescaled whenever an
-    // entry passes 1e10, so a nearly split matrix cannot overflow
-    Yr(tw) = 1.0;
-    double yc = 1.0;
-    for (int i = tw - 1; i >= 0; --i) {
-      double q = Dp(i);
-      const double qmin = 1e-280 * (1.0 + fabs(ee[i]));
-      if (fabs(q) < qmin) q = q < 0 ? -qmin : qmin;
-      yc = -(ee[i] / q) * yc;
-      Yr(i) = yc;
-      if (fabs(yc) > 1e10) {
-        const double sc = 1.0 / fabs(yc);
-        for (int j = i; j <= tw; ++j) Yr(j) *= sc;
-        yc *= sc;
-      }
-    }
-    yc = 1.0;
-    for (int i = tw + 1; i < r; ++i) {
-      double q = Dm(i);
-      const double qmin = 1e-280 * (1.0 + fabs(ee[i - 1]));
-      if (fabs(q) < qmin) q = q < 0 ? -qmin : qmin;
-      yc = -(ee[i - 1] / q) * yc;
-      Yr(i) = yc;
-      if (fabs(yc) > 1e10) {
-        const double sc = 1.0 / fabs(yc);
-        for (int j = 0; j <= i; ++j) Yr(j) *= sc;
-        yc *= sc;
-      }
-    }
-    double nrm = 0.0;
-    for (int i = 0; i < r; ++i) nrm += Yr(i) * Yr(i);
-    if (!(nrm > 0.0) || !(nrm < INFINITY)) {  // last resort: the twist's unit vector
-      for (int i = 0; i < r; ++i) Yr(i) = i == tw ? 1.0 : 0.0;
-      nrm = 1.0;
-    }
-    nrm = 1.0 / sqrt(nrm);
-    for (int i = 0; i < r; ++i) Yr(i) *= nrm;
-  }
-  __syncthreads();
-  // re-orthogonalise inside clusters of close eigenvalues (wave 0, in order)
-  if (tid < kWave) {
-    const double cl = 1e-5 * fmax(tnorm, 1e-300);
-    for (int c = 1; c < nb; ++c) {
-      bool any = false;
-      for (int j = 0; j < c; ++j) {
-        if (fabs(theta[c] - theta[j]) > cl) continue;
-        any = true;
-        double dot = 0.0;
-        for (int i = tid; i < r; i += kWave) dot += G[i][c] * G[i][j];
-        dot = wave_sum(dot);
-        for (int i = tid; i < r; i += kWave) G[i][c] -= dot * G[i][j];
-      }
-      if (any) {
-        double nrm = 0.0;
-        for (int i = tid; i < r; i += kWave) nrm += G[i][c] * G[i][c];
-        nrm = wave_sum(nrm);
-        nrm = 1.0 / sqrt(nrm);
-        for (int i = tid; i < r; i += kWave) G[i][c] *= nrm;
-      }
-    }
-  }
-  __syncthreads();
-  // 8. y <- Q y with the reflectors (last one first); 16 lanes per column,
-  //    each lane owning rows i = t mod 16 (no cross-lane memory hazards)
-  {
-    const int c = tid >> 4, t = tid & 15;
-    for (int k = r - 3; k >= 0; --k) {
-      const double bk = beta[k];
-      if (bk == 0.0) continue;
-      double dot = 0.0;
-      if (c < nb)
-        for (int i = k + 1 + t; i < r; i += 16) dot += Hm[i][k] * G[i][c];
-#pragma unroll
-      for (int o = 8; o > 0; o >>= 1) dot += __shfl_xor(dot, o, kWave);
-      if (c < nb)
-        for (int i = k + 1 + t; i < r; i += 16) G[i][c] -= bk * dot * Hm[i][k];
-    }
-  }
-  __syncthreads();
-  // 9. coefficients in S's columns
-  if (tid == 0) g.flag[0] = r;
-  for (int e = tid; e < ns_full * b; e += nt) {
-    const int k = e / b, c = e % b;
-    g.C[k * 2 * b + c] = 0.0;
-    g.C[k * 2 * b + b + c] = 0.0;
-  }
-  __syncthreads();
-  for (int e = tid; e < r * b; e += nt) {
-    const int a = e / b, c = e % b;
-    const int k = kidx[a];
-    double v = 0.0;
-    if (c < nb)
-      for (int q0 = a; q0 < r; q0 += 8) {
-        double zv[8], yv[8];
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-          const int q = min(q0 + t, r - 1);
-          zv[t] = Z[q][a];
-          yv[t] = G[q][c];
-        }
-#pragma unroll
-        for (int t = 0; t < 8; ++t)
-          if (q0 + t < r) v += zv[t] * yv[t];
-      }
-    v *= scale[k];
-    g.C[k * 2 * b + c] = v;
-    g.C[k * 2 * b + b + c] = k < b ? 0.0 : v;
-  }
-  for (int c = tid; c < b; c += nt) g.lam[c] = c < nb ? theta[c] : 0.0;
-}
+#include "rayleigh_ritz.hpp"
 
 __global__ __launch_bounds__(256) void k_rayleigh_ritz(RRArgs g) { rayleigh_ritz(g); }
 
@@ -1126,7 +614,7 @@ struct LobpcgRun {
   }
 
   RRArgs rr_args(int ns) const {
-    return RRArgs{ns, b, 1, gram.p, C.p, lam.p, flag.p, H.dtype == CIB_F64 ? 1e-10 : 1e-7, hlow.p};
+    return RRArgs{ns, b, gram.p, C.p, lam.p, flag.p, H.dtype == CIB_F64 ? 1e-10 : 1e-7, hlow.p};
   }
 
   void gram_step(int ns) {
