@@ -377,7 +377,7 @@ void launch_spmm_group(cib_dtype dt, int nvec, const VecArgs *dev_args, const in
 // Arguments of one Rayleigh-Ritz step (device pointers of one solve).
 struct RRArgs {
   int ns, b;
-  const double *gram;   // [S^T S | S^T H S], ns x 2 ns row-major
+  const double *gram;   // S^T S then S^T H S, each kNS x (kNS + 1) row-major (rows and columns < ns used)
   double *C;        // ns x 2b: [Cx | Cp]
   double *lam;      // b
   int32_t *flag;    // [0]: rank of the search space, [1]: fallback taken
@@ -414,6 +414,7 @@ struct SumArgs {   // out[g][e] = sum of in[q][e] over parts q of group g (group
   int nout, nparts, per;
   const double *in;
   double *out;
+  int pad;          // > 0: one [S^T S | S^T H S] pair of row length 2 pad, written padded (Rayleigh-Ritz layout)
 };
 struct FinishArgs {
   int b, nev, nparts;

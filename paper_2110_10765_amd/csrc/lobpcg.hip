@@ -255,7 +255,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 // (coalesced); all loads of a group are in flight together.  The Gram
 // reduction runs it twice: groups of 32 partial matrices, then the group sums.
 __device__ __forceinline__ void sum_parts_elem(int nout, int nparts, int per, const double *__restrict__ in,
-                                               double *__restrict__ out, int e, int grp) {
+                                               double *__restrict__ out, int e, int grp, int pad) {
   if (e >= nout) return;
   const int q0 = grp * per, q1 = min(nparts, q0 + per);
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
@@ -268,12 +268,18 @@ __device__ __forceinline__ void sum_parts_elem(int nout, int nparts, int per, co
     for (int t = 0; t < 8; ++t) acc[t & 3] += v[t];
   }
   for (; q < q1; ++q) acc[q & 3] += in[(int64_t)q * nout + e];
-  out[(int64_t)grp * nout + e] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+  const double v = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+  if (pad > 0) {   // one [S^T S | S^T H S] pair (pad = ns) into two kNS x kLd blocks
+    const int i = e / (2 * pad), j = e - i * 2 * pad;
+    out[(j < pad ? 0 : kNS * kLd) + i * kLd + (j < pad ? j : j - pad)] = v;
+  } else {
+    out[(int64_t)grp * nout + e] = v;
+  }
 }
 
 __global__ __launch_bounds__(256) void k_sum_parts(int nout, int nparts, int per, const double *__restrict__ in,
-                                                   double *__restrict__ out) {
-  sum_parts_elem(nout, nparts, per, in, out, blockIdx.x * blockDim.x + threadIdx.x, blockIdx.y);
+                                                   double *__restrict__ out, int pad) {
+  sum_parts_elem(nout, nparts, per, in, out, blockIdx.x * blockDim.x + threadIdx.x, blockIdx.y, pad);
 }
 
 // a job's workgroups cover (element block, group) as x + xblocks * group
@@ -283,7 +289,7 @@ __global__ __launch_bounds__(256) void k_sum_parts_group(const SumArgs *__restri
   const SumArgs a = as[j];
   const int loc = blockIdx.x - off[j];
   const int xb = (a.nout + 255) / 256;
-  sum_parts_elem(a.nout, a.nparts, a.per, a.in, a.out, (loc % xb) * 256 + threadIdx.x, loc / xb);
+  sum_parts_elem(a.nout, a.nparts, a.per, a.in, a.out, (loc % xb) * 256 + threadIdx.x, loc / xb, a.pad);
 }
 
 // Gershgorin lower bound of H: min_i (H_ii - sum_{j != i} |H_ij|), both halves.
@@ -564,7 +570,7 @@ struct LobpcgRun {
     upd_blocks = (int)((D + upd_rows - 1) / upd_rows);
     partial.reset(ctx, (size_t)gram_blocks * kNS * 2 * kNS);
     partial2.reset(ctx, (size_t)((gram_blocks + kSumGroup - 1) / kSumGroup) * kNS * 2 * kNS);
-    gram.reset(ctx, (size_t)kNS * 2 * kNS);
+    gram.reset(ctx, (size_t)2 * kNS * kLd);
     hlow.reset(ctx, 1);
     C.reset(ctx, kNS * 2 * kMaxBlock);
     lam.reset(ctx, kMaxBlock);
@@ -630,9 +636,9 @@ struct LobpcgRun {
       const int nout = ns * 2 * ns;
       const int groups = (gram_blocks + kSumGroup - 1) / kSumGroup;
       hipLaunchKernelGGL(k_sum_parts, dim3((nout + 255) / 256, groups), dim3(256), 0, s, nout, gram_blocks,
-                         kSumGroup, partial.p, partial2.p);
+                         kSumGroup, partial.p, partial2.p, 0);
       hipLaunchKernelGGL(k_sum_parts, dim3((nout + 255) / 256, 1), dim3(256), 0, s, nout, groups, groups,
-                         partial2.p, gram.p);
+                         partial2.p, gram.p, ns);
     }
   }
 
@@ -651,7 +657,7 @@ struct LobpcgRun {
     // per-block residual sums: groups of kSumGroup first, then k_finish
     const int ugroups = (upd_blocks + kSumGroup - 1) / kSumGroup;
     hipLaunchKernelGGL(k_sum_parts, dim3(1, ugroups), dim3(256), 0, s, 2 * b, upd_blocks, kSumGroup, npart.p,
-                       npart2.p);
+                       npart2.p, 0);
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, b, nev, ugroups, npart2.p, lam.p, tol, status.p, locked.p);
     CIB_HIP(hipGetLastError());
   }
@@ -731,9 +737,9 @@ struct LobpcgRun {
     p.gram_blocks = gram_blocks;
     const int nout = ns * 2 * ns, xb = (nout + 255) / 256;
     const int groups = (gram_blocks + kSumGroup - 1) / kSumGroup;
-    p.gs1 = SumArgs{nout, gram_blocks, kSumGroup, partial.p, partial2.p};
+    p.gs1 = SumArgs{nout, gram_blocks, kSumGroup, partial.p, partial2.p, 0};
     p.gs1_blocks = xb * groups;
-    p.gs2 = SumArgs{nout, groups, groups, partial2.p, gram.p};
+    p.gs2 = SumArgs{nout, groups, groups, partial2.p, gram.p, ns};
     p.gs2_blocks = xb;
     p.rr = rr_args(ns);
     p.TN = 2 * b <= 16 ? 1 : 2;
@@ -741,7 +747,7 @@ struct LobpcgRun {
                     locked.p};
     p.upd_blocks = upd_blocks;
     const int ugroups = (upd_blocks + kSumGroup - 1) / kSumGroup;
-    p.us = SumArgs{2 * b, upd_blocks, kSumGroup, npart.p, npart2.p};
+    p.us = SumArgs{2 * b, upd_blocks, kSumGroup, npart.p, npart2.p, 0};
     p.us_blocks = ugroups;   // 2b <= 32 outputs: one element block per group
     p.fin = FinishArgs{b, nev, ugroups, npart2.p, lam.p, tol, status.p, nullptr};
     p.fin.locked = locked.p;

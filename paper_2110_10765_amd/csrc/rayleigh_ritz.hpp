@@ -97,7 +97,9 @@ __device__ __forceinline__ int sturm_lds(const double *d, const double *es, int 
 
 __device__ __forceinline__ void rayleigh_ritz(const RRArgs &g) {
   constexpr int kCW = kNS / 4;   // columns per wave in the Cholesky and Z steps
-  __shared__ double G[kNS][kLd], Hm[kNS][kLd], Z[kNS][kLd];
+  __shared__ double GH[2][kNS][kLd], Z[kNS][kLd];
+  double (&G)[kNS][kLd] = GH[0];    // S^T S, then L, then workspace
+  double (&Hm)[kNS][kLd] = GH[1];   // S^T H S, then M and the reflectors
   __shared__ double scale[kNS], dd[kNS], ee[kNS], e2[kNS], beta[kNS], dinv[kNS];
   __shared__ double pw[4][kWave], hv[4][kWave], hw[4][kWave], sg[4], xb[kWave];   // Householder: partial products, v, w, next row and its norm
   __shared__ double colbuf[2][kWave];   // column k of L at Cholesky step k
@@ -113,35 +115,24 @@ __device__ __forceinline__ void rayleigh_ritz(const RRArgs &g) {
   double drop_tol = g.drop_tol, sc = 1.0, tns = 1.0;
   for (int attempt = 0; attempt < 2; ++attempt) {
   // -- phase 1
-  // 1. the Gram matrices [S^T S | S^T H S] (ns_full x 2 ns_full, row-major)
-  //    into G and Hm.
-  //    Wave w takes rows w, w + 4, ...; lane j columns j and j + 64, so a
-  //    lane's destination column is fixed and all of its reads are in flight
-  //    together.  A retry keeps only the first ns columns ([X W]).
+  // 1. S^T S and S^T H S, stored by the Gram reduction in this kernel's
+  //    layout (two kNS x kLd blocks), copied as they are in 16-byte pieces;
+  //    only rows and columns below ns are used (a retry keeps the leading
+  //    [X W] blocks)
   {
-    const int w2 = 2 * ns_full;
-    double *dst[2];
+    constexpr int kPieces = kNS * kLd;   // 16-byte pieces in both blocks
+    constexpr int kPer = (kPieces + 255) / 256;
+    const double2 *src = reinterpret_cast<const double2 *>(g.gram);
+    double2 *dst = reinterpret_cast<double2 *>(&GH[0][0][0]);
+    double2 v[kPer];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int j = lane + 64 * h;
-      dst[h] = j < ns ? &G[0][j] : ((j >= ns_full && j - ns_full < ns) ? &Hm[0][j - ns_full] : nullptr);
+    for (int t = 0; t < kPer; ++t) {
+      const int e = tid + 256 * t;
+      v[t] = src[e < kPieces ? e : 0];
     }
-    constexpr int kRows = kNS / 4;
-    double v[kRows][2];
 #pragma unroll
-    for (int m = 0; m < kRows; ++m)
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int i = wv + 4 * m, j = lane + 64 * h;
-        v[m][h] = (i < ns && j < w2) ? g.gram[i * w2 + j] : 0.0;
-      }
-#pragma unroll
-    for (int m = 0; m < kRows; ++m)
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int i = wv + 4 * m;
-        if (i < ns && dst[h]) dst[h][i * kLd] = v[m][h];
-      }
+    for (int t = 0; t < kPer; ++t)
+      if (tid + 256 * t < kPieces) dst[tid + 256 * t] = v[t];
   }
   __syncthreads();
   // -- phase 2
@@ -471,12 +462,17 @@ __device__ __forceinline__ void rayleigh_ritz(const RRArgs &g) {
       const double wi = pi - K * vi;
       hw[wv][i] = wi;
       wave_lds_sync();
-      double s2 = 0.0;
 #pragma unroll
-      for (int q = 0; q < kCW; ++q) {
-        ar[q] -= fma(vi, hw[wv][jw + q], wi * vv[q]);
-        const int j = jw + q;
-        s2 = (j > k + 1 && j < r) ? fma(ar[q], ar[q], s2) : s2;
+      for (int q = 0; q < kCW; ++q) ar[q] = fma(-wi, vv[q], fma(-vi, hw[wv][jw + q], ar[q]));
+      // squared norm of the next row right of its diagonal (columns past r
+      // hold zeros); only the wave holding column k + 1 needs a mask
+      double s2 = 0.0;
+      if (jw > k + 1) {
+#pragma unroll
+        for (int q = 0; q < kCW; ++q) s2 = fma(ar[q], ar[q], s2);
+      } else if (jw + kCW > k + 2) {
+#pragma unroll
+        for (int q = 0; q < kCW; ++q) s2 = jw + q > k + 1 ? fma(ar[q], ar[q], s2) : s2;
       }
       if (i == k + 1) {   // the next row, for the next step
 #pragma unroll
