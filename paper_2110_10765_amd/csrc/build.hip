@@ -245,6 +245,13 @@ __global__ __launch_bounds__(256) void k_state_diag(int64_t D, const int32_t *__
 // the lower triangle).  Kept: kA = 1, or kA = 2 with equal 2M_A (a kA = 2 pair
 // needs identical B configurations).  Tile data are computed with alpha as the
 // bra (row) and alpha' as the ket (column).
+// One tile (alpha, alpha') as the row passes read it: a single 16-byte load.
+// off = first state of alpha' (a CSR column, so below 2^31), len = states of
+// alpha', info and rb as written by k_tile_val.
+struct alignas(16) TileRec {
+  int32_t info, len, off, rb;
+};
+
 struct TileArgs {
   int nA;
   int nchunk;             // candidate chunks per configuration (units = nA * nchunk)
@@ -254,8 +261,8 @@ struct TileArgs {
   DevInter it;
   int32_t *tcnt;          // count pass: per unit
   const int64_t *t_ptr;   // fill pass: per unit
-  int64_t *t_off;
-  int32_t *t_len, *t_src, *t_dst;   // fill pass: (alpha, alpha') of every tile
+  TileRec *t_rec;         // fill pass: off and len of every tile
+  int32_t *t_src, *t_dst;   // fill pass: (alpha, alpha') of every tile
 };
 
 // Phase, info and value of one tile, alpha the bra (row) and alpha' the ket
@@ -268,8 +275,7 @@ __global__ __launch_bounds__(256) void k_tile_val(int64_t n, const int32_t *__re
                                                   const int32_t *__restrict__ dst,
                                                   const uint64_t *__restrict__ a_bits, int nAc,
                                                   const int32_t *__restrict__ a_seg, DevInter it,
-                                                  int32_t *__restrict__ t_info, double *__restrict__ t_val,
-                                                  int32_t *__restrict__ t_rb) {
+                                                  TileRec *__restrict__ t_rec, double *__restrict__ t_val) {
   const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (e >= n) return;
   const int alpha = src[e], j = dst[e];
@@ -284,7 +290,7 @@ __global__ __launch_bounds__(256) void k_tile_val(int64_t n, const int32_t *__re
   }
   const int p1 = pop_lowest<W>(part), h1 = pop_lowest<W>(hole);
   const int p2 = pop_lowest<W>(part), h2 = pop_lowest<W>(hole);
-  int info;
+  int info, rb = 0;
   double val;
   if (p2 < 0) {  // kA = 1
     const int sg = sign_single<W>(ca, p1, h1);
@@ -292,13 +298,14 @@ __global__ __launch_bounds__(256) void k_tile_val(int64_t n, const int32_t *__re
         common, [&](int x) { return vbar_same(it.pidxA, it.prowA, it.nA, it.vA, p1, x, h1); });
     val = sg * sum;
     info = 1 | (p1 << 2) | (h1 << 10) | ((sg < 0) << 18) | (a_seg[j] << 19);
-    t_rb[e] = it.arb ? it.arb[p1 * it.nA + h1] : 0;
+    rb = it.arb ? it.arb[p1 * it.nA + h1] : 0;
   } else {       // kA = 2
     const int sg = sign_double<W>(ca, p1, p2, h1, h2);
     val = sg * v_pair(it.pidxA, it.prowA, it.nA, it.vA, p1, p2, h1, h2);
     info = 2;
   }
-  t_info[e] = info;
+  t_rec[e].info = info;
+  t_rec[e].rb = rb;
   t_val[e] = val;
 }
 
@@ -351,8 +358,8 @@ __global__ __launch_bounds__(256) void k_tile_pass(TileArgs g) {
     const uint64_t msk = ballot(ok);
     if (FILL && ok) {
       const int64_t o = out + cnt + mask_rank(msk);
-      g.t_off[o] = g.a_off[j];
-      g.t_len[o] = g.a_len[j];
+      g.t_rec[o].off = (int32_t)g.a_off[j];
+      g.t_rec[o].len = g.a_len[j];
       g.t_src[o] = alpha;
       g.t_dst[o] = j;
     }
@@ -494,9 +501,9 @@ struct RowArgs {
   const int64_t *a_off;
   const uint64_t *a_bits, *b_bits;
   const double *eA;
-  const int64_t *t_ptr, *t_off;   // t_ptr per tile unit: alpha's tiles at [alpha * tstride, (alpha + 1) * tstride]
+  const int64_t *t_ptr;   // per tile unit: alpha's tiles at [alpha * tstride, (alpha + 1) * tstride]
   int tstride;
-  const int32_t *t_len, *t_info, *t_rb;
+  const TileRec *t_rec;
   const double *t_val;
   const int64_t *ls_ptr, *l1_seg;
   const int32_t *ls_self, *ls_pos, *ls_info, *l1_pos, *l1_info;
@@ -508,6 +515,34 @@ struct RowArgs {
   int32_t *col;
   void *val;
 };
+
+// The lower triangle's own arrays: its tile lists (the transposed tiles) and
+// its outputs.  Everything else it shares with the upper triangle's RowArgs;
+// passing only these (and making the lower RowArgs on the device from the
+// upper one) keeps one copy of the shared pointers in scalar registers
+// instead of two, which the fill kernel could not hold at eight waves per
+// SIMD without spilling them to vector lanes.
+struct LowerArgs {
+  const int64_t *t_ptr;
+  const TileRec *t_rec;
+  const double *t_val;
+  int32_t *rcnt;
+  const int64_t *row_ptr;
+  int32_t *col;
+  void *val;
+};
+
+__device__ __forceinline__ RowArgs lower_args(const RowArgs &g, const LowerArgs &l) {
+  RowArgs r = g;
+  r.t_ptr = l.t_ptr;
+  r.t_rec = l.t_rec;
+  r.t_val = l.t_val;
+  r.rcnt = l.rcnt;
+  r.row_ptr = l.row_ptr;
+  r.col = l.col;
+  r.val = l.val;
+  return r;
+}
 
 // Where a fill pass sends each entry (column j, value v): NoAcc stores it in
 // the CSR arrays; ApplyAcc multiplies it into row j of X (the matrix-free
@@ -623,11 +658,12 @@ __device__ __forceinline__ void row_tiles(const RowArgs &g, int64_t t0, int64_t 
   };
   auto fetch = [&](int64_t tb, Batch &d) {
     const int64_t t = min(tb + lane, t1 - 1);
-    d.info = g.t_info[t];
-    d.len = g.t_len[t];
+    const int4 r = reinterpret_cast<const int4 *>(g.t_rec)[t];
+    d.info = r.x;
+    d.len = r.y;
     if (FILL) {
-      d.off = (int)g.t_off[t];
-      d.rb = g.t_rb[t];
+      d.off = r.z;
+      d.rb = r.w;
       d.val = g.t_val[t];
     }
   };
@@ -723,7 +759,8 @@ __device__ __forceinline__ void row_tiles(const RowArgs &g, int64_t t0, int64_t 
 // Body of the row passes (count, fill, matrix-free apply) for row i, wave wv
 // of the workgroup; the kernels below describe the enumeration.
 template <int W, bool FILL, typename T, class Acc>
-__device__ __forceinline__ void row_pass(const RowArgs &g, const RowArgs &gl, int64_t i, int wv, Acc &acc) {
+__device__ __forceinline__ void row_pass(const RowArgs &g, const LowerArgs &lo, int64_t i, int wv, Acc &acc) {
+  const RowArgs gl = lower_args(g, lo);
   __shared__ int32_t s_pos[4][kL1Stage], s_info[4][FILL ? kL1Stage : 1], s_seg[4][kMaxSeg + 2];
   __shared__ int32_t s_mark[4][FILL ? kWave : 1];
   __shared__ __align__(16) int32_t s_spec[4][FILL ? 2 * kSpec : 1];
@@ -797,7 +834,7 @@ __device__ __forceinline__ void row_pass(const RowArgs &g, const RowArgs &gl, in
 // registers the compiler would otherwise keep cap it at seven (measured 12%
 // slower).
 template <int W, bool FILL, typename T>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_row_pass(RowArgs g, RowArgs gl) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_row_pass(RowArgs g, LowerArgs gl) {
   // plain block order: rows of very different lengths sit in runs, and
   // giving each XCD one contiguous range of rows (for L2 locality of the
   // tile lists) measured 30-40% slower from the imbalance between XCDs
@@ -814,7 +851,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
 // a fixed butterfly and lane 0 writes row i of Y.  X and Y rows of NV values
 // (8 or 16), 16-byte aligned.
 template <int W, typename T, int NV>
-__global__ __launch_bounds__(256) void k_row_apply(RowArgs g, RowArgs gl, const T *X, int64_t ldx, T *Y,
+__global__ __launch_bounds__(256) void k_row_apply(RowArgs g, LowerArgs gl, const T *X, int64_t ldx, T *Y,
                                                    int64_t ldy) {
   const int wv = uni((int)(threadIdx.x >> 6));
   const int64_t i = (int64_t)blockIdx.x * (blockDim.x / kWave) + wv;
@@ -1068,7 +1105,7 @@ struct Events {
 // SpMM) are built by the same passes side by side, so the host waits twice:
 // once for the sizes of the screens' lists, once for the two nonzero counts.
 template <int W, typename T, int NV>
-static void launch_apply(unsigned rblk, const RowArgs &ra, const RowArgs &rl, const ApplyReq &a, hipStream_t s) {
+static void launch_apply(unsigned rblk, const RowArgs &ra, const LowerArgs &rl, const ApplyReq &a, hipStream_t s) {
   hipLaunchKernelGGL((k_row_apply<W, T, NV>), dim3(rblk), dim3(256), 0, s, ra, rl, static_cast<const T *>(a.X),
                      a.ldx, static_cast<T *>(a.Y), a.ldy);
 }
@@ -1134,14 +1171,11 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
   if (reserve) {
     const size_t nt = at_least1(n_tiles), nl = at_least1(n_lt), ns = at_least1(n_ls), n1 = at_least1(n_l1);
     // screens, row counts, diagonal and the two offset arrays
-    reserve(1, (bytes(nt, 8) + 5 * bytes(nt, 4) + bytes(nt, 8)) + (bytes(nl, 8) + 5 * bytes(nl, 4) + bytes(nl, 8)) +
+    reserve(1, (bytes(nt, 16) + 2 * bytes(nt, 4) + bytes(nt, 8)) + (bytes(nl, 16) + 2 * bytes(nl, 4) + bytes(nl, 8)) +
                    bytes(nB, 4) + 4 * bytes(ns, 4) + 4 * bytes(n1, 4) + bytes(ns, 8) + 2 * bytes(p.D, 4) +
                    bytes(p.D, 8) + 2 * bytes(p.D + 1, 8));
   }
-  DBuf<int64_t> t_off(ctx, at_least1(n_tiles)), tl_off(ctx, at_least1(n_lt));
-  DBuf<int32_t> t_len(ctx, at_least1(n_tiles)), t_info(ctx, at_least1(n_tiles));
-  DBuf<int32_t> tl_len(ctx, at_least1(n_lt)), tl_info(ctx, at_least1(n_lt));
-  DBuf<int32_t> t_rb(ctx, at_least1(n_tiles)), tl_rb(ctx, at_least1(n_lt));
+  DBuf<TileRec> t_rec(ctx, at_least1(n_tiles)), tl_rec(ctx, at_least1(n_lt));
   DBuf<int32_t> t_src(ctx, at_least1(n_tiles)), t_dst(ctx, at_least1(n_tiles));
   DBuf<int32_t> tl_src(ctx, at_least1(n_lt)), tl_dst(ctx, at_least1(n_lt));
   DBuf<double> t_val(ctx, at_least1(n_tiles)), tl_val(ctx, at_least1(n_lt));
@@ -1151,8 +1185,8 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
   DBuf<int32_t> l1_src(ctx, at_least1(n_l1)), l1_dst(ctx, at_least1(n_l1));
   DBuf<double> ls_val(ctx, at_least1(n_ls));
   CIB_HIP(hipEventRecord(ev.e[2], s));
-  ta.t_ptr = t_ptr.p; ta.t_off = t_off.p; ta.t_len = t_len.p; ta.t_src = t_src.p; ta.t_dst = t_dst.p;
-  tl.t_ptr = tl_ptr.p; tl.t_off = tl_off.p; tl.t_len = tl_len.p; tl.t_src = tl_src.p; tl.t_dst = tl_dst.p;
+  ta.t_ptr = t_ptr.p; ta.t_rec = t_rec.p; ta.t_src = t_src.p; ta.t_dst = t_dst.p;
+  tl.t_ptr = tl_ptr.p; tl.t_rec = tl_rec.p; tl.t_src = tl_src.p; tl.t_dst = tl_dst.p;
   auto nb256 = [](int64_t n) { return dim3((unsigned)std::max<int64_t>((n + 255) / 256, 1)); };
   {
     KTimer kt(ctx, K_TILE, s);
@@ -1161,10 +1195,10 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
     // phases and values, one thread per tile
     if (n_tiles)
       hipLaunchKernelGGL((k_tile_val<W>), nb256(n_tiles), dim3(256), 0, s, n_tiles, t_src.p, t_dst.p,
-                         b.a_bits.p, nA, b.a_seg.p, it, t_info.p, t_val.p, t_rb.p);
+                         b.a_bits.p, nA, b.a_seg.p, it, t_rec.p, t_val.p);
     if (n_lt)
       hipLaunchKernelGGL((k_tile_val<W>), nb256(n_lt), dim3(256), 0, s, n_lt, tl_src.p, tl_dst.p,
-                         b.a_bits.p, nA, b.a_seg.p, it, tl_info.p, tl_val.p, tl_rb.p);
+                         b.a_bits.p, nA, b.a_seg.p, it, tl_rec.p, tl_val.p);
   }
   aa.ls_ptr = ls_ptr.p; aa.l1_seg = l1_seg.p; aa.ls_self = ls_self.p; aa.ls_pos = ls_pos.p;
   aa.l1_pos = l1_pos.p; aa.ls_src = ls_src.p; aa.ls_dst = ls_dst.p; aa.l1_src = l1_src.p; aa.l1_dst = l1_dst.p;
@@ -1187,23 +1221,20 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
   ra.D = p.D; ra.nA = nA; ra.nB = nB; ra.nseg = nseg;
   ra.row_a = b.row_a.p; ra.row_p = b.row_p.p; ra.row_b = b.row_b.p; ra.a_seg = b.a_seg.p; ra.a_len = b.a_len.p;
   ra.bseg_start = b.bseg_start.p; ra.a_off = b.a_off.p; ra.a_bits = b.a_bits.p; ra.b_bits = b.b_bits.p;
-  ra.eA = eA.p; ra.t_ptr = t_ptr.p; ra.tstride = nchunk; ra.t_off = t_off.p; ra.t_len = t_len.p; ra.t_info = t_info.p;
-  ra.t_val = t_val.p; ra.t_rb = t_rb.p; ra.ls_ptr = ls_ptr.p; ra.l1_seg = l1_seg.p; ra.ls_self = ls_self.p;
+  ra.eA = eA.p; ra.t_ptr = t_ptr.p; ra.tstride = nchunk; ra.t_rec = t_rec.p;
+  ra.t_val = t_val.p; ra.ls_ptr = ls_ptr.p; ra.l1_seg = l1_seg.p; ra.ls_self = ls_self.p;
   ra.ls_pos = ls_pos.p; ra.ls_info = ls_info.p; ra.l1_pos = l1_pos.p; ra.l1_info = l1_info.p;
   ra.ls_val = ls_val.p; ra.it = it;
   DBuf<int32_t> rcnt(ctx, p.D), rlcnt(ctx, p.D);
   ra.rcnt = rcnt.p;
-  RowArgs rl = ra;
-  rl.t_ptr = tl_ptr.p; rl.t_off = tl_off.p; rl.t_len = tl_len.p; rl.t_info = tl_info.p; rl.t_val = tl_val.p;
-  rl.t_rb = tl_rb.p;
-  rl.rcnt = rlcnt.p;
+  LowerArgs rl{tl_ptr.p, tl_rec.p, tl_val.p, rlcnt.p, nullptr, nullptr, nullptr};
   const unsigned rblk = (unsigned)((p.D + 3) / 4);
   DBuf<double> diag(ctx, p.D);
   if (ap) {
     hipLaunchKernelGGL((k_state_diag<W>), dim3((unsigned)((p.D + 255) / 256)), dim3(256), 0, s, p.D,
                        b.row_a.p, b.row_p.p, b.a_seg.p, b.bseg_start.p, b.a_bits.p, nA, b.b_bits.p, nB,
                        eA.p, eB.p, it, diag.p);
-    ra.diag = rl.diag = diag.p;
+    ra.diag = diag.p;
     {
       KTimer kt(ctx, K_APPLY_FREE, s);
       if (dt == CIB_F64) {
@@ -1226,7 +1257,6 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
                        eA.p, eB.p, it, diag.p);
   }
   ra.diag = diag.p;
-  rl.diag = diag.p;
   CIB_HIP(hipGetLastError());
   CIB_HIP(hipEventRecord(ev.e[4], s));
   H.row_ptr.reset(ctx, p.D + 1);

@@ -137,7 +137,9 @@ __global__ __launch_bounds__(256) void k_copy_cols(int64_t D, int n, const doubl
 // rows go from global memory straight into the operands (coalesced 128-byte
 // row pieces, no LDS).  Output tile (ti, tj): lane l, element v holds row
 // 16 ti + 4 v + (l / 16), column 16 tj + (l % 16) (checked on the device).
-// S^T S is symmetric: only its tiles ti <= tj are formed and mirrored.  The
+// S^T S and S^T HS are symmetric (H is): only their tiles ti <= tj are
+// formed, and mirrored (the Rayleigh-Ritz step symmetrises S^T HS anyway,
+// so the tiles below the diagonal added nothing but rounding).  The
 // four waves of a workgroup take alternate steps (the next step's rows load
 // during the current one) and are summed in LDS in wave order.  The matrix
 // cores are the limit here: measured about 36 TFLOP/s for this instruction.
@@ -156,13 +158,12 @@ __device__ __forceinline__ void gram_block(int64_t D, int ns, int ld, const doub
   const int w2 = 2 * ns;
   const int64_t r0 = (int64_t)blk * rows_per_blk;
   const int64_t r1 = min(D, r0 + rows_per_blk);
-  dbl4 ag[NG], ah[T][T];
+  dbl4 ag[NG], ah[NG];
 #pragma unroll
-  for (int a = 0; a < NG; ++a) ag[a] = dbl4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-  for (int a = 0; a < T; ++a)
-#pragma unroll
-    for (int c = 0; c < T; ++c) ah[a][c] = dbl4{0.0, 0.0, 0.0, 0.0};
+  for (int a = 0; a < NG; ++a) {
+    ag[a] = dbl4{0.0, 0.0, 0.0, 0.0};
+    ah[a] = dbl4{0.0, 0.0, 0.0, 0.0};
+  }
   // loads from a valid address in every lane, then select: a load under a
   // branch would make the compiler wait for the prefetch as well.  Columns
   // up to 16 T - 1 are read unclamped (S and HS carry kGramPad doubles of
@@ -189,9 +190,10 @@ __device__ __forceinline__ void gram_block(int64_t D, int ns, int ld, const doub
 #pragma unroll
     for (int a = 0; a < T; ++a) {
 #pragma unroll
-      for (int c = a; c < T; ++c, ++g) ag[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(xs[a], xs[c], ag[g], 0, 0, 0);
-#pragma unroll
-      for (int c = 0; c < T; ++c) ah[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(xs[a], xh[c], ah[a][c], 0, 0, 0);
+      for (int c = a; c < T; ++c, ++g) {
+        ag[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(xs[a], xs[c], ag[g], 0, 0, 0);
+        ah[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(xs[a], xh[c], ah[g], 0, 0, 0);
+      }
     }
 #pragma unroll
     for (int t = 0; t < T; ++t) {
@@ -217,15 +219,12 @@ __device__ __forceinline__ void gram_block(int64_t D, int ns, int ld, const doub
             const int i = 16 * a + 4 * v + kr, j = 16 * c + kc;
             if (i < ns && j < ns) {
               put(i, j, ag[g][v]);
-              if (c > a) put(j, i, ag[g][v]);
+              put(i, ns + j, ah[g][v]);
+              if (c > a) {
+                put(j, i, ag[g][v]);
+                put(j, ns + i, ah[g][v]);
+              }
             }
-          }
-#pragma unroll
-        for (int c = 0; c < T; ++c)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int i = 16 * a + 4 * v + kr, j = 16 * c + kc;
-            if (i < ns && j < ns) put(i, ns + j, ah[a][c][v]);
           }
       }
     }
