@@ -160,7 +160,10 @@ typedef struct {
   const double *v_ab;      /* cross-species blocked table; NULL for 1 species */
 } cib_tables;
 
-/* Upload the tables for `basis`'s orbital sets (host arrays, copied). */
+/* Upload the tables for `basis`'s orbital sets (host arrays, copied).
+ * CIB_E_OVERFLOW when the cross-species table, regrouped by orbital
+ * transitions, would hold 2^29 or more values (far beyond the bases of the
+ * paper's workloads). */
 cib_status cib_upload_interaction(cib_ctx *ctx, const cib_basis *basis, const cib_tables *t,
                                   cib_interaction **out);
 void cib_interaction_free(cib_interaction *it);

@@ -136,7 +136,11 @@ __global__ void k_build_vt(DevInter it, const VtBlock *blk, int nblk, const int3
 
 // V^AB_{(a,b),(c,d)} through the transition table (row base of a <- c from
 // the tile, column of b <- d from the B adjacency entry).
-__device__ __forceinline__ double vt_at(const DevInter &it, int32_t rb, int32_t col) { return it.vt[rb + col]; }
+// (a 32-bit byte offset: the load takes the scalar base and one vector
+// register; the table holds far fewer than 2^29 elements)
+__device__ __forceinline__ double vt_at(const DevInter &it, int32_t rb, int32_t col) {
+  return *reinterpret_cast<const double *>(reinterpret_cast<const char *>(it.vt) + (uint32_t)(rb + col) * 8u);
+}
 
 // Sum of f(k) over the set bits k of s (at most 64 * W), in ascending k, with
 // the table reads of four terms issued before their additions.  Skipped terms
@@ -376,6 +380,12 @@ __global__ __launch_bounds__(256) void k_tile_pass(TileArgs g) {
 // shift it (max_dm) holds no L1 entry and is not scanned.  Entry info:
 // orbitals changed (0, 1, 2) | phase bit << 2 | (one change b <- d) the column
 // of b <- d in the V^AB transition table << 3.
+// One B adjacency entry as the row passes read it (one 8-byte load): pos =
+// position of beta' in its 2M_B list, info as written by k_adj_val.
+struct alignas(8) AdjRec {
+  int32_t pos, info;
+};
+
 struct AdjArgs {
   int nB, nseg, max_dm;
   const uint64_t *b_bits;
@@ -384,7 +394,8 @@ struct AdjArgs {
   DevInter it;
   int32_t *ls_cnt, *l1_cnt;           // count pass
   const int64_t *ls_ptr, *l1_seg;     // fill pass
-  int32_t *ls_self, *ls_pos, *l1_pos;
+  int32_t *ls_self;
+  AdjRec *ls_rec, *l1_rec;                      // fill pass: pos of every entry
   int32_t *ls_src, *ls_dst, *l1_src, *l1_dst;   // (beta, beta') of every entry
 };
 
@@ -398,7 +409,7 @@ __global__ __launch_bounds__(256) void k_adj_val(int64_t n, const int32_t *__res
                                                  const int32_t *__restrict__ dst,
                                                  const uint64_t *__restrict__ b_bits, int nBc,
                                                  const double *__restrict__ eB, DevInter it,
-                                                 int32_t *__restrict__ info_out, double *__restrict__ val_out) {
+                                                 AdjRec *__restrict__ rec_out, double *__restrict__ val_out) {
   const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (e >= n) return;
   const int beta = src[e], bj = dst[e];
@@ -432,7 +443,7 @@ __global__ __launch_bounds__(256) void k_adj_val(int64_t n, const int32_t *__res
     info = 2;
     if (val_out) val = sg * v_pair(it.pidxB, it.prowB, it.nB, it.vB, p1, p2, h1, h2);
   }
-  info_out[e] = info;
+  rec_out[e].info = info;
   if (val_out) val_out[e] = val;
 }
 
@@ -473,14 +484,14 @@ __global__ __launch_bounds__(256) void k_adj_pass(AdjArgs g) {
     const uint64_t m_ls = ballot(in_ls), m_l1 = ballot(in_l1);
     if (FILL && in_ls) {
       const int64_t o = ls0 + c_ls + mask_rank(m_ls);
-      g.ls_pos[o] = j - lo;
+      g.ls_rec[o].pos = j - lo;
       g.ls_src[o] = beta;
       g.ls_dst[o] = j;
       if (d == 0) g.ls_self[beta] = (int32_t)o;
     }
     if (FILL && in_l1) {
       const int64_t o = l10 + c_l1 + mask_rank(m_l1);
-      g.l1_pos[o] = j - lo;
+      g.l1_rec[o].pos = j - lo;
       g.l1_src[o] = beta;
       g.l1_dst[o] = j;
     }
@@ -506,7 +517,8 @@ struct RowArgs {
   const TileRec *t_rec;
   const double *t_val;
   const int64_t *ls_ptr, *l1_seg;
-  const int32_t *ls_self, *ls_pos, *ls_info, *l1_pos, *l1_info;
+  const int32_t *ls_self;
+  const AdjRec *ls_rec, *l1_rec;
   const double *ls_val;
   const double *diag;       // fill pass: diagonal element of every state
   DevInter it;
@@ -595,8 +607,9 @@ __device__ __forceinline__ void row_diag(const RowArgs &g, int64_t i, int64_t e0
     const bool valid = k < e1;
     // all reads of the entry at once, at a clamped index
     const int64_t kq = valid ? k : e0;
-    const int pos = g.ls_pos[kq];
-    const int info = FILL ? g.ls_info[kq] : 0;
+    const int2 r = reinterpret_cast<const int2 *>(g.ls_rec)[kq];
+    const int pos = r.x;
+    const int info = FILL ? r.y : 0;
     const double lval = FILL ? g.ls_val[kq] : 0.0;
     const bool ok = valid && pos < len_a;
     const uint64_t m = ballot(ok);
@@ -610,12 +623,12 @@ __device__ __forceinline__ void row_diag(const RowArgs &g, int64_t i, int64_t e0
         const double s = (info >> 2) & 1 ? -1.0 : 1.0;
         v += s * spec_sum<W>(sa_idx, ab, g.it.arb, g.it.nA, [&](int32_t r) { return vt_at(g.it, r, bc); });
       }
-      const int64_t o = out + cnt + (k - k0);
       if constexpr (Acc::kApply) {
         acc.add((int32_t)(off_a + pos), v);
       } else {
-        g.col[o] = (int32_t)(off_a + pos);
-        val[o] = (T)v;
+        const uint32_t o = (uint32_t)(k - k0);   // from out + cnt, as a 32-bit byte offset below
+        *reinterpret_cast<int32_t *>(reinterpret_cast<char *>(g.col + (out + cnt)) + o * 4u) = (int32_t)(off_a + pos);
+        *reinterpret_cast<T *>(reinterpret_cast<char *>(val + (out + cnt)) + o * (uint32_t)sizeof(T)) = (T)v;
       }
     }
     cnt += __popcll(m);
@@ -632,11 +645,12 @@ struct L1View {
   const int32_t *seg32;   // ST: nseg + 1 offsets relative to the list start
   const int64_t *seg64;   // !ST: absolute offsets of beta's segments
   int64_t base;           // !ST: absolute offset of the list start
-  const int32_t *pos, *info;   // indexed relative to the list start
+  const int2 *rec;        // (pos, info), indexed relative to the list start
   __device__ __forceinline__ int seg(int h) const {
     if constexpr (ST) return seg32[h];
     else return (int)(seg64[h] - base);
   }
+  __device__ __forceinline__ int pos(int k) const { return rec[k].x; }
 };
 
 // Tile part of a row: tiles [t0, t1) in ascending alpha'.  Lanes over tiles;
@@ -685,7 +699,7 @@ __device__ __forceinline__ void row_tiles(const RowArgs &g, int64_t t0, int64_t 
         int lo = l0, hi = L.seg(gt + 1);
         while (lo < hi) {
           const int mid = (lo + hi) >> 1;
-          if (L.pos[mid] < len) lo = mid + 1; else hi = mid;
+          if (L.pos(mid) < len) lo = mid + 1; else hi = mid;
         }
         ne = lo - l0;
       }
@@ -697,19 +711,28 @@ __device__ __forceinline__ void row_tiles(const RowArgs &g, int64_t t0, int64_t 
       const bool two = (info & 3) == 2;
       const int32_t coff = ne ? cur.off : 0, rb = (!two && ne) ? cur.rb : 0;
       const double tv = ne ? cur.val : 0.0;
+      // this batch's outputs start at out + cnt (a matrix-free product
+      // stores nothing)
+      int32_t *const colb = Acc::kApply ? nullptr : g.col + (out + cnt);
+      T *const valb = Acc::kApply ? nullptr : val + (out + cnt);
       if (two && ne) {
         if constexpr (Acc::kApply) {
           acc.add(coff + p, tv);
         } else {
-          g.col[out + cnt + orel] = coff + p;
-          val[out + cnt + orel] = (T)tv;
+          colb[(uint32_t)orel] = coff + p;
+          valb[(uint32_t)orel] = (T)tv;
         }
       }
-      // kA = 1 entries, spread over the lanes
+      // kA = 1 entries, spread over the lanes.  What an entry's lane needs of
+      // its tile, made once per batch: list index = pl + k, output index
+      // (from the batch's first output) = po + k, the table row base with
+      // the tile's phase bit on top (rb < 2^31).
       const int n1 = two ? 0 : ne;
       const int incl1 = wave_incl_scan_dpp(n1);
       const int tot1 = __builtin_amdgcn_readlane(incl1, kWave - 1);
       const int st1 = incl1 - n1;
+      const int pl = l0 - st1, po = orel - st1;
+      const int prb = (int)((uint32_t)rb | ((uint32_t)(info >> 18) & 1u) << 31);
       // Window of 64 entries: each tile marks the slot where its entries
       // start (lane + 1), a prefix maximum spreads the marks, the owner of
       // the slot before the window covers the slots ahead of the first mark.
@@ -724,31 +747,31 @@ __device__ __forceinline__ void row_tiles(const RowArgs &g, int64_t t0, int64_t 
         const int own = max(wave_incl_max_dpp(mark[lane]), carry) - 1;
         wave_lds_sync();
         carry = __builtin_amdgcn_readlane(own + 1, kWave - 1);
-        const int q = k - __shfl(st1, own, kWave);
-        const int oinfo = __shfl(info, own, kWave);
-        const int ol0 = __shfl(l0, own, kWave);
+        const int il = __shfl(pl, own, kWave) + k;
+        const uint32_t io = (uint32_t)(__shfl(po, own, kWave) + k);   // unsigned: a 32-bit store offset
         const int ocoff = __shfl(coff, own, kWave);
-        const int orb = __shfl(rb, own, kWave);
-        const int oo = __shfl(orel, own, kWave);
+        const int orbs = __shfl(prb, own, kWave);
         if (k >= tot1) continue;
-        const double sa = (oinfo >> 18) & 1 ? -1.0 : 1.0;
-        const int li = L.info[ol0 + q];
-        const int lp = L.pos[ol0 + q];
+        const int orb = orbs & 0x7fffffff;
+        const int2 lr = L.rec[il];
+        const int li = lr.y, lp = lr.x;
         double v;
         if ((li & 3) == 0) {  // B unchanged: AA part + s_A sum_{y in beta} V^AB_{(a,y),(c,y)}
           double sum = 0.0;
           if (g.it.nB > 0)
             sum = spec_sum<W>(sb_idx, bb, g.it.bcol, g.it.nB, [&](int32_t c) { return vt_at(g.it, orb, c); });
-          v = g.t_val[tb + own] + sa * sum;   // (rare: a read, not a lane permute in a branch)
-        } else {              // one A and one B orbital change
-          const double sb = (li >> 2) & 1 ? -1.0 : 1.0;
-          v = sa * sb * vt_at(g.it, orb, li >> 3);
+          v = g.t_val[tb + own] + (orbs < 0 ? -sum : sum);   // (a read, not a lane permute in a branch)
+        } else {              // one A and one B orbital change: the two phases on the table element
+          const uint64_t neg = (uint64_t)(((uint32_t)orbs >> 31) ^ ((uint32_t)li >> 2 & 1u)) << 63;
+          v = __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, vt_at(g.it, orb, li >> 3)) ^ neg);
         }
         if constexpr (Acc::kApply) {
           acc.add(ocoff + lp, v);
         } else {
-          g.col[out + cnt + oo + q] = ocoff + lp;
-          val[out + cnt + oo + q] = (T)v;
+          // byte offsets as 32-bit values: the stores take the scalar base
+          // and a 32-bit vector offset (a row's outputs stay below 2^29)
+          *reinterpret_cast<int32_t *>(reinterpret_cast<char *>(colb) + io * 4u) = ocoff + lp;
+          *reinterpret_cast<T *>(reinterpret_cast<char *>(valb) + io * (uint32_t)sizeof(T)) = (T)v;
         }
       }
     }
@@ -761,7 +784,8 @@ __device__ __forceinline__ void row_tiles(const RowArgs &g, int64_t t0, int64_t 
 template <int W, bool FILL, typename T, class Acc>
 __device__ __forceinline__ void row_pass(const RowArgs &g, const LowerArgs &lo, int64_t i, int wv, Acc &acc) {
   const RowArgs gl = lower_args(g, lo);
-  __shared__ int32_t s_pos[4][kL1Stage], s_info[4][FILL ? kL1Stage : 1], s_seg[4][kMaxSeg + 2];
+  __shared__ int2 s_rec[4][kL1Stage];
+  __shared__ int32_t s_seg[4][kMaxSeg + 2];
   __shared__ int32_t s_mark[4][FILL ? kWave : 1];
   __shared__ __align__(16) int32_t s_spec[4][FILL ? 2 * kSpec : 1];
   const int lane = lane_id();
@@ -785,34 +809,37 @@ __device__ __forceinline__ void row_pass(const RowArgs &g, const LowerArgs &lo, 
   }
   // the CSR offsets of the row (a matrix-free product stores nothing)
   constexpr bool kStore = FILL && !Acc::kApply;
-  const int64_t out_u = kStore ? uni(g.row_ptr[i]) : 0, out_l = kStore ? uni(gl.row_ptr[i]) : 0;
+  const int64_t out_u = kStore ? uni(g.row_ptr[i]) : 0;
   const int64_t l1b = (int64_t)beta * g.nseg;
   const int64_t base = uni(g.l1_seg[l1b]);
   const int64_t n1 = uni(g.l1_seg[l1b + g.nseg]) - base;
   const int64_t t0u = uni(g.t_ptr[(int64_t)alpha * g.tstride]), t1u = uni(g.t_ptr[(int64_t)(alpha + 1) * g.tstride]);
-  const int64_t t0l = uni(gl.t_ptr[(int64_t)alpha * gl.tstride]);
-  const int64_t t1l = uni(gl.t_ptr[(int64_t)(alpha + 1) * gl.tstride]);
-  // beta's Lsame list: [ls_lo, ls_me) before beta itself, [ls_me, ls_hi) from it on
-  const int64_t ls_lo = uni(g.ls_ptr[beta]), ls_hi = uni(g.ls_ptr[beta + 1]), ls_me = uni((int64_t)g.ls_self[beta]);
   int64_t cu = 0, cl = 0;
+  // The four parts in column order.  What only the lower parts use is read
+  // after the upper parts (fewer values held in scalar registers across
+  // them).  beta's Lsame list: [ls_lo, ls_me) before beta itself, [ls_me,
+  // ls_hi) from it on.
+  auto parts = [&](const auto &L) {
+    constexpr bool ST = std::is_same<std::decay_t<decltype(L)>, L1View<true>>::value;
+    const int64_t ls_me = uni((int64_t)g.ls_self[beta]), ls_hi = uni(g.ls_ptr[beta + 1]);
+    row_diag<W, FILL, T>(g, i, ls_me, ls_hi, alpha, len_a, off_a, ab, sa_idx, out_u, cu, acc);
+    row_tiles<W, FILL, T, ST>(g, t0u, t1u, p, bb, sb_idx, out_u, cu, L, s_mark[wv], acc);
+    const int64_t out_l = kStore ? uni(gl.row_ptr[i]) : 0;
+    const int64_t t0l = uni(gl.t_ptr[(int64_t)alpha * gl.tstride]);
+    const int64_t t1l = uni(gl.t_ptr[(int64_t)(alpha + 1) * gl.tstride]);
+    row_tiles<W, FILL, T, ST>(gl, t0l, t1l, p, bb, sb_idx, out_l, cl, L, s_mark[wv], acc);
+    const int64_t ls_lo = uni(g.ls_ptr[beta]);
+    row_diag<W, FILL, T>(gl, i, ls_lo, ls_me, alpha, len_a, off_a, ab, sa_idx, out_l, cl, acc);
+  };
   if (n1 <= kL1Stage && g.nseg <= kMaxSeg + 1) {
     for (int64_t k = lane; k < n1; k += kWave) {
-      s_pos[wv][k] = g.l1_pos[base + k];
-      if (FILL) s_info[wv][k] = g.l1_info[base + k];
+      s_rec[wv][k] = reinterpret_cast<const int2 *>(g.l1_rec)[base + k];
     }
     for (int h = lane; h <= g.nseg; h += kWave) s_seg[wv][h] = (int32_t)(g.l1_seg[l1b + h] - base);
     wave_lds_sync();
-    const L1View<true> L{s_seg[wv], nullptr, 0, s_pos[wv], FILL ? s_info[wv] : nullptr};
-    row_diag<W, FILL, T>(g, i, ls_me, ls_hi, alpha, len_a, off_a, ab, sa_idx, out_u, cu, acc);
-    row_tiles<W, FILL, T, true>(g, t0u, t1u, p, bb, sb_idx, out_u, cu, L, s_mark[wv], acc);
-    row_tiles<W, FILL, T, true>(gl, t0l, t1l, p, bb, sb_idx, out_l, cl, L, s_mark[wv], acc);
-    row_diag<W, FILL, T>(gl, i, ls_lo, ls_me, alpha, len_a, off_a, ab, sa_idx, out_l, cl, acc);
+    parts(L1View<true>{s_seg[wv], nullptr, 0, s_rec[wv]});
   } else {
-    const L1View<false> L{nullptr, g.l1_seg + l1b, base, g.l1_pos + base, FILL ? g.l1_info + base : nullptr};
-    row_diag<W, FILL, T>(g, i, ls_me, ls_hi, alpha, len_a, off_a, ab, sa_idx, out_u, cu, acc);
-    row_tiles<W, FILL, T, false>(g, t0u, t1u, p, bb, sb_idx, out_u, cu, L, s_mark[wv], acc);
-    row_tiles<W, FILL, T, false>(gl, t0l, t1l, p, bb, sb_idx, out_l, cl, L, s_mark[wv], acc);
-    row_diag<W, FILL, T>(gl, i, ls_lo, ls_me, alpha, len_a, off_a, ab, sa_idx, out_l, cl, acc);
+    parts(L1View<false>{nullptr, g.l1_seg + l1b, base, reinterpret_cast<const int2 *>(g.l1_rec) + base});
   }
   if (!FILL && lane == 0) {
     g.rcnt[i] = (int32_t)cu;
@@ -1172,15 +1199,15 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
     const size_t nt = at_least1(n_tiles), nl = at_least1(n_lt), ns = at_least1(n_ls), n1 = at_least1(n_l1);
     // screens, row counts, diagonal and the two offset arrays
     reserve(1, (bytes(nt, 16) + 2 * bytes(nt, 4) + bytes(nt, 8)) + (bytes(nl, 16) + 2 * bytes(nl, 4) + bytes(nl, 8)) +
-                   bytes(nB, 4) + 4 * bytes(ns, 4) + 4 * bytes(n1, 4) + bytes(ns, 8) + 2 * bytes(p.D, 4) +
+                   bytes(nB, 4) + bytes(ns, 8) + 2 * bytes(ns, 4) + bytes(n1, 8) + 2 * bytes(n1, 4) + bytes(ns, 8) + 2 * bytes(p.D, 4) +
                    bytes(p.D, 8) + 2 * bytes(p.D + 1, 8));
   }
   DBuf<TileRec> t_rec(ctx, at_least1(n_tiles)), tl_rec(ctx, at_least1(n_lt));
   DBuf<int32_t> t_src(ctx, at_least1(n_tiles)), t_dst(ctx, at_least1(n_tiles));
   DBuf<int32_t> tl_src(ctx, at_least1(n_lt)), tl_dst(ctx, at_least1(n_lt));
   DBuf<double> t_val(ctx, at_least1(n_tiles)), tl_val(ctx, at_least1(n_lt));
-  DBuf<int32_t> ls_self(ctx, nB), ls_pos(ctx, at_least1(n_ls)), ls_info(ctx, at_least1(n_ls)),
-      l1_pos(ctx, at_least1(n_l1)), l1_info(ctx, at_least1(n_l1));
+  DBuf<int32_t> ls_self(ctx, nB);
+  DBuf<AdjRec> ls_rec(ctx, at_least1(n_ls)), l1_rec(ctx, at_least1(n_l1));
   DBuf<int32_t> ls_src(ctx, at_least1(n_ls)), ls_dst(ctx, at_least1(n_ls));
   DBuf<int32_t> l1_src(ctx, at_least1(n_l1)), l1_dst(ctx, at_least1(n_l1));
   DBuf<double> ls_val(ctx, at_least1(n_ls));
@@ -1200,18 +1227,18 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
       hipLaunchKernelGGL((k_tile_val<W>), nb256(n_lt), dim3(256), 0, s, n_lt, tl_src.p, tl_dst.p,
                          b.a_bits.p, nA, b.a_seg.p, it, tl_rec.p, tl_val.p);
   }
-  aa.ls_ptr = ls_ptr.p; aa.l1_seg = l1_seg.p; aa.ls_self = ls_self.p; aa.ls_pos = ls_pos.p;
-  aa.l1_pos = l1_pos.p; aa.ls_src = ls_src.p; aa.ls_dst = ls_dst.p; aa.l1_src = l1_src.p; aa.l1_dst = l1_dst.p;
+  aa.ls_ptr = ls_ptr.p; aa.l1_seg = l1_seg.p; aa.ls_self = ls_self.p; aa.ls_rec = ls_rec.p;
+  aa.l1_rec = l1_rec.p; aa.ls_src = ls_src.p; aa.ls_dst = ls_dst.p; aa.l1_src = l1_src.p; aa.l1_dst = l1_dst.p;
   {
     KTimer kt(ctx, K_ADJ, s);
     hipLaunchKernelGGL((k_adj_pass<W, true>), dim3(ablk), dim3(256), 0, s, aa);
     // phases, table columns and B-only values, one thread per entry
     if (n_ls)
       hipLaunchKernelGGL((k_adj_val<W>), nb256(n_ls), dim3(256), 0, s, n_ls, ls_src.p, ls_dst.p, b.b_bits.p,
-                         nB, eB.p, it, ls_info.p, ls_val.p);
+                         nB, eB.p, it, ls_rec.p, ls_val.p);
     if (n_l1)
       hipLaunchKernelGGL((k_adj_val<W>), nb256(n_l1), dim3(256), 0, s, n_l1, l1_src.p, l1_dst.p, b.b_bits.p,
-                         nB, eB.p, it, l1_info.p, (double *)nullptr);
+                         nB, eB.p, it, l1_rec.p, (double *)nullptr);
   }
   CIB_HIP(hipGetLastError());
   CIB_HIP(hipEventRecord(ev.e[3], s));
@@ -1223,7 +1250,7 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
   ra.bseg_start = b.bseg_start.p; ra.a_off = b.a_off.p; ra.a_bits = b.a_bits.p; ra.b_bits = b.b_bits.p;
   ra.eA = eA.p; ra.t_ptr = t_ptr.p; ra.tstride = nchunk; ra.t_rec = t_rec.p;
   ra.t_val = t_val.p; ra.ls_ptr = ls_ptr.p; ra.l1_seg = l1_seg.p; ra.ls_self = ls_self.p;
-  ra.ls_pos = ls_pos.p; ra.ls_info = ls_info.p; ra.l1_pos = l1_pos.p; ra.l1_info = l1_info.p;
+  ra.ls_rec = ls_rec.p; ra.l1_rec = l1_rec.p;
   ra.ls_val = ls_val.p; ra.it = it;
   DBuf<int32_t> rcnt(ctx, p.D), rlcnt(ctx, p.D);
   ra.rcnt = rcnt.p;

@@ -100,7 +100,8 @@ static TransLayout trans_layout(const Orbs &oa, const Orbs &ob) {
       T.atr.push_back(e);
     }
     T.total += (int64_t)B.na * nb;
-    CIB_REQUIRE(T.total < (int64_t(1) << 31), CIB_E_OVERFLOW, "transition table exceeds 2^31 entries");
+    // (the row passes address it with 32-bit byte offsets)
+    CIB_REQUIRE(T.total < (int64_t(1) << 29), CIB_E_OVERFLOW, "transition table exceeds 2^29 entries");
     if (nb) T.blocks.push_back(B);
   }
   return T;
