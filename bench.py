@@ -45,6 +45,14 @@ METRIC = "H nnz built/s; SpMM nnz·vec/s (FP64 vs FP32); solves/s + p99 latency"
 HBM_PEAK_GBS = 8000.0
 
 
+def _progress(msg):
+    """One line per finished phase on stderr (stdout carries only the JSON line)."""
+    print("bench: %s (%.0f s)" % (msg, time.perf_counter() - _T0), file=sys.stderr, flush=True)
+
+
+_T0 = time.perf_counter()
+
+
 def _sync():
     import torch
     torch.cuda.synchronize()
@@ -394,6 +402,7 @@ def serve_suite(cib, ctx, cigen, n_req, sweep=True):
     sub = {}
     for dt in ("f32", "f64"):
         sub["serve_" + dt] = serve_run(cib, ctx, cigen, dt, n_req)
+        _progress("serving stream %s done" % dt)
     if not sweep:
         return sub
     for dt, fracs in (("f32", (0.5, 0.8, 0.95)), ("f64", (0.8,))):
@@ -401,10 +410,12 @@ def serve_suite(cib, ctx, cigen, n_req, sweep=True):
         for f in fracs:
             sub["serve_%s_poisson_%02d" % (dt, round(100 * f))] = serve_run(cib, ctx, cigen, dt, n_req,
                                                                              rate=f * cap)
+            _progress("serving stream %s at %.2f of capacity done" % (dt, f))
     for dt in ("f32", "f64"):
         for gib in (2, 8):
             sub["serve_%s_budget_%dgib" % (dt, gib)] = serve_run(cib, ctx, cigen, dt, n_req,
                                                                  budget=gib << 30)
+            _progress("serving stream %s under %d GiB done" % (dt, gib))
     return sub
 
 
@@ -616,6 +627,7 @@ def main():
     for _ in range(args.warmup):
         step()
     _sync()
+    _progress("warm-up steps done")
     ctx.profile(True)
     rec = []
     _sync()
@@ -624,6 +636,7 @@ def main():
         step(rec)
     _sync()
     elapsed = time.perf_counter() - t0
+    _progress("timed steps done")
     kernels = {}
     for k in ("tile_screen", "adjacency", "row_count", "scan", "row_fill", "spmm_sym", "gram",
               "rayleigh_ritz", "update"):
@@ -673,12 +686,15 @@ def main():
         name, bb = item.split(":")
         ws[name] = workload_rates(cib, ctx, cigen, name, int(bb), copy_gbs=copy_gbs)
     sub["workloads"] = ws
+    _progress("workload rates done")
     sub["small_case"] = small_case_us(cib, ctx, cigen)
     if not args.no_next:
         sub["observables"] = observables_rate(cib, ctx, cigen, w.name, nnz)
         sub["lanczos"] = lanczos_rate(cib, ctx, cigen, w, inter)
+        _progress("observables and Lanczos done")
         sub["block_precond"] = precond_rates(cib, ctx, cigen, w, inter)
         sub["state_count"] = counting_rates(cib, ctx, cigen)
+        _progress("preconditioner and state counting done")
     if not args.no_serve:
         try:
             sub.update(serve_suite(cib, ctx, cigen, args.serve_requests, sweep=not args.no_serve_sweep))
@@ -697,8 +713,10 @@ def main():
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(cigen, w.name)
         line["cpu_baseline"]["phases"] = cpu_phase_baseline(cigen)
+        _progress("CPU oracle baseline done")
         if not args.no_serve:
             line["cpu_baseline"]["serve"] = cpu_serve_baseline(args.serve_requests)
+            _progress("CPU serving baseline done")
     print(json.dumps(line))
 
 
