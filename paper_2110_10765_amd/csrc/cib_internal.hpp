@@ -83,6 +83,11 @@ namespace cib {
 enum KernelId { K_TILE = 0, K_ADJ, K_ROW_COUNT, K_SCAN, K_ROW_FILL, K_SPMM, K_GRAM, K_RR, K_UPDATE, K_COUNT, K_APPLY_FREE, K_NKERN };
 extern const char *const kKernelNames[K_NKERN];
 
+// Timer marks recorded so far, and dropping the marks from index `from` on
+// (launches that turned out to do nothing: a solve's iterations queued past
+// its convergence).
+size_t profile_marks(cib_ctx *c);
+void profile_drop_marks(cib_ctx *c, size_t from);
 // Brackets one launch with events when profiling is on (RAII).
 struct KTimer {
   cib_ctx *ctx;
@@ -311,8 +316,14 @@ size_t interaction_device_bytes(const Plan &p);
 cib_interaction *upload_interaction(cib_ctx *ctx, const cib_basis &b, const cib_tables &t,
                                     hipStream_t s);
 
+// stop: optional device flag; the launched kernels return at once when it
+// is nonzero (a solve's iterations queued past its convergence).
 void spmm_sym(const cib_matrix &H, const void *X, int64_t ldx, void *Y, int64_t ldy, int nvec,
-              hipStream_t s);
+              hipStream_t s, const int32_t *stop = nullptr);
+// float32 H and X, Y written as float64 (the eigensolver's widened H W):
+// false, with nothing launched, when the vector kernel does not apply.
+bool spmm_sym_widen(const cib_matrix &H, const float *X, int64_t ldx, double *Y, int64_t ldy, int nvec,
+                    hipStream_t s, const int32_t *stop);
 // Matrix-free Y = H X (nvec 8 or 16, 16-byte aligned rows of the dtype):
 // the build's screens and values, then one row pass that multiplies every
 // entry into X instead of storing it.  Returns when Y is written.
@@ -349,8 +360,10 @@ void observables(cib_ctx *ctx, const cib_basis &b, const cib_tables *ops, int m,
 
 // Step-wise LOBPCG (used by the serving loop): all calls enqueue on the run's
 // stream; the status block (kStatusLen doubles: converged count, b relative
-// residuals, b Ritz values) is copied to host memory by lobpcg_copy_status.
-constexpr int kStatusLen = 1 + 2 * kMaxBlock;
+// residuals, b Ritz values, and the number of the iteration that wrote them)
+// is copied to host memory by lobpcg_copy_status.
+constexpr int kStatusIter = 1 + 2 * kMaxBlock;
+constexpr int kStatusLen = 2 + 2 * kMaxBlock;
 struct LobpcgRun;
 // Arguments of the SpMM row kernel for nvec 8 / 16 with 16-byte aligned rows.
 struct VecArgs {
@@ -366,6 +379,9 @@ struct VecArgs {
   void *Y;
   int64_t ldy;
   int64_t xr[9];     // XCD x takes rows [xr[x], xr[x + 1]) (single launches only)
+  const int32_t *stop = nullptr;   // a solve's stop flag: the launch does nothing once it is set
+  double *Y64 = nullptr;           // float32 matrix only: rows of Y written widened to float64 here
+  int64_t ldy64 = 0;
 };
 // false when the vector kernel does not apply (nvec, alignment); blocks =
 // workgroups of the matrix in a grouped launch
@@ -383,6 +399,7 @@ struct RRArgs {
   int32_t *flag;    // [0]: rank of the search space, [1]: fallback taken
   double drop_tol;
   const double *hlow;  // lower bound of the spectrum of H (Gershgorin)
+  const int32_t *stop = nullptr;   // a solve's stop flag: nothing is done once it is set
 };
 
 // Per-stage arguments of one LOBPCG iteration (device pointers of one solve).
@@ -395,6 +412,7 @@ struct UpdArgs {
   double *npart;          // per block: b residual sums, b |x|^2 sums
   int rows_per_blk;
   const int32_t *locked;  // per column: converged at the previous check (W = 0)
+  const int32_t *stop = nullptr;   // a solve's stop flag: nothing is done once it is set
 };
 struct WidenArgs {
   int64_t D;

@@ -108,7 +108,11 @@ __global__ __launch_bounds__(256) void k_narrow(int64_t D, int b, const double *
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k < D * b) out[k] = (float)in[(k / b) * ldi + (k % b)];
 }
-__global__ __launch_bounds__(256) void k_widen(int64_t D, int b, const float *in, double *out, int ldo) {
+// stop (here and below): a solve's stop flag; nonzero once it has converged,
+// so the launches of iterations queued past that point do nothing
+__global__ __launch_bounds__(256) void k_widen(int64_t D, int b, const float *in, double *out, int ldo,
+                                               const int32_t *stop) {
+  if (*stop) return;
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k < D * b) out[(k / b) * ldo + (k % b)] = (double)in[k];
 }
@@ -237,7 +241,8 @@ __device__ __forceinline__ void gram_block(int64_t D, int ns, int ld, const doub
 template <int T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_gram(
     int64_t D, int ns, int ld, const double *__restrict__ S, const double *__restrict__ HS,
-    int64_t rows_per_blk, double *__restrict__ partial) {
+    int64_t rows_per_blk, double *__restrict__ partial, const int32_t *stop) {
+  if (*stop) return;
   gram_block<T>(D, ns, ld, S, HS, rows_per_blk, partial, blockIdx.x);
 }
 
@@ -277,7 +282,8 @@ __device__ __forceinline__ void sum_parts_elem(int nout, int nparts, int per, co
 }
 
 __global__ __launch_bounds__(256) void k_sum_parts(int nout, int nparts, int per, const double *__restrict__ in,
-                                                   double *__restrict__ out, int pad) {
+                                                   double *__restrict__ out, int pad, const int32_t *stop) {
+  if (*stop) return;
   sum_parts_elem(nout, nparts, per, in, out, blockIdx.x * blockDim.x + threadIdx.x, blockIdx.y, pad);
 }
 
@@ -323,7 +329,10 @@ __global__ __launch_bounds__(1024) void k_min(int64_t n, const double *in, doubl
 
 #include "rayleigh_ritz.hpp"
 
-__global__ __launch_bounds__(256) void k_rayleigh_ritz(RRArgs g) { rayleigh_ritz(g); }
+__global__ __launch_bounds__(256) void k_rayleigh_ritz(RRArgs g) {
+  if (g.stop && *g.stop) return;
+  rayleigh_ritz(g);
+}
 
 // The Rayleigh-Ritz steps of several independent solves in one launch, one
 // workgroup each (each on its own compute unit): the serving loop's batch.
@@ -462,6 +471,7 @@ __device__ __forceinline__ void update_block(const UpdArgs &g, int blk) {
 
 template <int TN>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_update(UpdArgs g) {
+  if (g.stop && *g.stop) return;
   update_block<TN>(g, blockIdx.x);
 }
 
@@ -475,7 +485,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 
 // Relative residual norms and the count of converged leading pairs.
 __device__ __forceinline__ void finish_body(int b, int nev, int nparts, const double *npart, const double *lam,
-                                            double tol, double *status, int32_t *locked) {
+                                            double tol, double *status, int32_t *locked, int iter = 0,
+                                            int32_t *stop = nullptr) {
   // 16 slices of the partial sums per column, then a fixed-order sum
   __shared__ double ra[16][kMaxBlock], rx[16][kMaxBlock];
   __shared__ double rs[kMaxBlock];
@@ -501,13 +512,16 @@ __device__ __forceinline__ void finish_body(int b, int nev, int nparts, const do
     for (int k = 0; k < nev; ++k) conv += rs[k] <= tol;
     status[0] = conv;
     for (int k = 0; k < b; ++k) { status[1 + k] = rs[k]; status[1 + kMaxBlock + k] = lam[k]; }
+    status[kStatusIter] = iter;
+    if (stop && conv >= nev) *stop = 1;   // the iterations queued after this one do nothing
   }
 }
 
 __global__ __launch_bounds__(256) void k_finish(int b, int nev, int nparts, const double *npart,
                                                 const double *lam, double tol, double *status,
-                                                int32_t *locked) {
-  finish_body(b, nev, nparts, npart, lam, tol, status, locked);
+                                                int32_t *locked, int iter, int32_t *stop) {
+  if (*stop) return;
+  finish_body(b, nev, nparts, npart, lam, tol, status, locked, iter, stop);
 }
 
 __global__ __launch_bounds__(256) void k_finish_group(const FinishArgs *__restrict__ as) {
@@ -520,6 +534,10 @@ static inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t -
 
 // rows per Gram block: about 512 blocks, a multiple of the staging chunk
 constexpr int kSumGroup = 32;  // partial Gram matrices added per thread in the first pass
+// iterations a single solve queues before it waits for the status (at most
+// kIterBatch - 1 of them, each a few microseconds of launches that return at
+// once, follow the converged one; waiting after every iteration cost ~31 us)
+constexpr int kIterBatch = 8;
 
 // rows per Gram workgroup: about three workgroups per CU (three waves per
 // SIMD), a multiple of the 16 rows the four waves take per round
@@ -545,12 +563,12 @@ struct LobpcgRun {
   DBuf<int64_t> idx, seli;
   DBuf<double> selv;
   int64_t sel_half = 0;
-  DBuf<int32_t> flag, locked;
+  DBuf<int32_t> flag, locked, stop;
   int iters = 0;
   double t_spmm = 0.0;
   int64_t n_spmm = 0;
   bool timing = false;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipEvent_t ev0[kIterBatch] = {}, ev1[kIterBatch] = {};   // SpMM of each iteration of a batch
 
   LobpcgRun(cib_ctx *c, const cib_matrix &h, const cib_lobpcg_opts &o, hipStream_t st, bool time_spmm)
       : ctx(c), H(h), s(st), D(h.D), b(o.block), nev(o.nev), max_iter(o.max_iter), opts(o),
@@ -582,38 +600,46 @@ struct LobpcgRun {
     selv.reset(ctx, 2 * sel_half + kMaxBlock);
     flag.reset(ctx, 4);
     locked.reset(ctx, kMaxBlock);
+    stop.reset(ctx, 1);
     if (H.dtype == CIB_F32) {
       x32.reset(ctx, (size_t)D * b);
       y32.reset(ctx, (size_t)D * b);
     }
-    if (timing) {
-      CIB_HIP(hipEventCreate(&ev0));
-      CIB_HIP(hipEventCreate(&ev1));
-    }
+    if (timing)
+      for (int k = 0; k < kIterBatch; ++k) {
+        CIB_HIP(hipEventCreate(&ev0[k]));
+        CIB_HIP(hipEventCreate(&ev1[k]));
+      }
   }
   ~LobpcgRun() {
-    if (ev0) (void)hipEventDestroy(ev0);
-    if (ev1) (void)hipEventDestroy(ev1);
+    for (int k = 0; k < kIterBatch; ++k) {
+      if (ev0[k]) (void)hipEventDestroy(ev0[k]);
+      if (ev1[k]) (void)hipEventDestroy(ev1[k]);
+    }
   }
 
-  // HS[:, slot] = H S[:, slot]
-  void spmm(int slot, bool w32_ready) {
-    if (timing) CIB_HIP(hipEventRecord(ev0, s));
+  // HS[:, slot] = H S[:, slot]; ev = the batch position of the iteration
+  void spmm(int slot, bool w32_ready, int ev = 0) {
+    if (timing) CIB_HIP(hipEventRecord(ev0[ev], s));
     if (H.dtype == CIB_F64) {
-      spmm_sym(H, S.p + slot * b, ld, HS.p + slot * b, ld, b, s);
+      spmm_sym(H, S.p + slot * b, ld, HS.p + slot * b, ld, b, s, stop.p);
     } else {
       if (!w32_ready)
         hipLaunchKernelGGL(k_narrow, dim3(nblk(D * b)), dim3(256), 0, s, D, b, S.p + slot * b, ld, x32.p);
-      spmm_sym(H, x32.p, b, y32.p, b, b, s);
-      hipLaunchKernelGGL(k_widen, dim3(nblk(D * b)), dim3(256), 0, s, D, b, y32.p, HS.p + slot * b, ld);
+      // H W in float32, rows stored widened into HS (or through y32 and a
+      // widening pass where the vector kernel does not apply)
+      if (!spmm_sym_widen(H, x32.p, b, HS.p + slot * b, ld, b, s, stop.p)) {
+        spmm_sym(H, x32.p, b, y32.p, b, b, s, stop.p);
+        hipLaunchKernelGGL(k_widen, dim3(nblk(D * b)), dim3(256), 0, s, D, b, y32.p, HS.p + slot * b, ld, stop.p);
+      }
     }
-    if (timing) CIB_HIP(hipEventRecord(ev1, s));
-    ++n_spmm;
+    if (timing) CIB_HIP(hipEventRecord(ev1[ev], s));
   }
 
   void rr_update(int ns) {
     gram_step(ns);
     RRArgs ra = rr_args(ns);
+    ra.stop = stop.p;
     { KTimer kt(ctx, K_RR, s); hipLaunchKernelGGL(k_rayleigh_ritz, dim3(1), dim3(256), 0, s, ra); }
     update_step(ns);
   }
@@ -627,17 +653,20 @@ struct LobpcgRun {
       KTimer kt(ctx, K_GRAM, s);
       const int T = (ns + 15) / 16;
       if (T == 1)
-        hipLaunchKernelGGL(k_gram<1>, dim3(gram_blocks), dim3(256), 0, s, D, ns, ld, S.p, HS.p, gram_rows, partial.p);
+        hipLaunchKernelGGL(k_gram<1>, dim3(gram_blocks), dim3(256), 0, s, D, ns, ld, S.p, HS.p, gram_rows, partial.p,
+                           stop.p);
       else if (T == 2)
-        hipLaunchKernelGGL(k_gram<2>, dim3(gram_blocks), dim3(256), 0, s, D, ns, ld, S.p, HS.p, gram_rows, partial.p);
+        hipLaunchKernelGGL(k_gram<2>, dim3(gram_blocks), dim3(256), 0, s, D, ns, ld, S.p, HS.p, gram_rows, partial.p,
+                           stop.p);
       else
-        hipLaunchKernelGGL(k_gram<3>, dim3(gram_blocks), dim3(256), 0, s, D, ns, ld, S.p, HS.p, gram_rows, partial.p);
+        hipLaunchKernelGGL(k_gram<3>, dim3(gram_blocks), dim3(256), 0, s, D, ns, ld, S.p, HS.p, gram_rows, partial.p,
+                           stop.p);
       const int nout = ns * 2 * ns;
       const int groups = (gram_blocks + kSumGroup - 1) / kSumGroup;
       hipLaunchKernelGGL(k_sum_parts, dim3((nout + 255) / 256, groups), dim3(256), 0, s, nout, gram_blocks,
-                         kSumGroup, partial.p, partial2.p, 0);
+                         kSumGroup, partial.p, partial2.p, 0, stop.p);
       hipLaunchKernelGGL(k_sum_parts, dim3((nout + 255) / 256, 1), dim3(256), 0, s, nout, groups, groups,
-                         partial2.p, gram.p, ns);
+                         partial2.p, gram.p, ns, stop.p);
     }
   }
 
@@ -645,7 +674,7 @@ struct LobpcgRun {
     const cib_precond *P = opts.precond;
     float *w32 = H.dtype == CIB_F32 ? x32.p : nullptr;
     UpdArgs ua{D, b, ns, ld, S.p, HS.p, C.p, lam.p, P ? nullptr : diag.p, P ? nullptr : w32,
-               npart.p, (int)upd_rows, locked.p};
+               npart.p, (int)upd_rows, locked.p, stop.p};
     {
       KTimer kt(ctx, K_UPDATE, s);
       if (2 * b <= 16) hipLaunchKernelGGL(k_update<1>, dim3(upd_blocks), dim3(256), 0, s, ua);
@@ -656,8 +685,9 @@ struct LobpcgRun {
     // per-block residual sums: groups of kSumGroup first, then k_finish
     const int ugroups = (upd_blocks + kSumGroup - 1) / kSumGroup;
     hipLaunchKernelGGL(k_sum_parts, dim3(1, ugroups), dim3(256), 0, s, 2 * b, upd_blocks, kSumGroup, npart.p,
-                       npart2.p, 0);
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, b, nev, ugroups, npart2.p, lam.p, tol, status.p, locked.p);
+                       npart2.p, 0, stop.p);
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, s, b, nev, ugroups, npart2.p, lam.p, tol, status.p, locked.p,
+                       iters, stop.p);
     CIB_HIP(hipGetLastError());
   }
 
@@ -685,6 +715,7 @@ struct LobpcgRun {
   void start() {
     CIB_HIP(hipMemsetAsync(flag.p, 0, sizeof(int32_t) * 4, s));
     CIB_HIP(hipMemsetAsync(locked.p, 0, sizeof(int32_t) * kMaxBlock, s));
+    CIB_HIP(hipMemsetAsync(stop.p, 0, sizeof(int32_t), s));
     const unsigned rb = (unsigned)((D + 3) / 4);
     if (H.dtype == CIB_F64) {
       hipLaunchKernelGGL(k_diag<double>, dim3(nblk(D)), dim3(256), 0, s, D, H.row_ptr.p, H.val64.p, diag.p);
@@ -707,9 +738,10 @@ struct LobpcgRun {
     rr_update(b);
   }
 
-  void iterate() {
+  // ev: the iteration's position in a batch (its SpMM timer events)
+  void iterate(int ev = 0) {
     ++iters;
-    spmm(1, H.dtype == CIB_F32);
+    spmm(1, H.dtype == CIB_F32, ev);
     rr_update(iters == 1 ? 2 * b : 3 * b);
   }
 
@@ -760,11 +792,15 @@ struct LobpcgRun {
     CIB_HIP(hipMemcpyAsync(host, status.p, sizeof(double) * kStatusLen, hipMemcpyDeviceToHost, s));
   }
 
-  void spmm_time_accumulate() {
+  // the SpMMs of the first n iterations of the batch just waited for
+  void spmm_time_accumulate(int n) {
+    n_spmm += n;
     if (!timing) return;
-    float ms = 0.f;
-    CIB_HIP(hipEventElapsedTime(&ms, ev0, ev1));
-    t_spmm += ms * 1e-3;
+    for (int k = 0; k < n; ++k) {
+      float ms = 0.f;
+      CIB_HIP(hipEventElapsedTime(&ms, ev0[k], ev1[k]));
+      t_spmm += ms * 1e-3;
+    }
   }
 
   void copy_vectors(double *evecs, int64_t ld_evecs) {
@@ -788,7 +824,7 @@ size_t lobpcg_bytes(int64_t D, int b, cib_dtype dt) {
   size_t n = 2 * d8(D * 3 * b + kGramPad) + d8(D) + d8(gram_blocks * kNS * 2 * kNS) +
              d8(groups * kNS * 2 * kNS) + d8(kNS * 2 * kNS) + d8(1) + d8(kNS * 2 * kMaxBlock) + d8(kMaxBlock) +
              d8(upd_blocks * 2 * kMaxBlock) + d8(ugroups * 2 * kMaxBlock) + d8(kStatusLen) + d8(kMaxBlock) +
-             d8(2 * sel_half) + d8(2 * sel_half + kMaxBlock) + d4(4) + d4(kMaxBlock);
+             d8(2 * sel_half) + d8(2 * sel_half + kMaxBlock) + d4(4) + d4(kMaxBlock) + d4(1);
   if (dt == CIB_F32) n += 2 * d4(D * b);
   return n;
 }
@@ -930,7 +966,7 @@ cib_status lobpcg_solve(cib_ctx *ctx, const cib_matrix &H, const cib_lobpcg_opts
   L.start();
   L.copy_status(st);
   CIB_HIP(hipStreamSynchronize(L.s));
-  L.spmm_time_accumulate();
+  L.spmm_time_accumulate(1);
   auto finite = [&] {
     for (int k = 0; k < L.b; ++k)
       if (!std::isfinite(st[1 + k]) || !std::isfinite(st[1 + kMaxBlock + k])) return false;
@@ -938,11 +974,29 @@ cib_status lobpcg_solve(cib_ctx *ctx, const cib_matrix &H, const cib_lobpcg_opts
   };
   int conv = (int)st[0];
   CIB_REQUIRE(finite(), CIB_E_DEVICE, "LOBPCG produced non-finite Ritz values");
+  // Iterations are queued in batches without waiting for each one's status:
+  // the iteration that converges sets the stop flag on the device, and every
+  // launch of the iterations queued after it returns at once (their timer
+  // marks are dropped, their SpMMs not counted).  The results are those of a
+  // solve that waited after every iteration.  The block preconditioner's
+  // kernels do not look at the flag, so with it every iteration is waited for.
+  const int batch = o.precond ? 1 : kIterBatch;
   while (conv < L.nev && L.iters < L.max_iter) {
-    L.iterate();
+    const int first = L.iters + 1;
+    const int nq = std::min(batch, L.max_iter - L.iters);
+    size_t marks[kIterBatch];
+    for (int k = 0; k < nq; ++k) {
+      marks[k] = profile_marks(ctx);
+      L.iterate(k);
+    }
     L.copy_status(st);
     CIB_HIP(hipStreamSynchronize(L.s));
-    L.spmm_time_accumulate();
+    const int last = (int)st[kStatusIter];   // the last iteration that ran
+    const int ran = last - first + 1;
+    CIB_REQUIRE(ran >= 1 && ran <= nq, CIB_E_DEVICE, "LOBPCG status does not match the queued iterations");
+    if (ran < nq) profile_drop_marks(ctx, marks[ran]);
+    L.iters = last;
+    L.spmm_time_accumulate(ran);
     conv = (int)st[0];
     CIB_REQUIRE(finite(), CIB_E_DEVICE, "LOBPCG produced non-finite Ritz values");
   }

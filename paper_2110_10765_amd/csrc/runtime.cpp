@@ -152,6 +152,22 @@ void profile_collect(cib_ctx *c) {
   c->marks.clear();
 }
 
+size_t profile_marks(cib_ctx *c) {
+  std::lock_guard<std::mutex> g(c->mu);
+  return c->marks.size();
+}
+
+void profile_drop_marks(cib_ctx *c, size_t from) {
+  std::lock_guard<std::mutex> g(c->mu);
+  for (size_t k = from; k < c->marks.size(); ++k) {
+    // the events may still be pending: wait before they go back to the pool
+    (void)hipEventSynchronize(c->marks[k].b);
+    c->event_pool.push_back(c->marks[k].a);
+    c->event_pool.push_back(c->marks[k].b);
+  }
+  if (from < c->marks.size()) c->marks.resize(from);
+}
+
 cib_interaction *upload_interaction(cib_ctx *ctx, const cib_basis &b, const cib_tables &t,
                                     hipStream_t s) {
   const Plan &p = b.plan;

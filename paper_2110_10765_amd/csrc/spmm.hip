@@ -55,7 +55,8 @@ __global__ __launch_bounds__(256) void k_spmm_sym(int64_t D, const int64_t *__re
                                                   const int32_t *__restrict__ lcol,
                                                   const T *__restrict__ lval,
                                                   const T *__restrict__ X, int64_t ldx, T *__restrict__ Y,
-                                                  int64_t ldy, int nvec, int v0) {
+                                                  int64_t ldy, int nvec, int v0, const int32_t *stop) {
+  if (stop && *stop) return;   // a solve's iteration queued past its convergence
   const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
   const int64_t i = blk * (blockDim.x / kWave) + (threadIdx.x >> 6);
   if (i >= D) return;
@@ -203,7 +204,11 @@ __device__ __forceinline__ void spmm_vec_rows(const VecArgs &a, int64_t i0, int 
   // after the exchanges, lane bits above log2(64 / PER16) select the column
   constexpr int SEL = kWave / PER16;
   T *Y = static_cast<T *>(a.Y);
-  if (live && (lane & (SEL - 1) & ~(G - 1)) == 0) Y[i * a.ldy + g * PER16 + ((lane / SEL) & (PER16 - 1))] = acc[0];
+  if (live && (lane & (SEL - 1) & ~(G - 1)) == 0) {
+    const int c = g * PER16 + ((lane / SEL) & (PER16 - 1));
+    if (sizeof(T) == 4 && a.Y64) a.Y64[i * a.ldy64 + c] = (double)acc[0];
+    else Y[i * a.ldy + c] = acc[0];
+  }
 }
 
 // Rows per workgroup of the lockstep kernels: 8 for float32, 4 for float64
@@ -218,6 +223,7 @@ __global__ __launch_bounds__(64 * vec_rows_per_block<T>()) void k_spmm_vec(const
   // workgroups go to the 8 XCDs round-robin; XCD x (block mod 8) walks its
   // own range of rows, the ranges holding equal numbers of stored entries
   constexpr int R = vec_rows_per_block<T>();
+  if (a.stop && *a.stop) return;   // a solve's iteration queued past its convergence
   const int x = blockIdx.x & 7;
   const int64_t i0 = a.xr[x] + (int64_t)(blockIdx.x >> 3) * R;
   if (i0 >= a.xr[x + 1]) return;   // whole workgroup
@@ -239,7 +245,7 @@ __global__ __launch_bounds__(64 * kGroupRows) void k_spmm_vec_group(const VecArg
 // ------------------------------------------------------------ host side
 template <typename T>
 static void spmm_t(const cib_matrix &H, const T *X, int64_t ldx, T *Y, int64_t ldy, int nvec,
-                   hipStream_t s) {
+                   hipStream_t s, const int32_t *stop) {
   const int64_t D = H.D;
   const T *val = static_cast<const T *>(H.val());
   const T *lval = static_cast<const T *>(H.lo_val());
@@ -251,7 +257,7 @@ static void spmm_t(const cib_matrix &H, const T *X, int64_t ldx, T *Y, int64_t l
     // that XCD's L2, and the ranges are balanced.  Measured against plain
     // block order: 6-22% faster at D ~ 2e5, equal at D ~ 2e4; equal row
     // counts per XCD instead were up to 10% slower than plain order.
-    VecArgs a{D, H.row_ptr.p, H.col.p, val, H.lo_ptr.p, H.lo_col.p, lval, X, ldx, Y, ldy, {}};
+    VecArgs a{D, H.row_ptr.p, H.col.p, val, H.lo_ptr.p, H.lo_col.p, lval, X, ldx, Y, ldy, {}, stop};
     constexpr int R = vec_rows_per_block<T>();
     int64_t most = 0;
     for (int x = 0; x < 9; ++x) a.xr[x] = H.xcd_rows[x];
@@ -269,7 +275,7 @@ static void spmm_t(const cib_matrix &H, const T *X, int64_t ldx, T *Y, int64_t l
   auto launch = [&](auto bc, int v0) {
     constexpr int B = decltype(bc)::value;
     hipLaunchKernelGGL((k_spmm_sym<T, B>), dim3(nblk), dim3(256), 0, s, D, H.row_ptr.p, H.col.p, val,
-                       H.lo_ptr.p, H.lo_col.p, lval, X, ldx, Y, ldy, nvec, v0);
+                       H.lo_ptr.p, H.lo_col.p, lval, X, ldx, Y, ldy, nvec, v0, stop);
   };
   for (int v0 = 0; v0 < nvec; v0 += 16) {
     KTimer kt(H.ctx, K_SPMM, s);
@@ -281,6 +287,24 @@ static void spmm_t(const cib_matrix &H, const T *X, int64_t ldx, T *Y, int64_t l
     else launch(std::integral_constant<int, 16>{}, v0);
   }
   CIB_HIP(hipGetLastError());
+}
+
+bool spmm_sym_widen(const cib_matrix &H, const float *X, int64_t ldx, double *Y, int64_t ldy, int nvec,
+                    hipStream_t s, const int32_t *stop) {
+  const bool aligned = ((uintptr_t)X % 16 == 0) && ((ldx * sizeof(float)) % 16 == 0);
+  if (H.dtype != CIB_F32 || !aligned || (nvec != 8 && nvec != 16)) return false;
+  constexpr int R = vec_rows_per_block<float>();
+  VecArgs a{H.D, H.row_ptr.p, H.col.p, H.val(), H.lo_ptr.p, H.lo_col.p, H.lo_val(), X, ldx, nullptr, 0, {}, stop,
+            Y, ldy};
+  int64_t most = 0;
+  for (int x = 0; x < 9; ++x) a.xr[x] = H.xcd_rows[x];
+  for (int x = 0; x < 8; ++x) most = std::max<int64_t>(most, a.xr[x + 1] - a.xr[x]);
+  const unsigned grid = (unsigned)std::max<int64_t>(8, 8 * ((most + R - 1) / R));
+  KTimer kt(H.ctx, K_SPMM, s);
+  if (nvec == 8) hipLaunchKernelGGL((k_spmm_vec<float, 8>), dim3(grid), dim3(64 * R), 0, s, a);
+  else hipLaunchKernelGGL((k_spmm_vec<float, 16>), dim3(grid), dim3(64 * R), 0, s, a);
+  CIB_HIP(hipGetLastError());
+  return true;
 }
 
 bool spmm_vec_args(const cib_matrix &H, const void *X, int64_t ldx, void *Y, int64_t ldy, int nvec, VecArgs &a,
@@ -308,11 +332,11 @@ void launch_spmm_group(cib_dtype dt, int nvec, const VecArgs *dev_args, const in
 }
 
 void spmm_sym(const cib_matrix &H, const void *X, int64_t ldx, void *Y, int64_t ldy, int nvec,
-              hipStream_t s) {
+              hipStream_t s, const int32_t *stop) {
   if (H.dtype == CIB_F64)
-    spmm_t<double>(H, static_cast<const double *>(X), ldx, static_cast<double *>(Y), ldy, nvec, s);
+    spmm_t<double>(H, static_cast<const double *>(X), ldx, static_cast<double *>(Y), ldy, nvec, s, stop);
   else
-    spmm_t<float>(H, static_cast<const float *>(X), ldx, static_cast<float *>(Y), ldy, nvec, s);
+    spmm_t<float>(H, static_cast<const float *>(X), ldx, static_cast<float *>(Y), ldy, nvec, s, stop);
 }
 
 }  // namespace cib
