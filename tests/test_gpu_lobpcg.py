@@ -109,3 +109,32 @@ def test_lobpcg_not_converged_and_invalid():
     with pytest.raises(cib.CibError) as e:
         _solve(tiny, "f64")
     assert e.value.code == cib.CIB_E_INVALID
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_lobpcg_batched_iterations(dtype):
+    """A single solve queues its iterations in batches and the converging one
+    stops the rest on the device.  The count it reports must be the count
+    that ran: max_iter one short of it stops there unconverged (a count that
+    is not a multiple of the batch), max_iter equal to it gives the same bits,
+    and the SpMM launches timed (queued-but-skipped ones dropped) and counted
+    are one per iteration plus the start."""
+    from paper_2110_10765_amd import cib
+    w = cigen.WORKLOADS["sp1_n2_N4"]
+    ctx = gpu_ctx()
+    b = cib.build_basis(ctx, w.spec)
+    H = cib.build_H(ctx, b, oracle_tables(w.spec, w.seed), dtype)
+    ctx.profile(True)
+    ev, info, _ = cib.lobpcg(ctx, H, w.nev, block=w.block, max_iter=800)
+    n_launch, _ = ctx.kernel_time("spmm_sym")
+    ctx.profile(False)
+    n = info["iters"]
+    assert info["status"] == 0 and n > 9, info
+    assert n_launch == n + 1 and info["n_spmm"] == n + 1, (n_launch, info)
+    ev_short, info_short, _ = cib.lobpcg(ctx, H, w.nev, block=w.block, max_iter=n - 1)
+    assert info_short["status"] == cib.CIB_E_NOT_CONVERGED and info_short["iters"] == n - 1, info_short
+    assert info_short["n_spmm"] == n, info_short
+    ev_same, info_same, _ = cib.lobpcg(ctx, H, w.nev, block=w.block, max_iter=n)
+    assert info_same["status"] == 0 and info_same["iters"] == n, info_same
+    assert np.array_equal(ev_same, ev)
+    assert _rel(ev, np.asarray(golden(w.name)["evals_f64"])[:w.nev]).max() <= (1e-10 if dtype == "f64" else 1e-6)
