@@ -132,7 +132,9 @@ __global__ __launch_bounds__(256) void k_copy_cols(int64_t D, int n, const doubl
 
 // ------------------------------------------------------------ Gram matrices
 // partial[blk] = sum over the block's rows of S_i^T [S_i, HS_i] for the first
-// ns columns: an ns x 2ns matrix (left half S^T S, right half S^T HS).  This
+// ns columns, as its upper 16 x 16 tiles: first those of S^T S, then those
+// of S^T HS (gram_tiles(ns) doubles, the final partial-sum pass mirrors them
+// into the Rayleigh-Ritz layout).  This
 // is a dense contraction over the rows, done on the float64 matrix cores:
 // v_mfma_f64_16x16x4f64 multiplies a 16 x 4 by a 4 x 16 block.  Four
 // consecutive rows form one step; lane l holds row (l / 16), column
@@ -142,12 +144,20 @@ __global__ __launch_bounds__(256) void k_copy_cols(int64_t D, int n, const doubl
 // row pieces, no LDS).  Output tile (ti, tj): lane l, element v holds row
 // 16 ti + 4 v + (l / 16), column 16 tj + (l % 16) (checked on the device).
 // S^T S and S^T HS are symmetric (H is): only their tiles ti <= tj are
-// formed, and mirrored (the Rayleigh-Ritz step symmetrises S^T HS anyway,
-// so the tiles below the diagonal added nothing but rounding).  The
-// four waves of a workgroup take alternate steps (the next step's rows load
-// during the current one) and are summed in LDS in wave order.  The matrix
-// cores are the limit here: measured about 36 TFLOP/s for this instruction.
+// formed (the Rayleigh-Ritz step symmetrises S^T HS anyway, so the tiles
+// below the diagonal added nothing but rounding).  The four waves of a
+// workgroup take alternate steps (the next step's rows load during the
+// current one); waves 0 and 1 store their tiles in LDS, waves 2 and 3 add
+// theirs, and the workgroup writes (w0 + w2) + (w1 + w3) with coalesced
+// stores.  The main loop streams S and HS at about 5 TB/s; adding the four
+// waves one after another in the full layout had cost 15 of the kernel's
+// 50 us at ns = 48.
 constexpr int kGramSteps = 4;   // rows per matrix-core step
+// doubles of one workgroup's partial Gram matrices: the upper 16 x 16 tiles
+// of S^T S and of S^T HS, each tile lane-major (element v * 64 + lane)
+__host__ __device__ constexpr int gram_tiles(int ns) {
+  return 2 * ((ns + 15) / 16) * ((ns + 15) / 16 + 1) / 2 * 256;
+}
 constexpr int kGramPad = 48;    // doubles allocated past the last row of S and HS
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
@@ -155,11 +165,10 @@ template <int T>   // 16-column tiles per side: ns <= 16 T
 __device__ __forceinline__ void gram_block(int64_t D, int ns, int ld, const double *__restrict__ S,
                                            const double *__restrict__ HS, int64_t rows_per_blk,
                                            double *__restrict__ partial, int blk) {
-  constexpr int NG = T * (T + 1) / 2;   // upper tiles of S^T S
-  __shared__ double red[kNS * 2 * kNS];
+  constexpr int NG = T * (T + 1) / 2;   // upper tiles of S^T S (and of S^T HS)
+  __shared__ double red[2][2 * NG * 256];
   const int wv = uni((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
   const int kr = lane >> 4, kc = lane & 15;
-  const int w2 = 2 * ns;
   const int64_t r0 = (int64_t)blk * rows_per_blk;
   const int64_t r1 = min(D, r0 + rows_per_blk);
   dbl4 ag[NG], ah[NG];
@@ -205,37 +214,30 @@ __device__ __forceinline__ void gram_block(int64_t D, int ns, int ld, const doub
       xh[t] = yh[t];
     }
   }
-  // waves in order: wave 0 stores, waves 1-3 add
+  // waves 0 and 1 store their tiles, waves 2 and 3 add theirs: (w0 + w2) + (w1 + w3)
+  double *rw = red[wv & 1];
+  if (wv < 2) {
 #pragma unroll
-  for (int w = 0; w < 4; ++w) {
-    if (wv == w) {
-      auto put = [&](int i, int j, double v) {
-        if (w == 0) red[i * w2 + j] = v;
-        else red[i * w2 + j] += v;
-      };
-      int g = 0;
+    for (int g = 0; g < NG; ++g)
 #pragma unroll
-      for (int a = 0; a < T; ++a) {
-#pragma unroll
-        for (int c = a; c < T; ++c, ++g)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int i = 16 * a + 4 * v + kr, j = 16 * c + kc;
-            if (i < ns && j < ns) {
-              put(i, j, ag[g][v]);
-              put(i, ns + j, ah[g][v]);
-              if (c > a) {
-                put(j, i, ag[g][v]);
-                put(j, ns + i, ah[g][v]);
-              }
-            }
-          }
+      for (int v = 0; v < 4; ++v) {
+        rw[g * 256 + v * 64 + lane] = ag[g][v];
+        rw[(NG + g) * 256 + v * 64 + lane] = ah[g][v];
       }
-    }
-    __syncthreads();
   }
-  double *out = partial + (int64_t)blk * ns * w2;
-  for (int e = threadIdx.x; e < ns * w2; e += blockDim.x) out[e] = red[e];
+  __syncthreads();
+  if (wv >= 2) {
+#pragma unroll
+    for (int g = 0; g < NG; ++g)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        rw[g * 256 + v * 64 + lane] += ag[g][v];
+        rw[(NG + g) * 256 + v * 64 + lane] += ah[g][v];
+      }
+  }
+  __syncthreads();
+  double *out = partial + (int64_t)blk * (2 * NG * 256);
+  for (int e = threadIdx.x; e < 2 * NG * 256; e += blockDim.x) out[e] = red[0][e] + red[1][e];
 }
 
 template <int T>
@@ -273,9 +275,26 @@ __device__ __forceinline__ void sum_parts_elem(int nout, int nparts, int per, co
   }
   for (; q < q1; ++q) acc[q & 3] += in[(int64_t)q * nout + e];
   const double v = (acc[0] + acc[1]) + (acc[2] + acc[3]);
-  if (pad > 0) {   // one [S^T S | S^T H S] pair (pad = ns) into two kNS x kLd blocks
-    const int i = e / (2 * pad), j = e - i * 2 * pad;
-    out[(j < pad ? 0 : kNS * kLd) + i * kLd + (j < pad ? j : j - pad)] = v;
+  if (pad > 0) {   // the upper tiles of S^T S and S^T H S (pad = ns) into two kNS x kLd blocks, mirrored
+    const int T = (pad + 15) / 16, NG = T * (T + 1) / 2;
+    int tile = e >> 8;
+    const int which = tile >= NG;
+    if (which) tile -= NG;
+    int a = 0, c = 0;   // the tile's (row, column) among the upper tiles, row by row
+    for (int nrow = T; a < T; ++a, --nrow) {
+      if (tile < nrow) {
+        c = a + tile;
+        break;
+      }
+      tile -= nrow;
+    }
+    const int r = e & 255, lane = r & 63;
+    const int i = 16 * a + 4 * (r >> 6) + (lane >> 4), j = 16 * c + (lane & 15);
+    if (i < pad && j < pad) {
+      double *o = out + (which ? kNS * kLd : 0);
+      o[i * kLd + j] = v;
+      if (a < c) o[j * kLd + i] = v;
+    }
   } else {
     out[(int64_t)grp * nout + e] = v;
   }
@@ -585,8 +604,8 @@ struct LobpcgRun {
     gram_blocks = (int)((D + gram_rows - 1) / gram_rows);
     upd_rows = upd_rows_for(D);
     upd_blocks = (int)((D + upd_rows - 1) / upd_rows);
-    partial.reset(ctx, (size_t)gram_blocks * kNS * 2 * kNS);
-    partial2.reset(ctx, (size_t)((gram_blocks + kSumGroup - 1) / kSumGroup) * kNS * 2 * kNS);
+    partial.reset(ctx, (size_t)gram_blocks * gram_tiles(kNS));
+    partial2.reset(ctx, (size_t)((gram_blocks + kSumGroup - 1) / kSumGroup) * gram_tiles(kNS));
     gram.reset(ctx, (size_t)2 * kNS * kLd);
     hlow.reset(ctx, 1);
     C.reset(ctx, kNS * 2 * kMaxBlock);
@@ -661,7 +680,7 @@ struct LobpcgRun {
       else
         hipLaunchKernelGGL(k_gram<3>, dim3(gram_blocks), dim3(256), 0, s, D, ns, ld, S.p, HS.p, gram_rows, partial.p,
                            stop.p);
-      const int nout = ns * 2 * ns;
+      const int nout = gram_tiles(ns);
       const int groups = (gram_blocks + kSumGroup - 1) / kSumGroup;
       hipLaunchKernelGGL(k_sum_parts, dim3((nout + 255) / 256, groups), dim3(256), 0, s, nout, gram_blocks,
                          kSumGroup, partial.p, partial2.p, 0, stop.p);
@@ -766,7 +785,7 @@ struct LobpcgRun {
     p.T = (ns + 15) / 16;
     p.gram = GramArgs{D, ns, ld, S.p, HS.p, gram_rows, partial.p};
     p.gram_blocks = gram_blocks;
-    const int nout = ns * 2 * ns, xb = (nout + 255) / 256;
+    const int nout = gram_tiles(ns), xb = (nout + 255) / 256;
     const int groups = (gram_blocks + kSumGroup - 1) / kSumGroup;
     p.gs1 = SumArgs{nout, gram_blocks, kSumGroup, partial.p, partial2.p, 0};
     p.gs1_blocks = xb * groups;
@@ -821,8 +840,8 @@ size_t lobpcg_bytes(int64_t D, int b, cib_dtype dt) {
   const int64_t sel_half = std::max<int64_t>(1, (D + kSelChunk - 1) / kSelChunk) * b;
   auto d8 = [](int64_t n) { return dev_bytes((size_t)n * 8); };
   auto d4 = [](int64_t n) { return dev_bytes((size_t)n * 4); };
-  size_t n = 2 * d8(D * 3 * b + kGramPad) + d8(D) + d8(gram_blocks * kNS * 2 * kNS) +
-             d8(groups * kNS * 2 * kNS) + d8(kNS * 2 * kNS) + d8(1) + d8(kNS * 2 * kMaxBlock) + d8(kMaxBlock) +
+  size_t n = 2 * d8(D * 3 * b + kGramPad) + d8(D) + d8(gram_blocks * gram_tiles(kNS)) +
+             d8(groups * gram_tiles(kNS)) + d8(2 * kNS * kLd) + d8(1) + d8(kNS * 2 * kMaxBlock) + d8(kMaxBlock) +
              d8(upd_blocks * 2 * kMaxBlock) + d8(ugroups * 2 * kMaxBlock) + d8(kStatusLen) + d8(kMaxBlock) +
              d8(2 * sel_half) + d8(2 * sel_half + kMaxBlock) + d4(4) + d4(kMaxBlock) + d4(1);
   if (dt == CIB_F32) n += 2 * d4(D * b);
