@@ -279,7 +279,8 @@ __global__ __launch_bounds__(256) void k_tile_val(int64_t n, const int32_t *__re
                                                   const int32_t *__restrict__ dst,
                                                   const uint64_t *__restrict__ a_bits, int nAc,
                                                   const int32_t *__restrict__ a_seg, DevInter it,
-                                                  TileRec *__restrict__ t_rec, double *__restrict__ t_val) {
+                                                  TileRec *__restrict__ t_rec, double *__restrict__ t_val,
+                                                  const int32_t *__restrict__ a_q, int qcap) {
   const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (e >= n) return;
   const int alpha = src[e], j = dst[e];
@@ -303,6 +304,11 @@ __global__ __launch_bounds__(256) void k_tile_val(int64_t n, const int32_t *__re
     val = sg * sum;
     info = 1 | (p1 << 2) | (h1 << 10) | ((sg < 0) << 18) | (a_seg[j] << 19);
     rb = it.arb ? it.arb[p1 * it.nA + h1] : 0;
+    // a kA = 1 tile keeps, in place of alpha''s length, the Q level its B
+    // states stop at (qcap - Q_A(alpha'), qcap = qmax - qmin_B; 0 without a
+    // truncation): its entries are the L1 entries of the row's B
+    // configuration in alpha''s 2M_B list up to that level
+    t_rec[e].len = qcap >= 0 ? qcap - a_q[j] : 0;
   } else {       // kA = 2
     const int sg = sign_double<W>(ca, p1, p2, h1, h2);
     val = sg * v_pair(it.pidxA, it.prowA, it.nA, it.vA, p1, p2, h1, h2);
@@ -447,6 +453,33 @@ __global__ __launch_bounds__(256) void k_adj_val(int64_t n, const int32_t *__res
   if (val_out) val_out[e] = val;
 }
 
+// lev_cnt[(beta * nseg + h) * nlev + t] = number of the L1 entries of B
+// configuration beta in 2M_B list h whose Q_B is at most qmin_B + t (the
+// list is ordered by Q_B, so they are a prefix of the segment).  One thread
+// per entry: the last entry of each Q level writes the counts of the levels
+// from its own up to the next entry's, the first entry of a segment the
+// zeros below it (a segment without entries keeps the zeros it was cleared
+// to).  The row passes read a kA = 1 tile's entry count here instead of
+// searching the segment for the tile's length.
+__global__ __launch_bounds__(256) void k_l1_levels(int64_t n, int nseg, int nlev, int qminB,
+                                                   const int64_t *__restrict__ l1_seg,
+                                                   const int32_t *__restrict__ l1_src,
+                                                   const int32_t *__restrict__ l1_dst,
+                                                   const int32_t *__restrict__ b_seg,
+                                                   const int32_t *__restrict__ b_q, int32_t *__restrict__ lev_cnt) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const int dst = l1_dst[e];
+  const int64_t u = (int64_t)l1_src[e] * nseg + b_seg[dst];
+  const int64_t e0 = l1_seg[u], e1 = l1_seg[u + 1];
+  const int lev = nlev > 1 ? b_q[dst] - qminB : 0;
+  const int next = e + 1 < e1 ? (nlev > 1 ? b_q[l1_dst[e + 1]] - qminB : 0) : nlev;
+  int32_t *out = lev_cnt + u * nlev;
+  if (e == e0)
+    for (int t = 0; t < lev; ++t) out[t] = 0;
+  for (int t = lev; t < next; ++t) out[t] = (int32_t)(e - e0 + 1);
+}
+
 template <int W, bool FILL>
 __global__ __launch_bounds__(256) void k_adj_pass(AdjArgs g) {
   const int64_t unit = blockIdx.x * (int64_t)(blockDim.x / kWave) + uni((int)(threadIdx.x >> 6));
@@ -519,6 +552,8 @@ struct RowArgs {
   const int64_t *ls_ptr, *l1_seg;
   const int32_t *ls_self;
   const AdjRec *ls_rec, *l1_rec;
+  const int32_t *lev_cnt;   // k_l1_levels
+  int nlev;
   const double *ls_val;
   const double *diag;       // fill pass: diagonal element of every state
   DevInter it;
@@ -660,7 +695,7 @@ struct L1View {
 template <int W, bool FILL, typename T, bool ST, class Acc>
 __device__ __forceinline__ void row_tiles(const RowArgs &g, int64_t t0, int64_t t1, int p, const uint64_t *bb,
                                           const SpecIdx &sb_idx, int64_t out, int64_t &cnt, const L1View<ST> &L,
-                                          int32_t *mark, Acc &acc) {
+                                          const int32_t *lev, int32_t *mark, Acc &acc) {
   const int lane = lane_id();
   T *val = static_cast<T *>(g.val);
   // the tile data of a batch of 64 is read together, one batch ahead of its
@@ -693,15 +728,10 @@ __device__ __forceinline__ void row_tiles(const RowArgs &g, int64_t t0, int64_t 
       const int len = cur.len;
       if ((info & 3) == 2) {
         ne = p < len;
-      } else {  // first entry of the sorted segment with position >= len
+      } else {  // the segment's entries up to the tile's Q level (len holds the level)
         const int gt = (info >> 19) & 0x7f;
         l0 = L.seg(gt);
-        int lo = l0, hi = L.seg(gt + 1);
-        while (lo < hi) {
-          const int mid = (lo + hi) >> 1;
-          if (L.pos(mid) < len) lo = mid + 1; else hi = mid;
-        }
-        ne = lo - l0;
+        ne = lev[gt * g.nlev + len];
       }
     }
     const int incl = wave_incl_scan_dpp(ne);
@@ -814,6 +844,7 @@ __device__ __forceinline__ void row_pass(const RowArgs &g, const LowerArgs &lo, 
   const int64_t base = uni(g.l1_seg[l1b]);
   const int64_t n1 = uni(g.l1_seg[l1b + g.nseg]) - base;
   const int64_t t0u = uni(g.t_ptr[(int64_t)alpha * g.tstride]), t1u = uni(g.t_ptr[(int64_t)(alpha + 1) * g.tstride]);
+  const int32_t *const lev = g.lev_cnt + (int64_t)beta * g.nseg * g.nlev;   // beta's entry counts by list and level
   int64_t cu = 0, cl = 0;
   // The four parts in column order.  What only the lower parts use is read
   // after the upper parts (fewer values held in scalar registers across
@@ -823,11 +854,11 @@ __device__ __forceinline__ void row_pass(const RowArgs &g, const LowerArgs &lo, 
     constexpr bool ST = std::is_same<std::decay_t<decltype(L)>, L1View<true>>::value;
     const int64_t ls_me = uni((int64_t)g.ls_self[beta]), ls_hi = uni(g.ls_ptr[beta + 1]);
     row_diag<W, FILL, T>(g, i, ls_me, ls_hi, alpha, len_a, off_a, ab, sa_idx, out_u, cu, acc);
-    row_tiles<W, FILL, T, ST>(g, t0u, t1u, p, bb, sb_idx, out_u, cu, L, s_mark[wv], acc);
+    row_tiles<W, FILL, T, ST>(g, t0u, t1u, p, bb, sb_idx, out_u, cu, L, lev, s_mark[wv], acc);
     const int64_t out_l = kStore ? uni(gl.row_ptr[i]) : 0;
     const int64_t t0l = uni(gl.t_ptr[(int64_t)alpha * gl.tstride]);
     const int64_t t1l = uni(gl.t_ptr[(int64_t)(alpha + 1) * gl.tstride]);
-    row_tiles<W, FILL, T, ST>(gl, t0l, t1l, p, bb, sb_idx, out_l, cl, L, s_mark[wv], acc);
+    row_tiles<W, FILL, T, ST>(gl, t0l, t1l, p, bb, sb_idx, out_l, cl, L, lev, s_mark[wv], acc);
     const int64_t ls_lo = uni(g.ls_ptr[beta]);
     row_diag<W, FILL, T>(gl, i, ls_lo, ls_me, alpha, len_a, off_a, ab, sa_idx, out_l, cl, acc);
   };
@@ -1147,6 +1178,7 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
   const Plan &p = b.plan;
   const DevInter it = itr.view();
   const int nA = p.nA(), nB = p.nB(), nseg = p.nseg();
+  const int qcap = p.qmax >= 0 ? p.qmax - p.qminB : -1;   // Q_A + Q_B <= qmax as a cap on Q_A + (Q_B - qmin_B)
   Events ev;
   auto bytes = [](size_t count, size_t elem) { return dev_bytes(count * elem); };
 
@@ -1199,7 +1231,8 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
     const size_t nt = at_least1(n_tiles), nl = at_least1(n_lt), ns = at_least1(n_ls), n1 = at_least1(n_l1);
     // screens, row counts, diagonal and the two offset arrays
     reserve(1, (bytes(nt, 16) + 2 * bytes(nt, 4) + bytes(nt, 8)) + (bytes(nl, 16) + 2 * bytes(nl, 4) + bytes(nl, 8)) +
-                   bytes(nB, 4) + bytes(ns, 8) + 2 * bytes(ns, 4) + bytes(n1, 8) + 2 * bytes(n1, 4) + bytes(ns, 8) + 2 * bytes(p.D, 4) +
+                   bytes(nB, 4) + bytes(ns, 8) + 2 * bytes(ns, 4) + bytes(n1, 8) + 2 * bytes(n1, 4) + bytes(ns, 8) +
+                   bytes((size_t)nB * nseg * p.nlev, 4) + 2 * bytes(p.D, 4) +
                    bytes(p.D, 8) + 2 * bytes(p.D + 1, 8));
   }
   DBuf<TileRec> t_rec(ctx, at_least1(n_tiles)), tl_rec(ctx, at_least1(n_lt));
@@ -1211,6 +1244,7 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
   DBuf<int32_t> ls_src(ctx, at_least1(n_ls)), ls_dst(ctx, at_least1(n_ls));
   DBuf<int32_t> l1_src(ctx, at_least1(n_l1)), l1_dst(ctx, at_least1(n_l1));
   DBuf<double> ls_val(ctx, at_least1(n_ls));
+  DBuf<int32_t> lev_cnt(ctx, (size_t)nB * nseg * p.nlev);
   CIB_HIP(hipEventRecord(ev.e[2], s));
   ta.t_ptr = t_ptr.p; ta.t_rec = t_rec.p; ta.t_src = t_src.p; ta.t_dst = t_dst.p;
   tl.t_ptr = tl_ptr.p; tl.t_rec = tl_rec.p; tl.t_src = tl_src.p; tl.t_dst = tl_dst.p;
@@ -1222,10 +1256,10 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
     // phases and values, one thread per tile
     if (n_tiles)
       hipLaunchKernelGGL((k_tile_val<W>), nb256(n_tiles), dim3(256), 0, s, n_tiles, t_src.p, t_dst.p,
-                         b.a_bits.p, nA, b.a_seg.p, it, t_rec.p, t_val.p);
+                         b.a_bits.p, nA, b.a_seg.p, it, t_rec.p, t_val.p, b.a_q.p, qcap);
     if (n_lt)
       hipLaunchKernelGGL((k_tile_val<W>), nb256(n_lt), dim3(256), 0, s, n_lt, tl_src.p, tl_dst.p,
-                         b.a_bits.p, nA, b.a_seg.p, it, tl_rec.p, tl_val.p);
+                         b.a_bits.p, nA, b.a_seg.p, it, tl_rec.p, tl_val.p, b.a_q.p, qcap);
   }
   aa.ls_ptr = ls_ptr.p; aa.l1_seg = l1_seg.p; aa.ls_self = ls_self.p; aa.ls_rec = ls_rec.p;
   aa.l1_rec = l1_rec.p; aa.ls_src = ls_src.p; aa.ls_dst = ls_dst.p; aa.l1_src = l1_src.p; aa.l1_dst = l1_dst.p;
@@ -1239,6 +1273,10 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
     if (n_l1)
       hipLaunchKernelGGL((k_adj_val<W>), nb256(n_l1), dim3(256), 0, s, n_l1, l1_src.p, l1_dst.p, b.b_bits.p,
                          nB, eB.p, it, l1_rec.p, (double *)nullptr);
+    CIB_HIP(hipMemsetAsync(lev_cnt.p, 0, sizeof(int32_t) * (size_t)nB * nseg * p.nlev, s));
+    if (n_l1)
+      hipLaunchKernelGGL(k_l1_levels, nb256(n_l1), dim3(256), 0, s, n_l1, nseg, p.nlev, p.qminB, l1_seg.p,
+                         l1_src.p, l1_dst.p, b.b_seg.p, b.b_q.p, lev_cnt.p);
   }
   CIB_HIP(hipGetLastError());
   CIB_HIP(hipEventRecord(ev.e[3], s));
@@ -1250,7 +1288,7 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
   ra.bseg_start = b.bseg_start.p; ra.a_off = b.a_off.p; ra.a_bits = b.a_bits.p; ra.b_bits = b.b_bits.p;
   ra.eA = eA.p; ra.t_ptr = t_ptr.p; ra.tstride = nchunk; ra.t_rec = t_rec.p;
   ra.t_val = t_val.p; ra.ls_ptr = ls_ptr.p; ra.l1_seg = l1_seg.p; ra.ls_self = ls_self.p;
-  ra.ls_rec = ls_rec.p; ra.l1_rec = l1_rec.p;
+  ra.ls_rec = ls_rec.p; ra.l1_rec = l1_rec.p; ra.lev_cnt = lev_cnt.p; ra.nlev = p.nlev;
   ra.ls_val = ls_val.p; ra.it = it;
   DBuf<int32_t> rcnt(ctx, p.D), rlcnt(ctx, p.D);
   ra.rcnt = rcnt.p;

@@ -176,6 +176,8 @@ struct Plan {
   int W = 1;           // kernel word count: max over species
   int WA = 1, WB = 0;  // real word counts
   int qmax = -1;       // -1: no truncation
+  int qminB = 0;       // lowest Q of a B configuration
+  int nlev = 1;        // Q levels of B configurations a truncation can cut at (cut + 1; 1 without one)
   SubList A, B;        // A: non-empty blocks, ascending integer; B: (2M, Q, integer)
   std::vector<int64_t> a_off;                     // nA + 1
   std::vector<int32_t> a_len, a_seg;              // nA

@@ -99,6 +99,8 @@ void make_plan(const cib_basis_spec &s, Plan &p) {
   const int NA = s.n_particles[0], NB = p.ns == 2 ? s.n_particles[1] : 0;
   const int qminA = q_min(NA, p.oA), qminB = p.ns == 2 ? q_min(NB, p.oB) : 0;
   p.qmax = s.cut >= 0 ? qminA + qminB + s.cut : -1;
+  p.qminB = qminB;
+  p.nlev = s.cut >= 0 ? s.cut + 1 : 1;
 
   SubList A, B;
   enum_configs(p.oA, NA, p.qmax >= 0 ? p.qmax - qminB : -1, A);
