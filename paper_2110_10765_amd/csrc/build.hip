@@ -466,7 +466,8 @@ __global__ __launch_bounds__(256) void k_l1_levels(int64_t n, int nseg, int nlev
                                                    const int32_t *__restrict__ l1_src,
                                                    const int32_t *__restrict__ l1_dst,
                                                    const int32_t *__restrict__ b_seg,
-                                                   const int32_t *__restrict__ b_q, int32_t *__restrict__ lev_cnt) {
+                                                   const int32_t *__restrict__ b_q, int32_t *__restrict__ lev_cnt,
+                                                   int nB, int32_t *__restrict__ lev_t) {
   const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (e >= n) return;
   const int dst = l1_dst[e];
@@ -478,6 +479,13 @@ __global__ __launch_bounds__(256) void k_l1_levels(int64_t n, int nseg, int nlev
   if (e == e0)
     for (int t = 0; t < lev; ++t) out[t] = 0;
   for (int t = lev; t < next; ++t) out[t] = (int32_t)(e - e0 + 1);
+  if (lev_t) {   // the same counts bin-major: lev_t[((h * nlev) + t) * nB + beta]
+    const int beta = l1_src[e], h = (int)(u - (int64_t)beta * nseg);
+    int32_t *ot = lev_t + (int64_t)h * nlev * nB + beta;
+    if (e == e0)
+      for (int t = 0; t < lev; ++t) ot[(int64_t)t * nB] = 0;
+    for (int t = lev; t < next; ++t) ot[(int64_t)t * nB] = (int32_t)(e - e0 + 1);
+  }
 }
 
 template <int W, bool FILL>
@@ -534,6 +542,160 @@ __global__ __launch_bounds__(256) void k_adj_pass(AdjArgs g) {
   if (!FILL && lane == 0) {
     g.l1_cnt[unit] = c_l1;
     if (own) g.ls_cnt[beta] = c_ls;
+  }
+}
+
+// ------------------------------------------------------------ row counts
+// A row's entry counts depend on its A configuration only through alpha's
+// tiles, and on its B configuration only through the level tables:
+//   kA = 1 tiles: sum over (2M_B list g, Q level t) of [alpha's kA = 1
+//     tiles in (g, t)] x lev_cnt[beta][g][t];
+//   kA = 2 tiles: alpha's kA = 2 tiles whose length exceeds the row's
+//     position p in alpha's block;
+//   Lsame: its entries up to alpha's Q level, split at beta itself (those
+//     before it are the lower row's, the rest the upper row's).
+// tile_hist[(alpha * nseg + g) * nlev + t] counts the first, k2len lists the
+// lengths of alpha's kA = 2 tiles from alpha's first tile on (in tile
+// order), k2n[alpha] how many.  One wave per alpha: the histogram is added
+// up in LDS (integer adds: the result does not depend on their order) and
+// written out once; the kA = 2 lengths are compacted with ballots.
+constexpr int kHistBins = 2048;   // bins per wave in LDS (nseg x nlev at most this)
+__global__ __launch_bounds__(256) void k_tile_hist(int nA, const int64_t *__restrict__ t_ptr, int tstride,
+                                                   const TileRec *__restrict__ rec, int nlev, int nbin,
+                                                   int32_t *__restrict__ hist, int32_t *__restrict__ k2len,
+                                                   int32_t *__restrict__ k2n) {
+  __shared__ int32_t h[4][kHistBins];
+  const int wv = uni((int)(threadIdx.x >> 6));
+  const int alpha = (int)blockIdx.x * 4 + wv;
+  if (alpha >= nA) return;   // whole wave
+  const int lane = lane_id();
+  for (int k = lane; k < nbin; k += kWave) h[wv][k] = 0;
+  wave_lds_sync();
+  const int64_t t0 = uni(t_ptr[(int64_t)alpha * tstride]), t1 = uni(t_ptr[(int64_t)(alpha + 1) * tstride]);
+  int n2 = 0;
+  for (int64_t tb = t0; tb < t1; tb += kWave) {
+    const int64_t t = tb + lane;
+    int4 r = make_int4(0, 0, 0, 0);
+    if (t < t1) r = reinterpret_cast<const int4 *>(rec)[t];
+    const bool two = t < t1 && (r.x & 3) == 2;
+    if (t < t1 && !two) atomicAdd(&h[wv][((r.x >> 19) & 0x7f) * nlev + r.y], 1);   // kA = 1: r.y is the Q level
+    const uint64_t m = ballot(two);
+    if (two) k2len[t0 + n2 + mask_rank(m)] = r.y;
+    n2 += __popcll(m);
+  }
+  wave_lds_sync();
+  for (int k = lane; k < nbin; k += kWave) hist[(int64_t)alpha * nbin + k] = h[wv][k];
+  if (lane == 0) k2n[alpha] = n2;
+}
+
+// ls_lev[beta * nlev + t] = Lsame entries of beta with Q_B <= qmin_B + t (a
+// prefix: the list is ordered by position), one thread per entry, written
+// as k_l1_levels writes its table.
+__global__ __launch_bounds__(256) void k_ls_levels(int64_t n, int nlev, int qminB, const int64_t *__restrict__ ls_ptr,
+                                                   const int32_t *__restrict__ ls_src,
+                                                   const int32_t *__restrict__ ls_dst,
+                                                   const int32_t *__restrict__ b_q, int32_t *__restrict__ ls_lev) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const int beta = ls_src[e];
+  const int64_t e0 = ls_ptr[beta], e1 = ls_ptr[beta + 1];
+  const int lev = nlev > 1 ? b_q[ls_dst[e]] - qminB : 0;
+  const int next = e + 1 < e1 ? (nlev > 1 ? b_q[ls_dst[e + 1]] - qminB : 0) : nlev;
+  int32_t *out = ls_lev + (int64_t)beta * nlev;
+  if (e == e0)
+    for (int t = 0; t < lev; ++t) out[t] = 0;
+  for (int t = lev; t < next; ++t) out[t] = (int32_t)(e - e0 + 1);
+}
+
+struct CountArgs {
+  int nA, nB, nseg, nlev, nbin, qcap, tstride;
+  const int32_t *cstart;   // nA + 1: first wave of each A configuration (a wave per 64 rows)
+  int64_t nwaves;
+  const int64_t *a_off;
+  const int32_t *a_len, *a_q, *a_seg, *bseg_start, *ls_self;
+  const int64_t *ls_ptr, *t_ptr, *tl_ptr;
+  const int32_t *lev_t, *ls_lev;
+  const int32_t *hist_u, *hist_l, *k2len_u, *k2len_l, *k2n_u, *k2n_l;
+  int32_t *rcnt, *rlcnt;
+};
+
+// One wave per (A configuration alpha, 64 rows of its block), a lane per
+// row: row a_off[alpha] + p has B configuration bseg_start[a_seg[alpha]] + p,
+// so the lanes' B configurations are consecutive and the bin-major level
+// table is read coalesced.  alpha's histogram bins are walked in order (the
+// empty ones skipped: a uniform branch), its kA = 2 lengths one by one.
+constexpr int kCountBins = 4;   // histogram bins per lane kept in registers (nbin <= 256)
+__global__ __launch_bounds__(256) void k_row_count_tab(CountArgs c) {
+  __shared__ int32_t zb[4][kCountBins * kWave], zu[4][kCountBins * kWave], zl[4][kCountBins * kWave];
+  const int wv = uni((int)(threadIdx.x >> 6));
+  const int64_t w = (int64_t)blockIdx.x * 4 + wv;
+  if (w >= c.nwaves) return;   // whole wave
+  // the A configuration of this wave: last alpha with cstart[alpha] <= w
+  int lo = 0, hi = c.nA;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (uni(c.cstart[mid]) <= w) lo = mid; else hi = mid;
+  }
+  const int alpha = lo, chunk = (int)(w - uni(c.cstart[alpha]));
+  const int len = uni(c.a_len[alpha]);
+  const int lane = lane_id();
+  const int p = chunk * kWave + lane;
+  const bool live = p < len;
+  const int64_t r0 = uni(c.a_off[alpha]);
+  const int beta = uni(c.bseg_start[uni(c.a_seg[alpha])]) + (live ? p : 0);
+  // alpha's non-empty bins, listed in LDS in bin order
+  const int32_t *hu = c.hist_u + (int64_t)alpha * c.nbin, *hl = c.hist_l + (int64_t)alpha * c.nbin;
+  int nz = 0;
+#pragma unroll
+  for (int q = 0; q < kCountBins; ++q) {
+    const int k = q * kWave + lane;
+    const int vu = k < c.nbin ? hu[k] : 0, vl = k < c.nbin ? hl[k] : 0;
+    const bool use = (vu | vl) != 0;
+    const uint64_t m = ballot(use);
+    if (use) {
+      const int o = nz + mask_rank(m);
+      zb[wv][o] = k;
+      zu[wv][o] = vu;
+      zl[wv][o] = vl;
+    }
+    nz += __popcll(m);
+  }
+  wave_lds_sync();
+  int su = 0, sl = 0;
+  for (int t0 = 0; t0 < nz; t0 += 8) {   // eight table reads in flight, then the products
+    int f[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int t = min(t0 + u, nz - 1);
+      f[u] = c.lev_t[(int64_t)zb[wv][t] * c.nB + beta];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (t0 + u < nz) {
+        su += zu[wv][t0 + u] * f[u];
+        sl += zl[wv][t0 + u] * f[u];
+      }
+    }
+  }
+  // kA = 2 tiles: one entry each while p < the length of alpha'
+  const int64_t bu = uni(c.t_ptr[(int64_t)alpha * c.tstride]), bl = uni(c.tl_ptr[(int64_t)alpha * c.tstride]);
+  const int nu = uni(c.k2n_u[alpha]), nl = uni(c.k2n_l[alpha]);
+  for (int k0 = 0; k0 < nu; k0 += kWave) {   // lane k0 + j holds length j; the row's count from a ballot
+    const int k = k0 + lane;
+    const int lk = k < nu ? c.k2len_u[bu + k] : 0;
+    for (int j = 0; j < min(kWave, nu - k0); ++j) su += p < __builtin_amdgcn_readlane(lk, j);
+  }
+  for (int k0 = 0; k0 < nl; k0 += kWave) {
+    const int k = k0 + lane;
+    const int lk = k < nl ? c.k2len_l[bl + k] : 0;
+    for (int j = 0; j < min(kWave, nl - k0); ++j) sl += p < __builtin_amdgcn_readlane(lk, j);
+  }
+  if (live) {
+    // Lsame: the entries up to alpha's Q level, split at beta itself
+    const int lev = c.qcap >= 0 ? c.qcap - uni(c.a_q[alpha]) : 0;
+    const int before = (int)(c.ls_self[beta] - c.ls_ptr[beta]);
+    c.rcnt[r0 + p] = su + c.ls_lev[(int64_t)beta * c.nlev + lev] - before;
+    c.rlcnt[r0 + p] = sl + before;
   }
 }
 
@@ -1179,6 +1341,11 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
   const DevInter it = itr.view();
   const int nA = p.nA(), nB = p.nB(), nseg = p.nseg();
   const int qcap = p.qmax >= 0 ? p.qmax - p.qminB : -1;   // Q_A + Q_B <= qmax as a cap on Q_A + (Q_B - qmin_B)
+  // row counts from per-configuration tables (k_row_count_tab) unless the
+  // per-A-configuration histograms would be large
+  const int64_t nbin = (int64_t)nseg * p.nlev;
+  const bool tab_count = nbin <= kCountBins * kWave && (int64_t)nA * nbin <= (int64_t(1) << 25) &&
+                         (int64_t)nB * nbin <= (int64_t(1) << 28);
   Events ev;
   auto bytes = [](size_t count, size_t elem) { return dev_bytes(count * elem); };
 
@@ -1232,7 +1399,12 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
     // screens, row counts, diagonal and the two offset arrays
     reserve(1, (bytes(nt, 16) + 2 * bytes(nt, 4) + bytes(nt, 8)) + (bytes(nl, 16) + 2 * bytes(nl, 4) + bytes(nl, 8)) +
                    bytes(nB, 4) + bytes(ns, 8) + 2 * bytes(ns, 4) + bytes(n1, 8) + 2 * bytes(n1, 4) + bytes(ns, 8) +
-                   bytes((size_t)nB * nseg * p.nlev, 4) + 2 * bytes(p.D, 4) +
+                   bytes((size_t)nB * nseg * p.nlev, 4) +
+                   (tab_count ? 2 * bytes((size_t)nA * nseg * p.nlev, 4) + bytes(nt, 4) + bytes(nl, 4) +
+                                    bytes((size_t)nB * nseg * p.nlev, 4) + bytes(nA + 1, 4) +
+                                    2 * bytes(nA, 4) + bytes((size_t)nB * p.nlev, 4)
+                              : 0) +
+                   2 * bytes(p.D, 4) +
                    bytes(p.D, 8) + 2 * bytes(p.D + 1, 8));
   }
   DBuf<TileRec> t_rec(ctx, at_least1(n_tiles)), tl_rec(ctx, at_least1(n_lt));
@@ -1245,6 +1417,8 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
   DBuf<int32_t> l1_src(ctx, at_least1(n_l1)), l1_dst(ctx, at_least1(n_l1));
   DBuf<double> ls_val(ctx, at_least1(n_ls));
   DBuf<int32_t> lev_cnt(ctx, (size_t)nB * nseg * p.nlev);
+  DBuf<int32_t> lev_t;   // the same, bin-major (table-driven row counts only)
+  if (tab_count) lev_t.reset(ctx, (size_t)nB * nseg * p.nlev);
   CIB_HIP(hipEventRecord(ev.e[2], s));
   ta.t_ptr = t_ptr.p; ta.t_rec = t_rec.p; ta.t_src = t_src.p; ta.t_dst = t_dst.p;
   tl.t_ptr = tl_ptr.p; tl.t_rec = tl_rec.p; tl.t_src = tl_src.p; tl.t_dst = tl_dst.p;
@@ -1274,9 +1448,10 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
       hipLaunchKernelGGL((k_adj_val<W>), nb256(n_l1), dim3(256), 0, s, n_l1, l1_src.p, l1_dst.p, b.b_bits.p,
                          nB, eB.p, it, l1_rec.p, (double *)nullptr);
     CIB_HIP(hipMemsetAsync(lev_cnt.p, 0, sizeof(int32_t) * (size_t)nB * nseg * p.nlev, s));
+    if (tab_count) CIB_HIP(hipMemsetAsync(lev_t.p, 0, sizeof(int32_t) * (size_t)nB * nseg * p.nlev, s));
     if (n_l1)
       hipLaunchKernelGGL(k_l1_levels, nb256(n_l1), dim3(256), 0, s, n_l1, nseg, p.nlev, p.qminB, l1_seg.p,
-                         l1_src.p, l1_dst.p, b.b_seg.p, b.b_q.p, lev_cnt.p);
+                         l1_src.p, l1_dst.p, b.b_seg.p, b.b_q.p, lev_cnt.p, nB, tab_count ? lev_t.p : nullptr);
   }
   CIB_HIP(hipGetLastError());
   CIB_HIP(hipEventRecord(ev.e[3], s));
@@ -1314,9 +1489,41 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
     CIB_HIP(hipStreamSynchronize(s));   // the screens are freed on return
     return;
   }
+  // (at function scope: freed with the screens, after the final wait)
+  DBuf<int32_t> hist_u, hist_l, k2len_u, k2len_l, k2n_u, k2n_l, ls_lev, cstart;
+  std::vector<int32_t> cstart_h(nA + 1, 0);   // waves of k_row_count_tab: one per 64 rows of each block
+  if (tab_count) {
+    for (int a2 = 0; a2 < nA; ++a2) cstart_h[a2 + 1] = cstart_h[a2] + (p.a_len[a2] + kWave - 1) / kWave;
+    cstart.reset(ctx, nA + 1);
+    cstart.upload(cstart_h.data(), nA + 1, s);
+    hist_u.reset(ctx, (size_t)nA * nbin);
+    hist_l.reset(ctx, (size_t)nA * nbin);
+    k2len_u.reset(ctx, at_least1(n_tiles));
+    k2len_l.reset(ctx, at_least1(n_lt));
+    k2n_u.reset(ctx, nA);
+    k2n_l.reset(ctx, nA);
+    ls_lev.reset(ctx, (size_t)nB * p.nlev);
+  }
   {
     KTimer kt(ctx, K_ROW_COUNT, s);
-    hipLaunchKernelGGL((k_row_pass<W, false, double>), dim3(rblk), dim3(256), 0, s, ra, rl);
+    if (tab_count) {
+      CIB_HIP(hipMemsetAsync(ls_lev.p, 0, sizeof(int32_t) * (size_t)nB * p.nlev, s));
+      const unsigned ablk4 = (unsigned)((nA + 3) / 4);
+      hipLaunchKernelGGL(k_tile_hist, dim3(ablk4), dim3(256), 0, s, nA, t_ptr.p, nchunk, t_rec.p, p.nlev, (int)nbin,
+                         hist_u.p, k2len_u.p, k2n_u.p);
+      hipLaunchKernelGGL(k_tile_hist, dim3(ablk4), dim3(256), 0, s, nA, tl_ptr.p, nchunk, tl_rec.p, p.nlev, (int)nbin,
+                         hist_l.p, k2len_l.p, k2n_l.p);
+      if (n_ls)
+        hipLaunchKernelGGL(k_ls_levels, nb256(n_ls), dim3(256), 0, s, n_ls, p.nlev, p.qminB, ls_ptr.p, ls_src.p,
+                           ls_dst.p, b.b_q.p, ls_lev.p);
+      CountArgs ca{nA, nB, nseg, p.nlev, (int)nbin, qcap, nchunk, cstart.p, cstart_h[nA], b.a_off.p, b.a_len.p,
+                   b.a_q.p,
+                   b.a_seg.p, b.bseg_start.p, ls_self.p, ls_ptr.p, t_ptr.p, tl_ptr.p, lev_t.p, ls_lev.p,
+                   hist_u.p, hist_l.p, k2len_u.p, k2len_l.p, k2n_u.p, k2n_l.p, rcnt.p, rlcnt.p};
+      hipLaunchKernelGGL(k_row_count_tab, dim3((unsigned)((cstart_h[nA] + 3) / 4)), dim3(256), 0, s, ca);
+    } else {
+      hipLaunchKernelGGL((k_row_pass<W, false, double>), dim3(rblk), dim3(256), 0, s, ra, rl);
+    }
     hipLaunchKernelGGL((k_state_diag<W>), dim3((unsigned)((p.D + 255) / 256)), dim3(256), 0, s, p.D,
                        b.row_a.p, b.row_p.p, b.a_seg.p, b.bseg_start.p, b.a_bits.p, nA, b.b_bits.p, nB,
                        eA.p, eB.p, it, diag.p);
