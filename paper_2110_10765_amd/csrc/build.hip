@@ -922,6 +922,38 @@ __device__ __forceinline__ void row_tiles(const RowArgs &g, int64_t t0, int64_t 
       d.si = TAB ? g.t_si[t] : -1;
     }
   };
+  // the kept window's per-lane entry data, and how to write one entry
+  int rem = 0, w_il = 0, w_io = 0, w_coff = 0, w_orbs = 0;
+  double w_bu = 0.0;
+  auto emit = [&](bool on) {
+    if (!on) return;
+    const int orb = w_orbs & 0x7fffffff;
+    const int2 lr = L.rec[w_il];
+    const int li = lr.y, lp = lr.x;
+    double v;
+    if ((li & 3) == 0) {  // B unchanged: AA part + s_A sum_{y in beta} V^AB_{(a,y),(c,y)}
+      if constexpr (TAB) {
+        v = w_bu;
+      } else {
+        double sum = 0.0;
+        if (g.it.nB > 0)
+          sum = spec_sum<W>(sb_idx, bb, g.it.bcol, g.it.nB, [&](int32_t c) { return vt_at(g.it, orb, c); });
+        v = w_bu + (w_orbs < 0 ? -sum : sum);
+      }
+    } else {              // one A and one B orbital change: the two phases on the table element
+      const uint64_t neg = (uint64_t)(((uint32_t)w_orbs >> 31) ^ ((uint32_t)li >> 2 & 1u)) << 63;
+      v = __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, vt_at(g.it, orb, li >> 3)) ^ neg);
+    }
+    if constexpr (Acc::kApply) {
+      acc.add(w_coff + lp, v);
+    } else {
+      // byte offsets as 32-bit values: the stores take the scalar base
+      // and a 32-bit vector offset (a row's outputs stay below 2^29)
+      const uint32_t io = (uint32_t)w_io;
+      *reinterpret_cast<int32_t *>(reinterpret_cast<char *>(g.col + out) + io * 4u) = w_coff + lp;
+      *reinterpret_cast<T *>(reinterpret_cast<char *>(val + out) + io * (uint32_t)sizeof(T)) = (T)v;
+    }
+  };
   Batch nx;
   if (t0 < t1) fetch(t0, nx);
   for (int64_t tb = t0; tb < t1; tb += kWave) {
@@ -969,65 +1001,59 @@ __device__ __forceinline__ void row_tiles(const RowArgs &g, int64_t t0, int64_t 
           valb[(uint32_t)orel] = (T)tv;
         }
       }
-      // kA = 1 entries, spread over the lanes.  What an entry's lane needs of
-      // its tile, made once per batch: list index = pl + k, output index
-      // (from the batch's first output) = po + k, the table row base with
-      // the tile's phase bit on top (rb < 2^31).
+      // kA = 1 entries, spread over the lanes in windows of 64 that run on
+      // from one batch of tiles into the next.  What an entry's lane needs of
+      // its tile: list index = pl + k, output index (from the row's first
+      // output) = po + k, the column base, the table row base with the
+      // tile's phase bit on top (rb < 2^31) and the tile's value for the
+      // entry that keeps beta.  A window the batch leaves short is kept in
+      // registers (lanes [0, rem)) and completed by the next batch; the last
+      // one is written after the last batch.
       const int n1 = two ? 0 : ne;
       const int incl1 = wave_incl_scan_dpp(n1);
       const int tot1 = __builtin_amdgcn_readlane(incl1, kWave - 1);
       const int st1 = incl1 - n1;
-      const int pl = l0 - st1, po = orel - st1;
+      const int pl = l0 - st1, po = (int)cnt + orel - st1;
       const int prb = (int)((uint32_t)rb | ((uint32_t)(info >> 18) & 1u) << 31);
-      // Window of 64 entries: each tile marks the slot where its entries
+      const double pbu = TAB ? bu : tv;
+      // Window [kb, kb + 64) of this batch's entries (kb from -rem: the kept
+      // entries come first): each tile marks the slot where its entries
       // start (lane + 1), a prefix maximum spreads the marks, the owner of
       // the slot before the window covers the slots ahead of the first mark.
       // Every shuffle below runs with the whole wave active (uniform loop).
       int carry = 0;
-      for (int k0 = 0; k0 < tot1; k0 += kWave) {
-        const int k = k0 + lane;
+      for (int kb = -rem; tot1 > 0 && kb < tot1; kb += kWave) {
+        const int k = kb + lane;
         mark[lane] = 0;
         wave_lds_sync();
-        if (n1 > 0 && st1 >= k0 && st1 < k0 + kWave) mark[st1 - k0] = lane + 1;
+        if (n1 > 0 && st1 >= kb && st1 < kb + kWave) mark[st1 - kb] = lane + 1;
         wave_lds_sync();
         const int own = max(wave_incl_max_dpp(mark[lane]), carry) - 1;
         wave_lds_sync();
         carry = __builtin_amdgcn_readlane(own + 1, kWave - 1);
-        const int il = __shfl(pl, own, kWave) + k;
-        const uint32_t io = (uint32_t)(__shfl(po, own, kWave) + k);   // unsigned: a 32-bit store offset
-        const int ocoff = __shfl(coff, own, kWave);
-        const int orbs = __shfl(prb, own, kWave);
-        const double obu = TAB ? __shfl(bu, own, kWave) : 0.0;
-        if (k >= tot1) continue;
-        const int orb = orbs & 0x7fffffff;
-        const int2 lr = L.rec[il];
-        const int li = lr.y, lp = lr.x;
-        double v;
-        if ((li & 3) == 0) {  // B unchanged: AA part + s_A sum_{y in beta} V^AB_{(a,y),(c,y)}
-          if constexpr (TAB) {
-            v = obu;
-          } else {
-            double sum = 0.0;
-            if (g.it.nB > 0)
-              sum = spec_sum<W>(sb_idx, bb, g.it.bcol, g.it.nB, [&](int32_t c) { return vt_at(g.it, orb, c); });
-            v = g.t_val[tb + own] + (orbs < 0 ? -sum : sum);   // (a read, not a lane permute in a branch)
-          }
-        } else {              // one A and one B orbital change: the two phases on the table element
-          const uint64_t neg = (uint64_t)(((uint32_t)orbs >> 31) ^ ((uint32_t)li >> 2 & 1u)) << 63;
-          v = __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, vt_at(g.it, orb, li >> 3)) ^ neg);
+        const int nil = __shfl(pl, own, kWave) + k;
+        const int nio = __shfl(po, own, kWave) + k;
+        const int ncoff = __shfl(coff, own, kWave);
+        const int norbs = __shfl(prb, own, kWave);
+        const double nbu = __shfl(pbu, own, kWave);
+        if (k >= 0) {
+          w_il = nil;
+          w_io = nio;
+          w_coff = ncoff;
+          w_orbs = norbs;
+          w_bu = nbu;
         }
-        if constexpr (Acc::kApply) {
-          acc.add(ocoff + lp, v);
-        } else {
-          // byte offsets as 32-bit values: the stores take the scalar base
-          // and a 32-bit vector offset (a row's outputs stay below 2^29)
-          *reinterpret_cast<int32_t *>(reinterpret_cast<char *>(colb) + io * 4u) = ocoff + lp;
-          *reinterpret_cast<T *>(reinterpret_cast<char *>(valb) + io * (uint32_t)sizeof(T)) = (T)v;
+        if (kb + kWave > tot1) {   // short: kept for the next batch
+          rem = tot1 - kb;
+          break;
         }
+        emit(true);
+        rem = 0;
       }
     }
     cnt += total;
   }
+  if (FILL && rem > 0) emit(lane < rem);
 }
 
 // Body of the row passes (count, fill, matrix-free apply) for row i, wave wv
