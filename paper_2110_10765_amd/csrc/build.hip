@@ -1442,12 +1442,14 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
     reserve(0, bytes(nA, 8) + bytes(nB, 8) + 2 * bytes(nunit, 4) + bytes(nB, 4) + bytes((size_t)nB * nseg, 4) +
                    2 * bytes(nunit + 1, 8) + bytes(nB + 1, 8) + bytes((size_t)nB * nseg + 1, 8) + bytes(nscr, 8) +
                    bytes(4, 8));
-  CIB_HIP(hipEventRecord(ev.e[0], s));
+  // (each stage's buffers are taken before its first event: host work inside
+  // a timed interval would leave the device idle there)
   DBuf<double> eA(ctx, nA), eB(ctx, nB);
-  launch_substate_energy(b, it, eA.p, eB.p, s);
   DBuf<int32_t> tcnt(ctx, nunit), tlcnt(ctx, nunit), ls_cnt(ctx, nB), l1_cnt(ctx, (size_t)nB * nseg);
   DBuf<int64_t> t_ptr(ctx, nunit + 1), tl_ptr(ctx, nunit + 1), ls_ptr(ctx, nB + 1), l1_seg(ctx, (size_t)nB * nseg + 1);
   DBuf<int64_t> scratch(ctx, nscr), totals(ctx, 4);
+  CIB_HIP(hipEventRecord(ev.e[0], s));
+  launch_substate_energy(b, it, eA.p, eB.p, s);
   TileArgs ta{};
   ta.nA = nA; ta.nchunk = nchunk; ta.a_bits = b.a_bits.p; ta.a_m2 = b.a_m2.p; ta.a_len = b.a_len.p;
   ta.a_seg = b.a_seg.p; ta.a_off = b.a_off.p; ta.it = it; ta.tcnt = tcnt.p;
@@ -1505,6 +1507,27 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
   DBuf<int32_t> lev_cnt(ctx, (size_t)nB * nseg * p.nlev);
   DBuf<int32_t> lev_t;   // the same, bin-major (table-driven row counts only)
   if (tab_count) lev_t.reset(ctx, (size_t)nB * nseg * p.nlev);
+  // the row-count stage's buffers and the row offsets
+  DBuf<int32_t> rcnt(ctx, p.D), rlcnt(ctx, p.D);
+  DBuf<double> diag(ctx, p.D);
+  DBuf<int32_t> hist_u, hist_l, k2len_u, k2len_l, k2n_u, k2n_l, ls_lev, cstart;
+  std::vector<int32_t> cstart_h(nA + 1, 0);   // waves of k_row_count_tab: one per 64 rows of each block
+  if (tab_count && !ap) {
+    for (int a2 = 0; a2 < nA; ++a2) cstart_h[a2 + 1] = cstart_h[a2] + (p.a_len[a2] + kWave - 1) / kWave;
+    cstart.reset(ctx, nA + 1);
+    cstart.upload(cstart_h.data(), nA + 1, s);
+    hist_u.reset(ctx, (size_t)nA * nbin);
+    hist_l.reset(ctx, (size_t)nA * nbin);
+    k2len_u.reset(ctx, at_least1(n_tiles));
+    k2len_l.reset(ctx, at_least1(n_lt));
+    k2n_u.reset(ctx, nA);
+    k2n_l.reset(ctx, nA);
+    ls_lev.reset(ctx, (size_t)nB * p.nlev);
+  }
+  if (!ap) {
+    H.row_ptr.reset(ctx, p.D + 1);
+    H.lo_ptr.reset(ctx, p.D + 1);
+  }
   CIB_HIP(hipEventRecord(ev.e[2], s));
   ta.t_ptr = t_ptr.p; ta.t_rec = t_rec.p; ta.t_src = t_src.p; ta.t_dst = t_dst.p;
   tl.t_ptr = tl_ptr.p; tl.t_rec = tl_rec.p; tl.t_src = tl_src.p; tl.t_dst = tl_dst.p;
@@ -1551,7 +1574,6 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
   ra.t_val = t_val.p; ra.ls_ptr = ls_ptr.p; ra.l1_seg = l1_seg.p; ra.ls_self = ls_self.p;
   ra.ls_rec = ls_rec.p; ra.l1_rec = l1_rec.p; ra.lev_cnt = lev_cnt.p; ra.nlev = p.nlev;
   ra.ls_val = ls_val.p; ra.it = it; ra.t_si = t_si.p;
-  DBuf<int32_t> rcnt(ctx, p.D), rlcnt(ctx, p.D);
   ra.rcnt = rcnt.p;
   LowerArgs rl{tl_ptr.p, tl_rec.p, tl_val.p, tl_si.p, rlcnt.p, nullptr, nullptr, nullptr};
   // Spectator-sum tables of the fill (two species, up to kSpecTable values
@@ -1573,7 +1595,6 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
     ra.spec_u = spec_u.p;
   };
   const unsigned rblk = (unsigned)((p.D + 3) / 4);
-  DBuf<double> diag(ctx, p.D);
   if (ap) {
     hipLaunchKernelGGL((k_state_diag<W>), dim3((unsigned)((p.D + 255) / 256)), dim3(256), 0, s, p.D,
                        b.row_a.p, b.row_p.p, b.a_seg.p, b.bseg_start.p, b.a_bits.p, nA, b.b_bits.p, nB,
@@ -1592,21 +1613,6 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
     CIB_HIP(hipGetLastError());
     CIB_HIP(hipStreamSynchronize(s));   // the screens are freed on return
     return;
-  }
-  // (at function scope: freed with the screens, after the final wait)
-  DBuf<int32_t> hist_u, hist_l, k2len_u, k2len_l, k2n_u, k2n_l, ls_lev, cstart;
-  std::vector<int32_t> cstart_h(nA + 1, 0);   // waves of k_row_count_tab: one per 64 rows of each block
-  if (tab_count) {
-    for (int a2 = 0; a2 < nA; ++a2) cstart_h[a2 + 1] = cstart_h[a2] + (p.a_len[a2] + kWave - 1) / kWave;
-    cstart.reset(ctx, nA + 1);
-    cstart.upload(cstart_h.data(), nA + 1, s);
-    hist_u.reset(ctx, (size_t)nA * nbin);
-    hist_l.reset(ctx, (size_t)nA * nbin);
-    k2len_u.reset(ctx, at_least1(n_tiles));
-    k2len_l.reset(ctx, at_least1(n_lt));
-    k2n_u.reset(ctx, nA);
-    k2n_l.reset(ctx, nA);
-    ls_lev.reset(ctx, (size_t)nB * p.nlev);
   }
   {
     KTimer kt(ctx, K_ROW_COUNT, s);
@@ -1635,8 +1641,6 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
   ra.diag = diag.p;
   CIB_HIP(hipGetLastError());
   CIB_HIP(hipEventRecord(ev.e[4], s));
-  H.row_ptr.reset(ctx, p.D + 1);
-  H.lo_ptr.reset(ctx, p.D + 1);
   {
     KTimer kt(ctx, K_SCAN, s);
     launch_scans({{rcnt.p, p.D, H.row_ptr.p}, {rlcnt.p, p.D, H.lo_ptr.p}}, scratch.p, s);
