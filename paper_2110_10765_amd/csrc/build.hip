@@ -280,8 +280,7 @@ __global__ __launch_bounds__(256) void k_tile_val(int64_t n, const int32_t *__re
                                                   const uint64_t *__restrict__ a_bits, int nAc,
                                                   const int32_t *__restrict__ a_seg, DevInter it,
                                                   TileRec *__restrict__ t_rec, double *__restrict__ t_val,
-                                                  const int32_t *__restrict__ a_q, int qcap,
-                                                  int32_t *__restrict__ t_si) {
+                                                  const int32_t *__restrict__ a_q, int qcap) {
   const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (e >= n) return;
   const int alpha = src[e], j = dst[e];
@@ -296,7 +295,7 @@ __global__ __launch_bounds__(256) void k_tile_val(int64_t n, const int32_t *__re
   }
   const int p1 = pop_lowest<W>(part), h1 = pop_lowest<W>(hole);
   const int p2 = pop_lowest<W>(part), h2 = pop_lowest<W>(hole);
-  int info, rb = 0, si = -1;
+  int info, rb = 0;
   double val;
   if (p2 < 0) {  // kA = 1
     const int sg = sign_single<W>(ca, p1, h1);
@@ -305,9 +304,6 @@ __global__ __launch_bounds__(256) void k_tile_val(int64_t n, const int32_t *__re
     val = sg * sum;
     info = 1 | (p1 << 2) | (h1 << 10) | ((sg < 0) << 18) | (a_seg[j] << 19);
     rb = it.arb ? it.arb[p1 * it.nA + h1] : 0;
-    // p <- h keeps 2m when alpha and alpha' share their 2M_B list: its row
-    // in the block of such transitions indexes the spectator-sum table
-    if (it.vt0_nb > 0 && a_seg[alpha] == a_seg[j]) si = (int)(((int64_t)rb - it.vt0_base) / it.vt0_nb);
     // a kA = 1 tile keeps, in place of alpha''s length, the Q level its B
     // states stop at (qcap - Q_A(alpha'), qcap = qmax - qmin_B; 0 without a
     // truncation): its entries are the L1 entries of the row's B
@@ -321,41 +317,9 @@ __global__ __launch_bounds__(256) void k_tile_val(int64_t n, const int32_t *__re
   t_rec[e].info = info;
   t_rec[e].rb = rb;
   t_val[e] = val;
-  t_si[e] = si;
-}
-
-// Spectator sums of the transitions that keep 2m, as tables (two species):
-// S[beta * na + i] = sum over the occupied orbitals y of beta, ascending, of
-// V^AB_{(a,y),(c,y)} for row i = a <- c of that block of the transition
-// table; U[alpha * nb + j] = sum over the occupied x of alpha, ascending, of
-// V^AB_{(x,b),(x,d)} for its column j = b <- d.  A row pass reads one value
-// where it would otherwise add a sum per entry; the terms and their order
-// are the same, so are the results.
-template <int W>
-__global__ __launch_bounds__(256) void k_spec_rows(int64_t n, int nBc, const uint64_t *__restrict__ b_bits,
-                                                   DevInter it, double *__restrict__ S) {
-  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (e >= n) return;
-  const int beta = (int)(e / it.vt0_na), i = (int)(e % it.vt0_na);
-  uint64_t bb[W];
-  load_bits<W>(b_bits, nBc, beta, bb);
-  const int32_t rb = (int32_t)(it.vt0_base + (int64_t)i * it.vt0_nb);
-  S[e] = sum_over_bits<W>(bb, [&](int y) { return vt_at(it, rb, it.bcol[y * (it.nB + 1)]); });
-}
-
-template <int W>
-__global__ __launch_bounds__(256) void k_spec_cols(int64_t n, int nAc, const uint64_t *__restrict__ a_bits,
-                                                   DevInter it, double *__restrict__ U) {
-  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (e >= n) return;
-  const int alpha = (int)(e / it.vt0_nb), j = (int)(e % it.vt0_nb);
-  uint64_t ab[W];
-  load_bits<W>(a_bits, nAc, alpha, ab);
-  U[e] = sum_over_bits<W>(ab, [&](int x) { return vt_at(it, it.arb[x * (it.nA + 1)], j); });
 }
 
 constexpr int kTileChunk = 256;   // candidate configurations per wave
-constexpr int64_t kSpecTable = int64_t(1) << 24;   // values of each spectator-sum table at most
 
 // One wave per unit (alpha, chunk): candidates alpha' in the chunk's range of
 // kTileChunk configurations, restricted to alpha' > alpha (upper) or
@@ -752,10 +716,10 @@ struct RowArgs {
   const AdjRec *ls_rec, *l1_rec;
   const int32_t *lev_cnt;   // k_l1_levels
   int nlev;
+  const int32_t *b_q;       // fill pass: Q_B of every B configuration, and its minimum
+  int qminB;
   const double *ls_val;
   const double *diag;       // fill pass: diagonal element of every state
-  const int32_t *t_si;      // fill pass: per tile, its row of the spectator-sum table (-1: none)
-  const double *spec_s, *spec_u;   // k_spec_rows / k_spec_cols tables, or null (sums formed in the pass)
   DevInter it;
   int32_t *rcnt;            // count pass
   const int64_t *row_ptr;   // fill pass
@@ -773,7 +737,6 @@ struct LowerArgs {
   const int64_t *t_ptr;
   const TileRec *t_rec;
   const double *t_val;
-  const int32_t *t_si;
   int32_t *rcnt;
   const int64_t *row_ptr;
   int32_t *col;
@@ -785,7 +748,6 @@ __device__ __forceinline__ RowArgs lower_args(const RowArgs &g, const LowerArgs 
   r.t_ptr = l.t_ptr;
   r.t_rec = l.t_rec;
   r.t_val = l.t_val;
-  r.t_si = l.t_si;
   r.rcnt = l.rcnt;
   r.row_ptr = l.row_ptr;
   r.col = l.col;
@@ -833,7 +795,7 @@ struct ApplyAcc {
 
 // Diagonal A-block part of a row: Lsame(beta) entries [e0, e1) in position
 // order, kept while position < len(alpha) (a prefix).
-template <int W, bool FILL, typename T, bool TAB, class Acc>
+template <int W, bool FILL, typename T, class Acc>
 __device__ __forceinline__ void row_diag(const RowArgs &g, int64_t i, int64_t e0, int64_t e1, int alpha,
                                          int len_a, int64_t off_a, const uint64_t *ab, const SpecIdx &sa_idx,
                                          int64_t out, int64_t &cnt, Acc &acc) {
@@ -858,10 +820,7 @@ __device__ __forceinline__ void row_diag(const RowArgs &g, int64_t i, int64_t e0
       } else if (kb == 1) {  // B single: + s_B sum_{x in alpha} V^AB_{(x,b),(x,d)}
         const int32_t bc = info >> 3;
         const double s = (info >> 2) & 1 ? -1.0 : 1.0;
-        if constexpr (TAB)
-          v += s * g.spec_u[(int64_t)alpha * g.it.vt0_nb + bc];
-        else
-          v += s * spec_sum<W>(sa_idx, ab, g.it.arb, g.it.nA, [&](int32_t r) { return vt_at(g.it, r, bc); });
+        v += s * spec_sum<W>(sa_idx, ab, g.it.arb, g.it.nA, [&](int32_t r) { return vt_at(g.it, r, bc); });
       }
       if constexpr (Acc::kApply) {
         acc.add((int32_t)(off_a + pos), v);
@@ -897,8 +856,8 @@ struct L1View {
 // a kA = 2 tile holds at most one entry (same B position), a kA = 1 tile the
 // prefix of beta's L1 list for the tile's 2M_B list with position < len.
 // kA = 1 entries are expanded over all lanes of the wave.
-template <int W, bool FILL, typename T, bool ST, bool TAB, class Acc>
-__device__ __forceinline__ void row_tiles(const RowArgs &g, int64_t t0, int64_t t1, int p, int beta,
+template <int W, bool FILL, typename T, bool ST, class Acc>
+__device__ __forceinline__ void row_tiles(const RowArgs &g, int64_t t0, int64_t t1, int p, int seg_a, int lev_b,
                                           const uint64_t *bb, const SpecIdx &sb_idx, int64_t out, int64_t &cnt,
                                           const L1View<ST> &L, const int32_t *lev, int32_t *mark, Acc &acc) {
   const int lane = lane_id();
@@ -907,7 +866,7 @@ __device__ __forceinline__ void row_tiles(const RowArgs &g, int64_t t0, int64_t 
   // use (unconditional reads at a clamped index: a read under a branch would
   // make the compiler wait for the look-ahead as well)
   struct Batch {
-    int info, len, off, rb, si;
+    int info, len, off, rb;
     double val;
   };
   auto fetch = [&](int64_t tb, Batch &d) {
@@ -919,7 +878,6 @@ __device__ __forceinline__ void row_tiles(const RowArgs &g, int64_t t0, int64_t 
       d.off = r.z;
       d.rb = r.w;
       d.val = g.t_val[t];
-      d.si = TAB ? g.t_si[t] : -1;
     }
   };
   // the kept window's per-lane entry data, and how to write one entry
@@ -931,15 +889,8 @@ __device__ __forceinline__ void row_tiles(const RowArgs &g, int64_t t0, int64_t 
     const int2 lr = L.rec[w_il];
     const int li = lr.y, lp = lr.x;
     double v;
-    if ((li & 3) == 0) {  // B unchanged: AA part + s_A sum_{y in beta} V^AB_{(a,y),(c,y)}
-      if constexpr (TAB) {
-        v = w_bu;
-      } else {
-        double sum = 0.0;
-        if (g.it.nB > 0)
-          sum = spec_sum<W>(sb_idx, bb, g.it.bcol, g.it.nB, [&](int32_t c) { return vt_at(g.it, orb, c); });
-        v = w_bu + (w_orbs < 0 ? -sum : sum);
-      }
+    if ((li & 3) == 0) {  // B unchanged: the tile's value, formed per tile below
+      v = w_bu;
     } else {              // one A and one B orbital change: the two phases on the table element
       const uint64_t neg = (uint64_t)(((uint32_t)w_orbs >> 31) ^ ((uint32_t)li >> 2 & 1u)) << 63;
       v = __builtin_bit_cast(double, __builtin_bit_cast(uint64_t, vt_at(g.it, orb, li >> 3)) ^ neg);
@@ -979,14 +930,17 @@ __device__ __forceinline__ void row_tiles(const RowArgs &g, int64_t t0, int64_t 
       const bool two = (info & 3) == 2;
       const int32_t coff = ne ? cur.off : 0, rb = (!two && ne) ? cur.rb : 0;
       const double tv = ne ? cur.val : 0.0;
-      // With the spectator-sum table: the value of the tile's entry that
-      // keeps beta (only a kA = 1 tile that keeps 2m has one), its AA part
-      // plus the tile's phase times the table's sum over beta, made once per
-      // tile; the entry's lane takes it by a lane permute (a slot in LDS
-      // would cost the eighth workgroup per compute unit).
-      double bu = 0.0;
-      if constexpr (TAB) {
-        const double sum = cur.si >= 0 ? g.spec_s[(int64_t)beta * g.it.vt0_na + cur.si] : 0.0;
+      // The value of the tile's entry that keeps beta, AA part + s_A sum_{y
+      // in beta} V^AB_{(a,y),(c,y)}: a kA = 1 tile has one when its p <- h
+      // keeps 2m (alpha' in alpha's 2M_B list) and its Q level reaches
+      // beta's.  Formed once per tile here, with the batch's lanes together,
+      // not once per window of entries; the entry's lane takes it by a lane
+      // permute.
+      double bu;
+      {
+        double sum = 0.0;
+        if (!two && ne && g.it.nB > 0 && ((info >> 19) & 0x7f) == seg_a && cur.len >= lev_b)
+          sum = spec_sum<W>(sb_idx, bb, g.it.bcol, g.it.nB, [&](int32_t c) { return vt_at(g.it, rb, c); });
         bu = tv + ((info >> 18) & 1 ? -sum : sum);
       }
       // this batch's outputs start at out + cnt (a matrix-free product
@@ -1015,7 +969,6 @@ __device__ __forceinline__ void row_tiles(const RowArgs &g, int64_t t0, int64_t 
       const int st1 = incl1 - n1;
       const int pl = l0 - st1, po = (int)cnt + orel - st1;
       const int prb = (int)((uint32_t)rb | ((uint32_t)(info >> 18) & 1u) << 31);
-      const double pbu = TAB ? bu : tv;
       // Window [kb, kb + 64) of this batch's entries (kb from -rem: the kept
       // entries come first): each tile marks the slot where its entries
       // start (lane + 1), a prefix maximum spreads the marks, the owner of
@@ -1035,7 +988,7 @@ __device__ __forceinline__ void row_tiles(const RowArgs &g, int64_t t0, int64_t 
         const int nio = __shfl(po, own, kWave) + k;
         const int ncoff = __shfl(coff, own, kWave);
         const int norbs = __shfl(prb, own, kWave);
-        const double nbu = __shfl(pbu, own, kWave);
+        const double nbu = __shfl(bu, own, kWave);
         if (k >= 0) {
           w_il = nil;
           w_io = nio;
@@ -1058,7 +1011,7 @@ __device__ __forceinline__ void row_tiles(const RowArgs &g, int64_t t0, int64_t 
 
 // Body of the row passes (count, fill, matrix-free apply) for row i, wave wv
 // of the workgroup; the kernels below describe the enumeration.
-template <int W, bool FILL, typename T, bool TAB, class Acc>
+template <int W, bool FILL, typename T, class Acc>
 __device__ __forceinline__ void row_pass(const RowArgs &g, const LowerArgs &lo, int64_t i, int wv, Acc &acc) {
   const RowArgs gl = lower_args(g, lo);
   __shared__ int2 s_rec[4][kL1Stage];
@@ -1069,6 +1022,8 @@ __device__ __forceinline__ void row_pass(const RowArgs &g, const LowerArgs &lo, 
   const int alpha = uni(g.row_a[i]), p = uni(g.row_p[i]);
   const int beta = uni(g.row_b[i]);
   const int len_a = uni(g.a_len[alpha]);
+  const int seg_a = FILL ? uni(g.a_seg[alpha]) : 0;   // alpha's 2M_B list
+  const int lev_b = FILL && g.nlev > 1 ? uni(g.b_q[beta]) - g.qminB : 0;   // beta's Q level
   const int64_t off_a = uni(g.a_off[alpha]);
   uint64_t ab[W], bb[W];
   SpecIdx sa_idx{0, nullptr}, sb_idx{0, nullptr};
@@ -1100,14 +1055,14 @@ __device__ __forceinline__ void row_pass(const RowArgs &g, const LowerArgs &lo, 
   auto parts = [&](const auto &L) {
     constexpr bool ST = std::is_same<std::decay_t<decltype(L)>, L1View<true>>::value;
     const int64_t ls_me = uni((int64_t)g.ls_self[beta]), ls_hi = uni(g.ls_ptr[beta + 1]);
-    row_diag<W, FILL, T, TAB>(g, i, ls_me, ls_hi, alpha, len_a, off_a, ab, sa_idx, out_u, cu, acc);
-    row_tiles<W, FILL, T, ST, TAB>(g, t0u, t1u, p, beta, bb, sb_idx, out_u, cu, L, lev, s_mark[wv], acc);
+    row_diag<W, FILL, T>(g, i, ls_me, ls_hi, alpha, len_a, off_a, ab, sa_idx, out_u, cu, acc);
+    row_tiles<W, FILL, T, ST>(g, t0u, t1u, p, seg_a, lev_b, bb, sb_idx, out_u, cu, L, lev, s_mark[wv], acc);
     const int64_t out_l = kStore ? uni(gl.row_ptr[i]) : 0;
     const int64_t t0l = uni(gl.t_ptr[(int64_t)alpha * gl.tstride]);
     const int64_t t1l = uni(gl.t_ptr[(int64_t)(alpha + 1) * gl.tstride]);
-    row_tiles<W, FILL, T, ST, TAB>(gl, t0l, t1l, p, beta, bb, sb_idx, out_l, cl, L, lev, s_mark[wv], acc);
+    row_tiles<W, FILL, T, ST>(gl, t0l, t1l, p, seg_a, lev_b, bb, sb_idx, out_l, cl, L, lev, s_mark[wv], acc);
     const int64_t ls_lo = uni(g.ls_ptr[beta]);
-    row_diag<W, FILL, T, TAB>(gl, i, ls_lo, ls_me, alpha, len_a, off_a, ab, sa_idx, out_l, cl, acc);
+    row_diag<W, FILL, T>(gl, i, ls_lo, ls_me, alpha, len_a, off_a, ab, sa_idx, out_l, cl, acc);
   };
   if (n1 <= kL1Stage && g.nseg <= kMaxSeg + 1) {
     for (int64_t k = lane; k < n1; k += kWave) {
@@ -1138,7 +1093,7 @@ __device__ __forceinline__ void row_pass(const RowArgs &g, const LowerArgs &lo, 
 // explicitly: the pass waits on chains of dependent reads, and the scalar
 // registers the compiler would otherwise keep cap it at seven (measured 12%
 // slower).
-template <int W, bool FILL, typename T, bool TAB = false>
+template <int W, bool FILL, typename T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_row_pass(RowArgs g, LowerArgs gl) {
   // plain block order: rows of very different lengths sit in runs, and
   // giving each XCD one contiguous range of rows (for L2 locality of the
@@ -1147,7 +1102,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
   const int64_t i = (int64_t)blockIdx.x * (blockDim.x / kWave) + wv;
   if (i >= g.D) return;
   NoAcc acc;
-  row_pass<W, FILL, T, TAB>(g, gl, i, wv, acc);
+  row_pass<W, FILL, T>(g, gl, i, wv, acc);
 }
 
 // Matrix-free product Y = H X (the FMA variant of Fig. 2: compare, compute
@@ -1166,7 +1121,7 @@ __global__ __launch_bounds__(256) void k_row_apply(RowArgs g, LowerArgs gl, cons
   acc.ldx = ldx;
 #pragma unroll
   for (int u = 0; u < NV; ++u) acc.a[u] = T(0);
-  row_pass<W, true, T, false>(g, gl, i, wv, acc);
+  row_pass<W, true, T>(g, gl, i, wv, acc);
 #pragma unroll
   for (int u = 0; u < NV; ++u)
 #pragma unroll
@@ -1484,7 +1439,7 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
   if (reserve) {
     const size_t nt = at_least1(n_tiles), nl = at_least1(n_lt), ns = at_least1(n_ls), n1 = at_least1(n_l1);
     // screens, row counts, diagonal and the two offset arrays
-    reserve(1, (bytes(nt, 16) + 3 * bytes(nt, 4) + bytes(nt, 8)) + (bytes(nl, 16) + 3 * bytes(nl, 4) + bytes(nl, 8)) +
+    reserve(1, (bytes(nt, 16) + 2 * bytes(nt, 4) + bytes(nt, 8)) + (bytes(nl, 16) + 2 * bytes(nl, 4) + bytes(nl, 8)) +
                    bytes(nB, 4) + bytes(ns, 8) + 2 * bytes(ns, 4) + bytes(n1, 8) + 2 * bytes(n1, 4) + bytes(ns, 8) +
                    bytes((size_t)nB * nseg * p.nlev, 4) +
                    (tab_count ? 2 * bytes((size_t)nA * nseg * p.nlev, 4) + bytes(nt, 4) + bytes(nl, 4) +
@@ -1498,7 +1453,6 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
   DBuf<int32_t> t_src(ctx, at_least1(n_tiles)), t_dst(ctx, at_least1(n_tiles));
   DBuf<int32_t> tl_src(ctx, at_least1(n_lt)), tl_dst(ctx, at_least1(n_lt));
   DBuf<double> t_val(ctx, at_least1(n_tiles)), tl_val(ctx, at_least1(n_lt));
-  DBuf<int32_t> t_si(ctx, at_least1(n_tiles)), tl_si(ctx, at_least1(n_lt));
   DBuf<int32_t> ls_self(ctx, nB);
   DBuf<AdjRec> ls_rec(ctx, at_least1(n_ls)), l1_rec(ctx, at_least1(n_l1));
   DBuf<int32_t> ls_src(ctx, at_least1(n_ls)), ls_dst(ctx, at_least1(n_ls));
@@ -1539,10 +1493,10 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
     // phases and values, one thread per tile
     if (n_tiles)
       hipLaunchKernelGGL((k_tile_val<W>), nb256(n_tiles), dim3(256), 0, s, n_tiles, t_src.p, t_dst.p,
-                         b.a_bits.p, nA, b.a_seg.p, it, t_rec.p, t_val.p, b.a_q.p, qcap, t_si.p);
+                         b.a_bits.p, nA, b.a_seg.p, it, t_rec.p, t_val.p, b.a_q.p, qcap);
     if (n_lt)
       hipLaunchKernelGGL((k_tile_val<W>), nb256(n_lt), dim3(256), 0, s, n_lt, tl_src.p, tl_dst.p,
-                         b.a_bits.p, nA, b.a_seg.p, it, tl_rec.p, tl_val.p, b.a_q.p, qcap, tl_si.p);
+                         b.a_bits.p, nA, b.a_seg.p, it, tl_rec.p, tl_val.p, b.a_q.p, qcap);
   }
   aa.ls_ptr = ls_ptr.p; aa.l1_seg = l1_seg.p; aa.ls_self = ls_self.p; aa.ls_rec = ls_rec.p;
   aa.l1_rec = l1_rec.p; aa.ls_src = ls_src.p; aa.ls_dst = ls_dst.p; aa.l1_src = l1_src.p; aa.l1_dst = l1_dst.p;
@@ -1573,27 +1527,9 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
   ra.eA = eA.p; ra.t_ptr = t_ptr.p; ra.tstride = nchunk; ra.t_rec = t_rec.p;
   ra.t_val = t_val.p; ra.ls_ptr = ls_ptr.p; ra.l1_seg = l1_seg.p; ra.ls_self = ls_self.p;
   ra.ls_rec = ls_rec.p; ra.l1_rec = l1_rec.p; ra.lev_cnt = lev_cnt.p; ra.nlev = p.nlev;
-  ra.ls_val = ls_val.p; ra.it = it; ra.t_si = t_si.p;
+  ra.ls_val = ls_val.p; ra.it = it; ra.b_q = b.b_q.p; ra.qminB = p.qminB;
   ra.rcnt = rcnt.p;
-  LowerArgs rl{tl_ptr.p, tl_rec.p, tl_val.p, tl_si.p, rlcnt.p, nullptr, nullptr, nullptr};
-  // Spectator-sum tables of the fill (two species, up to kSpecTable values
-  // each; past that, and in the matrix-free product, the pass forms the sums
-  // itself), made in the fill's interval of the build.
-  const int64_t n_spec_s = (int64_t)nB * it.vt0_na, n_spec_u = (int64_t)nA * it.vt0_nb;
-  const bool spec_tab = p.ns == 2 && it.vt0_nb > 0 && n_spec_s <= kSpecTable && n_spec_u <= kSpecTable;
-  DBuf<double> spec_s, spec_u;
-  auto alloc_spec = [&]() {
-    if (!spec_tab) return;
-    spec_s.reset(ctx, (size_t)n_spec_s);
-    spec_u.reset(ctx, (size_t)n_spec_u);
-  };
-  auto make_spec = [&]() {
-    if (!spec_tab) return;
-    hipLaunchKernelGGL((k_spec_rows<W>), nb256(n_spec_s), dim3(256), 0, s, n_spec_s, nB, b.b_bits.p, it, spec_s.p);
-    hipLaunchKernelGGL((k_spec_cols<W>), nb256(n_spec_u), dim3(256), 0, s, n_spec_u, nA, b.a_bits.p, it, spec_u.p);
-    ra.spec_s = spec_s.p;
-    ra.spec_u = spec_u.p;
-  };
+  LowerArgs rl{tl_ptr.p, tl_rec.p, tl_val.p, rlcnt.p, nullptr, nullptr, nullptr};
   const unsigned rblk = (unsigned)((p.D + 3) / 4);
   if (ap) {
     hipLaunchKernelGGL((k_state_diag<W>), dim3((unsigned)((p.D + 255) / 256)), dim3(256), 0, s, p.D,
@@ -1652,8 +1588,7 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
   const size_t sv = dt == CIB_F64 ? 8 : 4;
   if (reserve)
     reserve(2, bytes(at_least1(nnz), 4) + bytes(at_least1(nlo), 4) + bytes(at_least1(nnz), sv) +
-                   bytes(at_least1(nlo), sv) + bytes(9, 8) +
-                   (spec_tab ? bytes((size_t)n_spec_s, 8) + bytes((size_t)n_spec_u, 8) : 0));
+                   bytes(at_least1(nlo), sv) + bytes(9, 8));
 
   // ---- filling passes
   H.col.reset(ctx, at_least1(nnz));
@@ -1671,18 +1606,13 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
   rl.row_ptr = H.lo_ptr.p;
   rl.col = H.lo_col.p;
   rl.val = dt == CIB_F64 ? (void *)H.lo_val64.p : (void *)H.lo_val32.p;
-  alloc_spec();
   CIB_HIP(hipEventRecord(ev.e[6], s));
   {
     KTimer kt(ctx, K_ROW_FILL, s);
-    make_spec();
-    if (dt == CIB_F64) {
-      if (spec_tab) hipLaunchKernelGGL((k_row_pass<W, true, double, true>), dim3(rblk), dim3(256), 0, s, ra, rl);
-      else hipLaunchKernelGGL((k_row_pass<W, true, double>), dim3(rblk), dim3(256), 0, s, ra, rl);
-    } else {
-      if (spec_tab) hipLaunchKernelGGL((k_row_pass<W, true, float, true>), dim3(rblk), dim3(256), 0, s, ra, rl);
-      else hipLaunchKernelGGL((k_row_pass<W, true, float>), dim3(rblk), dim3(256), 0, s, ra, rl);
-    }
+    if (dt == CIB_F64)
+      hipLaunchKernelGGL((k_row_pass<W, true, double>), dim3(rblk), dim3(256), 0, s, ra, rl);
+    else
+      hipLaunchKernelGGL((k_row_pass<W, true, float>), dim3(rblk), dim3(256), 0, s, ra, rl);
   }
   CIB_HIP(hipGetLastError());
   CIB_HIP(hipEventRecord(ev.e[7], s));

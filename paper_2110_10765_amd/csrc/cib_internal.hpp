@@ -209,10 +209,6 @@ struct DevInter {
   // value costs one memory access.
   const double *vt = nullptr;
   const int32_t *arb = nullptr, *bcol = nullptr;
-  // the block of vt whose transitions keep 2m (2m_a = 2m_c, 2m_b = 2m_d):
-  // rows vt0_na, columns vt0_nb, from offset vt0_base
-  int64_t vt0_base = 0;
-  int vt0_na = 0, vt0_nb = 0;
 };
 
 }  // namespace cib
@@ -249,8 +245,6 @@ struct cib_interaction {
   cib::DBuf<double> epsA, epsB, vA, vB, vAB, dab, vt;
   cib::DBuf<int32_t> pidxA, pidxB, pidxAB, arb, bcol;
   cib::DBuf<int64_t> prowA, prowB, prowAB;
-  int64_t vt0_base = 0;
-  int vt0_na = 0, vt0_nb = 0;
   cib::DevInter view() const;
 };
 

@@ -69,7 +69,6 @@ struct TransLayout {
   std::vector<int32_t> atr, btr;     // (a << 16 | c) and (b << 16 | d), group by group
   std::vector<int32_t> arb, bcol;    // per ordered orbital pair: row base, column index
   std::vector<VtBlock> blocks;
-  VtBlock keep{0, 0, 0, 0, 0};       // the block of the transitions that keep 2m
   int64_t total = 0;
 };
 
@@ -104,7 +103,6 @@ static TransLayout trans_layout(const Orbs &oa, const Orbs &ob) {
     // (the row passes address it with 32-bit byte offsets)
     CIB_REQUIRE(T.total < (int64_t(1) << 29), CIB_E_OVERFLOW, "transition table exceeds 2^29 entries");
     if (nb) T.blocks.push_back(B);
-    if (kv.first == 0 && nb) T.keep = B;
   }
   return T;
 }
@@ -216,9 +214,6 @@ cib_interaction *upload_interaction(cib_ctx *ctx, const cib_basis &b, const cib_
     it->bcol.reset(ctx, T.bcol.size());
     it->bcol.upload(T.bcol.data(), T.bcol.size(), s);
     it->vt.reset(ctx, (size_t)std::max<int64_t>(T.total, 1));
-    it->vt0_base = T.keep.base;
-    it->vt0_na = T.keep.na;
-    it->vt0_nb = T.keep.nb;
     launch_build_vt(it->view(), blk.p, (int)T.blocks.size(), atr.p, btr.p, T.total, it->vt.p, s);
     CIB_HIP(hipStreamSynchronize(s));
     // the blocked pair tables are not read after this point
@@ -323,7 +318,6 @@ cib::DevInter cib_interaction::view() const {
   v.pidxAB = pidxAB.p; v.prowAB = prowAB.p; v.vAB = vAB.p;
   v.dab = dab.p;
   v.vt = vt.p; v.arb = arb.p; v.bcol = bcol.p;
-  v.vt0_base = vt0_base; v.vt0_na = vt0_na; v.vt0_nb = vt0_nb;
   return v;
 }
 
