@@ -26,6 +26,10 @@ SMALL = {
     "ragged_1sp": cigen.Workload("ragged_1sp", cigen.BasisSpec.one(3, 3, 1, 2), 21, 4, 8, "f64"),
     "ragged_2sp": cigen.Workload("ragged_2sp", cigen.BasisSpec.two(2, 2, 3, 3, 1, 3), 22, 4, 8, "f64"),
     "tiny_2sp": cigen.Workload("tiny_2sp", cigen.BasisSpec.two(1, 1, 1, 1, 0, -1), 23, 2, 2, "f64"),
+    # two species with no truncation (a single Q level: every kA = 1 tile that
+    # keeps 2m holds its row's own B configuration), D = 6,040 over many
+    # 64-tile batches and entry windows
+    "nocut_2sp": cigen.Workload("nocut_2sp", cigen.BasisSpec.two(2, 2, 2, 2, 0, -1), 27, 4, 8, "f64"),
     "one_state": cigen.Workload("one_state", cigen.BasisSpec.one(1, 8, 0, -1), 24, 1, 1, "f64"),
     # the largest orbital sets: n <= 6 is 168 orbitals, three 64-bit words;
     # N = 2 connects every pair (a dense H), and a mixed basis has three
