@@ -393,13 +393,13 @@ struct alignas(8) AdjRec {
 };
 
 struct AdjArgs {
-  int nB, nseg, max_dm;
+  int nB, nseg, nchunk, ngroup, gsz;   // chunks of 64 configurations over all lists; groups of gsz <= 64 B configurations
   const uint64_t *b_bits;
-  const int32_t *b_seg, *b_m2, *bseg_start;
-  const double *eB;
-  DevInter it;
-  int32_t *ls_cnt, *l1_cnt;           // count pass
-  const int64_t *ls_ptr, *l1_seg;     // fill pass
+  const int32_t *b_seg, *bseg_start;
+  const int32_t *chunk_list, *coff;   // list of every chunk; first chunk of every list (nseg + 1)
+  const int32_t *ls_base;             // first Lsame cell of every beta (its own list's chunks), nB + 1
+  int32_t *ls_cnt, *l1_cnt;           // count pass: per (beta, own-list chunk); per (beta, chunk), beta-major
+  const int64_t *ls_off, *l1_off;     // fill pass: their exclusive scans
   int32_t *ls_self;
   AdjRec *ls_rec, *l1_rec;                      // fill pass: pos of every entry
   int32_t *ls_src, *ls_dst, *l1_src, *l1_dst;   // (beta, beta') of every entry
@@ -488,60 +488,100 @@ __global__ __launch_bounds__(256) void k_l1_levels(int64_t n, int nseg, int nlev
   }
 }
 
+// One wave per (chunk of 64 configurations of one 2M_B list, group of up to
+// 64 B configurations beta): the lanes hold the chunk's candidates beta', and the
+// wave takes the group's configurations one after another (their bits and
+// lists read once, coalesced, and broadcast from a lane).  Lsame(beta):
+// beta' in beta's own list with popcount <= 4; L1(beta): beta' in any list
+// with popcount <= 2.  The count pass writes the L1 count of every (beta,
+// chunk), beta-major, and the Lsame count of every chunk of beta's own
+// list, so that their scans place every chunk's entries: the entries of
+// beta come out grouped by list, ascending position.  (A wave per
+// (beta, list) instead waited on its setup reads: 145 K short waves at D =
+// 198,912.)
 template <int W, bool FILL>
 __global__ __launch_bounds__(256) void k_adj_pass(AdjArgs g) {
   const int64_t unit = blockIdx.x * (int64_t)(blockDim.x / kWave) + uni((int)(threadIdx.x >> 6));
-  if (unit >= (int64_t)g.nB * g.nseg) return;
-  const int beta = (int)(unit / g.nseg), h = (int)(unit % g.nseg);
+  if (unit >= (int64_t)g.nchunk * g.ngroup) return;
+  const int q = (int)(unit / g.ngroup), bg = (int)(unit % g.ngroup);
   const int lane = lane_id();
-  const int gs = uni(g.b_seg[beta]);
+  const int h = uni(g.chunk_list[q]);
   const int lo = uni(g.bseg_start[h]), hi = uni(g.bseg_start[h + 1]);
-  const bool own = h == gs;
-  if (!own && (hi <= lo || abs(g.b_m2[lo] - g.b_m2[beta]) > g.max_dm)) {
-    if (!FILL && lane == 0) g.l1_cnt[unit] = 0;
-    return;
+  const int j = lo + (q - uni(g.coff[h])) * kWave + lane;
+  const bool jv = j < hi;
+  uint64_t cb[W];
+  load_bits<W>(g.b_bits, g.nB, jv ? j : lo, cb);
+  const int b0 = bg * g.gsz, nb = min(g.gsz, g.nB - b0);
+  // lane k: the bits, list and (fill pass) output offsets of beta = b0 + k
+  const int bl = min(b0 + lane, g.nB - 1);
+  uint64_t vb[W];
+  load_bits<W>(g.b_bits, g.nB, bl, vb);
+  const int vseg = g.b_seg[bl];
+  const int64_t cell = (int64_t)bl * g.nchunk + q;
+  const int64_t lcell = g.ls_base[bl] + (q - uni(g.coff[h]));   // (a cell only where vseg == h)
+  int64_t vls = 0, vl1 = 0;
+  if (FILL) {
+    vls = vseg == h ? g.ls_off[lcell] : 0;
+    vl1 = g.l1_off[cell];
   }
-  uint64_t rb[W];
-  load_bits<W>(g.b_bits, g.nB, beta, rb);
+  int my_ls = 0, my_l1 = 0;
+  for (int k = 0; k < nb; ++k) {
+    uint64_t rb[W];
 #pragma unroll
-  for (int w = 0; w < W; ++w) rb[w] = uni(rb[w]);
-  int c_ls = 0, c_l1 = 0;
-  const int64_t ls0 = FILL && own ? uni(g.ls_ptr[beta]) : 0;
-  const int64_t l10 = FILL ? uni(g.l1_seg[unit]) : 0;
-  // candidate bits one chunk ahead (clamped, unconditional reads)
-  uint64_t nb_[W];
-  auto fetch = [&](int j0) { load_bits<W>(g.b_bits, g.nB, min(j0 + lane, hi - 1), nb_); };
-  if (lo < hi) fetch(lo);
-  for (int j0 = lo; j0 < hi; j0 += kWave) {
-    const int j = j0 + lane;
-    int d = 99;
-    uint64_t cb[W];
-#pragma unroll
-    for (int w = 0; w < W; ++w) cb[w] = nb_[w];
-    fetch(j0 + kWave);
-    if (j < hi) d = popc_xor<W>(rb, cb);
-    const bool in_ls = own && d <= 4;
-    const bool in_l1 = d <= 2;
+    for (int w = 0; w < W; ++w) {
+      const uint32_t lo32 = __builtin_amdgcn_readlane((int)(uint32_t)vb[w], k);
+      const uint32_t hi32 = __builtin_amdgcn_readlane((int)(uint32_t)(vb[w] >> 32), k);
+      rb[w] = (uint64_t)hi32 << 32 | lo32;
+    }
+    const bool own = __builtin_amdgcn_readlane(vseg, k) == h;
+    const int d = jv ? popc_xor<W>(rb, cb) : 99;
+    const bool in_ls = own && d <= 4, in_l1 = d <= 2;
     const uint64_t m_ls = ballot(in_ls), m_l1 = ballot(in_l1);
-    if (FILL && in_ls) {
-      const int64_t o = ls0 + c_ls + mask_rank(m_ls);
-      g.ls_rec[o].pos = j - lo;
-      g.ls_src[o] = beta;
-      g.ls_dst[o] = j;
-      if (d == 0) g.ls_self[beta] = (int32_t)o;
+    if constexpr (!FILL) {
+      if (lane == k) {
+        my_ls = __popcll(m_ls);
+        my_l1 = __popcll(m_l1);
+      }
+    } else {
+      const int beta = b0 + k;
+      if (in_ls) {
+        const int64_t o = readlane_i64(vls, k) + mask_rank(m_ls);
+        g.ls_rec[o].pos = j - lo;
+        g.ls_src[o] = beta;
+        g.ls_dst[o] = j;
+        if (j == beta) g.ls_self[beta] = (int32_t)o;
+      }
+      if (in_l1) {
+        const int64_t o = readlane_i64(vl1, k) + mask_rank(m_l1);
+        g.l1_rec[o].pos = j - lo;
+        g.l1_src[o] = beta;
+        g.l1_dst[o] = j;
+      }
     }
-    if (FILL && in_l1) {
-      const int64_t o = l10 + c_l1 + mask_rank(m_l1);
-      g.l1_rec[o].pos = j - lo;
-      g.l1_src[o] = beta;
-      g.l1_dst[o] = j;
-    }
-    c_ls += __popcll(m_ls);
-    c_l1 += __popcll(m_l1);
   }
-  if (!FILL && lane == 0) {
-    g.l1_cnt[unit] = c_l1;
-    if (own) g.ls_cnt[beta] = c_ls;
+  if (!FILL && lane < nb) {
+    if (vseg == h) g.ls_cnt[lcell] = my_ls;
+    g.l1_cnt[cell] = my_l1;
+  }
+}
+
+// The per-(beta, list) starts of the L1 lists and the per-beta starts of the
+// Lsame lists, from the per-(beta, chunk) scans (a list without chunks
+// starts where the next one does).
+__global__ __launch_bounds__(256) void k_adj_offsets(int nB, int nseg, int nchunk, const int32_t *__restrict__ coff,
+                                                     const int32_t *__restrict__ ls_base,
+                                                     const int64_t *__restrict__ ls_off,
+                                                     const int64_t *__restrict__ l1_off, int64_t *__restrict__ ls_ptr,
+                                                     int64_t *__restrict__ l1_seg) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t n = (int64_t)nB * nseg;
+  if (e < n) {
+    const int beta = (int)(e / nseg), h = (int)(e % nseg);
+    l1_seg[e] = l1_off[(int64_t)beta * nchunk + coff[h]];
+    if (h == 0) ls_ptr[beta] = ls_off[ls_base[beta]];
+  } else if (e == n) {
+    l1_seg[n] = l1_off[(int64_t)nB * nchunk];
+    ls_ptr[nB] = ls_off[ls_base[nB]];
   }
 }
 
@@ -1392,17 +1432,42 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
   // ---- counting passes of the two screens (tiles of both triangles)
   const int nchunk = (nA + kTileChunk - 1) / kTileChunk;
   const int64_t nunit = (int64_t)nA * nchunk;
-  const int64_t nscr = std::max(scan_scratch({nunit, nunit, nB, (int64_t)nB * nseg}), scan_scratch({p.D, p.D}));
+  // the adjacency screen's chunks: 64 configurations of one 2M_B list each
+  std::vector<int32_t> coff_h(nseg + 1, 0), chunk_list_h;
+  for (int h = 0; h < nseg; ++h) {
+    const int nc = (p.bseg_start[h + 1] - p.bseg_start[h] + kWave - 1) / kWave;
+    coff_h[h + 1] = coff_h[h] + nc;
+    for (int c = 0; c < nc; ++c) chunk_list_h.push_back(h);
+  }
+  // groups of 64 B configurations per wave, fewer where that would leave
+  // the grid short of eight waves per SIMD
+  const int nchunk_b = coff_h[nseg];
+  int gsz_b = kWave;
+  while (gsz_b > 16 && (int64_t)nchunk_b * ((nB + gsz_b - 1) / gsz_b) < 8192) gsz_b /= 2;
+  const int ngroup_b = (nB + gsz_b - 1) / gsz_b;
+  const int64_t ncell = (int64_t)nB * nchunk_b;
+  std::vector<int32_t> ls_base_h(nB + 1, 0);   // Lsame cells: the chunks of each beta's own list
+  for (int bb = 0; bb < nB; ++bb)
+    ls_base_h[bb + 1] = ls_base_h[bb] + (coff_h[p.b_seg[bb] + 1] - coff_h[p.b_seg[bb]]);
+  const int64_t nlcell = ls_base_h[nB];
+  const int64_t nscr = std::max(scan_scratch({nunit, nunit, nlcell, ncell}), scan_scratch({p.D, p.D}));
   if (reserve)
-    reserve(0, bytes(nA, 8) + bytes(nB, 8) + 2 * bytes(nunit, 4) + bytes(nB, 4) + bytes((size_t)nB * nseg, 4) +
-                   2 * bytes(nunit + 1, 8) + bytes(nB + 1, 8) + bytes((size_t)nB * nseg + 1, 8) + bytes(nscr, 8) +
-                   bytes(4, 8));
+    reserve(0, bytes(nA, 8) + bytes(nB, 8) + 2 * bytes(nunit, 4) + bytes(nlcell, 4) + bytes(ncell, 4) +
+                   2 * bytes(nunit + 1, 8) + bytes(nlcell + 1, 8) + bytes(ncell + 1, 8) + bytes(nB + 1, 8) +
+                   bytes((size_t)nB * nseg + 1, 8) + bytes(nscr, 8) + bytes(4, 8) +
+                   bytes(std::max<size_t>(chunk_list_h.size(), 1), 4) + bytes(nseg + 1, 4) + bytes(nB + 1, 4));
   // (each stage's buffers are taken before its first event: host work inside
   // a timed interval would leave the device idle there)
   DBuf<double> eA(ctx, nA), eB(ctx, nB);
-  DBuf<int32_t> tcnt(ctx, nunit), tlcnt(ctx, nunit), ls_cnt(ctx, nB), l1_cnt(ctx, (size_t)nB * nseg);
-  DBuf<int64_t> t_ptr(ctx, nunit + 1), tl_ptr(ctx, nunit + 1), ls_ptr(ctx, nB + 1), l1_seg(ctx, (size_t)nB * nseg + 1);
+  DBuf<int32_t> tcnt(ctx, nunit), tlcnt(ctx, nunit), ls_cnt(ctx, nlcell), l1_cnt(ctx, ncell);
+  DBuf<int64_t> t_ptr(ctx, nunit + 1), tl_ptr(ctx, nunit + 1), ls_off(ctx, nlcell + 1), l1_off(ctx, ncell + 1);
+  DBuf<int64_t> ls_ptr(ctx, nB + 1), l1_seg(ctx, (size_t)nB * nseg + 1);
   DBuf<int64_t> scratch(ctx, nscr), totals(ctx, 4);
+  DBuf<int32_t> chunk_list(ctx, std::max<size_t>(chunk_list_h.size(), 1)), coff(ctx, nseg + 1);
+  DBuf<int32_t> ls_base(ctx, nB + 1);
+  chunk_list.upload(chunk_list_h.data(), chunk_list_h.size(), s);
+  coff.upload(coff_h.data(), nseg + 1, s);
+  ls_base.upload(ls_base_h.data(), nB + 1, s);
   CIB_HIP(hipEventRecord(ev.e[0], s));
   launch_substate_energy(b, it, eA.p, eB.p, s);
   TileArgs ta{};
@@ -1417,18 +1482,18 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
     hipLaunchKernelGGL((k_tile_pass<W, false, true>), dim3(tblk), dim3(256), 0, s, tl);
   }
   AdjArgs aa{};
-  aa.nB = nB; aa.nseg = nseg; aa.b_bits = b.b_bits.p; aa.b_seg = b.b_seg.p; aa.b_m2 = b.b_m2.p;
-  aa.bseg_start = b.bseg_start.p; aa.eB = eB.p; aa.it = it; aa.ls_cnt = ls_cnt.p; aa.l1_cnt = l1_cnt.p;
-  aa.max_dm = 0;
-  if (p.ns == 2 && !p.oB.twom.empty())
-    aa.max_dm = *std::max_element(p.oB.twom.begin(), p.oB.twom.end()) -
-                *std::min_element(p.oB.twom.begin(), p.oB.twom.end());
-  const unsigned ablk = (unsigned)(((int64_t)nB * nseg + 3) / 4);
+  aa.nB = nB; aa.nseg = nseg; aa.nchunk = nchunk_b; aa.ngroup = ngroup_b; aa.gsz = gsz_b;
+  aa.b_bits = b.b_bits.p; aa.b_seg = b.b_seg.p; aa.bseg_start = b.bseg_start.p;
+  aa.chunk_list = chunk_list.p; aa.coff = coff.p; aa.ls_base = ls_base.p; aa.ls_cnt = ls_cnt.p;
+  aa.l1_cnt = l1_cnt.p;
+  const unsigned ablk = (unsigned)(((int64_t)nchunk_b * ngroup_b + 3) / 4);
   { KTimer kt(ctx, K_ADJ, s); hipLaunchKernelGGL((k_adj_pass<W, false>), dim3(ablk), dim3(256), 0, s, aa); }
   CIB_HIP(hipGetLastError());
-  launch_scans({{tcnt.p, nunit, t_ptr.p}, {tlcnt.p, nunit, tl_ptr.p}, {ls_cnt.p, nB, ls_ptr.p},
-                {l1_cnt.p, (int64_t)nB * nseg, l1_seg.p}},
+  launch_scans({{tcnt.p, nunit, t_ptr.p}, {tlcnt.p, nunit, tl_ptr.p}, {ls_cnt.p, nlcell, ls_off.p},
+                {l1_cnt.p, ncell, l1_off.p}},
                scratch.p, s);
+  hipLaunchKernelGGL(k_adj_offsets, dim3((unsigned)(((int64_t)nB * nseg + 256) / 256)), dim3(256), 0, s, nB, nseg,
+                     nchunk_b, coff.p, ls_base.p, ls_off.p, l1_off.p, ls_ptr.p, l1_seg.p);
   CIB_HIP(hipEventRecord(ev.e[1], s));
   int64_t n4[4];
   read_totals({t_ptr.p + nunit, tl_ptr.p + nunit, ls_ptr.p + nB, l1_seg.p + (int64_t)nB * nseg}, totals.p, n4, s);
@@ -1498,7 +1563,7 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
       hipLaunchKernelGGL((k_tile_val<W>), nb256(n_lt), dim3(256), 0, s, n_lt, tl_src.p, tl_dst.p,
                          b.a_bits.p, nA, b.a_seg.p, it, tl_rec.p, tl_val.p, b.a_q.p, qcap);
   }
-  aa.ls_ptr = ls_ptr.p; aa.l1_seg = l1_seg.p; aa.ls_self = ls_self.p; aa.ls_rec = ls_rec.p;
+  aa.ls_off = ls_off.p; aa.l1_off = l1_off.p; aa.ls_self = ls_self.p; aa.ls_rec = ls_rec.p;
   aa.l1_rec = l1_rec.p; aa.ls_src = ls_src.p; aa.ls_dst = ls_dst.p; aa.l1_src = l1_src.p; aa.l1_dst = l1_dst.p;
   {
     KTimer kt(ctx, K_ADJ, s);
