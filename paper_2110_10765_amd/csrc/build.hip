@@ -258,7 +258,8 @@ struct alignas(16) TileRec {
 
 struct TileArgs {
   int nA;
-  int nchunk;             // candidate chunks per configuration (units = nA * nchunk)
+  int nchunk;             // chunks of 64 candidate configurations (the tile lists' stride)
+  int ngroup, gsz;        // groups of gsz <= 64 configurations alpha, one wave per (chunk, group)
   const uint64_t *a_bits;
   const int32_t *a_m2, *a_len, *a_seg;
   const int64_t *a_off;
@@ -319,63 +320,73 @@ __global__ __launch_bounds__(256) void k_tile_val(int64_t n, const int32_t *__re
   t_val[e] = val;
 }
 
-constexpr int kTileChunk = 256;   // candidate configurations per wave
-
-// One wave per unit (alpha, chunk): candidates alpha' in the chunk's range of
-// kTileChunk configurations, restricted to alpha' > alpha (upper) or
-// alpha' < alpha (LOWER).  Units are laid out alpha-major, so the scan of
-// the per-unit counts lists each alpha's tiles in ascending alpha'.
+// One wave per (chunk of 64 candidate configurations alpha', group of up
+// to 64 configurations alpha), restricted to alpha' > alpha (upper) or
+// alpha' < alpha (LOWER): the lanes hold the candidates, the wave takes the
+// group's configurations one after another (their bits and 2M read once,
+// coalesced, and broadcast from a lane).  The count pass writes the count of
+// every (alpha, chunk), alpha-major, so that their scan lists each
+// alpha's tiles in ascending alpha' (alpha's tiles at [t_ptr[alpha *
+// nchunk], t_ptr[(alpha + 1) * nchunk])).  (A wave per (alpha, 256
+// candidates) instead waited on its setup reads.)
 template <int W, bool FILL, bool LOWER>
 __global__ __launch_bounds__(256) void k_tile_pass(TileArgs g) {
   const int64_t unit = blockIdx.x * (int64_t)(blockDim.x / kWave) + uni((int)(threadIdx.x >> 6));
-  if (unit >= (int64_t)g.nA * g.nchunk) return;
-  const int alpha = (int)(unit / g.nchunk), chunk = (int)(unit % g.nchunk);
+  if (unit >= (int64_t)g.nchunk * g.ngroup) return;
+  const int q = (int)(unit / g.ngroup), bg = (int)(unit % g.ngroup);
   const int lane = lane_id();
-  const int jb = max(chunk * kTileChunk, LOWER ? 0 : alpha + 1);
-  const int je = min((chunk + 1) * kTileChunk, LOWER ? alpha : g.nA);
-  if (jb >= je) {
-    if (!FILL && lane == 0) g.tcnt[unit] = 0;
+  const int j = q * kWave + lane;
+  const bool jv = j < g.nA;
+  const int a0 = bg * g.gsz, na = min(g.gsz, g.nA - a0);
+  // lane k: alpha = a0 + k
+  const int al = min(a0 + lane, g.nA - 1);
+  const int64_t cell = (int64_t)al * g.nchunk + q;
+  // no candidate of the chunk is on the wanted side of any alpha of the
+  // group: zero counts (count pass) or nothing to write
+  if (LOWER ? q * kWave >= a0 + na - 1 : q * kWave + kWave - 1 <= a0) {
+    if (!FILL && lane < na) g.tcnt[cell] = 0;
     return;
   }
-  uint64_t ra[W];
-  load_bits<W>(g.a_bits, g.nA, alpha, ra);
+  uint64_t cb[W], vb[W];
+  load_bits<W>(g.a_bits, g.nA, jv ? j : 0, cb);
+  const int cm = g.a_m2[jv ? j : 0];
+  load_bits<W>(g.a_bits, g.nA, al, vb);
+  const int vm = g.a_m2[al];
+  int64_t vo = 0;
+  int32_t coff = 0, clen = 0;
+  if (FILL) {
+    vo = g.t_ptr[cell];
+    coff = (int32_t)g.a_off[jv ? j : 0];
+    clen = g.a_len[jv ? j : 0];
+  }
+  int my = 0;
+  for (int k = 0; k < na; ++k) {
+    const int alpha = a0 + k;
+    uint64_t ra[W];
 #pragma unroll
-  for (int w = 0; w < W; ++w) ra[w] = uni(ra[w]);
-  const int m = uni(g.a_m2[alpha]);
-  int64_t out = FILL ? uni(g.t_ptr[unit]) : 0;
-  int cnt = 0;
-  // candidate bits one chunk ahead (clamped, unconditional reads)
-  uint64_t na[W];
-  int nm = 0;
-  auto fetch = [&](int j0) {
-    const int jj = min(j0 + lane, je - 1);
-    load_bits<W>(g.a_bits, g.nA, jj, na);
-    nm = g.a_m2[jj];
-  };
-  fetch(jb);
-  for (int j0 = jb; j0 < je; j0 += kWave) {
-    const int j = j0 + lane;
+    for (int w = 0; w < W; ++w) {
+      const uint32_t lo32 = __builtin_amdgcn_readlane((int)(uint32_t)vb[w], k);
+      const uint32_t hi32 = __builtin_amdgcn_readlane((int)(uint32_t)(vb[w] >> 32), k);
+      ra[w] = (uint64_t)hi32 << 32 | lo32;
+    }
+    const int m = __builtin_amdgcn_readlane(vm, k);
     bool ok = false;
-    uint64_t ca[W];
-#pragma unroll
-    for (int w = 0; w < W; ++w) ca[w] = na[w];
-    const int cm = nm;
-    fetch(j0 + kWave);
-    if (j < je) {
-      const int d = popc_xor<W>(ra, ca);
+    if (jv && (LOWER ? j < alpha : j > alpha)) {
+      const int d = popc_xor<W>(ra, cb);
       ok = d <= 2 || (d == 4 && cm == m);
     }
     const uint64_t msk = ballot(ok);
-    if (FILL && ok) {
-      const int64_t o = out + cnt + mask_rank(msk);
-      g.t_rec[o].off = (int32_t)g.a_off[j];
-      g.t_rec[o].len = g.a_len[j];
+    if constexpr (!FILL) {
+      if (lane == k) my = __popcll(msk);
+    } else if (ok) {
+      const int64_t o = readlane_i64(vo, k) + mask_rank(msk);
+      g.t_rec[o].off = coff;
+      g.t_rec[o].len = clen;
       g.t_src[o] = alpha;
       g.t_dst[o] = j;
     }
-    cnt += __popcll(msk);
   }
-  if (!FILL && lane == 0) g.tcnt[unit] = cnt;
+  if (!FILL && lane < na) g.tcnt[cell] = my;
 }
 
 // ------------------------------------------------------------ B adjacency
@@ -1430,8 +1441,13 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
   auto bytes = [](size_t count, size_t elem) { return dev_bytes(count * elem); };
 
   // ---- counting passes of the two screens (tiles of both triangles)
-  const int nchunk = (nA + kTileChunk - 1) / kTileChunk;
-  const int64_t nunit = (int64_t)nA * nchunk;
+  // tile screen: chunks of 64 candidates, groups of 64 configurations per
+  // wave, fewer where that would leave the grid short of eight waves per SIMD
+  const int nchunk = (nA + kWave - 1) / kWave;
+  int gsz_a = kWave;
+  while (gsz_a > 16 && (int64_t)nchunk * ((nA + gsz_a - 1) / gsz_a) < 8192) gsz_a /= 2;
+  const int ngroup_a = (nA + gsz_a - 1) / gsz_a;
+  const int64_t nunit = (int64_t)nA * nchunk;   // (alpha, chunk) cells
   // the adjacency screen's chunks: 64 configurations of one 2M_B list each
   std::vector<int32_t> coff_h(nseg + 1, 0), chunk_list_h;
   for (int h = 0; h < nseg; ++h) {
@@ -1471,11 +1487,11 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
   CIB_HIP(hipEventRecord(ev.e[0], s));
   launch_substate_energy(b, it, eA.p, eB.p, s);
   TileArgs ta{};
-  ta.nA = nA; ta.nchunk = nchunk; ta.a_bits = b.a_bits.p; ta.a_m2 = b.a_m2.p; ta.a_len = b.a_len.p;
+  ta.nA = nA; ta.nchunk = nchunk; ta.ngroup = ngroup_a; ta.gsz = gsz_a; ta.a_bits = b.a_bits.p; ta.a_m2 = b.a_m2.p; ta.a_len = b.a_len.p;
   ta.a_seg = b.a_seg.p; ta.a_off = b.a_off.p; ta.it = it; ta.tcnt = tcnt.p;
   TileArgs tl = ta;
   tl.tcnt = tlcnt.p;
-  const unsigned tblk = (unsigned)((nunit + 3) / 4);
+  const unsigned tblk = (unsigned)(((int64_t)nchunk * ngroup_a + 3) / 4);
   {
     KTimer kt(ctx, K_TILE, s);
     hipLaunchKernelGGL((k_tile_pass<W, false, false>), dim3(tblk), dim3(256), 0, s, ta);
