@@ -638,7 +638,7 @@ def main():
     elapsed = time.perf_counter() - t0
     _progress("timed steps done")
     kernels = {}
-    for k in ("tile_screen", "adjacency", "row_count", "scan", "row_fill", "spmm_sym", "gram",
+    for k in ("screens", "row_count", "scan", "row_fill", "spmm_sym", "gram",
               "rayleigh_ritz", "update"):
         n, t = ctx.kernel_time(k)
         kernels[k] = {"launches": n, "total_s": t, "mean_s": t / n if n else None}

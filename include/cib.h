@@ -88,11 +88,14 @@ cib_status cib_ctx_bytes(const cib_ctx *ctx, int64_t *live_bytes, int64_t *peak_
 /* Per-kernel device timing: when enabled, the library brackets every launch
  * of its hot kernels with HIP events on the launching stream.  Query sums the
  * elapsed times of all completed launches of one kernel since the last reset
- * (it synchronises those events).  Kernel names: "tile_screen",
- * "adjacency", "row_count", "scan", "row_fill", "spmm_sym", "gram",
- * "rayleigh_ritz", "update" (the build's row passes fill both stored
- * triangles), "state_count", "apply_free" (the matrix-free product's row
- * pass).  Unknown names report zero launches. */
+ * (it synchronises those events).  Kernel names: "spmm_sym", "gram",
+ * "rayleigh_ritz", "update", "state_count", "apply_free" (the matrix-free
+ * product's row pass), and the stages of a build, one launch each per
+ * cib_build_H, timed by the build's own stage events (the device time
+ * between them): "screens" (the tile and adjacency screens with their
+ * substate energies and scans), "row_count", "scan" (the row offsets),
+ * "row_fill" (the row pass that fills both stored triangles).  Unknown
+ * names report zero launches. */
 cib_status cib_profile_enable(cib_ctx *ctx, int on);
 cib_status cib_profile_reset(cib_ctx *ctx);
 cib_status cib_profile_query(cib_ctx *ctx, const char *kernel, int64_t *launches, double *total_s);

@@ -1493,7 +1493,6 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
   tl.tcnt = tlcnt.p;
   const unsigned tblk = (unsigned)(((int64_t)nchunk * ngroup_a + 3) / 4);
   {
-    KTimer kt(ctx, K_TILE, s);
     hipLaunchKernelGGL((k_tile_pass<W, false, false>), dim3(tblk), dim3(256), 0, s, ta);
     hipLaunchKernelGGL((k_tile_pass<W, false, true>), dim3(tblk), dim3(256), 0, s, tl);
   }
@@ -1503,7 +1502,7 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
   aa.chunk_list = chunk_list.p; aa.coff = coff.p; aa.ls_base = ls_base.p; aa.ls_cnt = ls_cnt.p;
   aa.l1_cnt = l1_cnt.p;
   const unsigned ablk = (unsigned)(((int64_t)nchunk_b * ngroup_b + 3) / 4);
-  { KTimer kt(ctx, K_ADJ, s); hipLaunchKernelGGL((k_adj_pass<W, false>), dim3(ablk), dim3(256), 0, s, aa); }
+  hipLaunchKernelGGL((k_adj_pass<W, false>), dim3(ablk), dim3(256), 0, s, aa);
   CIB_HIP(hipGetLastError());
   launch_scans({{tcnt.p, nunit, t_ptr.p}, {tlcnt.p, nunit, tl_ptr.p}, {ls_cnt.p, nlcell, ls_off.p},
                 {l1_cnt.p, ncell, l1_off.p}},
@@ -1568,7 +1567,6 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
   tl.t_ptr = tl_ptr.p; tl.t_rec = tl_rec.p; tl.t_src = tl_src.p; tl.t_dst = tl_dst.p;
   auto nb256 = [](int64_t n) { return dim3((unsigned)std::max<int64_t>((n + 255) / 256, 1)); };
   {
-    KTimer kt(ctx, K_TILE, s);
     hipLaunchKernelGGL((k_tile_pass<W, true, false>), dim3(tblk), dim3(256), 0, s, ta);
     hipLaunchKernelGGL((k_tile_pass<W, true, true>), dim3(tblk), dim3(256), 0, s, tl);
     // phases and values, one thread per tile
@@ -1582,7 +1580,6 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
   aa.ls_off = ls_off.p; aa.l1_off = l1_off.p; aa.ls_self = ls_self.p; aa.ls_rec = ls_rec.p;
   aa.l1_rec = l1_rec.p; aa.ls_src = ls_src.p; aa.ls_dst = ls_dst.p; aa.l1_src = l1_src.p; aa.l1_dst = l1_dst.p;
   {
-    KTimer kt(ctx, K_ADJ, s);
     hipLaunchKernelGGL((k_adj_pass<W, true>), dim3(ablk), dim3(256), 0, s, aa);
     // phases, table columns and B-only values, one thread per entry
     if (n_ls)
@@ -1632,7 +1629,6 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
     return;
   }
   {
-    KTimer kt(ctx, K_ROW_COUNT, s);
     if (tab_count) {
       CIB_HIP(hipMemsetAsync(ls_lev.p, 0, sizeof(int32_t) * (size_t)nB * p.nlev, s));
       const unsigned ablk4 = (unsigned)((nA + 3) / 4);
@@ -1659,7 +1655,6 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
   CIB_HIP(hipGetLastError());
   CIB_HIP(hipEventRecord(ev.e[4], s));
   {
-    KTimer kt(ctx, K_SCAN, s);
     launch_scans({{rcnt.p, p.D, H.row_ptr.p}, {rlcnt.p, p.D, H.lo_ptr.p}}, scratch.p, s);
   }
   CIB_HIP(hipEventRecord(ev.e[5], s));
@@ -1689,7 +1684,6 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
   rl.val = dt == CIB_F64 ? (void *)H.lo_val64.p : (void *)H.lo_val32.p;
   CIB_HIP(hipEventRecord(ev.e[6], s));
   {
-    KTimer kt(ctx, K_ROW_FILL, s);
     if (dt == CIB_F64)
       hipLaunchKernelGGL((k_row_pass<W, true, double>), dim3(rblk), dim3(256), 0, s, ra, rl);
     else
@@ -1712,6 +1706,13 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
   H.stats.t_scan_s = ev.ms(4, 5);
   H.stats.t_fill_s = ev.ms(6, 7);
   H.stats.t_total_s = H.stats.t_screen_s + H.stats.t_count_s + H.stats.t_scan_s + H.stats.t_fill_s;
+  // the per-stage device times of the profile come from the stage events
+  // above (timers of their own inside the stages would hold the device idle
+  // while the host records them between the short kernels)
+  profile_add(ctx, K_SCREEN, H.stats.t_screen_s);
+  profile_add(ctx, K_ROW_COUNT, H.stats.t_count_s);
+  profile_add(ctx, K_SCAN, H.stats.t_scan_s);
+  profile_add(ctx, K_ROW_FILL, H.stats.t_fill_s);
   H.stats.n_tiles = n_tiles;
   H.stats.n_adjacent = n_ls + n_l1;
 }

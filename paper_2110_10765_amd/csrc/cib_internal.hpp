@@ -80,7 +80,7 @@ struct cib_ctx {
 namespace cib {
 
 // Hot kernels known to the profiler.
-enum KernelId { K_TILE = 0, K_ADJ, K_ROW_COUNT, K_SCAN, K_ROW_FILL, K_SPMM, K_GRAM, K_RR, K_UPDATE, K_COUNT, K_APPLY_FREE, K_NKERN };
+enum KernelId { K_SCREEN = 0, K_ROW_COUNT, K_SCAN, K_ROW_FILL, K_SPMM, K_GRAM, K_RR, K_UPDATE, K_COUNT, K_APPLY_FREE, K_NKERN };
 extern const char *const kKernelNames[K_NKERN];
 
 // Timer marks recorded so far, and dropping the marks from index `from` on
@@ -89,6 +89,10 @@ extern const char *const kKernelNames[K_NKERN];
 size_t profile_marks(cib_ctx *c);
 void profile_drop_marks(cib_ctx *c, size_t from);
 // Brackets one launch with events when profiling is on (RAII).
+// A stage time measured by other events, added to the profile (when on)
+// as one launch of that kernel.
+void profile_add(cib_ctx *c, int kernel, double seconds);
+
 struct KTimer {
   cib_ctx *ctx;
   int k;

@@ -107,7 +107,7 @@ static TransLayout trans_layout(const Orbs &oa, const Orbs &ob) {
   return T;
 }
 
-const char *const kKernelNames[K_NKERN] = {"tile_screen", "adjacency", "row_count", "scan",
+const char *const kKernelNames[K_NKERN] = {"screens", "row_count", "scan",
                                            "row_fill", "spmm_sym", "gram", "rayleigh_ritz", "update",
                                            "state_count", "apply_free"};
 
@@ -150,6 +150,14 @@ void profile_collect(cib_ctx *c) {
     c->event_pool.push_back(m.b);
   }
   c->marks.clear();
+}
+
+void profile_add(cib_ctx *c, int kernel, double seconds) {
+  if (!c || !c->profiling) return;
+  std::lock_guard<std::mutex> g(c->mu);
+  auto &t = c->kernel_totals[kernel];
+  t.first += 1;
+  t.second += seconds;
 }
 
 size_t profile_marks(cib_ctx *c) {
