@@ -247,8 +247,9 @@ cib_status lanczos_solve(cib_ctx *ctx, const cib_matrix &H, int nev, int max_ite
   int n = 0, conv = 0;
   double t_spmv = 0.0;
   hipEvent_t e0, e1;
-  CIB_HIP(hipEventCreate(&e0));
-  CIB_HIP(hipEventCreate(&e1));
+  // timing only: no system-scope fence at every record
+  CIB_HIP(hipEventCreateWithFlags(&e0, hipEventDisableSystemFence));
+  CIB_HIP(hipEventCreateWithFlags(&e1, hipEventDisableSystemFence));
   std::vector<double> resid(nev, INFINITY);
   for (int k = 0; k < m; ++k) {
     double *vk = V.p + (int64_t)k * D;

@@ -638,8 +638,9 @@ struct LobpcgRun {
     }
     if (timing)
       for (int k = 0; k < kIterBatch; ++k) {
-        CIB_HIP(hipEventCreate(&ev0[k]));
-        CIB_HIP(hipEventCreate(&ev1[k]));
+        // timing only: no system-scope fence at every record
+        CIB_HIP(hipEventCreateWithFlags(&ev0[k], hipEventDisableSystemFence));
+        CIB_HIP(hipEventCreateWithFlags(&ev1[k], hipEventDisableSystemFence));
       }
   }
   ~LobpcgRun() {

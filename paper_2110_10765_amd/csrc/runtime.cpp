@@ -118,7 +118,9 @@ static hipEvent_t take_event(cib_ctx *c) {
     return e;
   }
   hipEvent_t e;
-  CIB_HIP(hipEventCreate(&e));
+  // timing only: no system-scope fence (no cache writeback and invalidate
+  // at every record)
+  CIB_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
   return e;
 }
 
