@@ -578,15 +578,26 @@ __global__ __launch_bounds__(256) void k_adj_pass(AdjArgs g) {
 
 // The per-(beta, list) starts of the L1 lists and the per-beta starts of the
 // Lsame lists, from the per-(beta, chunk) scans (a list without chunks
-// starts where the next one does).
+// starts where the next one does).  Also zeroes the level-count tables that
+// k_l1_levels and k_ls_levels fill later (nlev values per (beta, list), and
+// per beta; lev_t and ls_lev may be null), so that no fill is queued
+// between the build's kernels.
 __global__ __launch_bounds__(256) void k_adj_offsets(int nB, int nseg, int nchunk, const int32_t *__restrict__ coff,
                                                      const int32_t *__restrict__ ls_base,
                                                      const int64_t *__restrict__ ls_off,
                                                      const int64_t *__restrict__ l1_off, int64_t *__restrict__ ls_ptr,
-                                                     int64_t *__restrict__ l1_seg) {
+                                                     int64_t *__restrict__ l1_seg, int nlev,
+                                                     int32_t *__restrict__ lev_cnt, int32_t *__restrict__ lev_t,
+                                                     int32_t *__restrict__ ls_lev) {
   const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int64_t n = (int64_t)nB * nseg;
   if (e < n) {
+    for (int t = 0; t < nlev; ++t) {
+      lev_cnt[e * nlev + t] = 0;
+      if (lev_t) lev_t[e * nlev + t] = 0;
+    }
+    if (ls_lev && e < nB)
+      for (int t = 0; t < nlev; ++t) ls_lev[e * nlev + t] = 0;
     const int beta = (int)(e / nseg), h = (int)(e % nseg);
     l1_seg[e] = l1_off[(int64_t)beta * nchunk + coff[h]];
     if (h == 0) ls_ptr[beta] = ls_off[ls_base[beta]];
@@ -1472,7 +1483,9 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
     reserve(0, bytes(nA, 8) + bytes(nB, 8) + 2 * bytes(nunit, 4) + bytes(nlcell, 4) + bytes(ncell, 4) +
                    2 * bytes(nunit + 1, 8) + bytes(nlcell + 1, 8) + bytes(ncell + 1, 8) + bytes(nB + 1, 8) +
                    bytes((size_t)nB * nseg + 1, 8) + bytes(nscr, 8) + bytes(4, 8) +
-                   bytes(std::max<size_t>(chunk_list_h.size(), 1), 4) + bytes(nseg + 1, 4) + bytes(nB + 1, 4));
+                   bytes(std::max<size_t>(chunk_list_h.size(), 1), 4) + bytes(nseg + 1, 4) + bytes(nB + 1, 4) +
+                   (tab_count ? 2 : 1) * bytes((size_t)nB * nseg * p.nlev, 4) +
+                   (tab_count && !ap ? bytes((size_t)nB * p.nlev, 4) : 0));
   // (each stage's buffers are taken before its first event: host work inside
   // a timed interval would leave the device idle there)
   DBuf<double> eA(ctx, nA), eB(ctx, nB);
@@ -1482,6 +1495,11 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
   DBuf<int64_t> scratch(ctx, nscr), totals(ctx, 4);
   DBuf<int32_t> chunk_list(ctx, std::max<size_t>(chunk_list_h.size(), 1)), coff(ctx, nseg + 1);
   DBuf<int32_t> ls_base(ctx, nB + 1);
+  // level counts of the L1 lists (per (beta, list); also bin-major for the
+  // table-driven row counts) and of the Lsame lists, zeroed by k_adj_offsets
+  DBuf<int32_t> lev_cnt(ctx, (size_t)nB * nseg * p.nlev), lev_t, ls_lev;
+  if (tab_count) lev_t.reset(ctx, (size_t)nB * nseg * p.nlev);
+  if (tab_count && !ap) ls_lev.reset(ctx, (size_t)nB * p.nlev);
   chunk_list.upload(chunk_list_h.data(), chunk_list_h.size(), s);
   coff.upload(coff_h.data(), nseg + 1, s);
   ls_base.upload(ls_base_h.data(), nB + 1, s);
@@ -1509,7 +1527,8 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
                 {l1_cnt.p, ncell, l1_off.p}},
                scratch.p, s);
   hipLaunchKernelGGL(k_adj_offsets, dim3((unsigned)(((int64_t)nB * nseg + 256) / 256)), dim3(256), 0, s, nB, nseg,
-                     nchunk_b, coff.p, ls_base.p, ls_off.p, l1_off.p, ls_ptr.p, l1_seg.p);
+                     nchunk_b, coff.p, ls_base.p, ls_off.p, l1_off.p, ls_ptr.p, l1_seg.p, p.nlev, lev_cnt.p,
+                     tab_count ? lev_t.p : nullptr, tab_count && !ap ? ls_lev.p : nullptr);
   CIB_HIP(hipEventRecord(ev.e[1], s));
   int64_t n4[4];
   read_totals({t_ptr.p + nunit, tl_ptr.p + nunit, ls_ptr.p + nB, l1_seg.p + (int64_t)nB * nseg}, totals.p, n4, s);
@@ -1522,10 +1541,8 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
     // screens, row counts, diagonal and the two offset arrays
     reserve(1, (bytes(nt, 16) + 2 * bytes(nt, 4) + bytes(nt, 8)) + (bytes(nl, 16) + 2 * bytes(nl, 4) + bytes(nl, 8)) +
                    bytes(nB, 4) + bytes(ns, 8) + 2 * bytes(ns, 4) + bytes(n1, 8) + 2 * bytes(n1, 4) + bytes(ns, 8) +
-                   bytes((size_t)nB * nseg * p.nlev, 4) +
                    (tab_count ? 2 * bytes((size_t)nA * nseg * p.nlev, 4) + bytes(nt, 4) + bytes(nl, 4) +
-                                    bytes((size_t)nB * nseg * p.nlev, 4) + bytes(nA + 1, 4) +
-                                    2 * bytes(nA, 4) + bytes((size_t)nB * p.nlev, 4)
+                                    bytes(nA + 1, 4) + 2 * bytes(nA, 4)
                               : 0) +
                    2 * bytes(p.D, 4) +
                    bytes(p.D, 8) + 2 * bytes(p.D + 1, 8));
@@ -1539,13 +1556,10 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
   DBuf<int32_t> ls_src(ctx, at_least1(n_ls)), ls_dst(ctx, at_least1(n_ls));
   DBuf<int32_t> l1_src(ctx, at_least1(n_l1)), l1_dst(ctx, at_least1(n_l1));
   DBuf<double> ls_val(ctx, at_least1(n_ls));
-  DBuf<int32_t> lev_cnt(ctx, (size_t)nB * nseg * p.nlev);
-  DBuf<int32_t> lev_t;   // the same, bin-major (table-driven row counts only)
-  if (tab_count) lev_t.reset(ctx, (size_t)nB * nseg * p.nlev);
   // the row-count stage's buffers and the row offsets
   DBuf<int32_t> rcnt(ctx, p.D), rlcnt(ctx, p.D);
   DBuf<double> diag(ctx, p.D);
-  DBuf<int32_t> hist_u, hist_l, k2len_u, k2len_l, k2n_u, k2n_l, ls_lev, cstart;
+  DBuf<int32_t> hist_u, hist_l, k2len_u, k2len_l, k2n_u, k2n_l, cstart;
   std::vector<int32_t> cstart_h(nA + 1, 0);   // waves of k_row_count_tab: one per 64 rows of each block
   if (tab_count && !ap) {
     for (int a2 = 0; a2 < nA; ++a2) cstart_h[a2 + 1] = cstart_h[a2] + (p.a_len[a2] + kWave - 1) / kWave;
@@ -1557,7 +1571,6 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
     k2len_l.reset(ctx, at_least1(n_lt));
     k2n_u.reset(ctx, nA);
     k2n_l.reset(ctx, nA);
-    ls_lev.reset(ctx, (size_t)nB * p.nlev);
   }
   if (!ap) {
     H.row_ptr.reset(ctx, p.D + 1);
@@ -1589,8 +1602,6 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
     if (n_l1)
       hipLaunchKernelGGL((k_adj_val<W>), nb256(n_l1), dim3(256), 0, s, n_l1, l1_src.p, l1_dst.p, b.b_bits.p,
                          nB, eB.p, it, l1_rec.p, (double *)nullptr);
-    CIB_HIP(hipMemsetAsync(lev_cnt.p, 0, sizeof(int32_t) * (size_t)nB * nseg * p.nlev, s));
-    if (tab_count) CIB_HIP(hipMemsetAsync(lev_t.p, 0, sizeof(int32_t) * (size_t)nB * nseg * p.nlev, s));
     if (n_l1)
       hipLaunchKernelGGL(k_l1_levels, nb256(n_l1), dim3(256), 0, s, n_l1, nseg, p.nlev, p.qminB, l1_seg.p,
                          l1_src.p, l1_dst.p, b.b_seg.p, b.b_q.p, lev_cnt.p, nB, tab_count ? lev_t.p : nullptr);
@@ -1631,7 +1642,6 @@ static void build_w(cib_ctx *ctx, const cib_basis &b, const cib_interaction &itr
   }
   {
     if (tab_count) {
-      CIB_HIP(hipMemsetAsync(ls_lev.p, 0, sizeof(int32_t) * (size_t)nB * p.nlev, s));
       const unsigned ablk4 = (unsigned)((nA + 3) / 4);
       hipLaunchKernelGGL(k_tile_hist, dim3(ablk4), dim3(256), 0, s, nA, t_ptr.p, nchunk, t_rec.p, p.nlev, (int)nbin,
                          hist_u.p, k2len_u.p, k2n_u.p);
